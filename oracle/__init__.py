@@ -1,0 +1,165 @@
+"""FP64 CPU oracle of the multilevel asymptotic-preserving Monte Carlo method.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark.  The product package never imports it, and
+it imports nothing from the product package.
+
+Contents
+--------
+``oracle.c``           particle scheme, fine/coarse correlation, Philox4x32-10
+                       (plain C, double precision, one trajectory at a time)
+``closed_form.py``     exact second moment of the discrete scheme and its
+                       kinetic and diffusive limits
+``mlmc.py``            two-pass level statistics, optimal sample numbers
+                       (Section 4.1, eqs. Nopt1/Noptj) and the MLMC loop
+``build.py``           compiles ``oracle.c`` with gcc into ``liboracle.so``
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+# ORACLE_LIB_PATH lets the mutation tests load a deliberately broken build.
+_LIB_PATH = os.environ.get("ORACLE_LIB_PATH", os.path.join(_HERE, "liboracle.so"))
+_lib = None
+
+X0_DELTA, X0_NORMAL, X0_COSINE = 0, 1, 2
+EQ_TWO_POINT, EQ_MAXWELLIAN = 0, 1
+COUPLING_KICK_SUM, COUPLING_AGGREGATE = 0, 1
+
+
+def lib():
+    """Loads ``liboracle.so``, building it with gcc first if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _build
+            _build.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_uniform.argtypes = [ctypes.c_uint32]
+        L.oracle_uniform.restype = ctypes.c_double
+        L.oracle_cosine_icdf.argtypes = [ctypes.c_double]
+        L.oracle_cosine_icdf.restype = ctypes.c_double
+        L.oracle_coarse_threshold.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int]
+        L.oracle_coarse_threshold.restype = ctypes.c_uint64
+        L.oracle_level_consts.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int, ctypes.c_int, dp, u64p]
+        L.oracle_level_consts.restype = None
+        common = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                  ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                  ctypes.c_uint32]
+        L.oracle_simulate.argtypes = common + [ctypes.c_uint64, u64p, ctypes.c_uint64,
+                                               dp, dp, u32p, u32p, ctypes.c_int]
+        L.oracle_simulate.restype = ctypes.c_int
+        L.oracle_trace.argtypes = common + [ctypes.c_uint64, dp, ctypes.c_uint64, dp]
+        L.oracle_trace.restype = ctypes.c_uint64
+        L.oracle_words.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                   ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, u32p]
+        L.oracle_words.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def default_threads():
+    return max(1, len(os.sched_getaffinity(0)))
+
+
+def philox4x32_10(ctr, key):
+    """One Philox4x32-10 block: four counter words, two key words -> four words."""
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32),
+                               _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def uniform(w):
+    return lib().oracle_uniform(int(w))
+
+
+def cosine_icdf(u):
+    return lib().oracle_cosine_icdf(float(u))
+
+
+def coarse_threshold(thr_f, thr_c, M):
+    return int(lib().oracle_coarse_threshold(int(thr_f), int(thr_c), int(M)))
+
+
+def level_consts(eps, T, dt0, M, level):
+    """(dt, h, s, p, n_steps, threshold) of one level."""
+    d = np.zeros(4)
+    n = np.zeros(2, dtype=np.uint64)
+    lib().oracle_level_consts(eps, T, dt0, M, level, _ptr(d, ctypes.c_double),
+                              _ptr(n, ctypes.c_uint64))
+    return dict(dt=d[0], h=d[1], s=d[2], p=d[3], n_steps=int(n[0]), thr=int(n[1]))
+
+
+def _common_args(prob, level, single):
+    return (float(prob["eps"]), float(prob["T"]), float(prob["dt0"]), int(prob["M"]),
+            int(level), int(bool(single)), int(prob["x0_kind"]), float(prob.get("x0_a", 0.0)),
+            float(prob.get("x0_b", 0.0)), int(prob["eq_kind"]), int(prob.get("coupling", 0)),
+            int(prob.get("seed", 42)), int(prob.get("stream_id", 0)))
+
+
+def simulate(prob, level, sample_begin=0, n=None, samples=None, single=False, threads=None):
+    """Final positions and collision counts of fine/coarse pairs.
+
+    ``prob`` is a dict with keys eps, T, dt0, M, x0_kind, x0_a, x0_b, eq_kind,
+    coupling, seed, stream_id.  Either a contiguous range
+    [sample_begin, sample_begin+n) or an explicit index array ``samples``.
+    Returns dict(xf, xc, cf, cc) of numpy arrays.
+    """
+    if samples is not None:
+        idx = np.ascontiguousarray(samples, dtype=np.uint64)
+        count = idx.size
+        idx_p = _ptr(idx, ctypes.c_uint64)
+    else:
+        count = int(n)
+        idx = None
+        idx_p = None
+    xf = np.zeros(count)
+    xc = np.zeros(count)
+    cf = np.zeros(count, dtype=np.uint32)
+    cc = np.zeros(count, dtype=np.uint32)
+    if count:
+        lib().oracle_simulate(*_common_args(prob, level, single), int(sample_begin), idx_p,
+                              count, _ptr(xf, ctypes.c_double), _ptr(xc, ctypes.c_double),
+                              _ptr(cf, ctypes.c_uint32), _ptr(cc, ctypes.c_uint32),
+                              int(threads or default_threads()))
+    return dict(xf=xf, xc=xc, cf=cf, cc=cc)
+
+
+TRACE_COLUMNS = ("n", "w0", "w1", "w2", "w3", "u1", "u2", "xi", "g", "hit",
+                 "xf", "vf", "kick", "coarse_hit", "xc", "vc")
+
+
+def trace(prob, level, sample, single=False):
+    """Per-fine-step record of one sample (columns ``TRACE_COLUMNS``) and
+    the final (x_f, x_c)."""
+    nsteps = level_consts(prob["eps"], prob["T"], prob["dt0"], prob["M"], level)["n_steps"]
+    rows = np.zeros((nsteps, 16))
+    fin = np.zeros(2)
+    used = lib().oracle_trace(*_common_args(prob, level, single), int(sample),
+                              _ptr(rows, ctypes.c_double), nsteps, _ptr(fin, ctypes.c_double))
+    return rows[:used], fin
+
+
+def words(seed, stream_id, tag, sample_begin, n_samples, n_steps):
+    """Philox words, array [n_samples, n_steps, 4] for counters
+    (step, sample, tag, stream_id)."""
+    out = np.zeros((n_samples, n_steps, 4), dtype=np.uint32)
+    lib().oracle_words(int(seed), int(stream_id), int(tag), int(sample_begin), int(n_samples),
+                       int(n_steps), _ptr(out, ctypes.c_uint32))
+    return out

@@ -1,0 +1,352 @@
+/*
+ * FP64 CPU oracle for the multilevel asymptotic-preserving Monte Carlo
+ * particle method (Mortier, Robbe, Baelmans, Samaey, "Multilevel
+ * asymptotic-preserving Monte Carlo for kinetic-diffusive particle
+ * simulations of the Boltzmann-BGK equation").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product
+ * path (the HIP library) never calls it and shares no code with it.
+ *
+ * It is written to be slow and obviously correct: one trajectory at a time,
+ * every quantity in double precision, each step in the order the method
+ * states it.  Parity status of each function is given in its comment;
+ * every function here is pinned by the CPU tests (Philox known-answer
+ * vectors, closed-form moments, brute-force enumeration, distribution
+ * tests of the coarse random numbers).
+ *
+ * The particle scheme (asymptotic-preserving splitting, the scheme the paper
+ * cites from Dimarco et al. in its introduction) for the diffusively scaled
+ * BGK equation  df/dt + (v/eps) df/dx = (M rho - f)/eps^2  with an
+ * equilibrium M of unit variance, at fixed time step dt:
+ *     h = dt*eps/(eps^2+dt)              drift multiplier of the velocity
+ *     s = sqrt(2*dt*dt/(eps^2+dt))       standard deviation of the kick
+ *     p = dt/(eps^2+dt)                  collision probability
+ *   transport-diffusion:  x <- x + h*v + s*xi,  xi ~ N(0,1)
+ *   collision:            with probability p, v <- fresh draw from M
+ *
+ * Levels: dt_l = dt0 / M^l, n_l = T/dt_l steps (Section 4.1 uses T/2^l; the
+ * refinement factor M generalises the factor 2 as in Section 5.1).
+ *
+ * Fine/coarse correlation (Section 3): every coarse random number is built
+ * from fine random numbers mapped by the time at which they act (Section
+ * 3.1): coarse step K uses the fine steps K*M .. K*M+M-1.
+ *   - coarse kick: normalised weighted sum of the fine kick normals and of the
+ *     fine velocity normals that the coarse path does not reuse
+ *     (eq. chi-update, weights after eqs. for alpha and beta);
+ *   - coarse velocity: the fine velocity normal drawn last in the block
+ *     (eq. nu-update);
+ *   - coarse collision: a Bernoulli draw built from the fine collision
+ *     decisions and the conditionally uniform decision word of the first
+ *     fine collision in the block (the uniform analogue of the
+ *     memorylessness argument of eq. epsilon-update).
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
+ * random numbers: as easy as 1, 2, 3", SC 2011), key = seed, counter =
+ * (step, sample, level tag, stream).  Step 0xFFFFFFFF is the initial draw.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10, written from the published definition.               */
+/* ------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                          uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += 0x9E3779B9u;   /* Weyl key schedule */
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Uniform on (0,1): the odd multiple (2*(w>>9)+1) * 2^-24. */
+double oracle_uniform(uint32_t w)
+{
+    return (2.0 * (double)(w >> 9) + 1.0) * 0x1p-24;
+}
+
+/* Box-Muller pair from two words: cosine branch and sine branch. */
+static void box_muller(uint32_t wa, uint32_t wb, double *c, double *s)
+{
+    double u1 = oracle_uniform(wa);
+    double u2 = oracle_uniform(wb);
+    double r = sqrt(-2.0 * log(u1));
+    double theta = 2.0 * M_PI * u2;
+    *c = r * cos(theta);
+    *s = r * sin(theta);
+}
+
+/* Inverse CDF of the density 1 + cos(2 pi x) on [0,1]:
+ * F(x) = x + sin(2 pi x)/(2 pi), solved by plain bisection. */
+double oracle_cosine_icdf(double u)
+{
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double F = mid + sin(2.0 * M_PI * mid) / (2.0 * M_PI);
+        if (F < u) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* ------------------------------------------------------------------ */
+/* Level constants.                                                    */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    double dt, h, s, p;
+    uint64_t n_steps;
+    uint64_t thr;        /* collide iff word < thr; thr = round(p * 2^32) */
+} level_consts;
+
+static level_consts make_level(double eps, double T, double dt0, int M, int l)
+{
+    level_consts c;
+    c.dt = dt0 / pow((double)M, (double)l);
+    double denom = eps * eps + c.dt;
+    c.h = c.dt * eps / denom;
+    c.s = sqrt(2.0 * c.dt * c.dt / denom);
+    c.p = c.dt / denom;
+    c.n_steps = (uint64_t)llround(T / dt0) * (uint64_t)llround(pow((double)M, (double)l));
+    c.thr = (uint64_t)llround(c.p * 4294967296.0);
+    return c;
+}
+
+/* Threshold of the coarse decision word: the coarse path of level l
+ * collides iff the block of M fine steps holds a fine collision and the
+ * decision word of its first fine collision is below thr_c2.  Given a fine
+ * collision that word is uniform on [0, thr_f), so
+ *   P(coarse collision) = (1 - q_f^M) * thr_c2 / thr_f,
+ * and thr_c2 = thr_f * p_c / (1 - q_f^M) makes it the coarse level's own
+ * collision probability p_c = thr_c / 2^32. */
+uint64_t oracle_coarse_threshold(uint64_t thr_f, uint64_t thr_c, int M)
+{
+    if (thr_f == 0) return 0;
+    double pf = (double)thr_f / 4294967296.0;
+    double pc = (double)thr_c / 4294967296.0;
+    double any = -expm1((double)M * log1p(-pf));   /* P(>= 1 fine collision) */
+    double t = (double)thr_f * pc / any;
+    uint64_t r = (uint64_t)llround(t);
+    if (r > thr_f) r = thr_f;
+    return r;
+}
+
+void oracle_level_consts(double eps, double T, double dt0, int M, int l,
+                         double out_dhsp[4], uint64_t out_n_thr[2])
+{
+    level_consts c = make_level(eps, T, dt0, M, l);
+    out_dhsp[0] = c.dt; out_dhsp[1] = c.h; out_dhsp[2] = c.s; out_dhsp[3] = c.p;
+    out_n_thr[0] = c.n_steps; out_n_thr[1] = c.thr;
+}
+
+/* ------------------------------------------------------------------ */
+/* One fine/coarse pair (or one single-level trajectory).              */
+/* ------------------------------------------------------------------ */
+enum { X0_DELTA = 0, X0_NORMAL = 1, X0_COSINE = 2 };
+enum { EQ_TWO_POINT = 0, EQ_MAXWELLIAN = 1 };
+enum { COUPLING_KICK_SUM = 0, COUPLING_AGGREGATE = 1 };
+
+typedef struct {
+    double eps, T, dt0;
+    int M, level, single;
+    int x0_kind; double x0_a, x0_b;
+    int eq_kind, coupling;
+    uint32_t key[2];
+    uint32_t stream;
+} problem_t;
+
+/* Optional per-step record for tiny golden traces. */
+typedef struct {
+    double *rows;      /* n_rows x 16 doubles, or NULL */
+    uint64_t cap, used;
+} trace_t;
+
+static void trace_row(trace_t *tr, const double v[16])
+{
+    if (!tr || !tr->rows || tr->used >= tr->cap) return;
+    memcpy(tr->rows + 16 * tr->used, v, 16 * sizeof(double));
+    tr->used++;
+}
+
+/* Simulates sample `sample` and returns x_f(T), x_c(T), fine and coarse
+ * collision counts.  Level 0 (or single mode) has no coarse path. */
+static void simulate_one(const problem_t *P, uint64_t sample,
+                         double *xf_out, double *xc_out,
+                         uint32_t *cf_out, uint32_t *cc_out, trace_t *tr)
+{
+    const int l = P->level;
+    const int coarse = (!P->single && l >= 1);
+    const uint32_t tag = (uint32_t)l + (P->single ? 64u : 0u);
+    level_consts F = make_level(P->eps, P->T, P->dt0, P->M, l);
+    level_consts C = coarse ? make_level(P->eps, P->T, P->dt0, P->M, l - 1) : F;
+    uint64_t thr_c2 = coarse ? oracle_coarse_threshold(F.thr, C.thr, P->M) : 0;
+
+    uint32_t ctr[4], w[4];
+
+    /* Initial condition (shared by the fine and the coarse path). */
+    ctr[0] = 0xFFFFFFFFu; ctr[1] = (uint32_t)sample; ctr[2] = tag; ctr[3] = P->stream;
+    oracle_philox4x32_10(ctr, P->key, w);
+    double nc, ns;
+    box_muller(w[1], w[2], &nc, &ns);
+    double x0;
+    if (P->x0_kind == X0_DELTA) x0 = P->x0_a;
+    else if (P->x0_kind == X0_NORMAL) x0 = P->x0_a + P->x0_b * nc;
+    else x0 = oracle_cosine_icdf(oracle_uniform(w[0]));
+    double v0 = (P->eq_kind == EQ_MAXWELLIAN) ? ns : ((w[3] >> 31) ? -1.0 : 1.0);
+
+    double xf = x0, vf = v0, xc = x0, vc = v0;
+    uint32_t cf = 0, cc = 0;
+
+    /* Per-block coarse bookkeeping. */
+    double sum_xi = 0.0;          /* sum of the fine kick normals */
+    double vel_num = 0.0;         /* sum of n_j * nu_j over superseded draws */
+    double vel_den = 0.0;         /* sum of n_j^2 */
+    int have_draw = 0;            /* a fine velocity was drawn in this block */
+    double last_nu = 0.0;         /* normal of the latest in-block draw */
+    double last_uses = 0.0;       /* transport uses of that draw so far */
+    int block_hit = 0;            /* a fine collision happened in the block */
+    uint32_t first_word = 0;      /* decision word of the first one */
+
+    for (uint64_t n = 0; n < F.n_steps; ++n) {
+        ctr[0] = (uint32_t)n; ctr[1] = (uint32_t)sample; ctr[2] = tag; ctr[3] = P->stream;
+        oracle_philox4x32_10(ctr, P->key, w);
+        double xi, g;
+        box_muller(w[1], w[2], &xi, &g);
+        double v_new = (P->eq_kind == EQ_MAXWELLIAN) ? g : ((w[3] >> 31) ? -1.0 : 1.0);
+
+        /* transport-diffusion with the pre-collision velocity */
+        xf = xf + F.h * vf + F.s * xi;
+        if (have_draw) last_uses += 1.0;
+        sum_xi += xi;
+
+        /* collision */
+        int hit = ((uint64_t)w[0] < F.thr);
+        if (hit) {
+            vf = v_new;
+            cf++;
+            if (!block_hit) { block_hit = 1; first_word = w[0]; }
+            if (have_draw) {          /* previous in-block draw is superseded */
+                vel_num += last_uses * last_nu;
+                vel_den += last_uses * last_uses;
+            }
+            have_draw = 1; last_nu = v_new; last_uses = 0.0;
+        }
+
+        double row[16] = {(double)n, (double)w[0], (double)w[1], (double)w[2], (double)w[3],
+                          oracle_uniform(w[1]), oracle_uniform(w[2]), xi, g, (double)hit,
+                          xf, vf, 0, 0, 0, 0};
+
+        if (coarse && (n % (uint64_t)P->M) == (uint64_t)(P->M - 1)) {
+            int chit = block_hit && ((uint64_t)first_word < thr_c2);
+            double kick;
+            if (P->coupling == COUPLING_KICK_SUM) {
+                kick = sum_xi / sqrt((double)P->M);
+            } else {
+                /* the last in-block draw becomes the coarse velocity when the
+                 * coarse path collides; otherwise it joins the kick */
+                double num = vel_num, den = vel_den;
+                if (have_draw && !chit) {
+                    num += last_uses * last_nu;
+                    den += last_uses * last_uses;
+                }
+                kick = (F.s * sum_xi + F.h * num) /
+                       sqrt((double)P->M * F.s * F.s + F.h * F.h * den);
+            }
+            xc = xc + C.h * vc + C.s * kick;
+            if (chit) { vc = vf; cc++; }
+            row[12] = kick; row[13] = (double)chit; row[14] = xc; row[15] = vc;
+            sum_xi = 0.0; vel_num = 0.0; vel_den = 0.0;
+            have_draw = 0; last_nu = 0.0; last_uses = 0.0;
+            block_hit = 0; first_word = 0;
+        }
+        trace_row(tr, row);
+    }
+    if (!coarse) { xc = 0.0; cc = 0; }
+    *xf_out = xf; *xc_out = xc; *cf_out = cf; *cc_out = cc;
+}
+
+static problem_t make_problem(double eps, double T, double dt0, int M, int level,
+                              int single, int x0_kind, double x0_a, double x0_b,
+                              int eq_kind, int coupling, uint64_t seed, uint32_t stream)
+{
+    problem_t P;
+    P.eps = eps; P.T = T; P.dt0 = dt0; P.M = M; P.level = level; P.single = single;
+    P.x0_kind = x0_kind; P.x0_a = x0_a; P.x0_b = x0_b;
+    P.eq_kind = eq_kind; P.coupling = coupling;
+    P.key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
+    P.key[1] = (uint32_t)(seed >> 32);
+    P.stream = stream;
+    return P;
+}
+
+/* Simulates the listed sample indices (idx != NULL) or the contiguous range
+ * [sample_begin, sample_begin + n) (idx == NULL).  Outputs are indexed by
+ * position in the list.  Each sample is independent, so the threads only
+ * split the list; results do not depend on the thread count. */
+int oracle_simulate(double eps, double T, double dt0, int M, int level, int single,
+                    int x0_kind, double x0_a, double x0_b, int eq_kind, int coupling,
+                    uint64_t seed, uint32_t stream,
+                    uint64_t sample_begin, const uint64_t *idx, uint64_t n,
+                    double *xf, double *xc, uint32_t *cf, uint32_t *cc, int nthreads)
+{
+    problem_t P = make_problem(eps, T, dt0, M, level, single, x0_kind, x0_a, x0_b,
+                               eq_kind, coupling, seed, stream);
+    (void)nthreads;
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+        uint64_t s = idx ? idx[i] : sample_begin + (uint64_t)i;
+        simulate_one(&P, s, &xf[i], &xc[i], &cf[i], &cc[i], NULL);
+    }
+    return 0;
+}
+
+/* Per-step trace of one sample: 16 doubles per fine step
+ * (n, w0..w3, u1, u2, xi, g, hit, x_f, v_f, kick, coarse_hit, x_c, v_c);
+ * the last four are filled on the last fine step of each block. */
+uint64_t oracle_trace(double eps, double T, double dt0, int M, int level, int single,
+                      int x0_kind, double x0_a, double x0_b, int eq_kind, int coupling,
+                      uint64_t seed, uint32_t stream, uint64_t sample,
+                      double *rows, uint64_t cap, double out_final[2])
+{
+    problem_t P = make_problem(eps, T, dt0, M, level, single, x0_kind, x0_a, x0_b,
+                               eq_kind, coupling, seed, stream);
+    trace_t tr = {rows, cap, 0};
+    double xf, xc; uint32_t cf, cc;
+    simulate_one(&P, sample, &xf, &xc, &cf, &cc, &tr);
+    out_final[0] = xf; out_final[1] = xc;
+    return tr.used;
+}
+
+/* Raw Philox words for a grid of (step, sample) counters:
+ * out[((s - sample_begin) * n_steps + n) * 4 + j] for steps n < n_steps. */
+void oracle_words(uint64_t seed, uint32_t stream, uint32_t tag,
+                  uint64_t sample_begin, uint64_t n_samples, uint32_t n_steps,
+                  uint32_t *out)
+{
+    uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
+    for (uint64_t i = 0; i < n_samples; ++i) {
+        for (uint32_t n = 0; n < n_steps; ++n) {
+            uint32_t ctr[4] = {n, (uint32_t)(sample_begin + i), tag, stream};
+            oracle_philox4x32_10(ctr, key, out + (i * n_steps + n) * 4);
+        }
+    }
+}
