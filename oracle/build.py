@@ -10,10 +10,14 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def build(verbose=False):
+def build(verbose=False, force=True):
+    """Compiles the oracle; with force=False only if the library is missing
+    or older than its source."""
     src = os.path.join(HERE, "oracle.c")
     out = os.path.join(HERE, "liboracle.so")
-    tmp = out + ".tmp"
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
+        return out
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-shared", "-fPIC", "-Wall",
            src, "-o", tmp, "-lm"]
     if verbose:

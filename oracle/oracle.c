@@ -36,10 +36,11 @@
  *     (eq. chi-update, weights after eqs. for alpha and beta);
  *   - coarse velocity: the fine velocity normal drawn last in the block
  *     (eq. nu-update);
- *   - coarse collision: a Bernoulli draw built from the fine collision
- *     decisions and the conditionally uniform decision word of the first
- *     fine collision in the block (the uniform analogue of the
- *     memorylessness argument of eq. epsilon-update).
+ *   - coarse collision: decided by the fine decision words of the block:
+ *     it happens iff the smallest of them is below a threshold under the
+ *     fine one, so the fine words that caused fine collisions are reused
+ *     (the uniform analogue of reusing the fine exponential number in eq.
+ *     epsilon-update), and a coarse collision always comes with a fine one.
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
  * random numbers: as easy as 1, 2, 3", SC 2011), key = seed, counter =
@@ -131,20 +132,19 @@ static level_consts make_level(double eps, double T, double dt0, int M, int l)
     return c;
 }
 
-/* Threshold of the coarse decision word: the coarse path of level l
- * collides iff the block of M fine steps holds a fine collision and the
- * decision word of its first fine collision is below thr_c2.  Given a fine
- * collision that word is uniform on [0, thr_f), so
- *   P(coarse collision) = (1 - q_f^M) * thr_c2 / thr_f,
- * and thr_c2 = thr_f * p_c / (1 - q_f^M) makes it the coarse level's own
- * collision probability p_c = thr_c / 2^32. */
+/* Threshold of the coarse collision decision: the coarse path of level l
+ * collides in coarse step K iff the smallest fine decision word of the fine
+ * steps K*M .. K*M+M-1 is below thr_c2.  The M words are independent and
+ * uniform on [0, 2^32), so
+ *   P(coarse collision) = 1 - (1 - thr_c2/2^32)^M,
+ * and thr_c2 = 2^32 (1 - (1 - p_c)^(1/M)) makes it the coarse level's own
+ * collision probability p_c = thr_c/2^32.  Since (1-p_f)^M <= 1-p_c,
+ * thr_c2 <= thr_f: a word below thr_c2 is a fine collision, so a coarse
+ * collision always has a fine velocity draw in its block to take over. */
 uint64_t oracle_coarse_threshold(uint64_t thr_f, uint64_t thr_c, int M)
 {
-    if (thr_f == 0) return 0;
-    double pf = (double)thr_f / 4294967296.0;
     double pc = (double)thr_c / 4294967296.0;
-    double any = -expm1((double)M * log1p(-pf));   /* P(>= 1 fine collision) */
-    double t = (double)thr_f * pc / any;
+    double t = 4294967296.0 * -expm1(log1p(-pc) / (double)M);
     uint64_t r = (uint64_t)llround(t);
     if (r > thr_f) r = thr_f;
     return r;
@@ -223,8 +223,7 @@ static void simulate_one(const problem_t *P, uint64_t sample,
     int have_draw = 0;            /* a fine velocity was drawn in this block */
     double last_nu = 0.0;         /* normal of the latest in-block draw */
     double last_uses = 0.0;       /* transport uses of that draw so far */
-    int block_hit = 0;            /* a fine collision happened in the block */
-    uint32_t first_word = 0;      /* decision word of the first one */
+    uint32_t min_word = 0xFFFFFFFFu; /* smallest fine decision word of the block */
 
     for (uint64_t n = 0; n < F.n_steps; ++n) {
         ctr[0] = (uint32_t)n; ctr[1] = (uint32_t)sample; ctr[2] = tag; ctr[3] = P->stream;
@@ -240,10 +239,10 @@ static void simulate_one(const problem_t *P, uint64_t sample,
 
         /* collision */
         int hit = ((uint64_t)w[0] < F.thr);
+        if (w[0] < min_word) min_word = w[0];
         if (hit) {
             vf = v_new;
             cf++;
-            if (!block_hit) { block_hit = 1; first_word = w[0]; }
             if (have_draw) {          /* previous in-block draw is superseded */
                 vel_num += last_uses * last_nu;
                 vel_den += last_uses * last_uses;
@@ -256,7 +255,7 @@ static void simulate_one(const problem_t *P, uint64_t sample,
                           xf, vf, 0, 0, 0, 0};
 
         if (coarse && (n % (uint64_t)P->M) == (uint64_t)(P->M - 1)) {
-            int chit = block_hit && ((uint64_t)first_word < thr_c2);
+            int chit = ((uint64_t)min_word < thr_c2);
             double kick;
             if (P->coupling == COUPLING_KICK_SUM) {
                 kick = sum_xi / sqrt((double)P->M);
@@ -276,7 +275,7 @@ static void simulate_one(const problem_t *P, uint64_t sample,
             row[12] = kick; row[13] = (double)chit; row[14] = xc; row[15] = vc;
             sum_xi = 0.0; vel_num = 0.0; vel_den = 0.0;
             have_draw = 0; last_nu = 0.0; last_uses = 0.0;
-            block_hit = 0; first_word = 0;
+            min_word = 0xFFFFFFFFu;
         }
         trace_row(tr, row);
     }

@@ -17,6 +17,5 @@ def pytest_configure(config):
 def oracle_lib():
     import oracle
     from oracle import build
-    build.build()
-    oracle._lib = None
+    build.build(force=False)
     return oracle.lib()

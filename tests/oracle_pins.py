@@ -236,8 +236,10 @@ def pin_coupling_laws():
 
 
 def pin_coarse_threshold():
-    """P(coarse collision) = (1 - q_f^M) thr_c2 / thr_f equals the coarse
-    level's probability thr_c / 2^32 to within the 2^-32 quantum."""
+    """P(coarse collision) = 1 - (1 - thr_c2/2^32)^M (smallest of M uniform
+    words below thr_c2) equals the coarse level's probability thr_c / 2^32
+    to within the 2^-32 quantum, and thr_c2 <= thr_f (a coarse collision
+    implies a fine one)."""
     for eps in (0.0, 1e-4, 1e-2, 0.1, 1.0, 10.0):
         for M in (2, 3, 4, 8):
             for level in (1, 2, 5, 9):
@@ -245,11 +247,7 @@ def pin_coarse_threshold():
                 cc = O.level_consts(eps, 1.0, 0.5, M, level - 1)
                 t2 = O.coarse_threshold(cf["thr"], cc["thr"], M)
                 assert 0 <= t2 <= cf["thr"]
-                if cf["thr"] == 0:
-                    continue
-                pf = cf["thr"] / 2.0 ** 32
-                p_any = 1.0 - (1.0 - pf) ** M
-                got = p_any * t2 / cf["thr"]
+                got = -math.expm1(M * math.log1p(-t2 / 2.0 ** 32)) if t2 < 2 ** 32 else 1.0
                 want = cc["thr"] / 2.0 ** 32
                 assert abs(got - want) <= M * 2.0 ** -32 + 1e-15, (eps, M, level, got, want)
 

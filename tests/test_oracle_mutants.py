@@ -25,10 +25,10 @@ MUTANTS = [
     ("drift_missing_eps", "c.h = c.dt * eps / denom;", "c.h = c.dt / denom;"),
     ("level_dt_shifted", "c.dt = dt0 / pow((double)M, (double)l);",
      "c.dt = dt0 / pow((double)M, (double)(l + 1));"),
-    ("coarse_any_collision", "int chit = block_hit && ((uint64_t)first_word < thr_c2);",
-     "int chit = block_hit;"),
-    ("coarse_threshold_unadjusted", "int chit = block_hit && ((uint64_t)first_word < thr_c2);",
-     "int chit = block_hit && ((uint64_t)first_word < C.thr);"),
+    ("coarse_any_collision", "int chit = ((uint64_t)min_word < thr_c2);",
+     "int chit = ((uint64_t)min_word < F.thr);"),
+    ("coarse_threshold_unadjusted", "int chit = ((uint64_t)min_word < thr_c2);",
+     "int chit = ((uint64_t)min_word < C.thr);"),
     ("kick_sum_unnormalised", "kick = sum_xi / sqrt((double)P->M);", "kick = sum_xi;"),
     ("aggregate_norm_wrong", "sqrt((double)P->M * F.s * F.s + F.h * F.h * den)",
      "sqrt((double)P->M * F.s * F.s + F.h * den)"),
@@ -42,8 +42,8 @@ MUTANTS = [
      "double F = mid - sin(2.0 * M_PI * mid) / (2.0 * M_PI);"),
     ("normal_x0_ignores_std", "x0 = P->x0_a + P->x0_b * nc;", "x0 = P->x0_a + nc * 0.5;"),
     ("velocity_not_resampled", "vf = v_new;", "vf = vf;"),
-    ("coarse_threshold_no_any", "double t = (double)thr_f * pc / any;",
-     "double t = (double)thr_f * pc;"),
+    ("coarse_threshold_linearised", "-expm1(log1p(-pc) / (double)M)", "(pc / (double)M)"),
+    ("block_min_not_reset", "            min_word = 0xFFFFFFFFu;\n", "\n"),
 ]
 
 
