@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the multilevel asymptotic-preserving Monte Carlo hot path on
+one MI355X.
+
+One step = one complete MLMC estimate of E[x_8(T)^2] for the MLMC-AP
+workload (x0 ~ N(0,1), Maxwellian equilibrium, eps = 0.01, T = 1, dt0 = 0.5,
+M = 2, levels 0..8, RMSE 1e-3, FP32 particle state with FP64 statistics):
+warm-up samples on every level, optimal sample numbers, top-ups until the
+statistical constraint holds -- every level of an iteration in one persistent
+kernel launch replayed from a captured hipGraph.
+
+Printed: one JSON line.  ``value`` = particle-steps (fine + coarse) per
+second over the K timed estimates.  Extra fields: time-to-RMSE of the batched
+path, of plain per-level launches and of plain Monte Carlo at level 8; the
+eps-sweep batch; serving latency; the roofline of the particle kernel; the
+FP64 oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic VALU issue cost of the method, in full-rate lane-slots (one
+# slot = one lane of one full-rate VALU instruction).  Quarter-rate
+# operations (32x32->64 integer multiply, transcendentals) cost 4 slots.
+# Derivation and the instruction inventory are in DESIGN.md ("Roofline").
+SLOTS_FINE_STEP = 103.0     # Philox4x32-10 + Box-Muller pair + move + collision
+SLOTS_COARSE_FINE = 9.0     # per fine step of a pair: aggregation bookkeeping
+SLOTS_COARSE_STEP = 14.0    # per coarse step: kick normalisation, move, decision
+SLOTS_INIT = 95.0           # per trajectory: initial Philox draw + Box-Muller
+PEAK_SLOTS = 256 * 128 * 2.4e9     # CUs x FP32 lanes/CU/cycle x clock (157.3 TFLOP/s FMA)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_slots(prob, N):
+    """Algorithmic lane-slots of an estimate with N[l] samples per level."""
+    n0 = int(round(prob["T"] / prob["dt0"]))
+    M = prob["M"]
+    tot = 0.0
+    for l, n in enumerate(N):
+        nf = n0 * M ** l
+        per = SLOTS_INIT + nf * SLOTS_FINE_STEP
+        if l >= 1:
+            per += nf * SLOTS_COARSE_FINE + (nf // M) * SLOTS_COARSE_STEP
+        tot += n * per
+    return tot
+
+
+def cpu_baseline(prob, N, seconds):
+    """FP64 oracle on the host cores, on the MLMC sample numbers N scaled
+    down so the run takes about `seconds`."""
+    import oracle
+    from oracle import mlmc as OM
+    threads = oracle.default_threads()
+    # calibrate on a tiny slice
+    frac = 1e-4
+    for _ in range(6):
+        t0 = time.perf_counter()
+        steps = 0
+        for l, n in enumerate(N):
+            k = max(1, int(n * frac))
+            oracle.simulate(prob, l, 0, k, threads=threads)
+            steps += k * OM.level_cost(prob, l)
+        dt = time.perf_counter() - t0
+        if dt > 0.5:
+            break
+        frac *= 4
+    frac = min(1.0, frac * seconds / max(dt, 1e-3))
+    t0 = time.perf_counter()
+    steps = 0
+    for l, n in enumerate(N):
+        k = max(1, int(n * frac))
+        oracle.simulate(prob, l, 0, k, threads=threads)
+        steps += k * OM.level_cost(prob, l)
+    dt = time.perf_counter() - t0
+    return dict(value=steps / dt, unit="particle-steps/s", cores=threads, kind="oracle",
+                sample="MLMC-AP eps=0.01 L=8 sample numbers scaled by %.3g "
+                       "(%d particle-steps, %.1f s)" % (frac, steps, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed estimates (for profiler runs)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the estimator shards by sample ranges with one "
+              "statistics merge per iteration, which this build does not run across GPUs "
+              "(see DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2004_04071_amd as pkg
+    import workloads as W
+    from oracle import closed_form as CF
+
+    torch.cuda.set_device(0)
+    pkg.mlmc_ap_init()
+    prob = W.cfg2()
+    tol = W.CFG2_TOL
+    stream = torch.cuda.current_stream()
+
+    tuning = pkg.mlmc_ap_autotune(prob, None)
+    log("tuning", tuning)
+
+    opt = pkg.options(batched=1)
+    for _ in range(args.warmup):
+        pkg.mlmc_ap_estimate(prob, tol, opt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [pkg.mlmc_ap_estimate(prob, tol, opt) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    steps_total = sum(r["particle_steps"] for r in results)
+    value = steps_total / elapsed
+    ms_per = elapsed / args.steps * 1e3
+    last = results[-1]
+    exact = CF.level_second_moment(prob, prob["L"])
+    log("estimate %.6f exact %.6f sd %.2e N %s" % (last["estimate"], exact,
+                                                   math.sqrt(last["var_estimator"]), last["N"]))
+
+    # Dominant kernel: the persistent particle kernel, launched directly so
+    # that HIP events on the launch stream time it.
+    direct = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=2))
+    kern_s = direct["kernel_seconds"]
+    launches = direct["launches"]
+    slots = algorithmic_slots(prob, direct["N"])
+    achieved = slots / kern_s
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12,
+                    unit="TOP/s (full-rate VALU lane-slots)", frac=achieved / PEAK_SLOTS,
+                    traffic=None, kernel="persistent_kernel<float,%d>" % tuning["ppt"],
+                    avg_launch_ms=kern_s / launches * 1e3, launches=launches)
+    out = {
+        "metric": "particle-steps/s; MLMC time-to-RMSE 1e-3 vs plain MC; p50/p99 request latency",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "MLMC-AP eps=0.01 T=1 dt0=0.5 M=2 L=0..8 RMSE=1e-3 "
+                               "x0~N(0,1) Maxwellian, FP32 state / FP64 statistics",
+                   "rmse_tol": tol, "levels": prob["L"] + 1,
+                   "particle_steps_per_estimate": last["particle_steps"],
+                   "N": last["N"], "tuning": tuning},
+        "time_to_rmse_ms": ms_per,
+        "estimate": last["estimate"],
+        "estimate_exact": exact,
+        "roofline": roofline,
+    }
+    if not args.no_extras:
+        # plain per-level launches (same estimator, one kernel launch per level)
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            r0 = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=0))
+        per_level_ms = (time.perf_counter() - t0) / reps * 1e3
+        # plain Monte Carlo at level 8
+        t0 = time.perf_counter()
+        mc = pkg.mlmc_ap_plain_mc(prob, tol)
+        plain_ms = (time.perf_counter() - t0) * 1e3
+        out["per_level_launch_time_to_rmse_ms"] = per_level_ms
+        out["plain_mc_time_to_rmse_ms"] = plain_ms
+        out["plain_mc_particle_steps"] = mc["particle_steps"]
+        out["mlmc_speedup_vs_plain_mc"] = plain_ms / ms_per
+        out["batched_speedup_vs_per_level"] = per_level_ms / ms_per
+        log("per-level %.2f ms, batched %.2f ms, plain MC %.2f ms" % (per_level_ms, ms_per, plain_ms))
+
+        # eps sweep: 15 requests in one batched launch per iteration vs one by one
+        probs, tols = W.cfg3()
+        pkg.mlmc_ap_estimate_batch(probs, tols)
+        t0 = time.perf_counter()
+        batch = pkg.mlmc_ap_estimate_batch(probs, tols)
+        batch_ms = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        for p, t in zip(probs, tols):
+            pkg.mlmc_ap_estimate(p, t, pkg.options(batched=0))
+        seq_ms = (time.perf_counter() - t0) * 1e3
+        out["eps_sweep"] = dict(requests=len(probs), batched_ms=batch_ms,
+                                per_level_sequential_ms=seq_ms,
+                                particle_steps=sum(b["particle_steps"] for b in batch))
+
+        # serving: Poisson arrivals
+        n = args.serving_requests
+        arr, sprobs, stols = W.cfg5_trace(n)
+        srv = pkg.mlmc_ap_server_create(hbm_budget_bytes=4 << 30)
+        try:
+            lat, res = pkg.mlmc_ap_server_run_trace(srv, arr, sprobs, stols)
+            sstats = pkg.mlmc_ap_server_get_stats(srv)
+        finally:
+            pkg.mlmc_ap_server_destroy(srv)
+        lat_sorted = sorted(lat)
+        span = max(arr[-1], 1e-9)
+        out["serving"] = dict(requests=n, rate_per_s=200.0,
+                              p50_ms=lat_sorted[n // 2] * 1e3,
+                              p99_ms=lat_sorted[min(n - 1, int(0.99 * n))] * 1e3,
+                              particle_steps_per_s=sstats["particle_steps"] / (span + lat[-1]),
+                              ticks=sstats["ticks"])
+        log("serving", out["serving"])
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, last["N"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

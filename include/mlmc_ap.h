@@ -1,0 +1,335 @@
+/*
+ * mlmc_ap.h -- C ABI of the MI355X (gfx950) library for multilevel
+ * asymptotic-preserving Monte Carlo particle simulation in the diffusive
+ * scaling (Mortier, Robbe, Baelmans, Samaey, "Multilevel asymptotic-
+ * preserving Monte Carlo for kinetic-diffusive particle simulations of the
+ * Boltzmann-BGK equation").
+ *
+ * Problem (the paper's statement of the estimation task, Section 4.1):
+ * estimate E[Q_L] = E[x_L(T)^2] for particles of the diffusively scaled BGK
+ * equation  df/dt + (v/eps) df/dx = (M rho - f)/eps^2, where x_l is the
+ * position at end time T of the fixed-time-step asymptotic-preserving
+ * splitting scheme with step dt_l = dt0 / M^l:
+ *     x <- x + h v + s xi,          h = dt eps/(eps^2+dt),
+ *                                   s = sqrt(2 dt^2/(eps^2+dt)), xi ~ N(0,1)
+ *     with probability p = dt/(eps^2+dt): v <- fresh draw from the equilibrium
+ * (the asymptotic-preserving scheme of Dimarco et al. that the paper cites
+ * in Section 1; the equilibrium has unit variance).  Level l >= 1 simulates
+ * pairs: the fine path at dt_l and a coarse path at dt_{l-1} built only from
+ * the fine random numbers, mapped by the time at which they act (Section
+ * 3.1) and aggregated as in Section 3.2 (eqs. nu-update, epsilon-update,
+ * chi-update).  The MLMC estimator is eq. mlmc-compact, with sample numbers
+ * from eqs. Nopt1/Noptj and the statistical constraint of Section 4.1.
+ *
+ * Random numbers: Philox4x32-10 with key = seed and counter
+ * (step, sample, level tag, stream_id); step 0xFFFFFFFF is the initial
+ * draw.  The level tag is l for a fine/coarse pair and l + 64 for a
+ * single-level (plain Monte Carlo) trajectory.  Results therefore depend only
+ * on (problem, level, sample index range) -- never on launch shape, tuning,
+ * batching with other requests, or call splitting of a range into tiles of
+ * 256 samples.
+ *
+ * Conventions for every function:
+ *   - returns an mlmc_ap_status; nothing is thrown across the ABI;
+ *   - pointers named *_host are caller-owned host memory, *_dev are
+ *     caller-owned device memory on the current HIP device (e.g. from
+ *     PyTorch), and `stream` is a hipStream_t (NULL = default stream);
+ *   - the library owns its device workspace (grown on demand, freed by
+ *     mlmc_ap_release or at process exit);
+ *   - calls on one device are serialised by the library; results are
+ *     written before the call returns (the call synchronises `stream`).
+ */
+#ifndef MLMC_AP_H
+#define MLMC_AP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mlmc_ap_status {
+    MLMC_AP_OK = 0,
+    MLMC_AP_EINVAL = -1,      /* invalid argument; mlmc_ap_last_error() says which */
+    MLMC_AP_ENOMEM = -2,      /* device or pinned host allocation failed */
+    MLMC_AP_EDEVICE = -3,     /* HIP runtime error; mlmc_ap_last_error() has the text */
+    MLMC_AP_EBUSY = -4,       /* serving: the request can never fit the memory budget */
+    MLMC_AP_ECANCELLED = -5,  /* serving: the request was cancelled */
+    MLMC_AP_ENOTFOUND = -6,   /* serving: unknown ticket */
+    MLMC_AP_EAGAIN = -7       /* serving: request not finished yet */
+} mlmc_ap_status;
+
+/* Initial position law. */
+enum { MLMC_AP_X0_DELTA = 0,    /* x0 = x0_a */
+       MLMC_AP_X0_NORMAL = 1,   /* x0 ~ N(x0_a, x0_b^2) */
+       MLMC_AP_X0_COSINE = 2 }; /* density 1 + cos(2 pi x) on [0, 1] */
+
+/* Equilibrium (initial velocity law and collision resampling law). */
+enum { MLMC_AP_EQ_TWO_POINT = 0,   /* v = +1 or -1, each with probability 1/2 */
+       MLMC_AP_EQ_MAXWELLIAN = 1 };/* v ~ N(0, 1) */
+
+/* Coarse kick aggregation (eq. chi-update). */
+enum { MLMC_AP_COUPLING_KICK_SUM = 0,  /* normalised sum of the M fine kick normals */
+       MLMC_AP_COUPLING_AGGREGATE = 1  /* also the fine velocity normals the coarse
+                                          path does not reuse, weighted by their
+                                          fine transport uses; Maxwellian only */ };
+
+/* Quantity of interest. */
+enum { MLMC_AP_QOI_X2 = 0,        /* Q = x(T)^2 */
+       MLMC_AP_QOI_X2_HIST = 1 }; /* x(T)^2 plus a position histogram */
+
+#define MLMC_AP_MAX_LEVELS 31   /* levels 0..30 */
+#define MLMC_AP_MAX_BINS 1024
+#define MLMC_AP_TILE 256        /* samples per statistics tile */
+
+typedef struct mlmc_ap_problem {
+    double eps;          /* diffusive scaling parameter, >= 0 (0 = diffusion limit) */
+    double T;            /* end time, > 0 */
+    double dt0;          /* level-0 step; T/dt0 must be a positive integer (1e-9 rel.) */
+    int32_t M;           /* refinement factor dt_{l-1}/dt_l, 2..64 */
+    int32_t L;           /* finest level, 0..30; n_L = (T/dt0) M^L must be < 2^31 */
+    int32_t x0_kind;     /* MLMC_AP_X0_* */
+    int32_t eq_kind;     /* MLMC_AP_EQ_* */
+    double x0_a;         /* delta: position; normal: mean */
+    double x0_b;         /* normal: standard deviation (>= 0) */
+    int32_t coupling;    /* MLMC_AP_COUPLING_*; AGGREGATE needs MAXWELLIAN */
+    int32_t qoi;         /* MLMC_AP_QOI_* */
+    int32_t nbins;       /* histogram bins, 1..MLMC_AP_MAX_BINS (QOI_X2_HIST) */
+    int32_t fp64_state;  /* 0: FP32 particle state (default), 1: FP64 state */
+    double hist_lo;      /* histogram range [hist_lo, hist_hi) */
+    double hist_hi;
+    uint64_t seed;       /* Philox key */
+    uint32_t stream_id;  /* fourth counter word (request / stream id) */
+    uint32_t reserved;   /* must be 0 */
+} mlmc_ap_problem;
+
+/* Per-level statistics, mergeable (Chan et al. pairwise update) in FP64.
+ * dq = Q_f - Q_c (level 0 or single: dq = Q_f, Q_c = 0).  m2_* are sums of
+ * squared deviations (sample variance = m2/(n-1)); c_fc is the co-moment of
+ * Q_f and Q_c.  coll_* count fine and coarse collisions. */
+typedef struct mlmc_ap_level_stats {
+    uint64_t n;
+    double mean_dq, m2_dq;
+    double mean_qf, m2_qf;
+    double mean_qc, m2_qc;
+    double c_fc;
+    uint64_t coll_f, coll_c;
+} mlmc_ap_level_stats;
+
+/* Histogram counts of one level: for bin b (0 <= b < nbins)
+ *   hist[3b]   = #{x_f in bin b},
+ *   hist[3b+1] = #{x_c in bin b},
+ *   hist[3b+2] = #{x_f and x_c both in bin b},
+ * then hist[3 nbins + 0..3] = #{x_f below}, #{x_f above}, #{x_c below},
+ * #{x_c above}.  Total length 3*nbins + 4 (uint64). */
+
+/* Constants of one level, computed on the host in FP64 (for tests and
+ * tooling; no device work). */
+typedef struct mlmc_ap_level_info {
+    double dt, h, s, p;          /* fine step and scheme coefficients */
+    double dt_c, h_c, s_c, p_c;  /* coarse (level l-1) ones; zero at level 0 */
+    uint64_t n_steps;            /* fine steps n_l */
+    uint64_t thr_f;              /* collide iff word < thr_f = round(p 2^32) */
+    uint64_t thr_c;              /* round(p_c 2^32) (level l-1's own threshold) */
+    uint64_t thr_c2;             /* coarse decision word threshold (see below) */
+} mlmc_ap_level_info;
+
+/* Tuning of the particle kernels; zero fields select the defaults (or the
+ * autotuner's cached choice).  Results never depend on it. */
+typedef struct mlmc_ap_tuning {
+    int32_t block;          /* threads per block: 64, 128 or 256 */
+    int32_t ppt;            /* trajectories in flight per thread: 1, 2 or 4 */
+    int32_t waves_per_simd; /* persistent grid occupancy target, 1..8 */
+    int32_t reserved;
+} mlmc_ap_tuning;
+
+typedef struct mlmc_ap_options {
+    int32_t batched;        /* 1: all levels of an iteration in one persistent
+                               launch replayed from a captured hipGraph (default);
+                               0: one plain launch per level;
+                               2: the persistent launch issued directly (no graph),
+                                  so kernel_seconds is measured */
+    int32_t max_iter;       /* MLMC top-up iterations after warm-up (0 = 10) */
+    uint64_t n_warmup;      /* warm-up samples per level (0 = 1000) */
+    mlmc_ap_tuning tuning;
+} mlmc_ap_options;
+
+typedef struct mlmc_ap_result {
+    double estimate;         /* eq. mlmc-compact: sum_l mean(dQ_l) */
+    double var_estimator;    /* sum_l V_l / N_l with sample variances V_l */
+    int32_t L;
+    int32_t iterations;      /* top-up iterations run */
+    int32_t converged;       /* 1 if sum_l V_l/N_l <= tol^2/2 */
+    int32_t status;          /* mlmc_ap_status of the request (serving) */
+    uint64_t N[MLMC_AP_MAX_LEVELS];
+    mlmc_ap_level_stats lv[MLMC_AP_MAX_LEVELS];
+    uint64_t particle_steps; /* sum_l N_l (n_l + n_{l-1}) */
+    uint64_t launches;       /* particle-kernel launches or graph replays */
+    double seconds;          /* host wall clock of the call */
+    double gpu_seconds;      /* device time from table upload to statistics read-back */
+    double kernel_seconds;   /* device time of the particle kernels alone (plain and
+                                direct persistent launches; 0 for graph replays) */
+} mlmc_ap_result;
+
+/* Library and device set-up.  mlmc_ap_init is optional (every entry point
+ * initialises lazily); mlmc_ap_release frees the workspace of the current
+ * device. */
+mlmc_ap_status mlmc_ap_init(void);
+mlmc_ap_status mlmc_ap_release(void);
+const char* mlmc_ap_status_str(mlmc_ap_status s);
+/* Text of the last error of the calling thread ("" if none). */
+const char* mlmc_ap_last_error(void);
+/* Library version string. */
+const char* mlmc_ap_version(void);
+
+/* Validates a problem (the EINVAL rules listed in the struct comments). */
+mlmc_ap_status mlmc_ap_validate(const mlmc_ap_problem* p);
+
+/* Level constants (host only).  thr_c2 is the threshold of the coarse
+ * collision decision: the coarse path of level l collides in coarse step K
+ * iff the smallest fine decision word of fine steps K*M..K*M+M-1 is below
+ * thr_c2.  Those M words are independent and uniform, so the coarse
+ * collision probability is 1 - (1 - thr_c2/2^32)^M, and
+ * thr_c2 = round(2^32 (1 - (1 - thr_c/2^32)^(1/M))) makes it the coarse
+ * level's own thr_c/2^32 within M 2^-32.  thr_c2 <= thr_f, so every coarse
+ * collision reuses a fine one (the uniform analogue of reusing the fine
+ * exponential number in eq. epsilon-update) and its new velocity is the fine
+ * velocity drawn last in the block (eq. nu-update). */
+mlmc_ap_status mlmc_ap_level_constants(const mlmc_ap_problem* p, int32_t level,
+                                       mlmc_ap_level_info* out_host);
+
+/* Eqs. Nopt1/Noptj (host only): N_j = ceil((2/tol^2) sqrt(V_j/C_j)
+ * sum_i sqrt(V_i C_i)) for j < n.  V_j >= 0, C_j > 0, tol > 0. */
+mlmc_ap_status mlmc_ap_optimal_samples(const double* V_host, const double* C_host, int32_t n,
+                                       double tol, uint64_t* N_out_host);
+
+/* Pairwise merge of two statistics records (host only; the same update the
+ * device reductions apply): out = a (+) b.  out may alias a or b. */
+mlmc_ap_status mlmc_ap_merge_stats(const mlmc_ap_level_stats* a, const mlmc_ap_level_stats* b,
+                                   mlmc_ap_level_stats* out);
+
+/* Simulates samples [sample_begin, sample_begin + n_samples) of level
+ * `level` on the GPU (Section 4.1: the n-th realisation of Q_{l_1} or of the
+ * difference dQ_{l_j,l_{j-1}} of eq. mlmc-compact) and returns their
+ * statistics.
+ *   single = 0: fine/coarse pair (level 0: the fine path alone);
+ *   single = 1: one trajectory of level `level` alone (plain Monte Carlo,
+ *               level tag level + 64), statistics with Q_c = 0.
+ *   out_host  (required) statistics of this range only.
+ *   traj_dev  (nullable) 2*n_samples values, float (fp64_state = 0) or
+ *             double: x_f(T) at [i], x_c(T) at [n_samples + i], i = sample -
+ *             sample_begin.
+ *   coll_dev  (nullable) 2*n_samples uint32: fine collisions at [i], coarse
+ *             at [n_samples + i].
+ *   hist_host (nullable; required when qoi = QOI_X2_HIST) 3*nbins + 4
+ *             uint64 histogram counts of this range (layout above).
+ * sample_begin + n_samples must not exceed 2^32 (sample counter word). */
+mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, int32_t single,
+                                      uint64_t sample_begin, uint64_t n_samples,
+                                      mlmc_ap_level_stats* out_host, void* traj_dev,
+                                      uint32_t* coll_dev, uint64_t* hist_host, void* stream);
+
+/* MLMC estimate of E[Q_L] to RMSE tolerance rmse_tol (Section 4.1): warm-up
+ * samples on every level 0..L, then eqs. Nopt1/Noptj with sample variances
+ * and the deterministic cost C_0 = n_0, C_l = n_l + n_{l-1} (particle steps
+ * per sample), topped up until the statistical constraint
+ * sum_l V_l/N_l <= rmse_tol^2/2 holds.  Level l uses samples [0, N_l).
+ * opt may be NULL (defaults).  With qoi = QOI_X2_HIST, hist_host (nullable)
+ * receives (L+1) per-level histograms of 3*nbins+4 counts each. */
+mlmc_ap_status mlmc_ap_estimate(const mlmc_ap_problem* p, double rmse_tol,
+                                const mlmc_ap_options* opt, mlmc_ap_result* out_host,
+                                uint64_t* hist_host, void* stream);
+
+/* Plain Monte Carlo at level L (single-level trajectories, level tag
+ * L + 64): N = ceil(2 V_L / rmse_tol^2) samples after the warm-up,
+ * iterated like mlmc_ap_estimate.  Reported in out_host->N[L] / lv[L]. */
+mlmc_ap_status mlmc_ap_plain_mc(const mlmc_ap_problem* p, double rmse_tol,
+                                const mlmc_ap_options* opt, mlmc_ap_result* out_host,
+                                void* stream);
+
+/* Several independent MLMC estimates advanced together: every top-up
+ * iteration of every request is one persistent launch over a shared work
+ * table (uneven N_l across requests and levels), replayed from one captured
+ * hipGraph.  Each result equals what mlmc_ap_estimate returns for that
+ * request alone (bitwise).  n_req >= 1. */
+mlmc_ap_status mlmc_ap_estimate_batch(const mlmc_ap_problem* p, const double* rmse_tol,
+                                      int32_t n_req, const mlmc_ap_options* opt,
+                                      mlmc_ap_result* out_host, void* stream);
+
+/* Autotuner: times the persistent kernel on a work table shaped like the
+ * given problem's MLMC warm-up (and its finest levels) for every
+ * (block, ppt, waves_per_simd) candidate and returns the fastest.  If
+ * cache_path is non-NULL the choice is read from / written to that JSON
+ * file (keyed by the device name).  The choice becomes the default tuning of
+ * the current device. */
+mlmc_ap_status mlmc_ap_autotune(const mlmc_ap_problem* p, const char* cache_path,
+                                mlmc_ap_tuning* out_host, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of MLMC requests.                         */
+/* ---------------------------------------------------------------------- */
+typedef struct mlmc_ap_server mlmc_ap_server;
+
+typedef struct mlmc_ap_server_config {
+    uint64_t hbm_budget_bytes;     /* device memory the server may use for request
+                                      state and tile partials (0 = 1 GiB) */
+    uint64_t max_samples_per_tick; /* per request and level per tick (0 = 2^24) */
+    int32_t max_active;            /* admitted requests at once (0 = 256) */
+    int32_t reserved;
+    mlmc_ap_options options;       /* n_warmup, max_iter, tuning (batched is implied) */
+} mlmc_ap_server_config;
+
+typedef struct mlmc_ap_server_stats {
+    uint64_t submitted, admitted, completed, cancelled, rejected;
+    uint64_t ticks, particle_steps;
+    uint64_t bytes_reserved, bytes_peak;
+    int32_t active, queued;
+    double busy_seconds;          /* host time spent inside ticks */
+} mlmc_ap_server_stats;
+
+mlmc_ap_status mlmc_ap_server_create(const mlmc_ap_server_config* cfg, mlmc_ap_server** out);
+mlmc_ap_status mlmc_ap_server_destroy(mlmc_ap_server* srv);
+/* Queues a request; it is admitted at a later tick once its device memory
+ * (per-level state and per-tick tile partials) fits the budget.  EBUSY if it
+ * can never fit; EINVAL for an invalid problem or tolerance. */
+mlmc_ap_status mlmc_ap_server_submit(mlmc_ap_server* srv, const mlmc_ap_problem* p,
+                                     double rmse_tol, uint64_t* ticket_out);
+/* One tick: admit queued requests that fit, run one top-up iteration of every
+ * active request in one persistent launch (graph replay), update their level
+ * state and complete those whose statistical constraint holds.
+ * n_completed_out (nullable) receives the number completed in this tick. */
+mlmc_ap_status mlmc_ap_server_step(mlmc_ap_server* srv, int32_t* n_completed_out);
+/* OK with the result, EAGAIN while pending, ECANCELLED, ENOTFOUND.  A
+ * finished result stays available until polled once. */
+mlmc_ap_status mlmc_ap_server_poll(mlmc_ap_server* srv, uint64_t ticket, mlmc_ap_result* out_host);
+mlmc_ap_status mlmc_ap_server_cancel(mlmc_ap_server* srv, uint64_t ticket);
+mlmc_ap_status mlmc_ap_server_get_stats(const mlmc_ap_server* srv, mlmc_ap_server_stats* out);
+/* Replays an arrival trace in real time: request i is submitted when
+ * arrival_s[i] seconds (non-decreasing, from the call's start) have passed,
+ * ticks run back to back while work exists, and latency_s_out[i] receives
+ * completion minus arrival time.  results_out (nullable) gets every result. */
+mlmc_ap_status mlmc_ap_server_run_trace(mlmc_ap_server* srv, int32_t n, const double* arrival_s,
+                                        const mlmc_ap_problem* p, const double* rmse_tol,
+                                        mlmc_ap_result* results_out, double* latency_s_out);
+
+/* ---------------------------------------------------------------------- */
+/* Validation entry points (bit-exact checks of the random number path).  */
+/* ---------------------------------------------------------------------- */
+/* Philox4x32-10 words for counters (n, sample, tag, stream_id), key = seed:
+ * out_dev[((s - sample_begin) * n_steps + n) * 4 + j] for n < n_steps. */
+mlmc_ap_status mlmc_ap_philox_words(uint64_t seed, uint32_t stream_id, uint32_t tag,
+                                    uint64_t sample_begin, uint64_t n_samples, uint32_t n_steps,
+                                    uint32_t* out_dev, void* stream);
+/* Uniforms and Box-Muller normals of the same grid as computed by the FP32
+ * (fp64 = 0, float out_dev) or FP64 (fp64 = 1, double out_dev) particle
+ * path: out[((s - sample_begin) * n_steps + n) * 4 + {0,1,2,3}] =
+ * (u1, u2, xi, g). */
+mlmc_ap_status mlmc_ap_rng_normals(uint64_t seed, uint32_t stream_id, uint32_t tag,
+                                   uint64_t sample_begin, uint64_t n_samples, uint32_t n_steps,
+                                   int32_t fp64, void* out_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLMC_AP_H */

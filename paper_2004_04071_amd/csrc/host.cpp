@@ -1,0 +1,821 @@
+// C ABI of the MLMC-AP library: validation, level constants, device
+// workspace, work tables, launches and the MLMC control loop (Section 4.1).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+#include "stats.hpp"
+
+namespace mlmc {
+
+namespace {
+thread_local std::string g_last_error;
+constexpr double kTwo32 = 4294967296.0;
+// Fine steps per lane a persistent-kernel chunk aims at (load balance versus
+// work-counter traffic); chunks never exceed 64 tiles.
+constexpr uint64_t kChunkLaneSteps = 2048;
+}  // namespace
+
+mlmc_ap_status set_error(mlmc_ap_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Level constants: dt_l = dt0 / M^l; h, s, p of the splitting scheme;
+// thr = round(p 2^32).
+// ---------------------------------------------------------------------------
+LevelConst level_const(const mlmc_ap_problem& p, int level) {
+  LevelConst c;
+  c.dt = p.dt0 / std::pow((double)p.M, (double)level);
+  const double denom = p.eps * p.eps + c.dt;
+  c.h = c.dt * p.eps / denom;
+  c.s = std::sqrt(2.0 * c.dt * c.dt / denom);
+  c.p = c.dt / denom;
+  c.n_steps = (uint64_t)std::llround(p.T / p.dt0) *
+              (uint64_t)std::llround(std::pow((double)p.M, (double)level));
+  c.thr = (uint64_t)std::llround(c.p * kTwo32);
+  return c;
+}
+
+// Coarse collision threshold: the smallest of M independent uniform words is
+// below t with probability 1 - (1 - t/2^32)^M; t = 2^32 (1 - (1-p_c)^(1/M))
+// makes that the coarse level's p_c = thr_c/2^32.  t <= thr_f because
+// (1 - p_f)^M <= 1 - p_c, so a coarse collision implies a fine one.
+uint64_t coarse_threshold(uint64_t thr_f, uint64_t thr_c, int M) {
+  const double pc = (double)thr_c / kTwo32;
+  const double t = kTwo32 * -std::expm1(std::log1p(-pc) / (double)M);
+  uint64_t r = (uint64_t)std::llround(t);
+  return r > thr_f ? thr_f : r;
+}
+
+uint64_t sample_cost(const mlmc_ap_problem& p, int level, bool single) {
+  const uint64_t n = level_const(p, level).n_steps;
+  if (single || level == 0) return n;
+  return n + level_const(p, level - 1).n_steps;
+}
+
+mlmc_ap_status validate_problem(const mlmc_ap_problem* p) {
+  if (!p) return set_error(MLMC_AP_EINVAL, "problem is NULL");
+  if (!(p->eps >= 0.0) || !std::isfinite(p->eps))
+    return set_error(MLMC_AP_EINVAL, "eps must be finite and >= 0");
+  if (!(p->T > 0.0) || !std::isfinite(p->T)) return set_error(MLMC_AP_EINVAL, "T must be > 0");
+  if (!(p->dt0 > 0.0) || !std::isfinite(p->dt0))
+    return set_error(MLMC_AP_EINVAL, "dt0 must be > 0");
+  if (p->M < 2 || p->M > 64) return set_error(MLMC_AP_EINVAL, "M must be in [2, 64]");
+  if (p->L < 0 || p->L >= MLMC_AP_MAX_LEVELS) return set_error(MLMC_AP_EINVAL, "L must be in [0, 30]");
+  const double ratio = p->T / p->dt0;
+  const double n0 = std::round(ratio);
+  if (n0 < 1.0 || std::fabs(ratio - n0) > 1e-9 * n0)
+    return set_error(MLMC_AP_EINVAL, "T/dt0 must be a positive integer");
+  const double nL = n0 * std::pow((double)p->M, (double)p->L);
+  if (nL >= 2147483648.0) return set_error(MLMC_AP_EINVAL, "n_L = (T/dt0) M^L must be < 2^31");
+  if (p->x0_kind < MLMC_AP_X0_DELTA || p->x0_kind > MLMC_AP_X0_COSINE)
+    return set_error(MLMC_AP_EINVAL, "unknown x0_kind");
+  if (p->eq_kind != MLMC_AP_EQ_TWO_POINT && p->eq_kind != MLMC_AP_EQ_MAXWELLIAN)
+    return set_error(MLMC_AP_EINVAL, "unknown eq_kind");
+  if (!std::isfinite(p->x0_a) || !std::isfinite(p->x0_b) || p->x0_b < 0.0)
+    return set_error(MLMC_AP_EINVAL, "x0_a must be finite and x0_b finite and >= 0");
+  if (p->coupling != MLMC_AP_COUPLING_KICK_SUM && p->coupling != MLMC_AP_COUPLING_AGGREGATE)
+    return set_error(MLMC_AP_EINVAL, "unknown coupling");
+  if (p->coupling == MLMC_AP_COUPLING_AGGREGATE && p->eq_kind != MLMC_AP_EQ_MAXWELLIAN)
+    return set_error(MLMC_AP_EINVAL,
+                     "the aggregated coupling needs the Maxwellian equilibrium (a weighted sum "
+                     "of +-1 velocities is not Gaussian)");
+  if (p->qoi != MLMC_AP_QOI_X2 && p->qoi != MLMC_AP_QOI_X2_HIST)
+    return set_error(MLMC_AP_EINVAL, "unknown qoi");
+  if (p->qoi == MLMC_AP_QOI_X2_HIST) {
+    if (p->nbins < 1 || p->nbins > MLMC_AP_MAX_BINS)
+      return set_error(MLMC_AP_EINVAL, "nbins must be in [1, 1024]");
+    if (!(p->hist_lo < p->hist_hi) || !std::isfinite(p->hist_lo) || !std::isfinite(p->hist_hi))
+      return set_error(MLMC_AP_EINVAL, "histogram range must satisfy hist_lo < hist_hi");
+  }
+  if (p->fp64_state != 0 && p->fp64_state != 1)
+    return set_error(MLMC_AP_EINVAL, "fp64_state must be 0 or 1");
+  if (p->reserved != 0) return set_error(MLMC_AP_EINVAL, "reserved must be 0");
+  return MLMC_AP_OK;
+}
+
+LevelDesc make_desc(const ItemSpec& s) {
+  const mlmc_ap_problem& p = *s.prob;
+  const bool coarse = !s.single && s.level >= 1;
+  const LevelConst F = level_const(p, s.level);
+  const LevelConst C = coarse ? level_const(p, s.level - 1) : F;
+  const bool maxwell = p.eq_kind == MLMC_AP_EQ_MAXWELLIAN;
+  const bool agg = coarse && p.coupling == MLMC_AP_COUPLING_AGGREGATE;
+  LevelDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.h_f = F.h; d.s_f = F.s;
+  d.h_c = coarse ? C.h : 0.0;
+  d.s_c = coarse ? C.s : 0.0;
+  d.agg_ms2 = (double)p.M * F.s * F.s;
+  d.h_f2 = F.h * F.h;
+  d.rsqrt_m = 1.0 / std::sqrt((double)p.M);
+  d.x0_a = p.x0_a; d.x0_b = p.x0_b;
+  if (p.qoi == MLMC_AP_QOI_X2_HIST) {
+    d.hist_lo = p.hist_lo;
+    d.hist_inv_w = (double)p.nbins / (p.hist_hi - p.hist_lo);
+    d.nbins = (uint32_t)p.nbins;
+  }
+  d.sample_begin = s.sample_begin;
+  d.n_samples = s.n_samples;
+  d.hist = s.hist;
+  d.traj = s.traj;
+  d.coll = s.coll;
+  d.thr_f = F.thr;
+  d.thr_c2 = coarse ? coarse_threshold(F.thr, C.thr, p.M) : 1;
+  d.thr_f_m1 = d.thr_f >= 1 ? (uint32_t)(d.thr_f - 1) : 0u;
+  d.thr_c2_m1 = d.thr_c2 >= 1 ? (uint32_t)(d.thr_c2 - 1) : 0u;
+  d.n_steps = (uint32_t)F.n_steps;
+  d.M = (uint32_t)p.M;
+  d.tag = (uint32_t)s.level + (s.single ? 64u : 0u);
+  d.stream = p.stream_id;
+  d.key0 = (uint32_t)(p.seed & 0xFFFFFFFFull);
+  d.key1 = (uint32_t)(p.seed >> 32);
+  d.flags = (coarse ? kFlagCoarse : 0u) | (maxwell ? kFlagMaxwell : 0u) |
+            (agg ? kFlagAggregate : 0u) | (s.hist ? kFlagHist : 0u) | kFlagAccumulate;
+  if (d.thr_f == 0 || d.thr_c2 == 0) d.flags |= kFlagWide;
+  d.kind = coarse ? (maxwell ? (agg ? kKindPairMaxwellAggregate : kKindPairMaxwellSum)
+                             : kKindPairTwoPointSum)
+                  : (maxwell ? kKindFineMaxwell : kKindFineTwoPoint);
+  d.x0_kind = (uint32_t)p.x0_kind;
+  d.n_tiles = (uint32_t)((s.n_samples + kTile - 1) / kTile);
+  d.n_groups = (d.n_tiles + kGroupTiles - 1) / kGroupTiles;
+  uint64_t ct = kChunkLaneSteps / ((uint64_t)kSamplesPerLane * (F.n_steps + 1));
+  if (ct < 1) ct = 1;
+  if (ct > 64) ct = 64;
+  d.chunk_tiles = (uint32_t)ct;
+  d.n_chunks = (d.n_tiles + d.chunk_tiles - 1) / d.chunk_tiles;
+  d.result_slot = s.result_slot;
+  return d;
+}
+
+Stats stats_from_api(const mlmc_ap_level_stats& a) {
+  Stats s;
+  s.n = (double)a.n;
+  s.mean_dq = a.mean_dq; s.m2_dq = a.m2_dq;
+  s.mean_qf = a.mean_qf; s.m2_qf = a.m2_qf;
+  s.mean_qc = a.mean_qc; s.m2_qc = a.m2_qc;
+  s.c_fc = a.c_fc;
+  s.coll_f = a.coll_f; s.coll_c = a.coll_c;
+  return s;
+}
+
+mlmc_ap_level_stats stats_to_api(const Stats& s) {
+  mlmc_ap_level_stats a;
+  a.n = (uint64_t)s.n;
+  a.mean_dq = s.mean_dq; a.m2_dq = s.m2_dq;
+  a.mean_qf = s.mean_qf; a.m2_qf = s.m2_qf;
+  a.mean_qc = s.mean_qc; a.m2_qc = s.m2_qc;
+  a.c_fc = s.c_fc;
+  a.coll_f = s.coll_f; a.coll_c = s.coll_c;
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace.
+// ---------------------------------------------------------------------------
+template <typename T>
+static mlmc_ap_status grow_dev(T*& p, size_t& cap, size_t need) {
+  if (need <= cap && p) return MLMC_AP_OK;
+  size_t n = std::max(need, cap + cap / 2);
+  if (n < 64) n = 64;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+  if (hipMalloc((void**)&p, n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(MLMC_AP_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes");
+  }
+  cap = n;
+  return MLMC_AP_OK;
+}
+
+template <typename T>
+static mlmc_ap_status grow_pinned(T*& p, size_t cap_old, size_t cap_new) {
+  if (p && cap_old >= cap_new) return MLMC_AP_OK;
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  if (hipHostMalloc((void**)&p, cap_new * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(MLMC_AP_ENOMEM, "hipHostMalloc failed");
+  }
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status Workspace::ensure(size_t n_items, size_t n_tiles, size_t n_groups,
+                                 size_t n_slots, size_t n_hist) {
+  const void* before[5] = {items_dev, partials, groups, resident, hist_dev};
+  if (n_items > items_cap || !items_dev) {
+    MLMC_TRY(grow_dev(items_dev, items_cap, n_items));
+    MLMC_TRY(grow_pinned(items_host, 0, items_cap));
+  }
+  if (!hdr_dev) {
+    MLMC_HIP(hipMalloc((void**)&hdr_dev, sizeof(WorkHeader)));
+    MLMC_HIP(hipHostMalloc((void**)&hdr_host, sizeof(WorkHeader), hipHostMallocDefault));
+    MLMC_HIP(hipMalloc((void**)&counter_dev, 64));
+  }
+  MLMC_TRY(grow_dev(partials, partials_cap, std::max<size_t>(n_tiles, 1)));
+  MLMC_TRY(grow_dev(groups, groups_cap, std::max<size_t>(n_groups, 1)));
+  if (n_slots > resident_cap || !resident) {
+    MLMC_TRY(grow_dev(resident, resident_cap, std::max<size_t>(n_slots, 1)));
+    MLMC_TRY(grow_pinned(resident_host, 0, resident_cap));
+  }
+  MLMC_TRY(grow_dev(hist_dev, hist_cap, std::max<size_t>(n_hist, 1)));
+  const void* after[5] = {items_dev, partials, groups, resident, hist_dev};
+  if (std::memcmp(before, after, sizeof(before)) != 0) graph_key = 0;  // recapture
+  return MLMC_AP_OK;
+}
+
+void Workspace::release() {
+  if (graph) (void)hipGraphExecDestroy(graph);
+  if (graph_def) (void)hipGraphDestroy(graph_def);
+  graph = nullptr; graph_def = nullptr; graph_key = 0;
+  if (items_dev) (void)hipFree(items_dev);
+  if (items_host) (void)hipHostFree(items_host);
+  if (hdr_dev) (void)hipFree(hdr_dev);
+  if (hdr_host) (void)hipHostFree(hdr_host);
+  if (counter_dev) (void)hipFree(counter_dev);
+  if (partials) (void)hipFree(partials);
+  if (groups) (void)hipFree(groups);
+  if (resident) (void)hipFree(resident);
+  if (resident_host) (void)hipHostFree(resident_host);
+  if (hist_dev) (void)hipFree(hist_dev);
+  items_dev = nullptr; items_host = nullptr; hdr_dev = nullptr; hdr_host = nullptr;
+  counter_dev = nullptr; partials = nullptr; groups = nullptr; resident = nullptr;
+  resident_host = nullptr; hist_dev = nullptr;
+  items_cap = partials_cap = groups_cap = resident_cap = hist_cap = 0;
+}
+
+static std::mutex g_ws_mu;
+static std::map<int, std::unique_ptr<Workspace>> g_ws;
+
+Workspace::~Workspace() {
+  release();
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+mlmc_ap_status init_workspace(Workspace& ws) {
+  int dev = 0;
+  MLMC_HIP(hipGetDevice(&dev));
+  ws.device = dev;
+  hipDeviceProp_t prop;
+  MLMC_HIP(hipGetDeviceProperties(&prop, dev));
+  ws.n_cu = prop.multiProcessorCount;
+  ws.name = prop.gcnArchName;
+  MLMC_HIP(hipStreamCreateWithFlags(&ws.capture_stream, hipStreamNonBlocking));
+  for (auto& e : ws.ev) MLMC_HIP(hipEventCreate(&e));
+  ws.tuning.block = 256;
+  ws.tuning.ppt = 4;
+  ws.tuning.waves_per_simd = 4;
+  return MLMC_AP_OK;
+}
+
+Workspace* workspace() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error(MLMC_AP_EDEVICE, "no HIP device");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto it = g_ws.find(dev);
+  if (it != g_ws.end()) return it->second.get();
+  std::unique_ptr<Workspace> ws(new Workspace());
+  if (init_workspace(*ws) != MLMC_AP_OK) return nullptr;
+  Workspace* raw = ws.get();
+  g_ws[dev] = std::move(ws);
+  return raw;
+}
+
+mlmc_ap_tuning resolve_tuning(const Workspace& ws, const mlmc_ap_tuning* t) {
+  mlmc_ap_tuning r = ws.tuning;
+  if (t) {
+    if (t->block) r.block = t->block;
+    if (t->ppt) r.ppt = t->ppt;
+    if (t->waves_per_simd) r.waves_per_simd = t->waves_per_simd;
+  }
+  return r;
+}
+
+int persistent_grid(const Workspace& ws, const mlmc_ap_tuning& t) {
+  const int waves_per_block = t.block / kLanes;
+  const int waves = ws.n_cu * 4 * t.waves_per_simd;
+  return std::max(1, (waves + waves_per_block - 1) / waves_per_block);
+}
+
+static mlmc_ap_status check_tuning(const mlmc_ap_tuning& t) {
+  if (t.block != 64 && t.block != 128 && t.block != 256)
+    return set_error(MLMC_AP_EINVAL, "tuning.block must be 64, 128 or 256");
+  if (t.ppt != 1 && t.ppt != 2 && t.ppt != 4)
+    return set_error(MLMC_AP_EINVAL, "tuning.ppt must be 1, 2 or 4");
+  if (t.waves_per_simd < 1 || t.waves_per_simd > 8)
+    return set_error(MLMC_AP_EINVAL, "tuning.waves_per_simd must be in [1, 8]");
+  return MLMC_AP_OK;
+}
+
+static const int kReduceGridGroups = 1024;
+static const int kReduceGridItems = 256;
+
+static mlmc_ap_status record_device_work(Workspace& ws, bool fp64, const mlmc_ap_tuning& t,
+                                         hipStream_t s) {
+  MLMC_HIP(launch_fill_u32(ws.counter_dev, 1, 0u, s));
+  MLMC_HIP(launch_persistent(fp64, t.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev, ws.partials,
+                             t.block, persistent_grid(ws, t), s));
+  MLMC_HIP(launch_reduce(ws.items_dev, ws.hdr_dev, ws.partials, ws.groups, ws.resident,
+                         kReduceGridGroups, kReduceGridItems, s));
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size_t n_slots,
+                         int mode, const mlmc_ap_tuning& tuning, hipStream_t stream,
+                         LaunchTiming* timing) {
+  MLMC_TRY(check_tuning(tuning));
+  if (specs.empty()) return MLMC_AP_OK;
+  std::vector<LevelDesc> d(specs.size());
+  for (size_t i = 0; i < specs.size(); ++i) d[i] = make_desc(specs[i]);
+  const bool fp64 = specs[0].prob->fp64_state != 0;
+  for (const auto& s : specs)
+    if ((s.prob->fp64_state != 0) != fp64)
+      return set_error(MLMC_AP_EINVAL, "one launch cannot mix FP32 and FP64 particle state");
+  // most expensive chunks first (persistent kernel load balance)
+  std::stable_sort(d.begin(), d.end(), [](const LevelDesc& a, const LevelDesc& b) {
+    return a.n_steps > b.n_steps;
+  });
+  uint64_t tiles = 0, groups = 0, chunks = 0;
+  for (auto& x : d) {
+    x.tile_base = tiles;
+    x.group_base = groups;
+    x.chunk_base = chunks;
+    tiles += x.n_tiles;
+    groups += x.n_groups;
+    chunks += x.n_chunks;
+  }
+  if (chunks >= 0xFFFFFFF0ull || groups >= 0xFFFFFFF0ull)
+    return set_error(MLMC_AP_EINVAL, "work table too large for one launch");
+  MLMC_TRY(ws.ensure(d.size(), tiles, groups, n_slots, 0));
+  std::memcpy(ws.items_host, d.data(), d.size() * sizeof(LevelDesc));
+  ws.hdr_host->n_items = (uint32_t)d.size();
+  ws.hdr_host->total_chunks = (uint32_t)chunks;
+  ws.hdr_host->total_groups = (uint32_t)groups;
+  ws.hdr_host->pad = 0;
+
+  MLMC_HIP(hipEventRecord(ws.ev[0], stream));
+  MLMC_HIP(hipMemcpyAsync(ws.items_dev, ws.items_host, d.size() * sizeof(LevelDesc),
+                          hipMemcpyHostToDevice, stream));
+  MLMC_HIP(hipMemcpyAsync(ws.hdr_dev, ws.hdr_host, sizeof(WorkHeader), hipMemcpyHostToDevice,
+                          stream));
+  bool kernel_timed = false;
+  if (mode == 0) {
+    MLMC_HIP(hipEventRecord(ws.ev[1], stream));
+    for (size_t i = 0; i < d.size(); ++i)
+      MLMC_HIP(launch_level(fp64, tuning.ppt, d[i].kind, ws.items_dev, (uint32_t)i, d[i].n_tiles,
+                            tuning.block, ws.partials, stream));
+    MLMC_HIP(hipEventRecord(ws.ev[2], stream));
+    MLMC_HIP(launch_reduce(ws.items_dev, ws.hdr_dev, ws.partials, ws.groups, ws.resident,
+                           kReduceGridGroups, kReduceGridItems, stream));
+    kernel_timed = true;
+  } else if (mode == 2) {
+    MLMC_HIP(launch_fill_u32(ws.counter_dev, 1, 0u, stream));
+    MLMC_HIP(hipEventRecord(ws.ev[1], stream));
+    MLMC_HIP(launch_persistent(fp64, tuning.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev,
+                               ws.partials, tuning.block, persistent_grid(ws, tuning), stream));
+    MLMC_HIP(hipEventRecord(ws.ev[2], stream));
+    MLMC_HIP(launch_reduce(ws.items_dev, ws.hdr_dev, ws.partials, ws.groups, ws.resident,
+                           kReduceGridGroups, kReduceGridItems, stream));
+    kernel_timed = true;
+  } else {
+    const uint64_t key = ((uint64_t)tuning.block << 48) ^ ((uint64_t)tuning.ppt << 40) ^
+                         ((uint64_t)tuning.waves_per_simd << 32) ^ (fp64 ? 1ull : 2ull) ^
+                         ((uint64_t)(uintptr_t)ws.partials << 3);
+    if (!ws.graph || ws.graph_key != key) {
+      if (ws.graph) (void)hipGraphExecDestroy(ws.graph);
+      if (ws.graph_def) (void)hipGraphDestroy(ws.graph_def);
+      ws.graph = nullptr;
+      ws.graph_def = nullptr;
+      MLMC_HIP(hipStreamBeginCapture(ws.capture_stream, hipStreamCaptureModeRelaxed));
+      mlmc_ap_status st = record_device_work(ws, fp64, tuning, ws.capture_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(ws.capture_stream, &g);
+      if (st != MLMC_AP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return set_error(MLMC_AP_EDEVICE, "hipStreamEndCapture failed");
+      ws.graph_def = g;
+      MLMC_HIP(hipGraphInstantiate(&ws.graph, g, nullptr, nullptr, 0));
+      ws.graph_key = key;
+    }
+    MLMC_HIP(hipGraphLaunch(ws.graph, stream));
+  }
+  MLMC_HIP(hipMemcpyAsync(ws.resident_host, ws.resident, n_slots * sizeof(Stats),
+                          hipMemcpyDeviceToHost, stream));
+  MLMC_HIP(hipEventRecord(ws.ev[3], stream));
+  MLMC_HIP(hipStreamSynchronize(stream));
+  if (timing) {
+    float ms = 0.f;
+    MLMC_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[3]));
+    timing->total_s = ms * 1e-3;
+    timing->kernel_s = 0.0;
+    if (kernel_timed) {
+      MLMC_HIP(hipEventElapsedTime(&ms, ws.ev[1], ws.ev[2]));
+      timing->kernel_s = ms * 1e-3;
+    }
+  }
+  return MLMC_AP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// MLMC control of one request.
+// ---------------------------------------------------------------------------
+void McRequest::init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, uint64_t warmup,
+                     int iters, uint64_t cap) {
+  prob = p;
+  tol = rmse_tol;
+  plain = plain_mc;
+  n_warmup = warmup;
+  max_iter = iters;
+  max_per_tick = cap;
+  phase = 0;
+  iterations = 0;
+  converged = false;
+  need_check = false;
+  done.assign(p.L + 1, 0);
+  target.assign(p.L + 1, 0);
+  st.assign(p.L + 1, stats_empty());
+  for (int l = first_level(); l <= p.L; ++l) target[l] = n_warmup;
+  particle_steps = 0;
+  launches = 0;
+  gpu_seconds = kernel_seconds = 0.0;
+}
+
+bool McRequest::plan(std::vector<ItemSpec>& items, uint32_t slot_base,
+                     unsigned long long* hist_base, size_t hist_stride) {
+  if (phase == 2) return false;
+  bool any = false;
+  for (int l = first_level(); l <= prob.L; ++l) {
+    if (done[l] >= target[l]) continue;
+    uint64_t n = target[l] - done[l];
+    if (max_per_tick && n > max_per_tick) n = max_per_tick;
+    ItemSpec s;
+    s.prob = &prob;
+    s.level = l;
+    s.single = plain;
+    s.sample_begin = done[l];
+    s.n_samples = n;
+    s.result_slot = slot_base + (uint32_t)l;
+    s.hist = hist_base ? hist_base + (size_t)l * hist_stride : nullptr;
+    s.traj = nullptr;
+    s.coll = nullptr;
+    items.push_back(s);
+    any = true;
+  }
+  return any;
+}
+
+static double sample_var(const Stats& s) { return s.n > 1.0 ? s.m2_dq / (s.n - 1.0) : 0.0; }
+
+void McRequest::absorb(const Stats* slots) {
+  for (int l = first_level(); l <= prob.L; ++l) {
+    const uint64_t n_new = (uint64_t)slots[l].n;
+    if (n_new > done[l]) {
+      particle_steps += (n_new - done[l]) * sample_cost(prob, l, plain);
+      done[l] = n_new;
+    }
+    st[l] = slots[l];
+  }
+  for (;;) {
+    for (int l = first_level(); l <= prob.L; ++l)
+      if (done[l] < target[l]) return;  // the current round is not complete
+    if (phase == 0) {
+      phase = 1;
+    } else {
+      double v = 0.0;
+      for (int l = first_level(); l <= prob.L; ++l) v += sample_var(st[l]) / (double)done[l];
+      if (v <= 0.5 * tol * tol) {
+        converged = true;
+        phase = 2;
+        return;
+      }
+      if (iterations >= max_iter) {
+        phase = 2;
+        return;
+      }
+    }
+    // eqs. Nopt1/Noptj with sample variances and the deterministic costs
+    double S = 0.0;
+    for (int l = first_level(); l <= prob.L; ++l)
+      S += std::sqrt(sample_var(st[l]) * (double)sample_cost(prob, l, plain));
+    for (int l = first_level(); l <= prob.L; ++l) {
+      const double c = (double)sample_cost(prob, l, plain);
+      const double N = std::ceil(2.0 / (tol * tol) * std::sqrt(sample_var(st[l]) / c) * S);
+      const uint64_t Ni = N >= 4294967295.0 ? 4294967295ull : (uint64_t)N;
+      target[l] = std::max<uint64_t>(Ni, done[l]);
+    }
+    ++iterations;
+  }
+}
+
+void McRequest::fill_result(mlmc_ap_result* out) const {
+  std::memset(out, 0, sizeof(*out));
+  out->L = prob.L;
+  out->iterations = iterations;
+  out->converged = converged ? 1 : 0;
+  out->status = MLMC_AP_OK;
+  double est = 0.0, var = 0.0;
+  for (int l = first_level(); l <= prob.L; ++l) {
+    est += st[l].mean_dq;
+    if (done[l]) var += sample_var(st[l]) / (double)done[l];
+    out->N[l] = done[l];
+    out->lv[l] = stats_to_api(st[l]);
+  }
+  out->estimate = est;
+  out->var_estimator = var;
+  out->particle_steps = particle_steps;
+  out->launches = launches;
+  out->gpu_seconds = gpu_seconds;
+  out->kernel_seconds = kernel_seconds;
+}
+
+}  // namespace mlmc
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace mlmc;
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+mlmc_ap_options default_options(const mlmc_ap_options* opt) {
+  mlmc_ap_options o;
+  std::memset(&o, 0, sizeof(o));
+  o.batched = 1;
+  if (opt) o = *opt;
+  if (o.max_iter <= 0) o.max_iter = 10;
+  if (o.n_warmup == 0) o.n_warmup = 1000;
+  return o;
+}
+
+// Runs requests to completion, each MLMC iteration of all of them in one
+// launch (mode 1/2) or with one launch per level (mode 0).
+mlmc_ap_status run_requests(Workspace& ws, std::vector<McRequest>& reqs, int mode,
+                            const mlmc_ap_tuning& tuning, hipStream_t stream,
+                            unsigned long long* hist_dev, size_t hist_stride) {
+  const size_t n_slots = reqs.size() * MLMC_AP_MAX_LEVELS;
+  MLMC_TRY(ws.ensure(1, 1, 1, n_slots, 0));
+  std::vector<Stats> empty(n_slots, stats_empty());
+  MLMC_HIP(hipMemcpyAsync(ws.resident, empty.data(), n_slots * sizeof(Stats),
+                          hipMemcpyHostToDevice, stream));
+  MLMC_HIP(hipStreamSynchronize(stream));
+  for (int guard = 0; guard < 100000; ++guard) {
+    std::vector<ItemSpec> items;
+    std::vector<size_t> owners;
+    for (size_t r = 0; r < reqs.size(); ++r) {
+      const size_t before = items.size();
+      unsigned long long* hb = hist_dev ? hist_dev + r * (MLMC_AP_MAX_LEVELS * hist_stride) : nullptr;
+      reqs[r].plan(items, (uint32_t)(r * MLMC_AP_MAX_LEVELS), hb, hist_stride);
+      if (items.size() > before) owners.push_back(r);
+    }
+    if (items.empty()) return MLMC_AP_OK;
+    LaunchTiming t;
+    MLMC_TRY(run_table(ws, items, n_slots, mode, tuning, stream, &t));
+    for (size_t r : owners) {
+      reqs[r].launches += 1;
+      reqs[r].gpu_seconds += t.total_s;
+      reqs[r].kernel_seconds += t.kernel_s;
+      reqs[r].absorb(ws.resident_host + r * MLMC_AP_MAX_LEVELS);
+    }
+  }
+  return set_error(MLMC_AP_EDEVICE, "MLMC loop did not terminate");
+}
+
+}  // namespace
+
+extern "C" {
+
+mlmc_ap_status mlmc_ap_init(void) {
+  Workspace* ws = workspace();
+  return ws ? MLMC_AP_OK : MLMC_AP_EDEVICE;
+}
+
+mlmc_ap_status mlmc_ap_release(void) {
+  Workspace* ws = workspace();
+  if (!ws) return MLMC_AP_EDEVICE;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  ws->release();
+  return MLMC_AP_OK;
+}
+
+const char* mlmc_ap_status_str(mlmc_ap_status s) {
+  switch (s) {
+    case MLMC_AP_OK: return "ok";
+    case MLMC_AP_EINVAL: return "invalid argument";
+    case MLMC_AP_ENOMEM: return "out of memory";
+    case MLMC_AP_EDEVICE: return "device error";
+    case MLMC_AP_EBUSY: return "request exceeds the memory budget";
+    case MLMC_AP_ECANCELLED: return "cancelled";
+    case MLMC_AP_ENOTFOUND: return "unknown ticket";
+    case MLMC_AP_EAGAIN: return "not finished";
+  }
+  return "unknown status";
+}
+
+const char* mlmc_ap_last_error(void) { return g_last_error.c_str(); }
+
+const char* mlmc_ap_version(void) { return "mlmc_ap 0.1 (gfx950)"; }
+
+mlmc_ap_status mlmc_ap_validate(const mlmc_ap_problem* p) { return validate_problem(p); }
+
+mlmc_ap_status mlmc_ap_level_constants(const mlmc_ap_problem* p, int32_t level,
+                                       mlmc_ap_level_info* out) {
+  MLMC_TRY(validate_problem(p));
+  if (!out) return set_error(MLMC_AP_EINVAL, "out is NULL");
+  if (level < 0 || level > p->L) return set_error(MLMC_AP_EINVAL, "level must be in [0, L]");
+  std::memset(out, 0, sizeof(*out));
+  const LevelConst F = level_const(*p, level);
+  out->dt = F.dt; out->h = F.h; out->s = F.s; out->p = F.p;
+  out->n_steps = F.n_steps;
+  out->thr_f = F.thr;
+  if (level >= 1) {
+    const LevelConst C = level_const(*p, level - 1);
+    out->dt_c = C.dt; out->h_c = C.h; out->s_c = C.s; out->p_c = C.p;
+    out->thr_c = C.thr;
+    out->thr_c2 = coarse_threshold(F.thr, C.thr, p->M);
+  }
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_optimal_samples(const double* V, const double* C, int32_t n, double tol,
+                                       uint64_t* N) {
+  if (!V || !C || !N || n < 1) return set_error(MLMC_AP_EINVAL, "bad arrays");
+  if (!(tol > 0.0)) return set_error(MLMC_AP_EINVAL, "tol must be > 0");
+  double S = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (!(V[i] >= 0.0) || !(C[i] > 0.0)) return set_error(MLMC_AP_EINVAL, "need V >= 0, C > 0");
+    S += std::sqrt(V[i] * C[i]);
+  }
+  for (int i = 0; i < n; ++i) {
+    const double x = std::ceil(2.0 / (tol * tol) * std::sqrt(V[i] / C[i]) * S);
+    N[i] = x >= 1.8e19 ? UINT64_MAX : (uint64_t)x;
+  }
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_merge_stats(const mlmc_ap_level_stats* a, const mlmc_ap_level_stats* b,
+                                   mlmc_ap_level_stats* out) {
+  if (!a || !b || !out) return set_error(MLMC_AP_EINVAL, "NULL argument");
+  *out = stats_to_api(stats_merge(stats_from_api(*a), stats_from_api(*b)));
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, int32_t single,
+                                      uint64_t sample_begin, uint64_t n_samples,
+                                      mlmc_ap_level_stats* out_host, void* traj_dev,
+                                      uint32_t* coll_dev, uint64_t* hist_host, void* stream) {
+  MLMC_TRY(validate_problem(p));
+  if (!out_host) return set_error(MLMC_AP_EINVAL, "out_host is NULL");
+  if (level < 0 || level > p->L) return set_error(MLMC_AP_EINVAL, "level must be in [0, L]");
+  if (single != 0 && single != 1) return set_error(MLMC_AP_EINVAL, "single must be 0 or 1");
+  if (sample_begin > 4294967296ull || n_samples > 4294967296ull - sample_begin)
+    return set_error(MLMC_AP_EINVAL, "sample_begin + n_samples must not exceed 2^32");
+  const bool hist = p->qoi == MLMC_AP_QOI_X2_HIST;
+  if (hist && !hist_host)
+    return set_error(MLMC_AP_EINVAL, "hist_host is required with QOI_X2_HIST");
+  Workspace* ws = workspace();
+  if (!ws) return MLMC_AP_EDEVICE;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  hipStream_t s = (hipStream_t)stream;
+  std::memset(out_host, 0, sizeof(*out_host));
+  if (n_samples == 0) {
+    if (hist) std::memset(hist_host, 0, sizeof(uint64_t) * (3 * (size_t)p->nbins + 4));
+    return MLMC_AP_OK;
+  }
+  const size_t hist_n = hist ? 3 * (size_t)p->nbins + 4 : 0;
+  MLMC_TRY(ws->ensure(1, 1, 1, 1, hist_n));
+  const Stats e = stats_empty();
+  MLMC_HIP(hipMemcpyAsync(ws->resident, &e, sizeof(Stats), hipMemcpyHostToDevice, s));
+  MLMC_HIP(hipStreamSynchronize(s));
+  if (hist) MLMC_HIP(launch_fill_u64(ws->hist_dev, hist_n, 0ull, s));
+  ItemSpec it;
+  it.prob = p;
+  it.level = level;
+  it.single = single != 0;
+  it.sample_begin = sample_begin;
+  it.n_samples = n_samples;
+  it.result_slot = 0;
+  it.hist = hist ? ws->hist_dev : nullptr;
+  it.traj = traj_dev;
+  it.coll = coll_dev;
+  const mlmc_ap_tuning t = resolve_tuning(*ws, nullptr);
+  MLMC_TRY(run_table(*ws, std::vector<ItemSpec>{it}, 1, 0, t, s, nullptr));
+  *out_host = stats_to_api(ws->resident_host[0]);
+  if (hist) {
+    MLMC_HIP(hipMemcpy(hist_host, ws->hist_dev, hist_n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  }
+  return MLMC_AP_OK;
+}
+
+static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* tols, int32_t n_req,
+                                      bool plain, const mlmc_ap_options* opt,
+                                      mlmc_ap_result* out, uint64_t* hist_host, void* stream) {
+  if (n_req < 1 || !p || !tols || !out) return set_error(MLMC_AP_EINVAL, "bad arguments");
+  for (int i = 0; i < n_req; ++i) {
+    MLMC_TRY(validate_problem(&p[i]));
+    if (!(tols[i] > 0.0) || !std::isfinite(tols[i]))
+      return set_error(MLMC_AP_EINVAL, "rmse_tol must be > 0");
+    if ((p[i].fp64_state != 0) != (p[0].fp64_state != 0))
+      return set_error(MLMC_AP_EINVAL, "a batch cannot mix FP32 and FP64 particle state");
+  }
+  const mlmc_ap_options o = default_options(opt);
+  if (o.batched < 0 || o.batched > 2) return set_error(MLMC_AP_EINVAL, "options.batched must be 0, 1 or 2");
+  Workspace* ws = workspace();
+  if (!ws) return MLMC_AP_EDEVICE;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  const mlmc_ap_tuning t = resolve_tuning(*ws, &o.tuning);
+  MLMC_TRY(check_tuning(t));
+  const double t0 = now_s();
+  std::vector<McRequest> reqs(n_req);
+  for (int i = 0; i < n_req; ++i) reqs[i].init(p[i], tols[i], plain, o.n_warmup, o.max_iter, 0);
+  // histogram counters (single request with QOI_X2_HIST)
+  size_t hist_stride = 0;
+  unsigned long long* hist_dev = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  if (n_req == 1 && p[0].qoi == MLMC_AP_QOI_X2_HIST && hist_host) {
+    hist_stride = 3 * (size_t)p[0].nbins + 4;
+    MLMC_TRY(ws->ensure(1, 1, 1, MLMC_AP_MAX_LEVELS, hist_stride * MLMC_AP_MAX_LEVELS));
+    MLMC_HIP(launch_fill_u64(ws->hist_dev, hist_stride * MLMC_AP_MAX_LEVELS, 0ull, s));
+    hist_dev = ws->hist_dev;
+  }
+  MLMC_TRY(run_requests(*ws, reqs, o.batched, t, s, hist_dev, hist_stride));
+  const double el = now_s() - t0;
+  for (int i = 0; i < n_req; ++i) {
+    reqs[i].fill_result(&out[i]);
+    out[i].seconds = el;
+  }
+  if (hist_dev) {
+    MLMC_HIP(hipMemcpy(hist_host, hist_dev, sizeof(uint64_t) * hist_stride * (p[0].L + 1),
+                       hipMemcpyDeviceToHost));
+  }
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_estimate(const mlmc_ap_problem* p, double rmse_tol,
+                                const mlmc_ap_options* opt, mlmc_ap_result* out_host,
+                                uint64_t* hist_host, void* stream) {
+  return estimate_common(p, &rmse_tol, 1, false, opt, out_host, hist_host, stream);
+}
+
+mlmc_ap_status mlmc_ap_plain_mc(const mlmc_ap_problem* p, double rmse_tol,
+                                const mlmc_ap_options* opt, mlmc_ap_result* out_host,
+                                void* stream) {
+  return estimate_common(p, &rmse_tol, 1, true, opt, out_host, nullptr, stream);
+}
+
+mlmc_ap_status mlmc_ap_estimate_batch(const mlmc_ap_problem* p, const double* rmse_tol,
+                                      int32_t n_req, const mlmc_ap_options* opt,
+                                      mlmc_ap_result* out_host, void* stream) {
+  return estimate_common(p, rmse_tol, n_req, false, opt, out_host, nullptr, stream);
+}
+
+mlmc_ap_status mlmc_ap_philox_words(uint64_t seed, uint32_t stream_id, uint32_t tag,
+                                    uint64_t sample_begin, uint64_t n_samples, uint32_t n_steps,
+                                    uint32_t* out_dev, void* stream) {
+  if (!out_dev && n_samples && n_steps) return set_error(MLMC_AP_EINVAL, "out_dev is NULL");
+  if (sample_begin + n_samples > 4294967296ull)
+    return set_error(MLMC_AP_EINVAL, "sample indices must stay below 2^32");
+  MLMC_HIP(launch_words((uint32_t)seed, (uint32_t)(seed >> 32), stream_id, tag, sample_begin,
+                        n_samples, n_steps, out_dev, (hipStream_t)stream));
+  MLMC_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_rng_normals(uint64_t seed, uint32_t stream_id, uint32_t tag,
+                                   uint64_t sample_begin, uint64_t n_samples, uint32_t n_steps,
+                                   int32_t fp64, void* out_dev, void* stream) {
+  if (!out_dev && n_samples && n_steps) return set_error(MLMC_AP_EINVAL, "out_dev is NULL");
+  if (fp64 != 0 && fp64 != 1) return set_error(MLMC_AP_EINVAL, "fp64 must be 0 or 1");
+  if (sample_begin + n_samples > 4294967296ull)
+    return set_error(MLMC_AP_EINVAL, "sample indices must stay below 2^32");
+  MLMC_HIP(launch_normals(fp64 != 0, (uint32_t)seed, (uint32_t)(seed >> 32), stream_id, tag,
+                          sample_begin, n_samples, n_steps, out_dev, (hipStream_t)stream));
+  MLMC_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return MLMC_AP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// Internal host-side machinery shared by the C ABI entry points (host.cpp)
+// and the serving loop (server.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "mlmc_ap.h"
+#include "types.hpp"
+
+namespace mlmc {
+
+mlmc_ap_status set_error(mlmc_ap_status s, const std::string& msg);
+
+#define MLMC_HIP(expr)                                                                \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::mlmc::set_error(MLMC_AP_EDEVICE,                                      \
+                               std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+#define MLMC_TRY(expr)                          \
+  do {                                          \
+    mlmc_ap_status s_ = (expr);                 \
+    if (s_ != MLMC_AP_OK) return s_;            \
+  } while (0)
+
+// Host-side constants of one level (FP64).
+struct LevelConst {
+  double dt, h, s, p;
+  uint64_t n_steps;
+  uint64_t thr;
+};
+
+LevelConst level_const(const mlmc_ap_problem& p, int level);
+uint64_t coarse_threshold(uint64_t thr_f, uint64_t thr_c, int M);
+mlmc_ap_status validate_problem(const mlmc_ap_problem* p);
+// Particle steps of one sample: n_l (+ n_{l-1} for a pair at l >= 1).
+uint64_t sample_cost(const mlmc_ap_problem& p, int level, bool single);
+
+// One work item request: a sample range of one level of one problem.
+struct ItemSpec {
+  const mlmc_ap_problem* prob;
+  int level;
+  bool single;
+  uint64_t sample_begin, n_samples;
+  uint32_t result_slot;
+  unsigned long long* hist;  // device histogram counters or null
+  void* traj;
+  uint32_t* coll;
+};
+
+LevelDesc make_desc(const ItemSpec& s);
+
+// Device workspace of one device: work table, tile partials, group results,
+// resident statistics, histogram counters, pinned staging, captured graph.
+struct Workspace {
+  int device = -1;
+  int n_cu = 0;
+  std::string name;
+  std::mutex mu;
+  hipStream_t capture_stream = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  LevelDesc* items_dev = nullptr;
+  LevelDesc* items_host = nullptr;
+  size_t items_cap = 0;
+  WorkHeader* hdr_dev = nullptr;
+  WorkHeader* hdr_host = nullptr;
+  unsigned int* counter_dev = nullptr;
+  Stats* partials = nullptr;
+  size_t partials_cap = 0;  // tiles
+  Stats* groups = nullptr;
+  size_t groups_cap = 0;
+  Stats* resident = nullptr;
+  Stats* resident_host = nullptr;
+  size_t resident_cap = 0;  // slots
+  unsigned long long* hist_dev = nullptr;
+  size_t hist_cap = 0;      // counters
+
+  hipGraphExec_t graph = nullptr;
+  hipGraph_t graph_def = nullptr;
+  uint64_t graph_key = 0;
+
+  mlmc_ap_tuning tuning{};      // current default (autotuned or built-in)
+  bool tuned = false;
+
+  ~Workspace();
+
+  mlmc_ap_status ensure(size_t n_items, size_t n_tiles, size_t n_groups, size_t n_slots,
+                        size_t n_hist);
+  void release();
+};
+
+Workspace* workspace();  // of the current device (created on first use)
+// Sets up a private workspace on the current device (the serving loop owns one).
+mlmc_ap_status init_workspace(Workspace& ws);
+mlmc_ap_tuning resolve_tuning(const Workspace& ws, const mlmc_ap_tuning* t);
+int persistent_grid(const Workspace& ws, const mlmc_ap_tuning& t);
+
+// Device time measured by one launch of a table.
+struct LaunchTiming {
+  double total_s = 0.0;   // table upload to statistics read-back
+  double kernel_s = 0.0;  // particle kernel(s) only (0 when replayed from a graph)
+};
+
+// Builds the work table of `items` (assigning tile, group and chunk bases),
+// launches it in the given mode and reads the resident statistics slots
+// [0, n_slots) back into ws.resident_host.  Mode: 0 plain per-item launches,
+// 1 persistent kernel replayed from a captured graph, 2 persistent kernel
+// launched directly (timed with events).
+mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& items, size_t n_slots,
+                         int mode, const mlmc_ap_tuning& tuning, hipStream_t stream,
+                         LaunchTiming* timing);
+
+Stats stats_from_api(const mlmc_ap_level_stats& a);
+mlmc_ap_level_stats stats_to_api(const Stats& s);
+
+// MLMC control of one request (Section 4.1): warm-up, then eqs. Nopt1/Noptj
+// with sample variances and deterministic costs, topped up until the
+// statistical constraint holds (or max_iter top-ups ran).
+struct McRequest {
+  mlmc_ap_problem prob{};
+  double tol = 0.0;
+  bool plain = false;          // plain Monte Carlo at level L (single trajectories)
+  uint64_t n_warmup = 1000;
+  int max_iter = 10;
+  uint64_t max_per_tick = 0;   // 0 = unlimited samples per level per launch
+  int phase = 0;               // 0 warm-up pending, 1 top-ups, 2 finished
+  int iterations = 0;
+  bool converged = false;
+  bool need_check = false;     // statistics changed since the last constraint check
+  std::vector<uint64_t> done, target;
+  std::vector<Stats> st;       // host copy of the resident statistics per level
+  uint64_t particle_steps = 0;
+  uint64_t launches = 0;
+  double gpu_seconds = 0.0, kernel_seconds = 0.0;
+
+  void init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, uint64_t warmup,
+            int iters, uint64_t cap);
+  int first_level() const { return plain ? prob.L : 0; }
+  // Appends this request's work for the next launch; returns false if it has
+  // none (finished).  Slots are slot_base + level.
+  bool plan(std::vector<ItemSpec>& items, uint32_t slot_base, unsigned long long* hist_base,
+            size_t hist_stride);
+  // Takes the statistics of the launch and advances the state machine.
+  void absorb(const Stats* resident_slots);
+  void fill_result(mlmc_ap_result* out) const;
+};
+
+}  // namespace mlmc

@@ -1,0 +1,578 @@
+// Particle and reduction kernels of the MLMC-AP library (gfx950).
+//
+// One wavefront owns one tile of 256 consecutive samples of a work item:
+// lane i simulates samples tile*256 + 64 j + i, j = 0..3, P of them at a time
+// (P = trajectories in flight per lane, for instruction-level parallelism).
+// Particle state lives in registers for the whole trajectory; the only
+// memory traffic is one 80-byte statistics record per tile (plus optional
+// dumps and histogram counters).
+//
+// Per fine step (asymptotic-preserving splitting, fixed dt):
+//   x <- x + h v + s xi;  collide iff word0 < thr  ->  v <- equilibrium draw.
+// Coarse path (levels >= 1), one coarse step per block of M fine steps, built
+// from the fine random numbers of that block (Section 3.1 mapping by time of
+// action; Section 3.2 aggregation):
+//   kick   : eq. chi-update -- normalised weighted sum of the fine kick
+//            normals and (aggregated coupling) of the fine velocity normals the
+//            coarse path does not take, each weighted by its fine transport uses;
+//   collide: the smallest fine decision word of the block is below thr_c2
+//            <= thr_f, so a coarse collision reuses a fine one (the uniform
+//            analogue of eq. epsilon-update) and P = p_c exactly;
+//   v      : the fine velocity drawn last in the block (eq. nu-update).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace mlmc {
+
+// One fine step of P trajectories (and the coarse-block bookkeeping).
+template <typename Real, int P, int KIND, bool WIDE>
+struct Stepper {
+  static constexpr bool kCoarse = KIND >= kKindPairTwoPointSum;
+  static constexpr bool kMaxwell = KIND == kKindFineMaxwell || KIND == kKindPairMaxwellSum ||
+                                   KIND == kKindPairMaxwellAggregate;
+  static constexpr bool kAgg = KIND == kKindPairMaxwellAggregate;
+
+  Real h_f, s_f, h_c, s_c, agg_ms2, h_f2, rsqrt_m;
+  uint32_t thr_f_m1, thr_c2_m1;
+  uint64_t thr_f, thr_c2;
+  uint32_t tag, strm, key0, key1;
+
+  __device__ __forceinline__ explicit Stepper(const LevelDesc& d)
+      : h_f((Real)d.h_f), s_f((Real)d.s_f), h_c((Real)d.h_c), s_c((Real)d.s_c),
+        agg_ms2((Real)d.agg_ms2), h_f2((Real)d.h_f2), rsqrt_m((Real)d.rsqrt_m),
+        thr_f_m1(d.thr_f_m1), thr_c2_m1(d.thr_c2_m1), thr_f(d.thr_f), thr_c2(d.thr_c2),
+        tag(d.tag), strm(d.stream), key0(d.key0), key1(d.key1) {}
+
+  __device__ __forceinline__ Real new_velocity(Real g, uint32_t w3) const {
+    if constexpr (kMaxwell) return g;
+    else return ((int32_t)w3 < 0) ? Real(-1) : Real(1);
+  }
+
+  // Fine path only (level 0 or single-level trajectories).
+  __device__ __forceinline__ void fine(uint32_t n, const uint32_t (&smp)[P], Real (&xf)[P],
+                                       Real (&vf)[P], uint32_t (&cf)[P]) const {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const Words w = philox4x32_10(n, smp[p], tag, strm, key0, key1);
+      Real xi, g;
+      box_muller(w.w1, w.w2, xi, g);
+      Real vnew = new_velocity(g, w.w3);
+      keep(vnew);
+      xf[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, vf[p], xf[p]));
+      const bool hit = below<WIDE>(w.w0, thr_f_m1, thr_f);
+      vf[p] = hit ? vnew : vf[p];
+      cf[p] += hit ? 1u : 0u;
+    }
+  }
+
+  // Fine/coarse pairs: M fine steps, then the coarse step built from them.
+  // Aggregated kick bookkeeping per block: num accumulates, for every fine
+  // move made with an in-block velocity draw, that draw's normal (so it holds
+  // sum_j n_j nu_j), and den accumulates 2u+1 at the u-th further use of a
+  // draw (so it holds sum_j n_j^2).  If the coarse path collides, the last
+  // draw becomes its velocity and its n nu and n^2 are taken out again.
+  __device__ __forceinline__ void block(uint32_t b, uint32_t M, const uint32_t (&smp)[P],
+                                        Real (&xf)[P], Real (&vf)[P], Real (&xc)[P],
+                                        Real (&vc)[P], uint32_t (&cf)[P],
+                                        uint32_t (&cc)[P]) const {
+    Real sum_xi[P], num[P], den[P], lnu[P], uses[P], have[P];
+    uint32_t wmin[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      sum_xi[p] = Real(0); num[p] = Real(0); den[p] = Real(0);
+      lnu[p] = Real(0); uses[p] = Real(0); have[p] = Real(0);
+      wmin[p] = 0xFFFFFFFFu;
+    }
+#pragma unroll 1
+    for (uint32_t m = 0; m < M; ++m) {
+      const uint32_t n = b * M + m;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const Words w = philox4x32_10(n, smp[p], tag, strm, key0, key1);
+        Real xi, g;
+        box_muller(w.w1, w.w2, xi, g);
+        Real vnew = new_velocity(g, w.w3);
+        keep(vnew);
+        xf[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, vf[p], xf[p]));
+        const bool hit = below<WIDE>(w.w0, thr_f_m1, thr_f);
+        vf[p] = hit ? vnew : vf[p];
+        cf[p] += hit ? 1u : 0u;
+        sum_xi[p] += xi;
+        wmin[p] = min(wmin[p], w.w0);
+        if constexpr (kAgg) {
+          num[p] += lnu[p];  // zero until the first in-block draw
+          den[p] = fma_r<Real>(have[p], fma_r<Real>(Real(2), uses[p], Real(1)), den[p]);
+          uses[p] += have[p];
+          lnu[p] = hit ? vnew : lnu[p];
+          uses[p] = hit ? Real(0) : uses[p];
+          have[p] = hit ? Real(1) : have[p];
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      // coarse collision: the smallest fine decision word is below thr_c2
+      const bool chit = below<WIDE>(wmin[p], thr_c2_m1, thr_c2);
+      Real kick;
+      if constexpr (kAgg) {
+        const Real nn = chit ? fma_r<Real>(-uses[p], lnu[p], num[p]) : num[p];
+        const Real dd = chit ? fma_r<Real>(-uses[p], uses[p], den[p]) : den[p];
+        kick = fma_r<Real>(h_f, nn, s_f * sum_xi[p]) * rsqrt_r(fma_r<Real>(h_f2, dd, agg_ms2));
+      } else {
+        kick = sum_xi[p] * rsqrt_m;
+      }
+      xc[p] = fma_r<Real>(s_c, kick, fma_r<Real>(h_c, vc[p], xc[p]));
+      vc[p] = chit ? vf[p] : vc[p];
+      cc[p] += chit ? 1u : 0u;
+    }
+  }
+};
+
+template <typename Real, int P, int KIND, bool WIDE>
+__device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
+                                              Stats* __restrict__ partials) {
+  using S = Stepper<Real, P, KIND, WIDE>;
+  constexpr bool kCoarse = S::kCoarse;
+  constexpr int kRounds = kSamplesPerLane / P;
+  const S st(d);
+  const int lane = threadIdx.x & (kLanes - 1);
+  const uint32_t n_steps = d.n_steps, M = d.M;
+
+  // Shifted sums (shift = the values of the tile's first sample, lane 0).
+  double k_dq = 0.0, k_f = 0.0, k_c = 0.0;
+  double s1_dq = 0.0, s2_dq = 0.0, s1_f = 0.0, s2_f = 0.0, s1_c = 0.0, s2_c = 0.0, s_fc = 0.0;
+  uint32_t cnt = 0;
+  unsigned long long col_f = 0, col_c = 0;
+
+#pragma unroll 1
+  for (int r = 0; r < kRounds; ++r) {
+    uint64_t local[P];
+    bool valid[P];
+    uint32_t smp[P];
+    Real xf[P], vf[P], xc[P], vc[P];
+    uint32_t cf[P], cc[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int j = r * P + p;
+      local[p] = (uint64_t)tile * kTile + (uint64_t)(j * kLanes + lane);
+      valid[p] = local[p] < d.n_samples;
+      smp[p] = (uint32_t)(d.sample_begin + local[p]);
+      // initial condition, shared by the fine and the coarse path
+      const Words w = philox4x32_10(0xFFFFFFFFu, smp[p], st.tag, st.strm, st.key0, st.key1);
+      Real nc, ns;
+      box_muller(w.w1, w.w2, nc, ns);
+      Real x0;
+      if (d.x0_kind == 0) {
+        x0 = (Real)d.x0_a;
+      } else if (d.x0_kind == 1) {
+        x0 = fma_r<Real>((Real)d.x0_b, nc, (Real)d.x0_a);
+      } else {
+        x0 = (Real)cosine_icdf(uniform_f64(w.w0));
+      }
+      const Real v0 = st.new_velocity(ns, w.w3);
+      xf[p] = x0; vf[p] = v0; xc[p] = x0; vc[p] = v0;
+      cf[p] = 0u; cc[p] = 0u;
+    }
+
+    if constexpr (kCoarse) {
+      const uint32_t n_blocks = n_steps / M;
+#pragma unroll 1
+      for (uint32_t b = 0; b < n_blocks; ++b) st.block(b, M, smp, xf, vf, xc, vc, cf, cc);
+    } else {
+#pragma unroll 1
+      for (uint32_t n = 0; n < n_steps; ++n) st.fine(n, smp, xf, vf, cf);
+    }
+
+    // Quantity of interest in FP64 (exact squares of FP32 positions).
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const double qf = (double)xf[p] * (double)xf[p];
+      const double qc = kCoarse ? (double)xc[p] * (double)xc[p] : 0.0;
+      const double dq = qf - qc;
+      if (r == 0 && p == 0) {  // lane 0, sample 0 of the tile always exists
+        k_dq = __shfl(dq, 0, kLanes);
+        if constexpr (kCoarse) {
+          k_f = __shfl(qf, 0, kLanes);
+          k_c = __shfl(qc, 0, kLanes);
+        }
+      }
+      if (valid[p]) {
+        const double e_dq = dq - k_dq;
+        s1_dq += e_dq;
+        s2_dq += e_dq * e_dq;
+        if constexpr (kCoarse) {
+          const double e_f = qf - k_f, e_c = qc - k_c;
+          s1_f += e_f; s2_f += e_f * e_f;
+          s1_c += e_c; s2_c += e_c * e_c;
+          s_fc += e_f * e_c;
+        }
+        cnt += 1u;
+        col_f += cf[p];
+        col_c += cc[p];
+        if (d.traj) {
+          Real* t = (Real*)d.traj;
+          t[local[p]] = xf[p];
+          t[d.n_samples + local[p]] = kCoarse ? xc[p] : Real(0);
+        }
+        if (d.coll) {
+          d.coll[local[p]] = cf[p];
+          d.coll[d.n_samples + local[p]] = cc[p];
+        }
+        if (d.flags & kFlagHist) {
+          const int nb = (int)d.nbins;
+          const double tf = ((double)xf[p] - d.hist_lo) * d.hist_inv_w;
+          const int bf = tf < 0.0 ? -1 : (tf >= (double)nb ? nb : (int)tf);
+          unsigned long long* hst = d.hist;
+          if (bf < 0) atomicAdd(&hst[3 * nb + 0], 1ull);
+          else if (bf >= nb) atomicAdd(&hst[3 * nb + 1], 1ull);
+          else atomicAdd(&hst[3 * bf], 1ull);
+          if (kCoarse) {
+            const double tc = ((double)xc[p] - d.hist_lo) * d.hist_inv_w;
+            const int bc = tc < 0.0 ? -1 : (tc >= (double)nb ? nb : (int)tc);
+            if (bc < 0) atomicAdd(&hst[3 * nb + 2], 1ull);
+            else if (bc >= nb) atomicAdd(&hst[3 * nb + 3], 1ull);
+            else {
+              atomicAdd(&hst[3 * bc + 1], 1ull);
+              if (bc == bf) atomicAdd(&hst[3 * bc + 2], 1ull);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // Tile statistics: fixed xor-butterfly sums, then lane 0 writes the record.
+  const double n = (double)wave_sum_u64((unsigned long long)cnt);
+  const double t1_dq = wave_sum(s1_dq), t2_dq = wave_sum(s2_dq);
+  Stats out;
+  out.n = n;
+  out.mean_dq = k_dq + t1_dq / n;
+  out.m2_dq = fmax(t2_dq - t1_dq * (t1_dq / n), 0.0);
+  if constexpr (kCoarse) {
+    const double t1_f = wave_sum(s1_f), t2_f = wave_sum(s2_f);
+    const double t1_c = wave_sum(s1_c), t2_c = wave_sum(s2_c), t_fc = wave_sum(s_fc);
+    out.mean_qf = k_f + t1_f / n;
+    out.m2_qf = fmax(t2_f - t1_f * (t1_f / n), 0.0);
+    out.mean_qc = k_c + t1_c / n;
+    out.m2_qc = fmax(t2_c - t1_c * (t1_c / n), 0.0);
+    out.c_fc = t_fc - t1_f * (t1_c / n);
+  } else {
+    out.mean_qf = out.mean_dq;
+    out.m2_qf = out.m2_dq;
+    out.mean_qc = 0.0;
+    out.m2_qc = 0.0;
+    out.c_fc = 0.0;
+  }
+  out.coll_f = wave_sum_u64(col_f);
+  out.coll_c = wave_sum_u64(col_c);
+  if (lane == 0) partials[d.tile_base + tile] = out;
+}
+
+template <typename Real, int P, int KIND>
+__device__ __forceinline__ void run_tile(const LevelDesc& d, uint32_t tile,
+                                         Stats* __restrict__ partials) {
+  if (d.flags & kFlagWide) run_tile_impl<Real, P, KIND, true>(d, tile, partials);
+  else run_tile_impl<Real, P, KIND, false>(d, tile, partials);
+}
+
+// ---------------------------------------------------------------------------
+// Plain launch: one tile per wavefront over one work item.
+// ---------------------------------------------------------------------------
+template <typename Real, int P, int KIND>
+__global__ void __launch_bounds__(256) level_kernel(const LevelDesc* __restrict__ items,
+                                                     uint32_t item, Stats* __restrict__ partials) {
+  const LevelDesc d = items[item];
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
+  if (wave >= d.n_tiles) return;  // the whole wavefront leaves together
+  run_tile<Real, P, KIND>(d, wave, partials);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent launch over a work table.  Each wavefront takes the next chunk
+// (a run of tiles of one item) from an integer work counter until the table
+// is drained; items are ordered most expensive first.
+// ---------------------------------------------------------------------------
+template <typename Real, int P>
+__global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __restrict__ items,
+                                                          const WorkHeader* __restrict__ hdr,
+                                                          unsigned int* __restrict__ counter,
+                                                          Stats* __restrict__ partials) {
+  const uint32_t n_items = hdr->n_items;
+  const uint32_t total = hdr->total_chunks;
+  const int lane = threadIdx.x & (kLanes - 1);
+  for (;;) {
+    unsigned int g = 0;
+    if (lane == 0) g = atomicAdd(counter, 1u);
+    g = __builtin_amdgcn_readfirstlane(__shfl(g, 0, kLanes));
+    if (g >= total) break;
+    uint32_t lo = 0, hi = n_items;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (items[mid].chunk_base <= g) lo = mid; else hi = mid;
+    }
+    const LevelDesc d = items[lo];
+    const uint32_t c = g - (uint32_t)d.chunk_base;
+    const uint32_t t0 = c * d.chunk_tiles;
+    const uint32_t t1 = min(t0 + d.chunk_tiles, d.n_tiles);
+    switch (d.kind) {
+      case kKindFineTwoPoint:
+        for (uint32_t t = t0; t < t1; ++t) run_tile<Real, P, kKindFineTwoPoint>(d, t, partials);
+        break;
+      case kKindFineMaxwell:
+        for (uint32_t t = t0; t < t1; ++t) run_tile<Real, P, kKindFineMaxwell>(d, t, partials);
+        break;
+      case kKindPairTwoPointSum:
+        for (uint32_t t = t0; t < t1; ++t) run_tile<Real, P, kKindPairTwoPointSum>(d, t, partials);
+        break;
+      case kKindPairMaxwellSum:
+        for (uint32_t t = t0; t < t1; ++t) run_tile<Real, P, kKindPairMaxwellSum>(d, t, partials);
+        break;
+      default:
+        for (uint32_t t = t0; t < t1; ++t)
+          run_tile<Real, P, kKindPairMaxwellAggregate>(d, t, partials);
+        break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.  Stage 1: group g of an item merges tiles [4096 g, 4096 g +
+// 4096): thread t merges its 16 consecutive tiles in order, then a fixed LDS
+// tree.  Stage 2: one block per item merges the item's group results the
+// same way and folds the result into the item's resident statistics slot.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Stats block_tree(Stats acc, Stats* sh) {
+  const int t = threadIdx.x;
+  sh[t] = acc;
+  __syncthreads();
+#pragma unroll 1
+  for (int stride = kReduceThreads / 2; stride > 0; stride >>= 1) {
+    if (t < stride) sh[t] = stats_merge(sh[t], sh[t + stride]);
+    __syncthreads();
+  }
+  const Stats r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(kReduceThreads) reduce_groups_kernel(
+    const LevelDesc* __restrict__ items, const WorkHeader* __restrict__ hdr,
+    const Stats* __restrict__ partials, Stats* __restrict__ groups) {
+  __shared__ Stats sh[kReduceThreads];
+  const uint32_t n_items = hdr->n_items;
+  const uint32_t total = hdr->total_groups;
+  for (uint32_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    uint32_t lo = 0, hi = n_items;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (items[mid].group_base <= vb) lo = mid; else hi = mid;
+    }
+    const uint64_t tile_base = items[lo].tile_base;
+    const uint32_t n_tiles = items[lo].n_tiles;
+    const uint32_t g = vb - (uint32_t)items[lo].group_base;
+    Stats acc = stats_empty();
+    const uint32_t first = g * kGroupTiles + threadIdx.x * kReducePerThread;
+    for (int k = 0; k < kReducePerThread; ++k) {
+      const uint32_t idx = first + k;
+      if (idx < n_tiles) acc = stats_merge(acc, partials[tile_base + idx]);
+    }
+    const Stats r = block_tree(acc, sh);
+    if (threadIdx.x == 0) groups[vb] = r;
+  }
+}
+
+__global__ void __launch_bounds__(kReduceThreads) reduce_items_kernel(
+    const LevelDesc* __restrict__ items, const WorkHeader* __restrict__ hdr,
+    const Stats* __restrict__ groups, Stats* __restrict__ resident) {
+  __shared__ Stats sh[kReduceThreads];
+  const uint32_t n_items = hdr->n_items;
+  for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const uint64_t gbase = items[it].group_base;
+    const uint32_t n_groups = items[it].n_groups;
+    Stats acc = stats_empty();
+    const uint32_t first = threadIdx.x * kReducePerThread;
+    for (int k = 0; k < kReducePerThread; ++k) {
+      const uint32_t idx = first + k;
+      if (idx < n_groups) acc = stats_merge(acc, groups[gbase + idx]);
+    }
+    const Stats r = block_tree(acc, sh);
+    if (threadIdx.x == 0) {
+      const uint32_t slot = items[it].result_slot;
+      resident[slot] = (items[it].flags & kFlagAccumulate) ? stats_merge(resident[slot], r) : r;
+    }
+  }
+}
+
+__global__ void fill_u32_kernel(unsigned int* p, uint64_t n, unsigned int v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, uint64_t n, unsigned long long v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Validation kernels: the same Philox / uniform / Box-Muller code paths.
+// ---------------------------------------------------------------------------
+__global__ void words_kernel(uint32_t key0, uint32_t key1, uint32_t strm, uint32_t tag,
+                             uint64_t sample_begin, uint64_t n_samples, uint32_t n_steps,
+                             uint32_t* __restrict__ out) {
+  const uint64_t total = n_samples * n_steps;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t s = i / n_steps;
+    const uint32_t n = (uint32_t)(i % n_steps);
+    const Words w = philox4x32_10(n, (uint32_t)(sample_begin + s), tag, strm, key0, key1);
+    out[4 * i + 0] = w.w0; out[4 * i + 1] = w.w1;
+    out[4 * i + 2] = w.w2; out[4 * i + 3] = w.w3;
+  }
+}
+
+template <typename Real>
+__global__ void normals_kernel(uint32_t key0, uint32_t key1, uint32_t strm, uint32_t tag,
+                               uint64_t sample_begin, uint64_t n_samples, uint32_t n_steps,
+                               Real* __restrict__ out) {
+  const uint64_t total = n_samples * n_steps;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t s = i / n_steps;
+    const uint32_t n = (uint32_t)(i % n_steps);
+    const Words w = philox4x32_10(n, (uint32_t)(sample_begin + s), tag, strm, key0, key1);
+    Real xi, g;
+    box_muller(w.w1, w.w2, xi, g);
+    Real u1, u2;
+    if constexpr (sizeof(Real) == 4) { u1 = uniform_f32(w.w1); u2 = uniform_f32(w.w2); }
+    else { u1 = uniform_f64(w.w1); u2 = uniform_f64(w.w2); }
+    out[4 * i + 0] = u1; out[4 * i + 1] = u2;
+    out[4 * i + 2] = xi; out[4 * i + 3] = g;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+template <typename Real, int P>
+static hipError_t launch_level_p(int kind, const LevelDesc* items, uint32_t item, uint32_t n_tiles,
+                                 int block, Stats* partials, hipStream_t s) {
+  const uint32_t waves_per_block = (uint32_t)block / kLanes;
+  const dim3 grid((n_tiles + waves_per_block - 1) / waves_per_block);
+  switch (kind) {
+    case kKindFineTwoPoint:
+      hipLaunchKernelGGL((level_kernel<Real, P, kKindFineTwoPoint>), grid, dim3(block), 0, s,
+                         items, item, partials);
+      break;
+    case kKindFineMaxwell:
+      hipLaunchKernelGGL((level_kernel<Real, P, kKindFineMaxwell>), grid, dim3(block), 0, s,
+                         items, item, partials);
+      break;
+    case kKindPairTwoPointSum:
+      hipLaunchKernelGGL((level_kernel<Real, P, kKindPairTwoPointSum>), grid, dim3(block), 0, s,
+                         items, item, partials);
+      break;
+    case kKindPairMaxwellSum:
+      hipLaunchKernelGGL((level_kernel<Real, P, kKindPairMaxwellSum>), grid, dim3(block), 0, s,
+                         items, item, partials);
+      break;
+    default:
+      hipLaunchKernelGGL((level_kernel<Real, P, kKindPairMaxwellAggregate>), grid, dim3(block),
+                         0, s, items, item, partials);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev, uint32_t item,
+                        uint32_t n_tiles, int block, Stats* partials, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  if (fp64) {
+    if (ppt == 1) return launch_level_p<double, 1>(kind, items_dev, item, n_tiles, block, partials, s);
+    if (ppt == 2) return launch_level_p<double, 2>(kind, items_dev, item, n_tiles, block, partials, s);
+    return launch_level_p<double, 4>(kind, items_dev, item, n_tiles, block, partials, s);
+  }
+  if (ppt == 1) return launch_level_p<float, 1>(kind, items_dev, item, n_tiles, block, partials, s);
+  if (ppt == 2) return launch_level_p<float, 2>(kind, items_dev, item, n_tiles, block, partials, s);
+  return launch_level_p<float, 4>(kind, items_dev, item, n_tiles, block, partials, s);
+}
+
+hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
+                             const WorkHeader* hdr_dev, unsigned int* counter, Stats* partials,
+                             int block, int grid, hipStream_t s) {
+  const dim3 g(grid), b(block);
+#define MLMC_PERSIST(R, PP) \
+  hipLaunchKernelGGL((persistent_kernel<R, PP>), g, b, 0, s, items_dev, hdr_dev, counter, partials)
+  if (fp64) {
+    if (ppt == 1) MLMC_PERSIST(double, 1);
+    else if (ppt == 2) MLMC_PERSIST(double, 2);
+    else MLMC_PERSIST(double, 4);
+  } else {
+    if (ppt == 1) MLMC_PERSIST(float, 1);
+    else if (ppt == 2) MLMC_PERSIST(float, 2);
+    else MLMC_PERSIST(float, 4);
+  }
+#undef MLMC_PERSIST
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev,
+                         const Stats* partials, Stats* groups, Stats* resident, int grid_groups,
+                         int grid_items, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_groups_kernel, dim3(grid_groups), dim3(kReduceThreads), 0, s,
+                     items_dev, hdr_dev, partials, groups);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_items_kernel, dim3(grid_items), dim3(kReduceThreads), 0, s,
+                     items_dev, hdr_dev, groups, resident);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned int* p, uint64_t n, unsigned int v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256),
+                     0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256),
+                     0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_words(uint32_t key0, uint32_t key1, uint32_t strm, uint32_t tag,
+                        uint64_t sample_begin, uint64_t n_samples, uint32_t n_steps,
+                        uint32_t* out, hipStream_t s) {
+  const uint64_t total = n_samples * n_steps;
+  if (total == 0) return hipSuccess;
+  const uint64_t blocks = (total + 255) / 256;
+  hipLaunchKernelGGL(words_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0,
+                     s, key0, key1, strm, tag, sample_begin, n_samples, n_steps, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_normals(bool fp64, uint32_t key0, uint32_t key1, uint32_t strm, uint32_t tag,
+                          uint64_t sample_begin, uint64_t n_samples, uint32_t n_steps, void* out,
+                          hipStream_t s) {
+  const uint64_t total = n_samples * n_steps;
+  if (total == 0) return hipSuccess;
+  const uint64_t blocks = (total + 255) / 256;
+  const dim3 g((unsigned)(blocks < 4096 ? blocks : 4096));
+  if (fp64)
+    hipLaunchKernelGGL(normals_kernel<double>, g, dim3(256), 0, s, key0, key1, strm, tag,
+                       sample_begin, n_samples, n_steps, (double*)out);
+  else
+    hipLaunchKernelGGL(normals_kernel<float>, g, dim3(256), 0, s, key0, key1, strm, tag,
+                       sample_begin, n_samples, n_steps, (float*)out);
+  return hipGetLastError();
+}
+
+}  // namespace mlmc

@@ -1,0 +1,36 @@
+// Launchers of the device kernels (implemented in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "types.hpp"
+
+namespace mlmc {
+
+// Header of a device work table (read by the graph-captured kernels, so a
+// replay picks up whatever table the host uploaded last).
+struct alignas(16) WorkHeader {
+  uint32_t n_items;
+  uint32_t total_chunks;
+  uint32_t total_groups;
+  uint32_t pad;
+};
+
+hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev, uint32_t item,
+                        uint32_t n_tiles, int block, Stats* partials, hipStream_t s);
+hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
+                             const WorkHeader* hdr_dev, unsigned int* counter, Stats* partials,
+                             int block, int grid, hipStream_t s);
+hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev,
+                         const Stats* partials, Stats* groups, Stats* resident, int grid_groups,
+                         int grid_items, hipStream_t s);
+hipError_t launch_fill_u32(unsigned int* p, uint64_t n, unsigned int v, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_words(uint32_t key0, uint32_t key1, uint32_t strm, uint32_t tag,
+                        uint64_t sample_begin, uint64_t n_samples, uint32_t n_steps,
+                        uint32_t* out, hipStream_t s);
+hipError_t launch_normals(bool fp64, uint32_t key0, uint32_t key1, uint32_t strm, uint32_t tag,
+                          uint64_t sample_begin, uint64_t n_samples, uint32_t n_steps, void* out,
+                          hipStream_t s);
+
+}  // namespace mlmc

@@ -1,0 +1,432 @@
+// Continuous-batching server of MLMC requests and the launch-shape autotuner.
+//
+// Serving: every tick runs one top-up iteration (or warm-up) of every
+// admitted request in ONE persistent launch replayed from the server's
+// captured hipGraph.  Requests arriving while others are in flight are queued
+// and admitted at the next tick whose device-memory budget (per-request
+// resident statistics plus the tick's tile partials) has room.  A request's
+// sequence of sample ranges depends only on its own statistics and the
+// per-tick cap, so its result is bitwise the same alone or in any mix.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "host.hpp"
+#include "stats.hpp"
+
+using namespace mlmc;
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct ServerReq {
+  uint64_t ticket = 0;
+  McRequest mc;
+  int region = -1;            // resident slot region (admitted) or -1
+  bool cancelled = false;
+  double t_submit = 0.0;
+  double t_done = 0.0;
+};
+
+// Device bytes a request can need in one tick: its resident statistics and
+// the tile partials and group results of at most max_per_tick samples on
+// every level.
+uint64_t tick_bytes(const McRequest& mc) {
+  const uint64_t levels = (uint64_t)(mc.prob.L + 1);
+  const uint64_t per_level = std::max<uint64_t>(mc.n_warmup, mc.max_per_tick);
+  const uint64_t tiles = (per_level + kTile - 1) / kTile;
+  const uint64_t groups = (tiles + kGroupTiles - 1) / kGroupTiles;
+  return levels * (tiles + groups) * sizeof(Stats) + levels * sizeof(LevelDesc);
+}
+
+uint64_t state_bytes() { return (uint64_t)MLMC_AP_MAX_LEVELS * sizeof(Stats); }
+
+}  // namespace
+
+struct mlmc_ap_server {
+  mlmc_ap_server_config cfg{};
+  Workspace ws;
+  hipStream_t stream = nullptr;
+  std::mutex mu;
+  uint64_t next_ticket = 1;
+  std::deque<ServerReq*> queue;
+  std::vector<ServerReq*> active;
+  std::map<uint64_t, std::unique_ptr<ServerReq>> reqs;
+  std::vector<int> free_regions;
+  mlmc_ap_server_stats stats{};
+  mlmc_ap_tuning tuning{};
+
+  mlmc_ap_status tick(int32_t* n_completed, std::vector<uint64_t>* completed);
+};
+
+mlmc_ap_status mlmc_ap_server::tick(int32_t* n_completed, std::vector<uint64_t>* completed) {
+  const double t0 = now_s();
+  int done_count = 0;
+  // drop cancelled active requests
+  for (size_t i = 0; i < active.size();) {
+    if (active[i]->cancelled) {
+      free_regions.push_back(active[i]->region);
+      stats.bytes_reserved -= state_bytes();
+      active[i]->region = -1;
+      active.erase(active.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+  // plan: active requests first (admission order), then queued ones (FIFO)
+  const uint64_t budget = cfg.hbm_budget_bytes;
+  uint64_t used = stats.bytes_reserved;
+  std::vector<ItemSpec> items;
+  std::vector<ServerReq*> in_tick;
+  for (ServerReq* r : active) {
+    std::vector<ItemSpec> mine;
+    if (!r->mc.plan(mine, (uint32_t)(r->region * MLMC_AP_MAX_LEVELS), nullptr, 0)) continue;
+    const uint64_t b = tick_bytes(r->mc);
+    if (used + b > budget) continue;  // deferred to a later tick
+    used += b;
+    items.insert(items.end(), mine.begin(), mine.end());
+    in_tick.push_back(r);
+  }
+  while (!queue.empty() && (int)active.size() < cfg.max_active) {
+    ServerReq* r = queue.front();
+    if (r->cancelled) {
+      queue.pop_front();
+      continue;
+    }
+    const uint64_t b = tick_bytes(r->mc) + state_bytes();
+    if (used + b > budget) break;  // FIFO: wait for memory
+    queue.pop_front();
+    r->region = free_regions.back();
+    free_regions.pop_back();
+    stats.bytes_reserved += state_bytes();
+    stats.admitted++;
+    used += b;
+    // fresh statistics for the new request's slots
+    std::vector<Stats> empty(MLMC_AP_MAX_LEVELS, stats_empty());
+    MLMC_HIP(hipMemcpyAsync(ws.resident + (size_t)r->region * MLMC_AP_MAX_LEVELS, empty.data(),
+                            empty.size() * sizeof(Stats), hipMemcpyHostToDevice, stream));
+    MLMC_HIP(hipStreamSynchronize(stream));
+    active.push_back(r);
+    std::vector<ItemSpec> mine;
+    if (r->mc.plan(mine, (uint32_t)(r->region * MLMC_AP_MAX_LEVELS), nullptr, 0)) {
+      items.insert(items.end(), mine.begin(), mine.end());
+      in_tick.push_back(r);
+    }
+  }
+  stats.bytes_peak = std::max(stats.bytes_peak, used);
+  if (!items.empty()) {
+    LaunchTiming t;
+    MLMC_TRY(run_table(ws, items, (size_t)cfg.max_active * MLMC_AP_MAX_LEVELS, 1, tuning, stream,
+                       &t));
+    stats.ticks++;
+    const double tnow = now_s();
+    for (ServerReq* r : in_tick) {
+      const uint64_t before = r->mc.particle_steps;
+      r->mc.launches++;
+      r->mc.gpu_seconds += t.total_s;
+      r->mc.absorb(ws.resident_host + (size_t)r->region * MLMC_AP_MAX_LEVELS);
+      stats.particle_steps += r->mc.particle_steps - before;
+      if (r->mc.phase == 2) {
+        r->t_done = tnow;
+        free_regions.push_back(r->region);
+        stats.bytes_reserved -= state_bytes();
+        active.erase(std::find(active.begin(), active.end(), r));
+        stats.completed++;
+        done_count++;
+        if (completed) completed->push_back(r->ticket);
+      }
+    }
+  }
+  stats.active = (int32_t)active.size();
+  stats.queued = (int32_t)queue.size();
+  stats.busy_seconds += now_s() - t0;
+  if (n_completed) *n_completed = done_count;
+  return MLMC_AP_OK;
+}
+
+extern "C" {
+
+mlmc_ap_status mlmc_ap_server_create(const mlmc_ap_server_config* cfg, mlmc_ap_server** out) {
+  if (!out) return set_error(MLMC_AP_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::unique_ptr<mlmc_ap_server> s(new mlmc_ap_server());
+  if (cfg) s->cfg = *cfg;
+  if (s->cfg.hbm_budget_bytes == 0) s->cfg.hbm_budget_bytes = 1ull << 30;
+  if (s->cfg.max_samples_per_tick == 0) s->cfg.max_samples_per_tick = 1ull << 24;
+  if (s->cfg.max_active <= 0) s->cfg.max_active = 256;
+  if (s->cfg.max_active > 4096) return set_error(MLMC_AP_EINVAL, "max_active must be <= 4096");
+  if (s->cfg.options.max_iter <= 0) s->cfg.options.max_iter = 10;
+  if (s->cfg.options.n_warmup == 0) s->cfg.options.n_warmup = 1000;
+  MLMC_TRY(init_workspace(s->ws));
+  Workspace* global = workspace();
+  if (global) s->ws.tuning = global->tuning;  // inherit an autotuned shape
+  s->tuning = resolve_tuning(s->ws, &s->cfg.options.tuning);
+  MLMC_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+  const size_t slots = (size_t)s->cfg.max_active * MLMC_AP_MAX_LEVELS;
+  MLMC_TRY(s->ws.ensure(1, 1, 1, slots, 0));
+  for (int i = s->cfg.max_active - 1; i >= 0; --i) s->free_regions.push_back(i);
+  *out = s.release();
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_server_destroy(mlmc_ap_server* srv) {
+  if (!srv) return set_error(MLMC_AP_EINVAL, "server is NULL");
+  if (srv->stream) {
+    (void)hipStreamSynchronize(srv->stream);
+    (void)hipStreamDestroy(srv->stream);
+  }
+  delete srv;
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_server_submit(mlmc_ap_server* srv, const mlmc_ap_problem* p,
+                                     double rmse_tol, uint64_t* ticket_out) {
+  if (!srv || !ticket_out) return set_error(MLMC_AP_EINVAL, "NULL argument");
+  MLMC_TRY(validate_problem(p));
+  if (!(rmse_tol > 0.0) || !std::isfinite(rmse_tol))
+    return set_error(MLMC_AP_EINVAL, "rmse_tol must be > 0");
+  if (p->fp64_state != 0 || p->qoi != MLMC_AP_QOI_X2)
+    return set_error(MLMC_AP_EINVAL, "the server runs FP32-state requests with QOI_X2");
+  std::unique_ptr<ServerReq> r(new ServerReq());
+  r->mc.init(*p, rmse_tol, false, srv->cfg.options.n_warmup, srv->cfg.options.max_iter,
+             srv->cfg.max_samples_per_tick);
+  if (tick_bytes(r->mc) + state_bytes() > srv->cfg.hbm_budget_bytes) {
+    srv->stats.rejected++;
+    return set_error(MLMC_AP_EBUSY, "request can never fit the server's memory budget");
+  }
+  std::lock_guard<std::mutex> lk(srv->mu);
+  r->ticket = srv->next_ticket++;
+  r->t_submit = now_s();
+  *ticket_out = r->ticket;
+  srv->queue.push_back(r.get());
+  srv->reqs[r->ticket] = std::move(r);
+  srv->stats.submitted++;
+  srv->stats.queued = (int32_t)srv->queue.size();
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_server_step(mlmc_ap_server* srv, int32_t* n_completed_out) {
+  if (!srv) return set_error(MLMC_AP_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  return srv->tick(n_completed_out, nullptr);
+}
+
+mlmc_ap_status mlmc_ap_server_poll(mlmc_ap_server* srv, uint64_t ticket, mlmc_ap_result* out) {
+  if (!srv || !out) return set_error(MLMC_AP_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(ticket);
+  if (it == srv->reqs.end()) return set_error(MLMC_AP_ENOTFOUND, "unknown ticket");
+  ServerReq* r = it->second.get();
+  if (r->cancelled) {
+    if (r->region < 0) srv->reqs.erase(it);
+    return MLMC_AP_ECANCELLED;
+  }
+  if (r->mc.phase != 2) return MLMC_AP_EAGAIN;
+  r->mc.fill_result(out);
+  out->seconds = r->t_done - r->t_submit;
+  srv->reqs.erase(it);
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_server_cancel(mlmc_ap_server* srv, uint64_t ticket) {
+  if (!srv) return set_error(MLMC_AP_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(ticket);
+  if (it == srv->reqs.end()) return set_error(MLMC_AP_ENOTFOUND, "unknown ticket");
+  ServerReq* r = it->second.get();
+  if (r->mc.phase == 2) return MLMC_AP_OK;  // already finished
+  if (!r->cancelled) srv->stats.cancelled++;
+  r->cancelled = true;
+  auto q = std::find(srv->queue.begin(), srv->queue.end(), r);
+  if (q != srv->queue.end()) srv->queue.erase(q);  // never admitted
+  srv->stats.queued = (int32_t)srv->queue.size();
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_server_get_stats(const mlmc_ap_server* srv, mlmc_ap_server_stats* out) {
+  if (!srv || !out) return set_error(MLMC_AP_EINVAL, "NULL argument");
+  *out = srv->stats;
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_server_run_trace(mlmc_ap_server* srv, int32_t n, const double* arrival_s,
+                                        const mlmc_ap_problem* p, const double* rmse_tol,
+                                        mlmc_ap_result* results_out, double* latency_s_out) {
+  if (!srv || n < 0 || (n > 0 && (!arrival_s || !p || !rmse_tol || !latency_s_out)))
+    return set_error(MLMC_AP_EINVAL, "bad arguments");
+  for (int i = 1; i < n; ++i)
+    if (arrival_s[i] < arrival_s[i - 1])
+      return set_error(MLMC_AP_EINVAL, "arrival times must be non-decreasing");
+  std::vector<uint64_t> tickets(n, 0);
+  std::map<uint64_t, int> index;
+  std::vector<double> t_arrive(n, 0.0);
+  const double t0 = now_s();
+  int next = 0, finished = 0;
+  std::vector<uint64_t> completed;
+  while (finished < n) {
+    const double t = now_s() - t0;
+    while (next < n && arrival_s[next] <= t) {
+      uint64_t tk = 0;
+      mlmc_ap_status st = mlmc_ap_server_submit(srv, &p[next], rmse_tol[next], &tk);
+      if (st != MLMC_AP_OK) return st;
+      tickets[next] = tk;
+      index[tk] = next;
+      t_arrive[next] = t0 + arrival_s[next];
+      ++next;
+    }
+    bool idle;
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      idle = srv->active.empty() && srv->queue.empty();
+    }
+    if (idle) {
+      if (next < n) {
+        const double wait = arrival_s[next] - (now_s() - t0);
+        if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.01)));
+      }
+      continue;
+    }
+    completed.clear();
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      MLMC_TRY(srv->tick(nullptr, &completed));
+    }
+    for (uint64_t tk : completed) {
+      const int i = index[tk];
+      ServerReq* r = srv->reqs[tk].get();
+      latency_s_out[i] = r->t_done - t_arrive[i];
+      if (results_out) {
+        r->mc.fill_result(&results_out[i]);
+        results_out[i].seconds = latency_s_out[i];
+      }
+      std::lock_guard<std::mutex> lk(srv->mu);
+      srv->reqs.erase(tk);
+      ++finished;
+    }
+  }
+  return MLMC_AP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner.
+// ---------------------------------------------------------------------------
+static bool read_cache(const char* path, const std::string& dev, mlmc_ap_tuning* t) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  auto field = [&](const char* key, std::string* sval, int* ival) -> bool {
+    const std::string k = std::string("\"") + key + "\"";
+    size_t p = s.find(k);
+    if (p == std::string::npos) return false;
+    p = s.find(':', p);
+    if (p == std::string::npos) return false;
+    ++p;
+    while (p < s.size() && (s[p] == ' ' || s[p] == '\t')) ++p;
+    if (sval) {
+      if (p >= s.size() || s[p] != '"') return false;
+      const size_t e = s.find('"', p + 1);
+      if (e == std::string::npos) return false;
+      *sval = s.substr(p + 1, e - p - 1);
+      return true;
+    }
+    *ival = std::atoi(s.c_str() + p);
+    return true;
+  };
+  std::string d;
+  int b = 0, pp = 0, w = 0;
+  if (!field("device", &d, nullptr) || d != dev) return false;
+  if (!field("block", nullptr, &b) || !field("ppt", nullptr, &pp) ||
+      !field("waves_per_simd", nullptr, &w))
+    return false;
+  t->block = b;
+  t->ppt = pp;
+  t->waves_per_simd = w;
+  t->reserved = 0;
+  return (b == 64 || b == 128 || b == 256) && (pp == 1 || pp == 2 || pp == 4) && w >= 1 && w <= 8;
+}
+
+static void write_cache(const char* path, const std::string& dev, const mlmc_ap_tuning& t,
+                        double seconds) {
+  std::ofstream f(path);
+  if (!f) return;
+  f << "{\"device\": \"" << dev << "\", \"block\": " << t.block << ", \"ppt\": " << t.ppt
+    << ", \"waves_per_simd\": " << t.waves_per_simd << ", \"kernel_seconds\": " << seconds
+    << "}\n";
+}
+
+mlmc_ap_status mlmc_ap_autotune(const mlmc_ap_problem* p, const char* cache_path,
+                                mlmc_ap_tuning* out, void* stream) {
+  MLMC_TRY(validate_problem(p));
+  if (!out) return set_error(MLMC_AP_EINVAL, "out is NULL");
+  Workspace* ws = workspace();
+  if (!ws) return MLMC_AP_EDEVICE;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  if (cache_path && read_cache(cache_path, ws->name, out)) {
+    ws->tuning = *out;
+    ws->tuned = true;
+    return MLMC_AP_OK;
+  }
+  // Work table shaped like an MLMC iteration of p: every level with the same
+  // particle-step budget (2^27 steps per level).
+  std::vector<ItemSpec> items;
+  for (int l = 0; l <= p->L; ++l) {
+    ItemSpec s;
+    s.prob = p;
+    s.level = l;
+    s.single = false;
+    s.sample_begin = 0;
+    s.n_samples = std::max<uint64_t>(4096, (1ull << 27) / sample_cost(*p, l, false));
+    s.result_slot = (uint32_t)l;
+    s.hist = nullptr;
+    s.traj = nullptr;
+    s.coll = nullptr;
+    items.push_back(s);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int blocks[] = {64, 128, 256};
+  const int ppts[] = {1, 2, 4};
+  const int waves[] = {1, 2, 4, 8};
+  double best = 1e30;
+  mlmc_ap_tuning bt = ws->tuning;
+  for (int b : blocks)
+    for (int pp : ppts)
+      for (int w : waves) {
+        mlmc_ap_tuning t{b, pp, w, 0};
+        LaunchTiming tm;
+        MLMC_TRY(run_table(*ws, items, MLMC_AP_MAX_LEVELS, 2, t, s, &tm));  // warm
+        double acc = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {
+          MLMC_TRY(run_table(*ws, items, MLMC_AP_MAX_LEVELS, 2, t, s, &tm));
+          acc += tm.kernel_s;
+        }
+        if (acc < best) {
+          best = acc;
+          bt = t;
+        }
+      }
+  ws->tuning = bt;
+  ws->tuned = true;
+  *out = bt;
+  if (cache_path) write_cache(cache_path, ws->name, bt, best / 2);
+  return MLMC_AP_OK;
+}
+
+}  // extern "C"

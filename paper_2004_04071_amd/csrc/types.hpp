@@ -1,0 +1,87 @@
+// Host/device shared layouts of the MLMC-AP library (gfx950).
+//
+// A work item is one (request, level, sample range).  Its samples are split
+// into tiles of kTile = 256 consecutive global sample indices; every tile is
+// reduced by one wavefront (64 lanes x 4 samples) into a TilePartial, and the
+// partials of an item are merged by a fixed tree (groups of 4096 tiles, then
+// one group result per item).  The tree depends only on the item's sample
+// count, so the statistics are bitwise independent of launch shape, tuning,
+// and of other items sharing a launch.
+#pragma once
+#include <stdint.h>
+
+namespace mlmc {
+
+constexpr int kLanes = 64;                       // gfx950 wavefront
+constexpr int kTile = 256;                       // samples per statistics tile
+constexpr int kSamplesPerLane = kTile / kLanes;  // 4
+constexpr int kGroupTiles = 4096;                // tiles per first-stage group
+constexpr int kReduceThreads = 256;
+constexpr int kReducePerThread = kGroupTiles / kReduceThreads;  // 16
+constexpr uint64_t kMaxTilesPerItem = (uint64_t)kGroupTiles * kGroupTiles;  // 2^24
+
+// Work item flags.
+enum : uint32_t {
+  kFlagCoarse = 1u << 0,      // level >= 1 pair: coarse path present
+  kFlagMaxwell = 1u << 1,     // Maxwellian equilibrium (else two-point +-1)
+  kFlagAggregate = 1u << 2,   // aggregated coarse kick (else normalised kick sum)
+  kFlagHist = 1u << 3,        // histogram QoI
+  kFlagWide = 1u << 4,        // a decision threshold is 0: 64-bit compares
+  kFlagAccumulate = 1u << 6,  // merge into the resident statistics (else overwrite)
+};
+
+// Trajectory kinds (the compile-time specialisations of the particle loop).
+enum : int {
+  kKindFineTwoPoint = 0,
+  kKindFineMaxwell = 1,
+  kKindPairTwoPointSum = 2,
+  kKindPairMaxwellSum = 3,
+  kKindPairMaxwellAggregate = 4,
+};
+
+struct alignas(16) LevelDesc {
+  double h_f, s_f, h_c, s_c;    // scheme coefficients, fine and coarse
+  double agg_ms2;               // M s_f^2 (aggregated kick normalisation)
+  double h_f2;                  // h_f^2
+  double rsqrt_m;               // 1/sqrt(M)
+  double x0_a, x0_b;            // initial law parameters
+  double hist_lo, hist_inv_w;   // histogram origin and 1/bin width
+  uint64_t sample_begin;        // first global sample index of the item
+  uint64_t n_samples;
+  uint64_t tile_base;           // first tile slot in the partial buffer
+  uint64_t group_base;          // first group slot in the group buffer
+  uint64_t chunk_base;          // persistent kernel: first global chunk index
+  unsigned long long* hist;     // item histogram counters (3 nbins + 4), or null
+  void* traj;                   // trajectory dump (2 n_samples reals), or null
+  uint32_t* coll;               // collision dump (2 n_samples), or null
+  uint64_t thr_f, thr_c2;       // decision thresholds in [0, 2^32]
+  uint32_t thr_f_m1, thr_c2_m1; // threshold - 1 (used when both are >= 1)
+  uint32_t n_steps;             // fine steps
+  uint32_t M;                   // refinement factor
+  uint32_t tag, stream;         // counter words 2 and 3
+  uint32_t key0, key1;          // Philox key (seed)
+  uint32_t flags;
+  int32_t kind;                 // kKind*
+  uint32_t x0_kind;
+  uint32_t nbins;
+  uint32_t n_tiles;
+  uint32_t n_groups;
+  uint32_t chunk_tiles;         // persistent kernel: tiles per chunk
+  uint32_t n_chunks;
+  uint32_t result_slot;         // resident statistics slot
+  uint32_t pad0, pad1, pad2;
+};
+
+// Mergeable statistics of a set of samples (FP64 means and centred sums).
+struct alignas(16) Stats {
+  double n;
+  double mean_dq, m2_dq;
+  double mean_qf, m2_qf;
+  double mean_qc, m2_qc;
+  double c_fc;
+  unsigned long long coll_f, coll_c;
+};
+
+static_assert(sizeof(Stats) == 80, "Stats layout");
+
+}  // namespace mlmc

@@ -1,0 +1,165 @@
+"""C ABI of libmlmc_ap.so on the CPU: every declared symbol is exported, and
+the host-only entry points (validation, level constants, optimal sample
+numbers, statistics merge) agree with the oracle and the definitions."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2004_04071_amd as pkg
+from oracle import mlmc as OM
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pkg.LIB_PATH):
+        from paper_2004_04071_amd import build
+        build.build()
+    return pkg.lib()
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "mlmc_ap.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlmc_ap_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_symbols()
+    assert len(names) >= 24
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pkg._SIGNATURES), "binding and header list different entry points"
+
+
+def test_version_and_status_strings(lib):
+    assert "gfx950" in pkg.mlmc_ap_version()
+    for s in range(-7, 1):
+        assert pkg.mlmc_ap_status_str(s)
+
+
+def _random_problem(rng):
+    eq = int(rng.integers(0, 2))
+    n0 = int(rng.integers(1, 5))
+    dt0 = float(10.0 ** rng.uniform(-2, 0))
+    return pkg.problem(eps=float(rng.choice([0.0, 10.0 ** rng.uniform(-5, 1)])), T=n0 * dt0,
+                       dt0=dt0, M=int(rng.integers(2, 9)), L=int(rng.integers(1, 8)),
+                       eq_kind=eq, coupling=int(rng.integers(0, 2)) if eq == 1 else 0)
+
+
+def test_level_constants_match_oracle_bit_exactly(lib):
+    """Collision decisions are integer compares against these thresholds, so
+    the library and the oracle must compute the same integers."""
+    rng = np.random.default_rng(1)
+    for _ in range(400):
+        p = _random_problem(rng)
+        for level in range(0, p.L + 1):
+            got = pkg.mlmc_ap_level_constants(p, level)
+            ref = O.level_consts(p.eps, p.T, p.dt0, p.M, level)
+            assert got["n_steps"] == ref["n_steps"]
+            assert got["thr_f"] == ref["thr"]
+            assert got["dt"] == ref["dt"] and got["h"] == ref["h"] and got["s"] == ref["s"]
+            if level >= 1:
+                refc = O.level_consts(p.eps, p.T, p.dt0, p.M, level - 1)
+                assert got["thr_c"] == refc["thr"]
+                assert got["thr_c2"] == O.coarse_threshold(ref["thr"], refc["thr"], p.M)
+                assert got["thr_c2"] <= got["thr_f"]
+
+
+def test_optimal_samples_match_oracle(lib):
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        J = int(rng.integers(1, 12))
+        V = list(10.0 ** rng.uniform(-9, 2, J))
+        C = [float(c) for c in rng.integers(1, 5000, J)]
+        tol = float(10.0 ** rng.uniform(-4, -1))
+        assert pkg.mlmc_ap_optimal_samples(V, C, tol) == OM.optimal_samples(V, C, tol)
+
+
+def _stats(x_f, x_c):
+    qf, qc = x_f ** 2, x_c ** 2
+    dq = qf - qc
+    n = dq.size
+    return dict(n=n, mean_dq=dq.mean(), m2_dq=((dq - dq.mean()) ** 2).sum(), mean_qf=qf.mean(),
+                m2_qf=((qf - qf.mean()) ** 2).sum(), mean_qc=qc.mean(),
+                m2_qc=((qc - qc.mean()) ** 2).sum(),
+                c_fc=((qf - qf.mean()) * (qc - qc.mean())).sum(), coll_f=n, coll_c=2 * n)
+
+
+def test_merge_stats_equals_two_pass(lib):
+    rng = np.random.default_rng(3)
+    xf = rng.normal(1.0, 2.0, 5000)
+    xc = xf + rng.normal(0, 0.1, 5000)
+    for cut in (1, 17, 2500, 4999):
+        a = _stats(xf[:cut], xc[:cut])
+        b = _stats(xf[cut:], xc[cut:])
+        m = pkg.mlmc_ap_merge_stats(a, b)
+        full = _stats(xf, xc)
+        assert m["n"] == full["n"]
+        for k in ("mean_dq", "mean_qf", "mean_qc"):
+            assert m[k] == pytest.approx(full[k], rel=1e-13, abs=1e-13)
+        for k in ("m2_dq", "m2_qf", "m2_qc", "c_fc"):
+            assert m[k] == pytest.approx(full[k], rel=1e-11)
+        assert m["coll_f"] == a["coll_f"] + b["coll_f"]
+    empty = {k: 0 for k in a}
+    assert pkg.mlmc_ap_merge_stats(empty, a) == pytest.approx(a)
+    assert pkg.mlmc_ap_merge_stats(a, empty) == pytest.approx(a)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("eps", -1.0), ("eps", float("nan")), ("T", 0.0), ("dt0", -0.5), ("M", 1), ("M", 65),
+    ("L", -1), ("L", 31), ("dt0", 0.3), ("x0_kind", 3), ("eq_kind", 2), ("x0_b", -1.0),
+    ("coupling", 2), ("qoi", 2), ("fp64_state", 2), ("reserved", 1)])
+def test_validation_rejects(lib, field, value):
+    p = pkg.problem(eps=0.1, T=1.0, dt0=0.5, L=3)
+    setattr(p, field, value)
+    assert pkg.mlmc_ap_validate(p) == -1
+    assert pkg.mlmc_ap_last_error()
+
+
+def test_validation_special_cases(lib):
+    # aggregated coupling needs the Maxwellian equilibrium
+    p = pkg.problem(eps=0.1, T=1.0, dt0=0.5, L=3, eq_kind=pkg.EQ_TWO_POINT,
+                    coupling=pkg.COUPLING_AGGREGATE)
+    assert pkg.mlmc_ap_validate(p) == -1
+    # n_L must stay below 2^31
+    assert pkg.mlmc_ap_validate(pkg.problem(eps=0.1, T=1.0, dt0=0.5, M=2, L=30)) == -1
+    assert pkg.mlmc_ap_validate(pkg.problem(eps=0.1, T=1.0, dt0=0.5, M=2, L=29)) == 0
+    # histogram range
+    p = pkg.problem(eps=0.1, T=1.0, dt0=0.5, qoi=pkg.QOI_X2_HIST, nbins=0)
+    assert pkg.mlmc_ap_validate(p) == -1
+    p = pkg.problem(eps=0.1, T=1.0, dt0=0.5, qoi=pkg.QOI_X2_HIST, hist_lo=1.0, hist_hi=1.0)
+    assert pkg.mlmc_ap_validate(p) == -1
+    assert pkg.mlmc_ap_validate(pkg.problem(eps=0.0, T=1.0, dt0=0.5)) == 0
+
+
+def test_entry_points_report_errors_without_a_device(lib):
+    """On a machine without a GPU every device entry point fails with a
+    status (no crash, no CPU fallback)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    p = pkg.problem(eps=0.1, T=1.0, dt0=0.5, L=2)
+    with pytest.raises(pkg.MlmcApError) as e:
+        pkg.mlmc_ap_simulate_level(p, 0, 0, 10)
+    assert e.value.name == "EDEVICE"
+    with pytest.raises(pkg.MlmcApError):
+        pkg.mlmc_ap_estimate(p, 1e-2)
+
+
+def test_optimal_samples_rejects_bad_input(lib):
+    with pytest.raises(pkg.MlmcApError):
+        pkg.mlmc_ap_optimal_samples([1.0], [0.0], 1e-2)
+    with pytest.raises(pkg.MlmcApError):
+        pkg.mlmc_ap_optimal_samples([1.0], [1.0], 0.0)
+    assert pkg.mlmc_ap_optimal_samples([0.0, 1.0], [1.0, 1.0], 1.0) == [0, 2]
+    assert math.ceil(2.0 / 1e-4 * 18) == pkg.mlmc_ap_optimal_samples([18.0], [2.0], 1e-2)[0]

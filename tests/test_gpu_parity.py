@@ -1,0 +1,292 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars ("Parity bars"):
+  * Philox words, uniforms, collision decisions and counts: bit-exact;
+  * FP32 positions: |x_gpu - x_oracle| <= 1e-5 max(|x_oracle|, rms(x_oracle));
+    FP64 positions: 1e-12 relative to the same scale;
+  * statistics: the device reduction against two-pass FP64 statistics of the
+    oracle's trajectories;
+  * estimates: equal to the oracle's estimate on the same samples within the
+    FP32 rounding bound, and within 4 standard errors of the exact E[Q_L].
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import closed_form as CF
+from oracle import mlmc as OM
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2004_04071_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    pkg.mlmc_ap_init()
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def two_pass(xf, xc, level, single=False):
+    return OM.stats_of(xf, xc, 0 if single else level)
+
+
+def run_level(prob, level, n, begin=0, single=False):
+    """GPU dump and statistics of one level, with the oracle's values."""
+    P = pkg.as_problem(prob)
+    dt = torch.float64 if P.fp64_state else torch.float32
+    traj = torch.full((2 * n,), float("nan"), dtype=dt, device="cuda")
+    coll = torch.full((2 * n,), -1, dtype=torch.int32, device="cuda")
+    st = pkg.mlmc_ap_simulate_level(P, level, begin, n, single=single, traj=traj, coll=coll)
+    torch.cuda.synchronize()
+    ref = O.simulate(prob, level, begin, n, single=single)
+    x = traj.cpu().double().numpy()
+    c = coll.cpu().numpy().astype(np.int64)
+    return st, x[:n], x[n:], c[:n], c[n:], ref
+
+
+def check_trajectories(prob, level, n, begin=0, single=False, rel=None):
+    st, xf, xc, cf, cc, ref = run_level(prob, level, n, begin, single)
+    fp64 = bool(prob.get("fp64_state", 0))
+    if rel is None:
+        rel = 1e-12 if fp64 else 1e-5
+    coarse = level >= 1 and not single
+    assert np.array_equal(cf, ref["cf"].astype(np.int64)), "fine collision counts differ"
+    assert np.array_equal(cc, ref["cc"].astype(np.int64)), "coarse collision counts differ"
+    scale_f = np.maximum(np.abs(ref["xf"]), math.sqrt(np.mean(ref["xf"] ** 2)))
+    err_f = np.max(np.abs(xf - ref["xf"]) / scale_f)
+    err_c = 0.0
+    if coarse:
+        scale_c = np.maximum(np.abs(ref["xc"]), math.sqrt(np.mean(ref["xc"] ** 2)))
+        err_c = np.max(np.abs(xc - ref["xc"]) / scale_c)
+    else:
+        assert np.all(xc == 0.0)
+    say("level %d n %d: max scaled error fine %.3e coarse %.3e" % (level, n, err_f, err_c))
+    assert err_f <= rel and err_c <= rel
+    # device statistics against two-pass statistics of the device's own dump
+    dev = two_pass(xf, xc, level, single)
+    assert st["n"] == n
+    assert st["coll_f"] == int(cf.sum()) and st["coll_c"] == int(cc.sum())
+    sd = math.sqrt(dev["m2_dq"] / max(n - 1, 1)) + 1e-300
+    assert abs(st["mean_dq"] - dev["mean_dq"]) <= 1e-12 * (abs(dev["mean_dq"]) + sd)
+    assert st["m2_dq"] == pytest.approx(dev["m2_dq"], rel=1e-9, abs=1e-18)
+    if coarse:
+        for k in ("mean_qf", "mean_qc"):
+            assert st[k] == pytest.approx(dev[k], rel=1e-12, abs=1e-14)
+        for k in ("m2_qf", "m2_qc", "c_fc"):
+            assert st[k] == pytest.approx(dev[k], rel=1e-9, abs=1e-12)
+    return st, ref
+
+
+# ---------------------------------------------------------------------------
+# Random number path
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,stream_id,tag,begin", [
+    (42, 0, 0, 0), (42, 7, 8, 1000), (2 ** 63 + 5, 1234, 72, 2 ** 32 - 300),
+    (0xDEADBEEFCAFEF00D, 2 ** 32 - 1, 30, 12345)])
+def test_philox_words_bit_exact(seed, stream_id, tag, begin):
+    ns, nt = 300, 7
+    out = torch.zeros(ns * nt * 4, dtype=torch.int32, device="cuda")
+    pkg.mlmc_ap_philox_words(seed, stream_id, tag, begin, ns, nt, out)
+    got = out.cpu().numpy().view(np.uint32).reshape(ns, nt, 4)
+    ref = O.words(seed, stream_id, tag, begin, ns, nt)
+    assert np.array_equal(got, ref)
+
+
+def test_uniforms_and_normals():
+    ns, nt = 2000, 16
+    out32 = torch.zeros(ns * nt * 4, dtype=torch.float32, device="cuda")
+    out64 = torch.zeros(ns * nt * 4, dtype=torch.float64, device="cuda")
+    pkg.mlmc_ap_rng_normals(42, 3, 5, 0, ns, nt, 0, out32)
+    pkg.mlmc_ap_rng_normals(42, 3, 5, 0, ns, nt, 1, out64)
+    g32 = out32.cpu().double().numpy().reshape(-1, 4)
+    g64 = out64.cpu().numpy().reshape(-1, 4)
+    w = O.words(42, 3, 5, 0, ns, nt).reshape(-1, 4)
+    u1 = (2.0 * (w[:, 1] >> 9).astype(np.float64) + 1.0) * 2.0 ** -24
+    u2 = (2.0 * (w[:, 2] >> 9).astype(np.float64) + 1.0) * 2.0 ** -24
+    for u, col in ((u1, 0), (u2, 1)):
+        assert np.array_equal(g32[:, col], u) and np.array_equal(g64[:, col], u)
+    r = np.sqrt(-2.0 * np.log(u1))
+    xi = r * np.cos(2 * np.pi * u2)
+    g = r * np.sin(2 * np.pi * u2)
+    e32 = max(np.max(np.abs(g32[:, 2] - xi)), np.max(np.abs(g32[:, 3] - g)))
+    e64 = max(np.max(np.abs(g64[:, 2] - xi)), np.max(np.abs(g64[:, 3] - g)))
+    say("normals: max abs error FP32 %.3e, FP64 %.3e" % (e32, e64))
+    assert e64 <= 1e-13
+    assert e32 <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Trajectories, collision counts and tile statistics
+# ---------------------------------------------------------------------------
+CASES = {
+    "cfg1_fp64": (W.cfg1(), 0, 1000, 0, False),
+    "cfg1_fp32": (dict(W.cfg1(), fp64_state=0), 0, 1000, 0, False),
+    "cfg2_l0": (W.cfg2(), 0, 777, 0, False),
+    "cfg2_l1": (W.cfg2(), 1, 1000, 0, False),
+    "cfg2_l4": (W.cfg2(), 4, 600, 0, False),
+    "cfg2_l8": (W.cfg2(), 8, 300, 0, False),
+    "cfg2_l3_kick_sum": (W.cfg2(coupling=0), 3, 513, 0, False),
+    "cfg2_l5_offset": (W.cfg2(), 5, 400, 123456789, False),
+    "cfg2_single_l3": (W.cfg2(), 3, 500, 0, True),
+    "eps0_l4": (W.cfg2(eps=0.0), 4, 500, 0, False),
+    "eps1e-4_l6": (W.cfg2(eps=1e-4), 6, 300, 0, False),
+    "eps1_l6": (W.cfg2(eps=1.0), 6, 300, 0, False),
+    "free_streaming_wide": (W.cfg2(eps=1e6), 3, 300, 0, False),
+    "twopoint_M4_l2": (dict(W.cfg1(), fp64_state=0, M=4, L=3, T=0.5, dt0=0.05), 2, 700, 0, False),
+    "maxwell_M4_agg_l2": (dict(W.cfg2(eps=0.05), M=4, L=3), 2, 700, 0, False),
+    "cfg4_cos_l2_fp32": (dict(W.cfg4(0), qoi=0), 2, 900, 0, False),
+    "cfg4_cos_l2_fp64": (dict(W.cfg4(1), qoi=0), 2, 900, 0, False),
+    "cfg2_fp64_l3": (dict(W.cfg2(), fp64_state=1), 3, 500, 0, False),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES), ids=list(CASES))
+def test_trajectory_parity(case):
+    prob, level, n, begin, single = CASES[case]
+    say("case", case)
+    check_trajectories(prob, level, n, begin, single)
+
+
+def test_wide_thresholds_used():
+    c = pkg.mlmc_ap_level_constants(pkg.as_problem(W.cfg2(eps=1e6)), 3)
+    assert c["thr_f"] == 0
+
+
+@pytest.mark.parametrize("n", [1, 255, 256, 257, 4097 * 256 + 3])
+def test_tile_and_group_boundaries(n):
+    """Ragged tiles and more than one 4096-tile reduction group."""
+    prob = W.cfg2(eps=0.3)
+    st = pkg.mlmc_ap_simulate_level(prob, 0, 5, n)
+    ref = O.simulate(prob, 0, 5, n)
+    r = two_pass(ref["xf"], ref["xc"], 0)
+    assert st["n"] == n and st["coll_f"] == int(ref["cf"].astype(np.int64).sum())
+    sd = math.sqrt(r["m2_dq"] / max(n - 1, 1))
+    assert abs(st["mean_dq"] - r["mean_dq"]) <= 2e-6 * (abs(r["mean_dq"]) + sd)
+    if n > 1:
+        assert st["m2_dq"] == pytest.approx(r["m2_dq"], rel=1e-5)
+
+
+def test_zero_samples():
+    st = pkg.mlmc_ap_simulate_level(W.cfg2(), 2, 0, 0)
+    assert st["n"] == 0
+
+
+def test_split_ranges_merge():
+    """Statistics of [0,a) merged with [a,n) equal those of [0,n) to rounding."""
+    prob = W.cfg2(eps=0.1)
+    a, n = 3000, 10000
+    s1 = pkg.mlmc_ap_simulate_level(prob, 3, 0, a)
+    s2 = pkg.mlmc_ap_simulate_level(prob, 3, a, n - a)
+    s = pkg.mlmc_ap_simulate_level(prob, 3, 0, n)
+    m = pkg.mlmc_ap_merge_stats(s1, s2)
+    assert m["n"] == s["n"] and m["coll_f"] == s["coll_f"] and m["coll_c"] == s["coll_c"]
+    for k in ("mean_dq", "mean_qf", "mean_qc"):
+        assert m[k] == pytest.approx(s[k], rel=1e-12, abs=1e-15)
+    for k in ("m2_dq", "m2_qf", "m2_qc", "c_fc"):
+        assert m[k] == pytest.approx(s[k], rel=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Histogram (precision study)
+# ---------------------------------------------------------------------------
+def oracle_hist(x, lo, hi, nb):
+    t = (x - lo) * (nb / (hi - lo))
+    b = np.floor(t).astype(np.int64)
+    return b
+
+
+@pytest.mark.parametrize("fp64", [0, 1])
+def test_histogram_counts(fp64):
+    prob = W.cfg4(fp64)
+    level, n = 3, 20000
+    st, h = pkg.mlmc_ap_simulate_level(prob, level, 0, n, hist=True)
+    ref = O.simulate(prob, level, 0, n)
+    nb = 64
+    bf = oracle_hist(ref["xf"], -4.0, 5.0, nb)
+    bc = oracle_hist(ref["xc"], -4.0, 5.0, nb)
+    h = np.array(h, dtype=np.int64)
+    assert h[:3 * nb:3].sum() + h[3 * nb] + h[3 * nb + 1] == n
+    assert h[1:3 * nb:3].sum() + h[3 * nb + 2] + h[3 * nb + 3] == n
+    for b in range(nb):
+        assert abs(h[3 * b] - np.sum(bf == b)) <= 2
+        assert abs(h[3 * b + 1] - np.sum(bc == b)) <= 2
+        assert abs(h[3 * b + 2] - np.sum((bf == b) & (bc == b))) <= 2
+
+
+# ---------------------------------------------------------------------------
+# Estimates: launch modes, tunings, graph replays, batching
+# ---------------------------------------------------------------------------
+def _key(r):
+    return (r["estimate"], r["var_estimator"], tuple(r["N"]),
+            tuple(tuple(sorted(l.items())) for l in r["levels"]))
+
+
+def test_estimate_bitwise_across_modes_and_tunings():
+    prob = W.cfg2(eps=0.05)
+    base = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=1))
+    say("estimate", base["estimate"], "N", base["N"])
+    for opt in (pkg.options(batched=0), pkg.options(batched=2),
+                pkg.options(batched=1, block=64, ppt=1, waves_per_simd=2),
+                pkg.options(batched=2, block=128, ppt=2, waves_per_simd=8),
+                pkg.options(batched=0, block=256, ppt=1)):
+        r = pkg.mlmc_ap_estimate(prob, 1e-2, opt)
+        assert _key(r) == _key(base)
+
+
+def test_graph_replays_match_eager():
+    prob = W.cfg2(eps=0.2, stream_id=9)
+    eager = pkg.mlmc_ap_estimate(prob, 5e-3, pkg.options(batched=2))
+    for _ in range(3):
+        _ = torch.randn(1000, device="cuda").sum().item()  # unrelated eager work in between
+        r = pkg.mlmc_ap_estimate(prob, 5e-3, pkg.options(batched=1))
+        assert _key(r) == _key(eager)
+
+
+def test_estimate_batch_equals_alone():
+    probs = [W.cfg2(eps=e, stream_id=20 + i) for i, e in enumerate((1e-3, 0.05, 1.0))]
+    tols = [1e-2, 5e-3, 1e-2]
+    batch = pkg.mlmc_ap_estimate_batch(probs, tols)
+    for p, t, b in zip(probs, tols, batch):
+        alone = pkg.mlmc_ap_estimate(p, t)
+        assert _key(alone) == _key(b)
+
+
+def test_estimate_matches_oracle_and_closed_form():
+    prob = W.cfg2(eps=0.05, stream_id=31)
+    L = prob["L"]
+    res = pkg.mlmc_ap_estimate(prob, 5e-3)
+    assert res["converged"] and res["var_estimator"] <= 0.5 * 5e-3 ** 2
+    exact = CF.level_second_moment(prob, L)
+    assert abs(res["estimate"] - exact) <= 4.0 * math.sqrt(res["var_estimator"])
+    est, levels = OM.estimate_fixed(prob, res["N"])
+    say("gpu %.9f oracle %.9f exact %.9f sd %.2e" % (res["estimate"], est, exact,
+                                                      math.sqrt(res["var_estimator"])))
+    assert abs(res["estimate"] - est) <= 2e-5 * abs(exact)
+    for l in range(L + 1):
+        g, o = res["levels"][l], levels[l]
+        assert g["n"] == o["n"]
+        assert g["coll_f"] == o["coll_f"] and g["coll_c"] == o["coll_c"]
+        assert g["m2_dq"] == pytest.approx(o["m2_dq"], rel=1e-3)
+
+
+def test_plain_mc_estimate():
+    prob = W.cfg2(eps=0.1, stream_id=41)
+    res = pkg.mlmc_ap_plain_mc(prob, 1e-2)
+    L = prob["L"]
+    assert res["N"][:L] == [0] * L and res["N"][L] > 0
+    exact = CF.level_second_moment(prob, L)
+    assert abs(res["estimate"] - exact) <= 4.0 * math.sqrt(res["var_estimator"])
