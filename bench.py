@@ -96,7 +96,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed estimates (for profiler runs)")
+    ap.add_argument("--tuning", default=None,
+                    help="block,ppt,waves_per_simd instead of running the autotuner")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (the known-size "
+                         "kernel that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe * 1024 * 1024 // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the estimator shards by sample ranges with one "
@@ -115,10 +130,15 @@ def main():
     tol = W.CFG2_TOL
     stream = torch.cuda.current_stream()
 
-    tuning = pkg.mlmc_ap_autotune(prob, None)
+    if args.tuning:
+        b, p_, w = (int(v) for v in args.tuning.split(","))
+        tuning = dict(block=b, ppt=p_, waves_per_simd=w)
+    else:
+        tuning = pkg.mlmc_ap_autotune(prob, None)
     log("tuning", tuning)
+    tk = dict(block=tuning["block"], ppt=tuning["ppt"], waves_per_simd=tuning["waves_per_simd"])
 
-    opt = pkg.options(batched=1)
+    opt = pkg.options(batched=1, **tk)
     for _ in range(args.warmup):
         pkg.mlmc_ap_estimate(prob, tol, opt)
     torch.cuda.synchronize()
@@ -136,7 +156,7 @@ def main():
 
     # Dominant kernel: the persistent particle kernel, launched directly so
     # that HIP events on the launch stream time it.
-    direct = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=2))
+    direct = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=2, **tk))
     kern_s = direct["kernel_seconds"]
     launches = direct["launches"]
     slots = algorithmic_slots(prob, direct["N"])
@@ -173,7 +193,7 @@ def main():
         t0 = time.perf_counter()
         reps = 3
         for _ in range(reps):
-            r0 = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=0))
+            pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=0, **tk))
         per_level_ms = (time.perf_counter() - t0) / reps * 1e3
         # plain Monte Carlo at level 8
         t0 = time.perf_counter()

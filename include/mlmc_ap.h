@@ -25,9 +25,9 @@
  * (step, sample, level tag, stream_id); step 0xFFFFFFFF is the initial
  * draw.  The level tag is l for a fine/coarse pair and l + 64 for a
  * single-level (plain Monte Carlo) trajectory.  Results therefore depend only
- * on (problem, level, sample index range) -- never on launch shape, tuning,
- * batching with other requests, or call splitting of a range into tiles of
- * 256 samples.
+ * on (problem, level, sample index range) -- never on launch shape, tuning
+ * or batching with other requests.  (Splitting one range into several calls
+ * changes only the rounding of the merged statistics.)
  *
  * Conventions for every function:
  *   - returns an mlmc_ap_status; nothing is thrown across the ABI;
@@ -80,7 +80,6 @@ enum { MLMC_AP_QOI_X2 = 0,        /* Q = x(T)^2 */
 
 #define MLMC_AP_MAX_LEVELS 31   /* levels 0..30 */
 #define MLMC_AP_MAX_BINS 1024
-#define MLMC_AP_TILE 256        /* samples per statistics tile */
 
 typedef struct mlmc_ap_problem {
     double eps;          /* diffusive scaling parameter, >= 0 (0 = diffusion limit) */

@@ -16,7 +16,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmlmc_ap.so")
 
 MAX_LEVELS = 31
-TILE = 256
 
 X0_DELTA, X0_NORMAL, X0_COSINE = 0, 1, 2
 EQ_TWO_POINT, EQ_MAXWELLIAN = 0, 1

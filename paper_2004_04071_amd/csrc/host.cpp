@@ -149,9 +149,11 @@ LevelDesc make_desc(const ItemSpec& s) {
                              : kKindPairTwoPointSum)
                   : (maxwell ? kKindFineMaxwell : kKindFineTwoPoint);
   d.x0_kind = (uint32_t)p.x0_kind;
-  d.n_tiles = (uint32_t)((s.n_samples + kTile - 1) / kTile);
+  d.spl = samples_per_lane((uint32_t)F.n_steps);
+  const uint64_t tile_samples = (uint64_t)kLanes * d.spl;
+  d.n_tiles = (uint32_t)((s.n_samples + tile_samples - 1) / tile_samples);
   d.n_groups = (d.n_tiles + kGroupTiles - 1) / kGroupTiles;
-  uint64_t ct = kChunkLaneSteps / ((uint64_t)kSamplesPerLane * (F.n_steps + 1));
+  uint64_t ct = kChunkLaneSteps / ((uint64_t)d.spl * (F.n_steps + 1));
   if (ct < 1) ct = 1;
   if (ct > 64) ct = 64;
   d.chunk_tiles = (uint32_t)ct;

@@ -1,8 +1,9 @@
 // Particle and reduction kernels of the MLMC-AP library (gfx950).
 //
-// One wavefront owns one tile of 256 consecutive samples of a work item:
-// lane i simulates samples tile*256 + 64 j + i, j = 0..3, P of them at a time
-// (P = trajectories in flight per lane, for instruction-level parallelism).
+// One wavefront owns one tile of 64 spl consecutive samples of a work item:
+// lane i simulates samples tile*64*spl + 64 j + i, j < spl, P of them at a
+// time (P = trajectories in flight per lane, for instruction-level
+// parallelism; spl = 4 on levels of fewer than 64 fine steps, else 1).
 // Particle state lives in registers for the whole trajectory; the only
 // memory traffic is one 80-byte statistics record per tile (plus optional
 // dumps and histogram counters).
@@ -136,7 +137,8 @@ __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
                                               Stats* __restrict__ partials) {
   using S = Stepper<Real, P, KIND, WIDE>;
   constexpr bool kCoarse = S::kCoarse;
-  constexpr int kRounds = kSamplesPerLane / P;
+  const int rounds = (int)d.spl / P;
+  const uint64_t tile_samples = (uint64_t)kLanes * d.spl;
   const S st(d);
   const int lane = threadIdx.x & (kLanes - 1);
   const uint32_t n_steps = d.n_steps, M = d.M;
@@ -148,7 +150,7 @@ __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
   unsigned long long col_f = 0, col_c = 0;
 
 #pragma unroll 1
-  for (int r = 0; r < kRounds; ++r) {
+  for (int r = 0; r < rounds; ++r) {
     uint64_t local[P];
     bool valid[P];
     uint32_t smp[P];
@@ -157,7 +159,7 @@ __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int j = r * P + p;
-      local[p] = (uint64_t)tile * kTile + (uint64_t)(j * kLanes + lane);
+      local[p] = (uint64_t)tile * tile_samples + (uint64_t)(j * kLanes + lane);
       valid[p] = local[p] < d.n_samples;
       smp[p] = (uint32_t)(d.sample_begin + local[p]);
       // initial condition, shared by the fine and the coarse path
@@ -274,8 +276,15 @@ __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
 template <typename Real, int P, int KIND>
 __device__ __forceinline__ void run_tile(const LevelDesc& d, uint32_t tile,
                                          Stats* __restrict__ partials) {
-  if (d.flags & kFlagWide) run_tile_impl<Real, P, KIND, true>(d, tile, partials);
-  else run_tile_impl<Real, P, KIND, false>(d, tile, partials);
+  // one trajectory per lane on the long levels (64-sample tiles)
+  constexpr int P1 = 1;
+  if (d.spl == 1) {
+    if (d.flags & kFlagWide) run_tile_impl<Real, P1, KIND, true>(d, tile, partials);
+    else run_tile_impl<Real, P1, KIND, false>(d, tile, partials);
+  } else {
+    if (d.flags & kFlagWide) run_tile_impl<Real, P, KIND, true>(d, tile, partials);
+    else run_tile_impl<Real, P, KIND, false>(d, tile, partials);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -344,7 +353,8 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
 // tree.  Stage 2: one block per item merges the item's group results the
 // same way and folds the result into the item's resident statistics slot.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ Stats block_tree(Stats acc, Stats* sh) {
+// Fixed LDS tree over the block's 256 records; the result is left in sh[0].
+__device__ __forceinline__ void block_tree(const Stats& acc, Stats* sh) {
   const int t = threadIdx.x;
   sh[t] = acc;
   __syncthreads();
@@ -353,9 +363,6 @@ __device__ __forceinline__ Stats block_tree(Stats acc, Stats* sh) {
     if (t < stride) sh[t] = stats_merge(sh[t], sh[t + stride]);
     __syncthreads();
   }
-  const Stats r = sh[0];
-  __syncthreads();
-  return r;
 }
 
 __global__ void __launch_bounds__(kReduceThreads) reduce_groups_kernel(
@@ -379,8 +386,9 @@ __global__ void __launch_bounds__(kReduceThreads) reduce_groups_kernel(
       const uint32_t idx = first + k;
       if (idx < n_tiles) acc = stats_merge(acc, partials[tile_base + idx]);
     }
-    const Stats r = block_tree(acc, sh);
-    if (threadIdx.x == 0) groups[vb] = r;
+    block_tree(acc, sh);
+    if (threadIdx.x == 0) groups[vb] = sh[0];
+    __syncthreads();
   }
 }
 
@@ -398,11 +406,13 @@ __global__ void __launch_bounds__(kReduceThreads) reduce_items_kernel(
       const uint32_t idx = first + k;
       if (idx < n_groups) acc = stats_merge(acc, groups[gbase + idx]);
     }
-    const Stats r = block_tree(acc, sh);
+    block_tree(acc, sh);
     if (threadIdx.x == 0) {
       const uint32_t slot = items[it].result_slot;
-      resident[slot] = (items[it].flags & kFlagAccumulate) ? stats_merge(resident[slot], r) : r;
+      resident[slot] = (items[it].flags & kFlagAccumulate) ? stats_merge(resident[slot], sh[0])
+                                                          : sh[0];
     }
+    __syncthreads();
   }
 }
 

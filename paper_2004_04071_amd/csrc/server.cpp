@@ -50,7 +50,7 @@ struct ServerReq {
 uint64_t tick_bytes(const McRequest& mc) {
   const uint64_t levels = (uint64_t)(mc.prob.L + 1);
   const uint64_t per_level = std::max<uint64_t>(mc.n_warmup, mc.max_per_tick);
-  const uint64_t tiles = (per_level + kTile - 1) / kTile;
+  const uint64_t tiles = (per_level + kLanes - 1) / kLanes;  // 64-sample tiles at worst
   const uint64_t groups = (tiles + kGroupTiles - 1) / kGroupTiles;
   return levels * (tiles + groups) * sizeof(Stats) + levels * sizeof(LevelDesc);
 }

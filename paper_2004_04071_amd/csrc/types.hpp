@@ -1,20 +1,28 @@
 // Host/device shared layouts of the MLMC-AP library (gfx950).
 //
 // A work item is one (request, level, sample range).  Its samples are split
-// into tiles of kTile = 256 consecutive global sample indices; every tile is
-// reduced by one wavefront (64 lanes x 4 samples) into a TilePartial, and the
-// partials of an item are merged by a fixed tree (groups of 4096 tiles, then
-// one group result per item).  The tree depends only on the item's sample
-// count, so the statistics are bitwise independent of launch shape, tuning,
-// and of other items sharing a launch.
+// into tiles of consecutive global sample indices -- 64 lanes x spl samples,
+// with spl = 4 for levels of fewer than 64 fine steps and spl = 1 above (so
+// that one wavefront's serial work per tile stays short on the long levels).
+// Every tile is reduced by one wavefront into a Stats record, and the records
+// of an item are merged by a fixed tree (groups of 4096 tiles, then one group
+// result per item).  The tile size is a function of the level and the tree a
+// function of the item's sample count, so the statistics are bitwise
+// independent of launch shape, tuning, and of other items sharing a launch.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace mlmc {
 
 constexpr int kLanes = 64;                       // gfx950 wavefront
-constexpr int kTile = 256;                       // samples per statistics tile
-constexpr int kSamplesPerLane = kTile / kLanes;  // 4
+constexpr int kMaxSamplesPerLane = 4;            // short levels: 256-sample tiles
+constexpr uint32_t kLongLevelSteps = 64;         // from here on: 64-sample tiles
+
+// Samples per lane of a tile of a level with n_steps fine steps.
+__host__ __device__ inline uint32_t samples_per_lane(uint32_t n_steps) {
+  return n_steps >= kLongLevelSteps ? 1u : (uint32_t)kMaxSamplesPerLane;
+}
 constexpr int kGroupTiles = 4096;                // tiles per first-stage group
 constexpr int kReduceThreads = 256;
 constexpr int kReducePerThread = kGroupTiles / kReduceThreads;  // 16
@@ -69,7 +77,8 @@ struct alignas(16) LevelDesc {
   uint32_t chunk_tiles;         // persistent kernel: tiles per chunk
   uint32_t n_chunks;
   uint32_t result_slot;         // resident statistics slot
-  uint32_t pad0, pad1, pad2;
+  uint32_t spl;                 // samples per lane of a tile (tile = 64 spl samples)
+  uint32_t pad1, pad2;
 };
 
 // Mergeable statistics of a set of samples (FP64 means and centred sums).

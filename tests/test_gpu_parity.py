@@ -166,16 +166,19 @@ def test_wide_thresholds_used():
     assert c["thr_f"] == 0
 
 
-@pytest.mark.parametrize("n", [1, 255, 256, 257, 4097 * 256 + 3])
-def test_tile_and_group_boundaries(n):
-    """Ragged tiles and more than one 4096-tile reduction group."""
+@pytest.mark.parametrize("level,n", [(0, 1), (0, 255), (0, 256), (0, 257), (0, 4097 * 256 + 3),
+                                     (5, 63), (5, 65), (5, 4097 * 64 + 3)])
+def test_tile_and_group_boundaries(level, n):
+    """Ragged tiles (256 samples below 64 fine steps, 64 from there on) and
+    more than one 4096-tile reduction group."""
     prob = W.cfg2(eps=0.3)
-    st = pkg.mlmc_ap_simulate_level(prob, 0, 5, n)
-    ref = O.simulate(prob, 0, 5, n)
-    r = two_pass(ref["xf"], ref["xc"], 0)
+    st = pkg.mlmc_ap_simulate_level(prob, level, 5, n)
+    ref = O.simulate(prob, level, 5, n)
+    r = two_pass(ref["xf"], ref["xc"], level)
     assert st["n"] == n and st["coll_f"] == int(ref["cf"].astype(np.int64).sum())
+    assert st["coll_c"] == int(ref["cc"].astype(np.int64).sum())
     sd = math.sqrt(r["m2_dq"] / max(n - 1, 1))
-    assert abs(st["mean_dq"] - r["mean_dq"]) <= 2e-6 * (abs(r["mean_dq"]) + sd)
+    assert abs(st["mean_dq"] - r["mean_dq"]) <= 2e-6 * (abs(r["mean_dq"]) + sd + abs(r["mean_qf"]))
     if n > 1:
         assert st["m2_dq"] == pytest.approx(r["m2_dq"], rel=1e-5)
 
