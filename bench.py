@@ -26,13 +26,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic VALU issue cost of the method, in full-rate lane-slots (one
-# slot = one lane of one full-rate VALU instruction).  Quarter-rate
-# operations (32x32->64 integer multiply, transcendentals) cost 4 slots.
-# Derivation and the instruction inventory are in DESIGN.md ("Roofline").
-SLOTS_FINE_STEP = 103.0     # Philox4x32-10 + Box-Muller pair + move + collision
-SLOTS_COARSE_FINE = 9.0     # per fine step of a pair: aggregation bookkeeping
-SLOTS_COARSE_STEP = 14.0    # per coarse step: kick normalisation, move, decision
-SLOTS_INIT = 95.0           # per trajectory: initial Philox draw + Box-Muller
+# slot = one lane of one full-rate VALU instruction): full-rate ops 1 slot,
+# 32x32->64-bit integer multiplies 2, transcendentals 4 (weights from the
+# measured gfx950 issue rates).  The instruction inventory is in the design doc
+# ("Roofline").
+SLOTS_FINE_STEP = 78.0      # Philox4x32-10 (50) + uniforms (4) + Box-Muller (19) + move/collide (5)
+SLOTS_COARSE_FINE = 9.0     # per fine step of a pair: block minimum, kick sum, aggregation
+SLOTS_COARSE_STEP = 17.0    # per coarse step: kick normalisation, move, decision, velocity
+SLOTS_INIT = 75.0           # per trajectory: initial Philox draw + Box-Muller + x0
+SLOTS_SAMPLE_FINE = 14.0    # per level-0 sample: FP64 QoI and shifted-sum update
+SLOTS_SAMPLE_PAIR = 30.0    # per pair: the same for dQ, Q_f, Q_c and their co-moment
 PEAK_SLOTS = 256 * 128 * 2.4e9     # CUs x FP32 lanes/CU/cycle x clock (157.3 TFLOP/s FMA)
 
 
@@ -47,11 +50,41 @@ def algorithmic_slots(prob, N):
     tot = 0.0
     for l, n in enumerate(N):
         nf = n0 * M ** l
-        per = SLOTS_INIT + nf * SLOTS_FINE_STEP
+        per = SLOTS_INIT + nf * SLOTS_FINE_STEP + SLOTS_SAMPLE_FINE
         if l >= 1:
             per += nf * SLOTS_COARSE_FINE + (nf // M) * SLOTS_COARSE_STEP
+            per += SLOTS_SAMPLE_PAIR - SLOTS_SAMPLE_FINE
         tot += n * per
     return tot
+
+
+KERNEL_SOURCES = ("kernels.hip", "device.hpp", "types.hpp", "stats.hpp")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "persistent_kernel_hbm_traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2004_04071_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(tuning):
+    """HBM bytes per launch of the particle kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE record, if it was taken on the current
+    kernel sources and launch shape; else None."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if rec.get("tuning") != tuning:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(prob, N, seconds):
@@ -134,7 +167,7 @@ def main():
         b, p_, w = (int(v) for v in args.tuning.split(","))
         tuning = dict(block=b, ppt=p_, waves_per_simd=w)
     else:
-        tuning = pkg.mlmc_ap_autotune(prob, None)
+        tuning = pkg.mlmc_ap_autotune(prob, tol, None)
     log("tuning", tuning)
     tk = dict(block=tuning["block"], ppt=tuning["ppt"], waves_per_simd=tuning["waves_per_simd"])
 
@@ -163,7 +196,8 @@ def main():
     achieved = slots / kern_s
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12,
                     unit="TOP/s (full-rate VALU lane-slots)", frac=achieved / PEAK_SLOTS,
-                    traffic=None, kernel="persistent_kernel<float,%d>" % tuning["ppt"],
+                    traffic=recorded_traffic(tuning),
+                    kernel="persistent_kernel<float,%d>" % tuning["ppt"],
                     avg_launch_ms=kern_s / launches * 1e3, launches=launches)
     out = {
         "metric": "particle-steps/s; MLMC time-to-RMSE 1e-3 vs plain MC; p50/p99 request latency",

@@ -255,14 +255,14 @@ mlmc_ap_status mlmc_ap_estimate_batch(const mlmc_ap_problem* p, const double* rm
                                       int32_t n_req, const mlmc_ap_options* opt,
                                       mlmc_ap_result* out_host, void* stream);
 
-/* Autotuner: times the persistent kernel on a work table shaped like the
- * given problem's MLMC warm-up (and its finest levels) for every
- * (block, ppt, waves_per_simd) candidate and returns the fastest.  If
- * cache_path is non-NULL the choice is read from / written to that JSON
- * file (keyed by the device name).  The choice becomes the default tuning of
- * the current device. */
-mlmc_ap_status mlmc_ap_autotune(const mlmc_ap_problem* p, const char* cache_path,
-                                mlmc_ap_tuning* out_host, void* stream);
+/* Autotuner: runs complete MLMC estimates of p at rmse_tol (persistent
+ * launches issued directly, timed with HIP events on `stream`) for every
+ * (block, ppt, waves_per_simd) candidate and returns the one with the least
+ * particle-kernel time.  If cache_path is non-NULL the choice is read from /
+ * written to that JSON file (keyed by the device name).  The choice becomes
+ * the default tuning of the current device.  Results never depend on it. */
+mlmc_ap_status mlmc_ap_autotune(const mlmc_ap_problem* p, double rmse_tol,
+                                const char* cache_path, mlmc_ap_tuning* out_host, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of MLMC requests.                         */

@@ -110,7 +110,7 @@ _SIGNATURES = {
     "mlmc_ap_plain_mc": [_P(Problem), ctypes.c_double, _P(Options), _P(Result), _vp],
     "mlmc_ap_estimate_batch": [_P(Problem), _P(ctypes.c_double), ctypes.c_int32, _P(Options),
                                _P(Result), _vp],
-    "mlmc_ap_autotune": [_P(Problem), ctypes.c_char_p, _P(Tuning), _vp],
+    "mlmc_ap_autotune": [_P(Problem), ctypes.c_double, ctypes.c_char_p, _P(Tuning), _vp],
     "mlmc_ap_server_create": [_P(ServerConfig), _P(_vp)],
     "mlmc_ap_server_destroy": [_vp],
     "mlmc_ap_server_submit": [_vp, _P(Problem), ctypes.c_double, _P(ctypes.c_uint64)],
@@ -326,9 +326,9 @@ def mlmc_ap_estimate_batch(problems, rmse_tols, opt=None, stream=None):
     return [result_dict(r) for r in res]
 
 
-def mlmc_ap_autotune(p, cache_path=None, stream=None):
+def mlmc_ap_autotune(p, rmse_tol, cache_path=None, stream=None):
     out = Tuning()
-    _check(lib().mlmc_ap_autotune(ctypes.byref(as_problem(p)),
+    _check(lib().mlmc_ap_autotune(ctypes.byref(as_problem(p)), float(rmse_tol),
                                   cache_path.encode() if cache_path else None, ctypes.byref(out),
                                   _stream(stream)), "mlmc_ap_autotune")
     return dict(block=out.block, ppt=out.ppt, waves_per_simd=out.waves_per_simd)

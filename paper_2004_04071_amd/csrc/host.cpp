@@ -22,8 +22,9 @@ namespace {
 thread_local std::string g_last_error;
 constexpr double kTwo32 = 4294967296.0;
 // Fine steps per lane a persistent-kernel chunk aims at (load balance versus
-// work-counter traffic); chunks never exceed 64 tiles.
-constexpr uint64_t kChunkLaneSteps = 2048;
+// work-counter traffic); chunks never exceed 64 tiles, and on the long levels
+// a chunk is a single tile so that the slowest chunks end early.
+constexpr uint64_t kChunkLaneSteps = 256;
 }  // namespace
 
 mlmc_ap_status set_error(mlmc_ap_status s, const std::string& msg) {

@@ -372,56 +372,45 @@ static void write_cache(const char* path, const std::string& dev, const mlmc_ap_
     << "}\n";
 }
 
-mlmc_ap_status mlmc_ap_autotune(const mlmc_ap_problem* p, const char* cache_path,
-                                mlmc_ap_tuning* out, void* stream) {
+mlmc_ap_status mlmc_ap_autotune(const mlmc_ap_problem* p, double rmse_tol,
+                                const char* cache_path, mlmc_ap_tuning* out, void* stream) {
   MLMC_TRY(validate_problem(p));
   if (!out) return set_error(MLMC_AP_EINVAL, "out is NULL");
+  if (!(rmse_tol > 0.0)) return set_error(MLMC_AP_EINVAL, "rmse_tol must be > 0");
   Workspace* ws = workspace();
   if (!ws) return MLMC_AP_EDEVICE;
-  std::lock_guard<std::mutex> lk(ws->mu);
-  if (cache_path && read_cache(cache_path, ws->name, out)) {
-    ws->tuning = *out;
-    ws->tuned = true;
-    return MLMC_AP_OK;
+  {
+    std::lock_guard<std::mutex> lk(ws->mu);
+    if (cache_path && read_cache(cache_path, ws->name, out)) {
+      ws->tuning = *out;
+      ws->tuned = true;
+      return MLMC_AP_OK;
+    }
   }
-  // Work table shaped like an MLMC iteration of p: every level with the same
-  // particle-step budget (2^27 steps per level).
-  std::vector<ItemSpec> items;
-  for (int l = 0; l <= p->L; ++l) {
-    ItemSpec s;
-    s.prob = p;
-    s.level = l;
-    s.single = false;
-    s.sample_begin = 0;
-    s.n_samples = std::max<uint64_t>(4096, (1ull << 27) / sample_cost(*p, l, false));
-    s.result_slot = (uint32_t)l;
-    s.hist = nullptr;
-    s.traj = nullptr;
-    s.coll = nullptr;
-    items.push_back(s);
-  }
-  hipStream_t s = (hipStream_t)stream;
   const int blocks[] = {64, 128, 256};
   const int ppts[] = {1, 2, 4};
-  const int waves[] = {1, 2, 4, 8};
+  const int waves[] = {2, 4, 8};
   double best = 1e30;
-  mlmc_ap_tuning bt = ws->tuning;
+  mlmc_ap_tuning bt{256, 4, 8, 0};
   for (int b : blocks)
     for (int pp : ppts)
       for (int w : waves) {
-        mlmc_ap_tuning t{b, pp, w, 0};
-        LaunchTiming tm;
-        MLMC_TRY(run_table(*ws, items, MLMC_AP_MAX_LEVELS, 2, t, s, &tm));  // warm
-        double acc = 0.0;
-        for (int rep = 0; rep < 2; ++rep) {
-          MLMC_TRY(run_table(*ws, items, MLMC_AP_MAX_LEVELS, 2, t, s, &tm));
-          acc += tm.kernel_s;
+        mlmc_ap_options o;
+        std::memset(&o, 0, sizeof(o));
+        o.batched = 2;
+        o.tuning = mlmc_ap_tuning{b, pp, w, 0};
+        mlmc_ap_result r;
+        double t = 0.0;
+        for (int rep = 0; rep < 3; ++rep) {  // first run warms the workspace
+          MLMC_TRY(mlmc_ap_estimate(p, rmse_tol, &o, &r, nullptr, stream));
+          if (rep > 0) t += r.kernel_seconds;
         }
-        if (acc < best) {
-          best = acc;
-          bt = t;
+        if (t < best) {
+          best = t;
+          bt = o.tuning;
         }
       }
+  std::lock_guard<std::mutex> lk(ws->mu);
   ws->tuning = bt;
   ws->tuned = true;
   *out = bt;
