@@ -30,12 +30,13 @@ sys.path.insert(0, ROOT)
 # 32x32->64-bit integer multiplies 2, transcendentals 4 (weights from the
 # measured gfx950 issue rates).  The instruction inventory is in the design doc
 # ("Roofline").
-SLOTS_FINE_STEP = 78.0      # Philox4x32-10 (50) + uniforms (4) + Box-Muller (19) + move/collide (5)
+SLOTS_PHILOX_BLOCK = 50.0   # 16 lane-varying 64-bit products (2) + 18 three-input xors (1)
+SLOTS_NORMAL_PAIR = 23.0    # two uniforms (4) + log, sqrt, sin, cos (16) + 3 multiplies
+SLOTS_FINE_MOVE = 5.0       # move (2 FMA) + collision compare, select, count
 SLOTS_COARSE_FINE = 9.0     # per fine step of a pair: block minimum, kick sum, aggregation
 SLOTS_COARSE_STEP = 17.0    # per coarse step: kick normalisation, move, decision, velocity
-SLOTS_INIT = 75.0           # per trajectory: initial Philox draw + Box-Muller + x0
-SLOTS_SAMPLE_FINE = 14.0    # per level-0 sample: FP64 QoI and shifted-sum update
-SLOTS_SAMPLE_PAIR = 30.0    # per pair: the same for dQ, Q_f, Q_c and their co-moment
+SLOTS_SAMPLE_FINE = 15.0    # per level-0 sample: x0, FP64 QoI and shifted-sum update
+SLOTS_SAMPLE_PAIR = 31.0    # per pair: the same for dQ, Q_f, Q_c and their co-moment
 PEAK_SLOTS = 256 * 128 * 2.4e9     # CUs x FP32 lanes/CU/cycle x clock (157.3 TFLOP/s FMA)
 
 
@@ -44,16 +45,20 @@ def log(*a):
 
 
 def algorithmic_slots(prob, N):
-    """Algorithmic lane-slots of an estimate with N[l] samples per level."""
+    """Algorithmic lane-slots of an estimate with N[l] samples per level: a
+    trajectory of n fine steps reads 2 + 3n words of its Philox word stream
+    (ceil((2 + 3n)/4) blocks) and forms n + 1 Box-Muller pairs."""
     n0 = int(round(prob["T"] / prob["dt0"]))
     M = prob["M"]
     tot = 0.0
     for l, n in enumerate(N):
         nf = n0 * M ** l
-        per = SLOTS_INIT + nf * SLOTS_FINE_STEP + SLOTS_SAMPLE_FINE
+        blocks = (2 + 3 * nf + 3) // 4
+        per = blocks * SLOTS_PHILOX_BLOCK + (nf + 1) * SLOTS_NORMAL_PAIR + nf * SLOTS_FINE_MOVE
         if l >= 1:
-            per += nf * SLOTS_COARSE_FINE + (nf // M) * SLOTS_COARSE_STEP
-            per += SLOTS_SAMPLE_PAIR - SLOTS_SAMPLE_FINE
+            per += nf * SLOTS_COARSE_FINE + (nf // M) * SLOTS_COARSE_STEP + SLOTS_SAMPLE_PAIR
+        else:
+            per += SLOTS_SAMPLE_FINE
         tot += n * per
     return tot
 

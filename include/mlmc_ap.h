@@ -21,13 +21,19 @@
  * chi-update).  The MLMC estimator is eq. mlmc-compact, with sample numbers
  * from eqs. Nopt1/Noptj and the statistical constraint of Section 4.1.
  *
- * Random numbers: Philox4x32-10 with key = seed and counter
- * (step, sample, level tag, stream_id); step 0xFFFFFFFF is the initial
- * draw.  The level tag is l for a fine/coarse pair and l + 64 for a
- * single-level (plain Monte Carlo) trajectory.  Results therefore depend only
- * on (problem, level, sample index range) -- never on launch shape, tuning
- * or batching with other requests.  (Splitting one range into several calls
- * changes only the rounding of the merged statistics.)
+ * Random numbers: Philox4x32-10 with key = seed.  The random numbers of one
+ * trajectory are the word stream of its blocks 0, 1, 2, ... with counter
+ * (block, sample, level tag, stream_id); the level tag is l for a
+ * fine/coarse pair and l + 64 for a single-level (plain Monte Carlo)
+ * trajectory.  The initial condition takes words 0-1 (a Box-Muller pair;
+ * the density 1 + cos 2 pi x also word 2, and words 3-5 are skipped); every
+ * fine step takes the next three: the collision decision word, then the
+ * Box-Muller radius and angle words (the +-1 velocity sign is the top bit of
+ * the angle word).  The coarse path draws nothing of its own.  Results
+ * therefore depend only on (problem, level, sample index range) -- never on
+ * launch shape, tuning or batching with other requests.  (Splitting one
+ * range into several calls changes only the rounding of the merged
+ * statistics.)
  *
  * Conventions for every function:
  *   - returns an mlmc_ap_status; nothing is thrown across the ABI;

@@ -141,8 +141,8 @@ def simulate(prob, level, sample_begin=0, n=None, samples=None, single=False, th
     return dict(xf=xf, xc=xc, cf=cf, cc=cc)
 
 
-TRACE_COLUMNS = ("n", "w0", "w1", "w2", "w3", "u1", "u2", "xi", "g", "hit",
-                 "xf", "vf", "kick", "coarse_hit", "xc", "vc")
+TRACE_COLUMNS = ("n", "w_decision", "w_radius", "w_angle", "words_used", "u1", "u2", "xi", "g",
+                 "hit", "xf", "vf", "kick", "coarse_hit", "xc", "vc")
 
 
 def trace(prob, level, sample, single=False):

@@ -43,8 +43,13 @@
  *     epsilon-update), and a coarse collision always comes with a fine one.
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
- * random numbers: as easy as 1, 2, 3", SC 2011), key = seed, counter =
- * (step, sample, level tag, stream).  Step 0xFFFFFFFF is the initial draw.
+ * random numbers: as easy as 1, 2, 3", SC 2011), key = seed.  The random
+ * numbers of one trajectory are the word stream W_0, W_1, ... of its blocks
+ * b = 0, 1, 2, ... with counter (b, sample, level tag, stream): W_k is word
+ * k mod 4 of block k/4.  The initial condition takes W_0, W_1 (a Box-Muller
+ * pair; for the density 1 + cos 2 pi x also W_2, and W_3..W_5 are skipped),
+ * then every fine step takes the next three words: the collision decision
+ * word and a Box-Muller pair.
  */
 #include <math.h>
 #include <stdint.h>
@@ -85,7 +90,8 @@ double oracle_uniform(uint32_t w)
     return (2.0 * (double)(w >> 9) + 1.0) * 0x1p-24;
 }
 
-/* Box-Muller pair from two words: cosine branch and sine branch. */
+/* Box-Muller pair from two words: cosine branch and sine branch.  The
+ * first word gives the radius, the second the angle. */
 static void box_muller(uint32_t wa, uint32_t wb, double *c, double *s)
 {
     double u1 = oracle_uniform(wa);
@@ -159,6 +165,44 @@ void oracle_level_consts(double eps, double T, double dt0, int M, int l,
 }
 
 /* ------------------------------------------------------------------ */
+/* The word stream of one trajectory.                                   */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    uint32_t key[2];
+    uint32_t sample, tag, stream;
+    uint32_t block;      /* next block index */
+    uint32_t buf[4];
+    int pos;             /* next word of buf; 4 = empty */
+} words_t;
+
+static void words_init(words_t *s, const uint32_t key[2], uint32_t sample, uint32_t tag,
+                       uint32_t stream)
+{
+    s->key[0] = key[0]; s->key[1] = key[1];
+    s->sample = sample; s->tag = tag; s->stream = stream;
+    s->block = 0; s->pos = 4;
+}
+
+static uint32_t next_word(words_t *s)
+{
+    if (s->pos == 4) {
+        uint32_t ctr[4] = {s->block, s->sample, s->tag, s->stream};
+        oracle_philox4x32_10(ctr, s->key, s->buf);
+        s->block++;
+        s->pos = 0;
+    }
+    return s->buf[s->pos++];
+}
+
+/* +1 or -1 from the top bit of a word: for the angle word of a Box-Muller
+ * pair this is the sign of its sine branch, and it is independent of the
+ * cosine branch. */
+static double sign_of(uint32_t w)
+{
+    return (w >> 31) ? -1.0 : 1.0;
+}
+
+/* ------------------------------------------------------------------ */
 /* One fine/coarse pair (or one single-level trajectory).              */
 /* ------------------------------------------------------------------ */
 enum { X0_DELTA = 0, X0_NORMAL = 1, X0_COSINE = 2 };
@@ -200,18 +244,21 @@ static void simulate_one(const problem_t *P, uint64_t sample,
     level_consts C = coarse ? make_level(P->eps, P->T, P->dt0, P->M, l - 1) : F;
     uint64_t thr_c2 = coarse ? oracle_coarse_threshold(F.thr, C.thr, P->M) : 0;
 
-    uint32_t ctr[4], w[4];
+    words_t ws;
+    words_init(&ws, P->key, (uint32_t)sample, tag, P->stream);
 
     /* Initial condition (shared by the fine and the coarse path). */
-    ctr[0] = 0xFFFFFFFFu; ctr[1] = (uint32_t)sample; ctr[2] = tag; ctr[3] = P->stream;
-    oracle_philox4x32_10(ctr, P->key, w);
+    uint32_t ia = next_word(&ws), ib = next_word(&ws);
     double nc, ns;
-    box_muller(w[1], w[2], &nc, &ns);
+    box_muller(ia, ib, &nc, &ns);
     double x0;
     if (P->x0_kind == X0_DELTA) x0 = P->x0_a;
     else if (P->x0_kind == X0_NORMAL) x0 = P->x0_a + P->x0_b * nc;
-    else x0 = oracle_cosine_icdf(oracle_uniform(w[0]));
-    double v0 = (P->eq_kind == EQ_MAXWELLIAN) ? ns : ((w[3] >> 31) ? -1.0 : 1.0);
+    else {
+        x0 = oracle_cosine_icdf(oracle_uniform(next_word(&ws)));
+        for (int k = 0; k < 3; ++k) (void)next_word(&ws);   /* W_3..W_5 unused */
+    }
+    double v0 = (P->eq_kind == EQ_MAXWELLIAN) ? ns : sign_of(ib);
 
     double xf = x0, vf = v0, xc = x0, vc = v0;
     uint32_t cf = 0, cc = 0;
@@ -226,11 +273,12 @@ static void simulate_one(const problem_t *P, uint64_t sample,
     uint32_t min_word = 0xFFFFFFFFu; /* smallest fine decision word of the block */
 
     for (uint64_t n = 0; n < F.n_steps; ++n) {
-        ctr[0] = (uint32_t)n; ctr[1] = (uint32_t)sample; ctr[2] = tag; ctr[3] = P->stream;
-        oracle_philox4x32_10(ctr, P->key, w);
+        uint32_t wd = next_word(&ws);      /* collision decision */
+        uint32_t wa = next_word(&ws);      /* Box-Muller radius */
+        uint32_t wb = next_word(&ws);      /* Box-Muller angle */
         double xi, g;
-        box_muller(w[1], w[2], &xi, &g);
-        double v_new = (P->eq_kind == EQ_MAXWELLIAN) ? g : ((w[3] >> 31) ? -1.0 : 1.0);
+        box_muller(wa, wb, &xi, &g);
+        double v_new = (P->eq_kind == EQ_MAXWELLIAN) ? g : sign_of(wb);
 
         /* transport-diffusion with the pre-collision velocity */
         xf = xf + F.h * vf + F.s * xi;
@@ -238,8 +286,8 @@ static void simulate_one(const problem_t *P, uint64_t sample,
         sum_xi += xi;
 
         /* collision */
-        int hit = ((uint64_t)w[0] < F.thr);
-        if (w[0] < min_word) min_word = w[0];
+        int hit = ((uint64_t)wd < F.thr);
+        if (wd < min_word) min_word = wd;
         if (hit) {
             vf = v_new;
             cf++;
@@ -250,8 +298,9 @@ static void simulate_one(const problem_t *P, uint64_t sample,
             have_draw = 1; last_nu = v_new; last_uses = 0.0;
         }
 
-        double row[16] = {(double)n, (double)w[0], (double)w[1], (double)w[2], (double)w[3],
-                          oracle_uniform(w[1]), oracle_uniform(w[2]), xi, g, (double)hit,
+        double row[16] = {(double)n, (double)wd, (double)wa, (double)wb,
+                          (double)(ws.block * 4u - (uint32_t)(4 - ws.pos)),
+                          oracle_uniform(wa), oracle_uniform(wb), xi, g, (double)hit,
                           xf, vf, 0, 0, 0, 0};
 
         if (coarse && (n % (uint64_t)P->M) == (uint64_t)(P->M - 1)) {
@@ -319,7 +368,8 @@ int oracle_simulate(double eps, double T, double dt0, int M, int level, int sing
 }
 
 /* Per-step trace of one sample: 16 doubles per fine step
- * (n, w0..w3, u1, u2, xi, g, hit, x_f, v_f, kick, coarse_hit, x_c, v_c);
+ * (n, decision word, radius word, angle word, words consumed so far, u1, u2,
+ * xi, g, hit, x_f, v_f, kick, coarse_hit, x_c, v_c);
  * the last four are filled on the last fine step of each block. */
 uint64_t oracle_trace(double eps, double T, double dt0, int M, int level, int single,
                       int x0_kind, double x0_a, double x0_b, int eq_kind, int coupling,

@@ -10,7 +10,7 @@ namespace mlmc {
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011).  Counter layout used
-// by the particle kernels: (step, sample, tag, stream).  Step, tag and
+// by the particle kernels: (block, sample, tag, stream).  Block, tag and
 // stream are wave-uniform and only the sample word varies across lanes, so
 // both products of the first round, one of the second and one of the third
 // stay on the scalar unit.

@@ -8,8 +8,9 @@
 // memory traffic is one 80-byte statistics record per tile (plus optional
 // dumps and histogram counters).
 //
-// Per fine step (asymptotic-preserving splitting, fixed dt):
-//   x <- x + h v + s xi;  collide iff word0 < thr  ->  v <- equilibrium draw.
+// Per fine step (asymptotic-preserving splitting, fixed dt), from three words
+// of the trajectory's Philox word stream (decision, radius, angle):
+//   x <- x + h v + s xi;  collide iff decision word < thr  ->  v <- equilibrium draw.
 // Coarse path (levels >= 1), one coarse step per block of M fine steps, built
 // from the fine random numbers of that block (Section 3.1 mapping by time of
 // action; Section 3.2 aggregation):
@@ -28,9 +29,15 @@
 
 namespace mlmc {
 
-// One fine step of P trajectories (and the coarse-block bookkeeping).
+// The P trajectories of one lane: state, coarse-block bookkeeping, and the
+// word stream.  Each trajectory's random numbers are the words of its Philox
+// blocks 0, 1, 2, ... (counter (block, sample, tag, stream)); the initial
+// condition takes words 0-1 (0-5 for the cosine law) and every fine step the
+// next three: decision word, Box-Muller radius word, Box-Muller angle word.
+// Four fine steps therefore use exactly three blocks, and a group of four
+// steps always starts with two words left over from the previous block.
 template <typename Real, int P, int KIND, bool WIDE>
-struct Stepper {
+struct Lane {
   static constexpr bool kCoarse = KIND >= kKindPairTwoPointSum;
   static constexpr bool kMaxwell = KIND == kKindFineMaxwell || KIND == kKindPairMaxwellSum ||
                                    KIND == kKindPairMaxwellAggregate;
@@ -39,86 +46,107 @@ struct Stepper {
   Real h_f, s_f, h_c, s_c, agg_ms2, h_f2, rsqrt_m;
   uint32_t thr_f_m1, thr_c2_m1;
   uint64_t thr_f, thr_c2;
-  uint32_t tag, strm, key0, key1;
+  uint32_t tag, strm, key0, key1, M;
 
-  __device__ __forceinline__ explicit Stepper(const LevelDesc& d)
+  uint32_t smp[P];
+  Real xf[P], vf[P], xc[P], vc[P];
+  uint32_t cf[P], cc[P];
+  Real sum_xi[P], num[P], den[P], lnu[P], uses[P], have[P];
+  uint32_t wmin[P];
+  uint32_t l0[P], l1[P];  // words carried into the next group of four steps
+  uint32_t m;             // fine steps taken in the current coarse block
+
+  __device__ __forceinline__ explicit Lane(const LevelDesc& d)
       : h_f((Real)d.h_f), s_f((Real)d.s_f), h_c((Real)d.h_c), s_c((Real)d.s_c),
         agg_ms2((Real)d.agg_ms2), h_f2((Real)d.h_f2), rsqrt_m((Real)d.rsqrt_m),
         thr_f_m1(d.thr_f_m1), thr_c2_m1(d.thr_c2_m1), thr_f(d.thr_f), thr_c2(d.thr_c2),
-        tag(d.tag), strm(d.stream), key0(d.key0), key1(d.key1) {}
+        tag(d.tag), strm(d.stream), key0(d.key0), key1(d.key1), M(d.M), m(0) {}
 
-  __device__ __forceinline__ Real new_velocity(Real g, uint32_t w3) const {
-    if constexpr (kMaxwell) return g;
-    else return ((int32_t)w3 < 0) ? Real(-1) : Real(1);
+  __device__ __forceinline__ Words block(uint32_t b, int p) const {
+    return philox4x32_10(b, smp[p], tag, strm, key0, key1);
   }
 
-  // Fine path only (level 0 or single-level trajectories).
-  __device__ __forceinline__ void fine(uint32_t n, const uint32_t (&smp)[P], Real (&xf)[P],
-                                       Real (&vf)[P], uint32_t (&cf)[P]) const {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const Words w = philox4x32_10(n, smp[p], tag, strm, key0, key1);
-      Real xi, g;
-      box_muller(w.w1, w.w2, xi, g);
-      Real vnew = new_velocity(g, w.w3);
-      keep(vnew);
-      xf[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, vf[p], xf[p]));
-      const bool hit = below<WIDE>(w.w0, thr_f_m1, thr_f);
-      vf[p] = hit ? vnew : vf[p];
-      cf[p] += hit ? 1u : 0u;
-    }
+  // +1 or -1 from the top bit of the angle word (the sign of the sine branch)
+  __device__ __forceinline__ static Real sign_of(uint32_t w) {
+    return ((int32_t)w < 0) ? Real(-1) : Real(1);
   }
 
-  // Fine/coarse pairs: M fine steps, then the coarse step built from them.
-  // Aggregated kick bookkeeping per block: num accumulates, for every fine
-  // move made with an in-block velocity draw, that draw's normal (so it holds
-  // sum_j n_j nu_j), and den accumulates 2u+1 at the u-th further use of a
-  // draw (so it holds sum_j n_j^2).  If the coarse path collides, the last
-  // draw becomes its velocity and its n nu and n^2 are taken out again.
-  __device__ __forceinline__ void block(uint32_t b, uint32_t M, const uint32_t (&smp)[P],
-                                        Real (&xf)[P], Real (&vf)[P], Real (&xc)[P],
-                                        Real (&vc)[P], uint32_t (&cf)[P],
-                                        uint32_t (&cc)[P]) const {
-    Real sum_xi[P], num[P], den[P], lnu[P], uses[P], have[P];
-    uint32_t wmin[P];
+  __device__ __forceinline__ void reset_block() {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       sum_xi[p] = Real(0); num[p] = Real(0); den[p] = Real(0);
       lnu[p] = Real(0); uses[p] = Real(0); have[p] = Real(0);
       wmin[p] = 0xFFFFFFFFu;
     }
-#pragma unroll 1
-    for (uint32_t m = 0; m < M; ++m) {
-      const uint32_t n = b * M + m;
+  }
+
+  // Initial condition of every trajectory (shared by fine and coarse path);
+  // returns the index of the next block.
+  __device__ __forceinline__ uint32_t init(const LevelDesc& d) {
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const Words w = philox4x32_10(n, smp[p], tag, strm, key0, key1);
-        Real xi, g;
-        box_muller(w.w1, w.w2, xi, g);
-        Real vnew = new_velocity(g, w.w3);
-        keep(vnew);
-        xf[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, vf[p], xf[p]));
-        const bool hit = below<WIDE>(w.w0, thr_f_m1, thr_f);
-        vf[p] = hit ? vnew : vf[p];
-        cf[p] += hit ? 1u : 0u;
-        sum_xi[p] += xi;
-        wmin[p] = min(wmin[p], w.w0);
-        if constexpr (kAgg) {
-          num[p] += lnu[p];  // zero until the first in-block draw
-          den[p] = fma_r<Real>(have[p], fma_r<Real>(Real(2), uses[p], Real(1)), den[p]);
-          uses[p] += have[p];
-          lnu[p] = hit ? vnew : lnu[p];
-          uses[p] = hit ? Real(0) : uses[p];
-          have[p] = hit ? Real(1) : have[p];
-        }
+    for (int p = 0; p < P; ++p) {
+      const Words w = block(0, p);
+      Real nc, ns;
+      box_muller(w.w0, w.w1, nc, ns);
+      Real x0;
+      l0[p] = w.w2;
+      l1[p] = w.w3;
+      if (d.x0_kind == 0) {
+        x0 = (Real)d.x0_a;
+      } else if (d.x0_kind == 1) {
+        x0 = fma_r<Real>((Real)d.x0_b, nc, (Real)d.x0_a);
+      } else {
+        x0 = (Real)cosine_icdf(uniform_f64(w.w2));
+        const Words w1 = block(1, p);  // words 4, 5 unused
+        l0[p] = w1.w2;
+        l1[p] = w1.w3;
+      }
+      const Real v0 = kMaxwell ? ns : sign_of(w.w1);
+      xf[p] = x0; vf[p] = v0; xc[p] = x0; vc[p] = v0;
+      cf[p] = 0u; cc[p] = 0u;
+    }
+    reset_block();
+    m = 0;
+    return d.x0_kind == 2 ? 2u : 1u;
+  }
+
+  // One fine step of trajectory p: decision word wd, Box-Muller words (wa, wb).
+  __device__ __forceinline__ void step(int p, uint32_t wd, uint32_t wa, uint32_t wb) {
+    Real xi, g;
+    box_muller(wa, wb, xi, g);
+    Real vnew = kMaxwell ? g : sign_of(wb);
+    keep(vnew);  // computed unconditionally: the select below stays branch-free
+    xf[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, vf[p], xf[p]));
+    const bool hit = below<WIDE>(wd, thr_f_m1, thr_f);
+    vf[p] = hit ? vnew : vf[p];
+    cf[p] += hit ? 1u : 0u;
+    if constexpr (kCoarse) {
+      sum_xi[p] += xi;
+      wmin[p] = min(wmin[p], wd);
+      if constexpr (kAgg) {
+        // num accumulates, per fine move made with an in-block velocity draw,
+        // that draw's normal (-> sum_j n_j nu_j); den accumulates 2u+1 at the
+        // u-th further use of a draw (-> sum_j n_j^2)
+        num[p] += lnu[p];
+        den[p] = fma_r<Real>(have[p], fma_r<Real>(Real(2), uses[p], Real(1)), den[p]);
+        uses[p] += have[p];
+        lnu[p] = hit ? vnew : lnu[p];
+        uses[p] = hit ? Real(0) : uses[p];
+        have[p] = hit ? Real(1) : have[p];
       }
     }
+  }
+
+  // Coarse step of every trajectory at the end of a block of M fine steps.
+  __device__ __forceinline__ void coarse() {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       // coarse collision: the smallest fine decision word is below thr_c2
       const bool chit = below<WIDE>(wmin[p], thr_c2_m1, thr_c2);
       Real kick;
       if constexpr (kAgg) {
+        // if the coarse path collides, the last in-block draw becomes its
+        // velocity and leaves the kick
         const Real nn = chit ? fma_r<Real>(-uses[p], lnu[p], num[p]) : num[p];
         const Real dd = chit ? fma_r<Real>(-uses[p], uses[p], den[p]) : den[p];
         kick = fma_r<Real>(h_f, nn, s_f * sum_xi[p]) * rsqrt_r(fma_r<Real>(h_f2, dd, agg_ms2));
@@ -129,19 +157,107 @@ struct Stepper {
       vc[p] = chit ? vf[p] : vc[p];
       cc[p] += chit ? 1u : 0u;
     }
+    reset_block();
+  }
+
+  // After a fine step: the coarse step when a block of M fine steps is
+  // complete.  MS = 2 or 4 (M divides 4, so blocks align with groups of four
+  // steps and the positions are static); MS = 0: M read at run time.
+  template <int MS>
+  __device__ __forceinline__ void end_step(int k) {
+    if constexpr (kCoarse) {
+      if constexpr (MS != 0) {
+        if ((k + 1) % MS == 0) coarse();
+      } else {
+        if (++m == M) {  // wave-uniform
+          coarse();
+          m = 0;
+        }
+      }
+    }
+  }
+
+  // Four fine steps from blocks b, b+1, b+2.
+  template <int MS>
+  __device__ __forceinline__ void group4(uint32_t b) {
+    Words w[P];
+    uint32_t t[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) w[p] = block(b, p);
+#pragma unroll
+    for (int p = 0; p < P; ++p) step(p, l0[p], l1[p], w[p].w0);
+    end_step<MS>(0);
+#pragma unroll
+    for (int p = 0; p < P; ++p) step(p, w[p].w1, w[p].w2, w[p].w3);
+    end_step<MS>(1);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      w[p] = block(b + 1, p);
+      step(p, w[p].w0, w[p].w1, w[p].w2);
+      t[p] = w[p].w3;
+    }
+    end_step<MS>(2);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      w[p] = block(b + 2, p);
+      step(p, t[p], w[p].w0, w[p].w1);
+      l0[p] = w[p].w2;
+      l1[p] = w[p].w3;
+    }
+    end_step<MS>(3);
+  }
+
+  // The first `count` (1..3) steps of a group (coarse positions at run time).
+  __device__ __forceinline__ void group_tail(uint32_t b, uint32_t count) {
+    Words w[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) w[p] = block(b, p);
+#pragma unroll
+    for (int p = 0; p < P; ++p) step(p, l0[p], l1[p], w[p].w0);
+    end_step<0>(0);
+    if (count > 1) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) step(p, w[p].w1, w[p].w2, w[p].w3);
+      end_step<0>(1);
+    }
+    if (count > 2) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        w[p] = block(b + 1, p);
+        step(p, w[p].w0, w[p].w1, w[p].w2);
+      }
+      end_step<0>(2);
+    }
+  }
+
+  __device__ __forceinline__ void run(const LevelDesc& d) {
+    uint32_t b = init(d);
+    const uint32_t n_steps = d.n_steps;
+    uint32_t n = 0;
+    if (!kCoarse || M == 2) {
+#pragma unroll 1
+      for (; n + 4 <= n_steps; n += 4, b += 3) group4<2>(b);
+    } else if (M == 4) {
+#pragma unroll 1
+      for (; n + 4 <= n_steps; n += 4, b += 3) group4<4>(b);
+    } else {
+#pragma unroll 1
+      for (; n + 4 <= n_steps; n += 4, b += 3) group4<0>(b);
+    }
+    // blocks of M in {2, 4} end on group boundaries, so the run-time
+    // counter starts the tail at zero
+    if (n < n_steps) group_tail(b, n_steps - n);
   }
 };
 
 template <typename Real, int P, int KIND, bool WIDE>
 __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
                                               Stats* __restrict__ partials) {
-  using S = Stepper<Real, P, KIND, WIDE>;
+  using S = Lane<Real, P, KIND, WIDE>;
   constexpr bool kCoarse = S::kCoarse;
+  const int lane = threadIdx.x & (kLanes - 1);
   const int rounds = (int)d.spl / P;
   const uint64_t tile_samples = (uint64_t)kLanes * d.spl;
-  const S st(d);
-  const int lane = threadIdx.x & (kLanes - 1);
-  const uint32_t n_steps = d.n_steps, M = d.M;
 
   // Shifted sums (shift = the values of the tile's first sample, lane 0).
   double k_dq = 0.0, k_f = 0.0, k_c = 0.0;
@@ -151,42 +267,21 @@ __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
 
 #pragma unroll 1
   for (int r = 0; r < rounds; ++r) {
+    S st(d);
     uint64_t local[P];
     bool valid[P];
-    uint32_t smp[P];
-    Real xf[P], vf[P], xc[P], vc[P];
-    uint32_t cf[P], cc[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int j = r * P + p;
       local[p] = (uint64_t)tile * tile_samples + (uint64_t)(j * kLanes + lane);
       valid[p] = local[p] < d.n_samples;
-      smp[p] = (uint32_t)(d.sample_begin + local[p]);
-      // initial condition, shared by the fine and the coarse path
-      const Words w = philox4x32_10(0xFFFFFFFFu, smp[p], st.tag, st.strm, st.key0, st.key1);
-      Real nc, ns;
-      box_muller(w.w1, w.w2, nc, ns);
-      Real x0;
-      if (d.x0_kind == 0) {
-        x0 = (Real)d.x0_a;
-      } else if (d.x0_kind == 1) {
-        x0 = fma_r<Real>((Real)d.x0_b, nc, (Real)d.x0_a);
-      } else {
-        x0 = (Real)cosine_icdf(uniform_f64(w.w0));
-      }
-      const Real v0 = st.new_velocity(ns, w.w3);
-      xf[p] = x0; vf[p] = v0; xc[p] = x0; vc[p] = v0;
-      cf[p] = 0u; cc[p] = 0u;
+      st.smp[p] = (uint32_t)(d.sample_begin + local[p]);
     }
-
-    if constexpr (kCoarse) {
-      const uint32_t n_blocks = n_steps / M;
-#pragma unroll 1
-      for (uint32_t b = 0; b < n_blocks; ++b) st.block(b, M, smp, xf, vf, xc, vc, cf, cc);
-    } else {
-#pragma unroll 1
-      for (uint32_t n = 0; n < n_steps; ++n) st.fine(n, smp, xf, vf, cf);
-    }
+    st.run(d);
+    auto& xf = st.xf;
+    auto& xc = st.xc;
+    auto& cf = st.cf;
+    auto& cc = st.cc;
 
     // Quantity of interest in FP64 (exact squares of FP32 positions).
 #pragma unroll

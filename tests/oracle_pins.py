@@ -68,6 +68,24 @@ def pin_philox_kat():
         assert [int(w) for w in out] == v[6:10], (r, [hex(int(w)) for w in out])
 
 
+def pin_word_layout():
+    """The documented random-number layout: the stream of Philox words of
+    blocks 0, 1, 2, ... (counter (block, sample, tag, stream)); the initial
+    condition takes 2 words (6 for the cosine law), then each fine step the
+    decision word and a Box-Muller pair (radius, angle)."""
+    for x0_kind, first in ((1, 2), (2, 6)):
+        prob = dict(maxwell_problem(0.3, T=1.0, dt0=0.125, stream=77), x0_kind=x0_kind)
+        rows, _ = O.trace(prob, 1, 12345)
+        n = rows.shape[0]
+        blocks = (first + 3 * n + 3) // 4
+        w = O.words(42, 77, 1, 12345, 1, blocks).reshape(-1)
+        for k in range(n):
+            assert rows[k, 1] == w[first + 3 * k]
+            assert rows[k, 2] == w[first + 3 * k + 1]
+            assert rows[k, 3] == w[first + 3 * k + 2]
+            assert rows[k, 4] == first + 3 * k + 3
+
+
 def pin_uniform():
     """Odd multiples of 2^-24 strictly inside (0,1), symmetric about 1/2."""
     assert O.uniform(0) == 2.0 ** -24
@@ -294,7 +312,7 @@ def pin_mlmc_unbiased():
     assert res["var_estimator"] <= 0.5 * 2e-2 ** 2 * 1.0000001
 
 
-ALL_PINS = [pin_philox_kat, pin_uniform, pin_normals, pin_second_moment_cfg1,
+ALL_PINS = [pin_philox_kat, pin_word_layout, pin_uniform, pin_normals, pin_second_moment_cfg1,
             pin_second_moment_levels, pin_cosine_initial, pin_heat_limit, pin_kinetic_limit,
             pin_two_point_bruteforce, pin_telescoping, pin_coupling_laws, pin_coarse_threshold,
             pin_symmetry, pin_optimal_samples, pin_mlmc_unbiased]
