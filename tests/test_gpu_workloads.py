@@ -1,0 +1,147 @@
+"""The full-size workloads on the GPU, through the C ABI.
+
+* eps sweep at RMSE 1e-3 (eps in {1e-4, 1e-3, 1e-2, 1e-1, 1}, the batched
+  launch): each estimate within 4 standard errors of the exact E[Q_8] and
+  with the statistical constraint met; at the full sample numbers, sampled
+  trajectories (runs of 256 samples at random offsets of every level) equal
+  the oracle's one by one.
+* precision study (density 1 + cos 2 pi x, eps = 1e-3, L = 10): FP32 and
+  FP64 particle state against the oracle per level, and both MLMC estimates
+  against the exact E[Q_10].
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import closed_form as CF
+from oracle import mlmc as OM
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2004_04071_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    pkg.mlmc_ap_init()
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dump(prob, level, begin, n):
+    P = pkg.as_problem(prob)
+    dt = torch.float64 if P.fp64_state else torch.float32
+    traj = torch.empty(2 * n, dtype=dt, device="cuda")
+    coll = torch.empty(2 * n, dtype=torch.int32, device="cuda")
+    st = pkg.mlmc_ap_simulate_level(P, level, begin, n, traj=traj, coll=coll)
+    torch.cuda.synchronize()
+    x = traj.cpu().double().numpy()
+    c = coll.cpu().numpy().astype(np.int64)
+    return st, x[:n], x[n:], c[:n], c[n:]
+
+
+@pytest.fixture(scope="module")
+def sweep():
+    probs, tols = W.cfg3()
+    sel = [(p, t) for p, t in zip(probs, tols) if t == 1e-3]
+    res = pkg.mlmc_ap_estimate_batch([p for p, _ in sel], [t for _, t in sel])
+    return sel, res
+
+
+def test_eps_sweep_rmse_1e3(sweep):
+    sel, res = sweep
+    for (p, t), r in zip(sel, res):
+        exact = CF.level_second_moment(p, p["L"])
+        sd = math.sqrt(r["var_estimator"])
+        say("eps %.0e: estimate %.7f exact %.7f sd %.2e N %s" % (p["eps"], r["estimate"], exact,
+                                                                 sd, r["N"]))
+        assert r["converged"] and r["var_estimator"] <= 0.5 * t * t * (1 + 1e-12)
+        assert abs(r["estimate"] - exact) <= 4.0 * sd
+        # the coarse path of every level has the law of the level below
+        for l in range(1, p["L"] + 1):
+            lv = r["levels"][l]
+            e_c = CF.level_second_moment(p, l - 1)
+            sd_c = math.sqrt(lv["m2_qc"] / (lv["n"] - 1) / lv["n"])
+            assert abs(lv["mean_qc"] - e_c) <= 4.5 * sd_c + 1e-12
+
+
+def test_eps_sweep_sampled_trajectories(sweep):
+    """At the sample numbers of the full runs: runs of 256 samples at random
+    offsets of every level against the oracle, one by one."""
+    sel, res = sweep
+    rng = np.random.default_rng(11)
+    for (p, t), r in zip(sel, res):
+        for l in range(p["L"] + 1):
+            N = r["N"][l]
+            for begin in rng.integers(0, max(N - 256, 1), size=2):
+                n = int(min(256, N - begin))
+                st, xf, xc, cf, cc = dump(p, l, int(begin), n)
+                ref = O.simulate(p, l, int(begin), n)
+                assert np.array_equal(cf, ref["cf"].astype(np.int64))
+                assert np.array_equal(cc, ref["cc"].astype(np.int64))
+                # per-trajectory bar: 1e-5 max(|x_oracle|, rms(x_oracle))
+                sf = np.maximum(np.abs(ref["xf"]), math.sqrt(np.mean(ref["xf"] ** 2)))
+                assert np.max(np.abs(xf - ref["xf"]) / sf) <= 1e-5
+                if l >= 1:
+                    sc = np.maximum(np.abs(ref["xc"]), math.sqrt(np.mean(ref["xc"] ** 2)))
+                    assert np.max(np.abs(xc - ref["xc"]) / sc) <= 1e-5
+
+
+@pytest.mark.parametrize("level,n", [(0, 20000), (2, 20000), (5, 8000), (8, 2000), (10, 1000)])
+def test_precision_study_levels(level, n):
+    """FP32 and FP64 particle state against the FP64 oracle on the same
+    samples: per-trajectory error and the error of the level mean."""
+    p32 = dict(W.cfg4(0), qoi=0)
+    p64 = dict(W.cfg4(1), qoi=0)
+    ref = O.simulate(p32, level, 0, n)
+    dq_ref = ref["xf"] ** 2 - (ref["xc"] ** 2 if level else 0.0)
+    sd = math.sqrt(np.var(dq_ref) / n) + 1e-300
+    out = {}
+    worst = {}
+    for name, p, tol in (("fp32", p32, 1e-5), ("fp64", p64, 1e-12)):
+        st, xf, xc, cf, cc = dump(p, level, 0, n)
+        dq = xf ** 2 - (xc ** 2 if level else 0.0)
+        worst[name] = np.max(np.abs(dq - dq_ref))
+        assert np.array_equal(cf, ref["cf"].astype(np.int64))
+        assert np.array_equal(cc, ref["cc"].astype(np.int64))
+        scale = np.maximum(np.abs(ref["xf"]), math.sqrt(np.mean(ref["xf"] ** 2)))
+        err = np.max(np.abs(xf - ref["xf"]) / scale)
+        assert err <= tol, (name, err)
+        out[name] = (st["mean_dq"] - dq_ref.mean(), err)
+    say("level %d: mean dQ error fp32 %.3e fp64 %.3e (standard error %.3e); "
+        "max trajectory error fp32 %.2e fp64 %.2e" % (level, out["fp32"][0], out["fp64"][0], sd,
+                                                     out["fp32"][1], out["fp64"][1]))
+    # FP64 state: rounding only; FP32 state: far below the 1e-3 RMSE target
+    assert abs(out["fp64"][0]) <= worst["fp64"] + 1e-15 <= 1e-10
+    assert abs(out["fp32"][0]) <= worst["fp32"] + 1e-15
+    assert abs(out["fp32"][0]) <= 1e-5
+
+
+def test_precision_study_estimates():
+    """cfg4 MLMC estimates with FP32 and FP64 state: both within 4 standard
+    errors of the exact E[Q_10] = 2.3819542840; histograms sum to N."""
+    tol = 3e-3
+    exact = CF.level_second_moment(W.cfg4(0), 10)
+    assert abs(exact - 2.3819542840) < 1e-9
+    r32 = pkg.mlmc_ap_estimate(W.cfg4(0), tol, hist=True)
+    r64 = pkg.mlmc_ap_estimate(W.cfg4(1), tol, hist=True)
+    for r in (r32, r64):
+        sd = math.sqrt(r["var_estimator"])
+        assert r["converged"] and abs(r["estimate"] - exact) <= 4.0 * sd
+        for l, h in enumerate(r["hist"]):
+            nb = 64
+            assert sum(h[:3 * nb:3]) + h[3 * nb] + h[3 * nb + 1] == r["N"][l]
+    say("cfg4: fp32 %.7f fp64 %.7f exact %.7f sd %.2e" % (r32["estimate"], r64["estimate"], exact,
+                                                           math.sqrt(r32["var_estimator"])))
