@@ -144,7 +144,8 @@ LevelDesc make_desc(const ItemSpec& s) {
   d.key0 = (uint32_t)(p.seed & 0xFFFFFFFFull);
   d.key1 = (uint32_t)(p.seed >> 32);
   d.flags = (coarse ? kFlagCoarse : 0u) | (maxwell ? kFlagMaxwell : 0u) |
-            (agg ? kFlagAggregate : 0u) | (s.hist ? kFlagHist : 0u) | kFlagAccumulate;
+            (agg ? kFlagAggregate : 0u) | (s.hist ? kFlagHist : 0u) |
+            (s.accumulate ? kFlagAccumulate : 0u);
   if (d.thr_f == 0 || d.thr_c2 == 0) d.flags |= kFlagWide;
   d.kind = coarse ? (maxwell ? (agg ? kKindPairMaxwellAggregate : kKindPairMaxwellSum)
                              : kKindPairTwoPointSum)
@@ -204,38 +205,52 @@ static mlmc_ap_status grow_dev(T*& p, size_t& cap, size_t need) {
   return MLMC_AP_OK;
 }
 
+// Pinned host memory that kernels read and write directly (fine-grained, so
+// no GPU cache holds a stale copy between launches); `dp` is its device
+// address.
 template <typename T>
-static mlmc_ap_status grow_pinned(T*& p, size_t cap_old, size_t cap_new) {
+static mlmc_ap_status grow_pinned(T*& p, T*& dp, size_t cap_old, size_t cap_new) {
   if (p && cap_old >= cap_new) return MLMC_AP_OK;
   if (p) (void)hipHostFree(p);
   p = nullptr;
-  if (hipHostMalloc((void**)&p, cap_new * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+  dp = nullptr;
+  if (hipHostMalloc((void**)&p, cap_new * sizeof(T), hipHostMallocCoherent) != hipSuccess) {
     (void)hipGetLastError();
+    p = nullptr;
     return set_error(MLMC_AP_ENOMEM, "hipHostMalloc failed");
+  }
+  if (hipHostGetDevicePointer((void**)&dp, p, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(p);
+    p = nullptr;
+    dp = nullptr;
+    return set_error(MLMC_AP_EDEVICE, "hipHostGetDevicePointer failed");
   }
   return MLMC_AP_OK;
 }
 
 mlmc_ap_status Workspace::ensure(size_t n_items, size_t n_tiles, size_t n_groups,
                                  size_t n_slots, size_t n_hist) {
-  const void* before[5] = {items_dev, partials, groups, resident, hist_dev};
-  if (n_items > items_cap || !items_dev) {
+  const void* before[7] = {items_dev, partials, groups, resident, hist_dev, items_host_dev,
+                           resident_host_dev};
+  if (n_items > items_cap || !items_dev || !items_host) {
     MLMC_TRY(grow_dev(items_dev, items_cap, n_items));
-    MLMC_TRY(grow_pinned(items_host, 0, items_cap));
+    MLMC_TRY(grow_pinned(items_host, items_host_dev, 0, items_cap));
   }
   if (!hdr_dev) {
     MLMC_HIP(hipMalloc((void**)&hdr_dev, sizeof(WorkHeader)));
-    MLMC_HIP(hipHostMalloc((void**)&hdr_host, sizeof(WorkHeader), hipHostMallocDefault));
     MLMC_HIP(hipMalloc((void**)&counter_dev, 64));
   }
+  if (!hdr_host) MLMC_TRY(grow_pinned(hdr_host, hdr_host_dev, 0, 1));
   MLMC_TRY(grow_dev(partials, partials_cap, std::max<size_t>(n_tiles, 1)));
   MLMC_TRY(grow_dev(groups, groups_cap, std::max<size_t>(n_groups, 1)));
-  if (n_slots > resident_cap || !resident) {
+  if (n_slots > resident_cap || !resident || !resident_host) {
     MLMC_TRY(grow_dev(resident, resident_cap, std::max<size_t>(n_slots, 1)));
-    MLMC_TRY(grow_pinned(resident_host, 0, resident_cap));
+    MLMC_TRY(grow_pinned(resident_host, resident_host_dev, 0, resident_cap));
   }
   MLMC_TRY(grow_dev(hist_dev, hist_cap, std::max<size_t>(n_hist, 1)));
-  const void* after[5] = {items_dev, partials, groups, resident, hist_dev};
+  const void* after[7] = {items_dev, partials, groups, resident, hist_dev, items_host_dev,
+                          resident_host_dev};
   if (std::memcmp(before, after, sizeof(before)) != 0) graph_key = 0;  // recapture
   return MLMC_AP_OK;
 }
@@ -257,6 +272,7 @@ void Workspace::release() {
   items_dev = nullptr; items_host = nullptr; hdr_dev = nullptr; hdr_host = nullptr;
   counter_dev = nullptr; partials = nullptr; groups = nullptr; resident = nullptr;
   resident_host = nullptr; hist_dev = nullptr;
+  items_host_dev = nullptr; hdr_host_dev = nullptr; resident_host_dev = nullptr;
   items_cap = partials_cap = groups_cap = resident_cap = hist_cap = 0;
 }
 
@@ -332,13 +348,26 @@ static mlmc_ap_status check_tuning(const mlmc_ap_tuning& t) {
 static const int kReduceGridGroups = 1024;
 static const int kReduceGridItems = 256;
 
+static mlmc_ap_status stage(Workspace& ws, hipStream_t s) {
+  MLMC_HIP(launch_stage(ws.hdr_host_dev, ws.items_host_dev, (uint32_t)ws.items_cap, ws.hdr_dev,
+                        ws.items_dev, ws.counter_dev, s));
+  return MLMC_AP_OK;
+}
+
+static mlmc_ap_status reduce(Workspace& ws, hipStream_t s) {
+  MLMC_HIP(launch_reduce(ws.items_dev, ws.hdr_dev, ws.partials, ws.groups, ws.resident,
+                         ws.resident_host_dev, kReduceGridGroups, kReduceGridItems, s));
+  return MLMC_AP_OK;
+}
+
+// The whole launch as one stream of kernels: stage the table, simulate,
+// reduce (the host mirror of the resident slots is written by the last one).
 static mlmc_ap_status record_device_work(Workspace& ws, bool fp64, const mlmc_ap_tuning& t,
                                          hipStream_t s) {
-  MLMC_HIP(launch_fill_u32(ws.counter_dev, 1, 0u, s));
+  MLMC_TRY(stage(ws, s));
   MLMC_HIP(launch_persistent(fp64, t.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev, ws.partials,
                              t.block, persistent_grid(ws, t), s));
-  MLMC_HIP(launch_reduce(ws.items_dev, ws.hdr_dev, ws.partials, ws.groups, ws.resident,
-                         kReduceGridGroups, kReduceGridItems, s));
+  MLMC_TRY(reduce(ws, s));
   return MLMC_AP_OK;
 }
 
@@ -376,28 +405,23 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
   ws.hdr_host->pad = 0;
 
   MLMC_HIP(hipEventRecord(ws.ev[0], stream));
-  MLMC_HIP(hipMemcpyAsync(ws.items_dev, ws.items_host, d.size() * sizeof(LevelDesc),
-                          hipMemcpyHostToDevice, stream));
-  MLMC_HIP(hipMemcpyAsync(ws.hdr_dev, ws.hdr_host, sizeof(WorkHeader), hipMemcpyHostToDevice,
-                          stream));
   bool kernel_timed = false;
   if (mode == 0) {
+    MLMC_TRY(stage(ws, stream));
     MLMC_HIP(hipEventRecord(ws.ev[1], stream));
     for (size_t i = 0; i < d.size(); ++i)
       MLMC_HIP(launch_level(fp64, tuning.ppt, d[i].kind, ws.items_dev, (uint32_t)i, d[i].n_tiles,
                             tuning.block, ws.partials, stream));
     MLMC_HIP(hipEventRecord(ws.ev[2], stream));
-    MLMC_HIP(launch_reduce(ws.items_dev, ws.hdr_dev, ws.partials, ws.groups, ws.resident,
-                           kReduceGridGroups, kReduceGridItems, stream));
+    MLMC_TRY(reduce(ws, stream));
     kernel_timed = true;
   } else if (mode == 2) {
-    MLMC_HIP(launch_fill_u32(ws.counter_dev, 1, 0u, stream));
+    MLMC_TRY(stage(ws, stream));
     MLMC_HIP(hipEventRecord(ws.ev[1], stream));
     MLMC_HIP(launch_persistent(fp64, tuning.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev,
                                ws.partials, tuning.block, persistent_grid(ws, tuning), stream));
     MLMC_HIP(hipEventRecord(ws.ev[2], stream));
-    MLMC_HIP(launch_reduce(ws.items_dev, ws.hdr_dev, ws.partials, ws.groups, ws.resident,
-                           kReduceGridGroups, kReduceGridItems, stream));
+    MLMC_TRY(reduce(ws, stream));
     kernel_timed = true;
   } else {
     const uint64_t key = ((uint64_t)tuning.block << 48) ^ ((uint64_t)tuning.ppt << 40) ^
@@ -423,8 +447,6 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
     }
     MLMC_HIP(hipGraphLaunch(ws.graph, stream));
   }
-  MLMC_HIP(hipMemcpyAsync(ws.resident_host, ws.resident, n_slots * sizeof(Stats),
-                          hipMemcpyDeviceToHost, stream));
   MLMC_HIP(hipEventRecord(ws.ev[3], stream));
   MLMC_HIP(hipStreamSynchronize(stream));
   if (timing) {
@@ -482,6 +504,7 @@ bool McRequest::plan(std::vector<ItemSpec>& items, uint32_t slot_base,
     s.hist = hist_base ? hist_base + (size_t)l * hist_stride : nullptr;
     s.traj = nullptr;
     s.coll = nullptr;
+    s.accumulate = done[l] > 0;  // the slot holds samples [0, done[l])
     items.push_back(s);
     any = true;
   }
@@ -582,10 +605,9 @@ mlmc_ap_status run_requests(Workspace& ws, std::vector<McRequest>& reqs, int mod
                             unsigned long long* hist_dev, size_t hist_stride) {
   const size_t n_slots = reqs.size() * MLMC_AP_MAX_LEVELS;
   MLMC_TRY(ws.ensure(1, 1, 1, n_slots, 0));
-  std::vector<Stats> empty(n_slots, stats_empty());
-  MLMC_HIP(hipMemcpyAsync(ws.resident, empty.data(), n_slots * sizeof(Stats),
-                          hipMemcpyHostToDevice, stream));
-  MLMC_HIP(hipStreamSynchronize(stream));
+  // A slot's first launch overwrites it on the device; the host mirror of the
+  // slots no launch has written yet reads as empty.
+  for (size_t i = 0; i < n_slots; ++i) ws.resident_host[i] = stats_empty();
   for (int guard = 0; guard < 100000; ++guard) {
     std::vector<ItemSpec> items;
     std::vector<size_t> owners;
@@ -711,9 +733,6 @@ mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, i
   }
   const size_t hist_n = hist ? 3 * (size_t)p->nbins + 4 : 0;
   MLMC_TRY(ws->ensure(1, 1, 1, 1, hist_n));
-  const Stats e = stats_empty();
-  MLMC_HIP(hipMemcpyAsync(ws->resident, &e, sizeof(Stats), hipMemcpyHostToDevice, s));
-  MLMC_HIP(hipStreamSynchronize(s));
   if (hist) MLMC_HIP(launch_fill_u64(ws->hist_dev, hist_n, 0ull, s));
   ItemSpec it;
   it.prob = p;
@@ -725,6 +744,7 @@ mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, i
   it.hist = hist ? ws->hist_dev : nullptr;
   it.traj = traj_dev;
   it.coll = coll_dev;
+  it.accumulate = false;
   const mlmc_ap_tuning t = resolve_tuning(*ws, nullptr);
   MLMC_TRY(run_table(*ws, std::vector<ItemSpec>{it}, 1, 0, t, s, nullptr));
   *out_host = stats_to_api(ws->resident_host[0]);

@@ -53,6 +53,7 @@ struct ItemSpec {
   unsigned long long* hist;  // device histogram counters or null
   void* traj;
   uint32_t* coll;
+  bool accumulate = true;    // merge into the result slot (else overwrite it)
 };
 
 LevelDesc make_desc(const ItemSpec& s);
@@ -67,18 +68,22 @@ struct Workspace {
   hipStream_t capture_stream = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 
+  // *_host: pinned host memory the kernels access directly at *_host_dev
   LevelDesc* items_dev = nullptr;
   LevelDesc* items_host = nullptr;
+  LevelDesc* items_host_dev = nullptr;
   size_t items_cap = 0;
   WorkHeader* hdr_dev = nullptr;
   WorkHeader* hdr_host = nullptr;
+  WorkHeader* hdr_host_dev = nullptr;
   unsigned int* counter_dev = nullptr;
   Stats* partials = nullptr;
   size_t partials_cap = 0;  // tiles
   Stats* groups = nullptr;
   size_t groups_cap = 0;
   Stats* resident = nullptr;
-  Stats* resident_host = nullptr;
+  Stats* resident_host = nullptr;  // written by the item reduction
+  Stats* resident_host_dev = nullptr;
   size_t resident_cap = 0;  // slots
   unsigned long long* hist_dev = nullptr;
   size_t hist_cap = 0;      // counters

@@ -11,6 +11,10 @@
 // Per fine step (asymptotic-preserving splitting, fixed dt), from three words
 // of the trajectory's Philox word stream (decision, radius, angle):
 //   x <- x + h v + s xi;  collide iff decision word < thr  ->  v <- equilibrium draw.
+// Positions never feed back into the dynamics, so with FP32 state the
+// increments of 16 steps are summed on their own and added to x by a
+// compensated (Fast2Sum) update: the position then carries about one rounding
+// of its own size instead of two per step.
 // Coarse path (levels >= 1), one coarse step per block of M fine steps, built
 // from the fine random numbers of that block (Section 3.1 mapping by time of
 // action; Section 3.2 aggregation):
@@ -42,6 +46,7 @@ struct Lane {
   static constexpr bool kMaxwell = KIND == kKindFineMaxwell || KIND == kKindPairMaxwellSum ||
                                    KIND == kKindPairMaxwellAggregate;
   static constexpr bool kAgg = KIND == kKindPairMaxwellAggregate;
+  static constexpr bool kCompensate = sizeof(Real) == 4;
 
   Real h_f, s_f, h_c, s_c, agg_ms2, h_f2, rsqrt_m;
   uint32_t thr_f_m1, thr_c2_m1;
@@ -50,6 +55,7 @@ struct Lane {
 
   uint32_t smp[P];
   Real xf[P], vf[P], xc[P], vc[P];
+  Real af[P], ef[P], ac[P], ec[P];  // group increments and compensation terms
   uint32_t cf[P], cc[P];
   Real sum_xi[P], num[P], den[P], lnu[P], uses[P], have[P];
   uint32_t wmin[P];
@@ -103,6 +109,7 @@ struct Lane {
       }
       const Real v0 = kMaxwell ? ns : sign_of(w.w1);
       xf[p] = x0; vf[p] = v0; xc[p] = x0; vc[p] = v0;
+      af[p] = Real(0); ef[p] = Real(0); ac[p] = Real(0); ec[p] = Real(0);
       cf[p] = 0u; cc[p] = 0u;
     }
     reset_block();
@@ -116,7 +123,10 @@ struct Lane {
     box_muller(wa, wb, xi, g);
     Real vnew = kMaxwell ? g : sign_of(wb);
     keep(vnew);  // computed unconditionally: the select below stays branch-free
-    xf[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, vf[p], xf[p]));
+    if constexpr (kCompensate)
+      af[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, vf[p], af[p]));
+    else
+      xf[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, vf[p], xf[p]));
     const bool hit = below<WIDE>(wd, thr_f_m1, thr_f);
     vf[p] = hit ? vnew : vf[p];
     cf[p] += hit ? 1u : 0u;
@@ -153,11 +163,41 @@ struct Lane {
       } else {
         kick = sum_xi[p] * rsqrt_m;
       }
-      xc[p] = fma_r<Real>(s_c, kick, fma_r<Real>(h_c, vc[p], xc[p]));
+      if constexpr (kCompensate)
+        ac[p] = fma_r<Real>(s_c, kick, fma_r<Real>(h_c, vc[p], ac[p]));
+      else
+        xc[p] = fma_r<Real>(s_c, kick, fma_r<Real>(h_c, vc[p], xc[p]));
       vc[p] = chit ? vf[p] : vc[p];
       cc[p] += chit ? 1u : 0u;
     }
     reset_block();
+  }
+
+  // x + a as the pair (t, e + ((x - t) + a)) with t = x + a (Fast2Sum: exact
+  // when |x| >= |a|; otherwise wrong by at most a rounding of a).
+  __device__ __forceinline__ static void fold(Real& x, Real& e, Real& a) {
+    const Real t = x + a;
+    e += (x - t) + a;
+    x = t;
+    a = Real(0);
+  }
+
+  __device__ __forceinline__ void fold_all() {
+    if constexpr (kCompensate) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        fold(xf[p], ef[p], af[p]);
+        if constexpr (kCoarse) fold(xc[p], ec[p], ac[p]);
+      }
+    }
+  }
+
+  // Final positions (after run()).
+  __device__ __forceinline__ Real pos_f(int p) const {
+    return kCompensate ? xf[p] + ef[p] : xf[p];
+  }
+  __device__ __forceinline__ Real pos_c(int p) const {
+    return kCompensate ? xc[p] + ec[p] : xc[p];
   }
 
   // After a fine step: the coarse step when a block of M fine steps is
@@ -234,19 +274,30 @@ struct Lane {
     uint32_t b = init(d);
     const uint32_t n_steps = d.n_steps;
     uint32_t n = 0;
+    // increments are folded into the positions every 16 steps and at the end
     if (!kCoarse || M == 2) {
 #pragma unroll 1
-      for (; n + 4 <= n_steps; n += 4, b += 3) group4<2>(b);
+      for (; n + 4 <= n_steps; n += 4, b += 3) {
+        group4<2>(b);
+        if ((n & 12) == 12) fold_all();
+      }
     } else if (M == 4) {
 #pragma unroll 1
-      for (; n + 4 <= n_steps; n += 4, b += 3) group4<4>(b);
+      for (; n + 4 <= n_steps; n += 4, b += 3) {
+        group4<4>(b);
+        if ((n & 12) == 12) fold_all();
+      }
     } else {
 #pragma unroll 1
-      for (; n + 4 <= n_steps; n += 4, b += 3) group4<0>(b);
+      for (; n + 4 <= n_steps; n += 4, b += 3) {
+        group4<0>(b);
+        if ((n & 12) == 12) fold_all();
+      }
     }
     // blocks of M in {2, 4} end on group boundaries, so the run-time
     // counter starts the tail at zero
     if (n < n_steps) group_tail(b, n_steps - n);
+    fold_all();
   }
 };
 
@@ -278,8 +329,12 @@ __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
       st.smp[p] = (uint32_t)(d.sample_begin + local[p]);
     }
     st.run(d);
-    auto& xf = st.xf;
-    auto& xc = st.xc;
+    Real xf[P], xc[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      xf[p] = st.pos_f(p);
+      xc[p] = st.pos_c(p);
+    }
     auto& cf = st.cf;
     auto& cc = st.cc;
 
@@ -443,10 +498,11 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Reductions.  Stage 1: group g of an item merges tiles [4096 g, 4096 g +
-// 4096): thread t merges its 16 consecutive tiles in order, then a fixed LDS
+// Reductions.  Stage 1: group g of an item merges tiles [1024 g, 1024 g +
+// 1024): thread t merges its 4 consecutive tiles in order, then a fixed LDS
 // tree.  Stage 2: one block per item merges the item's group results the
-// same way and folds the result into the item's resident statistics slot.
+// same way (thread t merges groups [t q, t q + q), q = ceil(n_groups / 256))
+// and folds the result into the item's resident statistics slot.
 // ---------------------------------------------------------------------------
 // Fixed LDS tree over the block's 256 records; the result is left in sh[0].
 __device__ __forceinline__ void block_tree(const Stats& acc, Stats* sh) {
@@ -489,25 +545,50 @@ __global__ void __launch_bounds__(kReduceThreads) reduce_groups_kernel(
 
 __global__ void __launch_bounds__(kReduceThreads) reduce_items_kernel(
     const LevelDesc* __restrict__ items, const WorkHeader* __restrict__ hdr,
-    const Stats* __restrict__ groups, Stats* __restrict__ resident) {
+    const Stats* __restrict__ groups, Stats* __restrict__ resident, Stats* __restrict__ mirror) {
   __shared__ Stats sh[kReduceThreads];
   const uint32_t n_items = hdr->n_items;
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const uint64_t gbase = items[it].group_base;
     const uint32_t n_groups = items[it].n_groups;
     Stats acc = stats_empty();
-    const uint32_t first = threadIdx.x * kReducePerThread;
-    for (int k = 0; k < kReducePerThread; ++k) {
-      const uint32_t idx = first + k;
-      if (idx < n_groups) acc = stats_merge(acc, groups[gbase + idx]);
-    }
+    const uint32_t q = (n_groups + kReduceThreads - 1) / kReduceThreads;
+    const uint32_t first = threadIdx.x * q;
+    for (uint32_t idx = first; idx < n_groups && idx < first + q; ++idx)
+      acc = stats_merge(acc, groups[gbase + idx]);
     block_tree(acc, sh);
     if (threadIdx.x == 0) {
       const uint32_t slot = items[it].result_slot;
-      resident[slot] = (items[it].flags & kFlagAccumulate) ? stats_merge(resident[slot], sh[0])
+      const Stats r = (items[it].flags & kFlagAccumulate) ? stats_merge(resident[slot], sh[0])
                                                           : sh[0];
+      resident[slot] = r;
+      if (mirror) mirror[slot] = r;  // host-mapped copy, read after the stream syncs
     }
     __syncthreads();
+  }
+}
+
+// First node of every launch: copies the work table and its header from
+// host-mapped pinned memory (written by the host before the launch) into
+// device memory and clears the chunk counter, so one launch needs no copy
+// commands.  At most `cap` descriptors are copied.
+__global__ void stage_kernel(const WorkHeader* __restrict__ hdr_src,
+                             const LevelDesc* __restrict__ items_src, uint32_t cap,
+                             WorkHeader* __restrict__ hdr_dst, LevelDesc* __restrict__ items_dst,
+                             unsigned int* __restrict__ counter) {
+  static_assert(sizeof(LevelDesc) % sizeof(uint4) == 0, "descriptor copy granularity");
+  const uint32_t n_items = min(hdr_src->n_items, cap);
+  const uint64_t words = (uint64_t)n_items * (sizeof(LevelDesc) / sizeof(uint4));
+  const uint4* src = reinterpret_cast<const uint4*>(items_src);
+  uint4* dst = reinterpret_cast<uint4*>(items_dst);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    WorkHeader h = *hdr_src;
+    h.n_items = n_items;
+    *hdr_dst = h;
+    *counter = 0u;
   }
 }
 
@@ -626,14 +707,22 @@ hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
 }
 
 hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev,
-                         const Stats* partials, Stats* groups, Stats* resident, int grid_groups,
-                         int grid_items, hipStream_t s) {
+                         const Stats* partials, Stats* groups, Stats* resident, Stats* mirror,
+                         int grid_groups, int grid_items, hipStream_t s) {
   hipLaunchKernelGGL(reduce_groups_kernel, dim3(grid_groups), dim3(kReduceThreads), 0, s,
                      items_dev, hdr_dev, partials, groups);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reduce_items_kernel, dim3(grid_items), dim3(kReduceThreads), 0, s,
-                     items_dev, hdr_dev, groups, resident);
+                     items_dev, hdr_dev, groups, resident, mirror);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(const WorkHeader* hdr_src, const LevelDesc* items_src, uint32_t cap,
+                        WorkHeader* hdr_dst, LevelDesc* items_dst, unsigned int* counter,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(stage_kernel, dim3(16), dim3(256), 0, s, hdr_src, items_src, cap, hdr_dst,
+                     items_dst, counter);
   return hipGetLastError();
 }
 

@@ -21,9 +21,16 @@ hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev
 hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
                              const WorkHeader* hdr_dev, unsigned int* counter, Stats* partials,
                              int block, int grid, hipStream_t s);
+// Tile records -> group records -> resident slots; `mirror` (host-mapped
+// pinned memory, or null) receives a copy of every slot written.
 hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev,
-                         const Stats* partials, Stats* groups, Stats* resident, int grid_groups,
-                         int grid_items, hipStream_t s);
+                         const Stats* partials, Stats* groups, Stats* resident, Stats* mirror,
+                         int grid_groups, int grid_items, hipStream_t s);
+// Work table and header from host-mapped pinned memory to the device; clears
+// the persistent kernel's chunk counter.
+hipError_t launch_stage(const WorkHeader* hdr_src, const LevelDesc* items_src, uint32_t cap,
+                        WorkHeader* hdr_dst, LevelDesc* items_dst, unsigned int* counter,
+                        hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, uint64_t n, unsigned int v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_words(uint32_t key0, uint32_t key1, uint32_t strm, uint32_t tag,

@@ -117,11 +117,10 @@ mlmc_ap_status mlmc_ap_server::tick(int32_t* n_completed, std::vector<uint64_t>*
     stats.bytes_reserved += state_bytes();
     stats.admitted++;
     used += b;
-    // fresh statistics for the new request's slots
-    std::vector<Stats> empty(MLMC_AP_MAX_LEVELS, stats_empty());
-    MLMC_HIP(hipMemcpyAsync(ws.resident + (size_t)r->region * MLMC_AP_MAX_LEVELS, empty.data(),
-                            empty.size() * sizeof(Stats), hipMemcpyHostToDevice, stream));
-    MLMC_HIP(hipStreamSynchronize(stream));
+    // fresh statistics for the new request's slots: its first launch of a
+    // level overwrites the device slot; the host mirror starts empty
+    for (int l = 0; l < MLMC_AP_MAX_LEVELS; ++l)
+      ws.resident_host[(size_t)r->region * MLMC_AP_MAX_LEVELS + l] = stats_empty();
     active.push_back(r);
     std::vector<ItemSpec> mine;
     if (r->mc.plan(mine, (uint32_t)(r->region * MLMC_AP_MAX_LEVELS), nullptr, 0)) {

@@ -5,7 +5,7 @@
 // with spl = 4 for levels of fewer than 64 fine steps and spl = 1 above (so
 // that one wavefront's serial work per tile stays short on the long levels).
 // Every tile is reduced by one wavefront into a Stats record, and the records
-// of an item are merged by a fixed tree (groups of 4096 tiles, then one group
+// of an item are merged by a fixed tree (groups of 1024 tiles, then one group
 // result per item).  The tile size is a function of the level and the tree a
 // function of the item's sample count, so the statistics are bitwise
 // independent of launch shape, tuning, and of other items sharing a launch.
@@ -16,17 +16,24 @@
 namespace mlmc {
 
 constexpr int kLanes = 64;                       // gfx950 wavefront
-constexpr int kMaxSamplesPerLane = 4;            // short levels: 256-sample tiles
+constexpr int kMaxSamplesPerLane = 16;           // shortest levels: 1024-sample tiles
+constexpr uint32_t kShortLevelSteps = 16;        // from here on: 256-sample tiles
 constexpr uint32_t kLongLevelSteps = 64;         // from here on: 64-sample tiles
 
-// Samples per lane of a tile of a level with n_steps fine steps.
+// Samples per lane of a tile of a level with n_steps fine steps: the tile's
+// closing wave reduction is spread over more samples where trajectories are
+// short, and long trajectories keep one sample per lane.
 __host__ __device__ inline uint32_t samples_per_lane(uint32_t n_steps) {
-  return n_steps >= kLongLevelSteps ? 1u : (uint32_t)kMaxSamplesPerLane;
+  return n_steps >= kLongLevelSteps ? 1u : (n_steps >= kShortLevelSteps ? 4u : 16u);
 }
-constexpr int kGroupTiles = 4096;                // tiles per first-stage group
+constexpr int kGroupTiles = 1024;                // tiles per first-stage group
 constexpr int kReduceThreads = 256;
-constexpr int kReducePerThread = kGroupTiles / kReduceThreads;  // 16
-constexpr uint64_t kMaxTilesPerItem = (uint64_t)kGroupTiles * kGroupTiles;  // 2^24
+constexpr int kReducePerThread = kGroupTiles / kReduceThreads;  // 4
+// An item holds at most 2^32 samples (the sample counter word), so at most
+// 2^26 tiles and 2^16 groups.
+constexpr uint64_t kMaxGroupsPerItem = 1ull << 16;
+static_assert((uint64_t)kGroupTiles * kMaxGroupsPerItem * kLanes >= (1ull << 32),
+              "an item of 2^32 samples must fit the two-stage reduction");
 
 // Work item flags.
 enum : uint32_t {

@@ -166,11 +166,12 @@ def test_wide_thresholds_used():
     assert c["thr_f"] == 0
 
 
-@pytest.mark.parametrize("level,n", [(0, 1), (0, 255), (0, 256), (0, 257), (0, 4097 * 256 + 3),
-                                     (5, 63), (5, 65), (5, 4097 * 64 + 3)])
+@pytest.mark.parametrize("level,n", [(0, 1), (0, 1023), (0, 1024), (0, 1025), (0, 1025 * 1024 + 3),
+                                     (4, 255), (4, 257), (4, 1025 * 256 + 3),
+                                     (5, 63), (5, 65), (5, 1025 * 64 + 3)])
 def test_tile_and_group_boundaries(level, n):
-    """Ragged tiles (256 samples below 64 fine steps, 64 from there on) and
-    more than one 4096-tile reduction group."""
+    """Ragged tiles (1024 samples below 16 fine steps, 256 below 64, 64 from
+    there on) and more than one 1024-tile reduction group."""
     prob = W.cfg2(eps=0.3)
     st = pkg.mlmc_ap_simulate_level(prob, level, 5, n)
     ref = O.simulate(prob, level, 5, n)
