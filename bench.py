@@ -28,8 +28,7 @@ sys.path.insert(0, ROOT)
 # Algorithmic VALU issue cost of the method, in full-rate lane-slots (one
 # slot = one lane of one full-rate VALU instruction): full-rate ops 1 slot,
 # 32x32->64-bit integer multiplies 2, transcendentals 4 (weights from the
-# measured gfx950 issue rates).  The instruction inventory is in the design doc
-# ("Roofline").
+# measured gfx950 issue rates), per unit of the method as listed below.
 SLOTS_PHILOX_BLOCK = 50.0   # 16 lane-varying 64-bit products (2) + 18 three-input xors (1)
 SLOTS_NORMAL_PAIR = 23.0    # two uniforms (4) + log, sqrt, sin, cos (16) + 3 multiplies
 SLOTS_FINE_MOVE = 5.0       # move (2 FMA) + collision compare, select, count
@@ -152,9 +151,9 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the estimator shards by sample ranges with one "
-              "statistics merge per iteration, which this build does not run across GPUs "
-              "(see DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the estimator would shard by sample ranges with "
+              "one statistics merge per iteration, which is not implemented across GPUs; "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -140,12 +140,18 @@ typedef struct mlmc_ap_level_info {
 } mlmc_ap_level_info;
 
 /* Tuning of the particle kernels; zero fields select the defaults (or the
- * autotuner's cached choice).  Results never depend on it. */
+ * autotuner's cached choice).  Results never depend on it: the
+ * time-parallel path (one trajectory per wavefront, its fine steps spread
+ * over the lanes; for few long trajectories such as a warm-up) repeats the
+ * per-lane arithmetic in the same order and gives bitwise identical
+ * trajectories and statistics. */
 typedef struct mlmc_ap_tuning {
     int32_t block;          /* threads per block: 64, 128 or 256 */
     int32_t ppt;            /* trajectories in flight per thread: 1, 2 or 4 */
     int32_t waves_per_simd; /* persistent grid occupancy target, 1..8 */
-    int32_t reserved;
+    int32_t tp_max_samples; /* time-parallel path for work items of at most this
+                               many samples with >= 64 fine steps (pairs: M = 2
+                               or 4); 0 = 4096, < 0 = never */
 } mlmc_ap_tuning;
 
 typedef struct mlmc_ap_options {
@@ -269,6 +275,11 @@ mlmc_ap_status mlmc_ap_estimate_batch(const mlmc_ap_problem* p, const double* rm
  * the default tuning of the current device.  Results never depend on it. */
 mlmc_ap_status mlmc_ap_autotune(const mlmc_ap_problem* p, double rmse_tol,
                                 const char* cache_path, mlmc_ap_tuning* out_host, void* stream);
+
+/* Sets the default tuning of the current device (what estimates without
+ * an explicit tuning, mlmc_ap_simulate_level and new servers use); zero
+ * fields keep the current value.  EINVAL for an invalid shape. */
+mlmc_ap_status mlmc_ap_set_tuning(const mlmc_ap_tuning* tuning_host);
 
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of MLMC requests.                         */

@@ -57,7 +57,7 @@ class LevelInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("ppt", ctypes.c_int32),
-                ("waves_per_simd", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("waves_per_simd", ctypes.c_int32), ("tp_max_samples", ctypes.c_int32)]
 
 
 class Options(ctypes.Structure):
@@ -111,6 +111,7 @@ _SIGNATURES = {
     "mlmc_ap_estimate_batch": [_P(Problem), _P(ctypes.c_double), ctypes.c_int32, _P(Options),
                                _P(Result), _vp],
     "mlmc_ap_autotune": [_P(Problem), ctypes.c_double, ctypes.c_char_p, _P(Tuning), _vp],
+    "mlmc_ap_set_tuning": [_P(Tuning)],
     "mlmc_ap_server_create": [_P(ServerConfig), _P(_vp)],
     "mlmc_ap_server_destroy": [_vp],
     "mlmc_ap_server_submit": [_vp, _P(Problem), ctypes.c_double, _P(ctypes.c_uint64)],
@@ -136,8 +137,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libmlmc_ap.so is not built (%s); run __graft_entry__.build()"
-                               % LIB_PATH)
+            raise RuntimeError("libmlmc_ap.so is not built (%s); run "
+                               "python -m paper_2004_04071_amd.build" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
         for name, args in _SIGNATURES.items():
             f = getattr(L, name)
@@ -211,9 +212,11 @@ def result_dict(r):
                 seconds=r.seconds, gpu_seconds=r.gpu_seconds, kernel_seconds=r.kernel_seconds)
 
 
-def options(batched=1, max_iter=0, n_warmup=0, block=0, ppt=0, waves_per_simd=0):
+def options(batched=1, max_iter=0, n_warmup=0, block=0, ppt=0, waves_per_simd=0,
+            tp_max_samples=0):
     return Options(batched=batched, max_iter=max_iter, n_warmup=n_warmup,
-                   tuning=Tuning(block=block, ppt=ppt, waves_per_simd=waves_per_simd, reserved=0))
+                   tuning=Tuning(block=block, ppt=ppt, waves_per_simd=waves_per_simd,
+                                 tp_max_samples=tp_max_samples))
 
 
 # ---------------------------------------------------------------------------
@@ -332,6 +335,13 @@ def mlmc_ap_autotune(p, rmse_tol, cache_path=None, stream=None):
                                   cache_path.encode() if cache_path else None, ctypes.byref(out),
                                   _stream(stream)), "mlmc_ap_autotune")
     return dict(block=out.block, ppt=out.ppt, waves_per_simd=out.waves_per_simd)
+
+
+def mlmc_ap_set_tuning(block=0, ppt=0, waves_per_simd=0, tp_max_samples=0):
+    """Default tuning of the current device; zero arguments keep the current
+    value (tp_max_samples < 0 switches the time-parallel path off)."""
+    t = Tuning(block=block, ppt=ppt, waves_per_simd=waves_per_simd, tp_max_samples=tp_max_samples)
+    _check(lib().mlmc_ap_set_tuning(ctypes.byref(t)), "mlmc_ap_set_tuning")
 
 
 def mlmc_ap_server_create(hbm_budget_bytes=0, max_samples_per_tick=0, max_active=0, opt=None):

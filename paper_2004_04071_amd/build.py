@@ -21,8 +21,11 @@ ARCH = "gfx950"
 
 FLAGS = [
     "-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
-    # no packed FP32 instructions (build flags)
+    # no packed FP32 instructions: the compiler must not emit v_pk_*_f32
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # every fused multiply-add is written out (fma_r): the one-trajectory-per-lane
+    # loop and the time-parallel path must round identically
+    "-ffp-contract=off",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wall", "-Wno-unused-result",
 ]

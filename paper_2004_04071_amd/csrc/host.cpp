@@ -107,7 +107,42 @@ mlmc_ap_status validate_problem(const mlmc_ap_problem* p) {
   return MLMC_AP_OK;
 }
 
-LevelDesc make_desc(const ItemSpec& s) {
+bool time_parallel_candidate(const ItemSpec& s, int32_t tp_max_samples) {
+  const mlmc_ap_problem& p = *s.prob;
+  const int64_t limit = tp_max_samples == 0 ? kTpDefaultMaxSamples : tp_max_samples;
+  if (limit <= 0 || s.n_samples == 0 || s.n_samples > (uint64_t)limit) return false;
+  const bool coarse = !s.single && s.level >= 1;
+  if (coarse && p.M != 2 && p.M != 4) return false;  // coarse blocks inside a 64-step chunk
+  return level_const(p, s.level).n_steps >= (int64_t)kLongLevelSteps;
+}
+
+std::vector<bool> choose_time_parallel(const std::vector<ItemSpec>& specs,
+                                       int32_t tp_max_samples) {
+  std::vector<bool> tp(specs.size(), false);
+  std::vector<std::pair<int64_t, size_t>> cand;  // (fine steps, index)
+  for (size_t i = 0; i < specs.size(); ++i)
+    if (time_parallel_candidate(specs[i], tp_max_samples))
+      cand.push_back({level_const(*specs[i].prob, specs[i].level).n_steps, i});
+  if (cand.empty()) return tp;
+  std::stable_sort(cand.begin(), cand.end(),
+                   [](const auto& a, const auto& b) { return a.first > b.first; });
+  // The one-trajectory-per-lane loop needs about (longest n_steps) x 50
+  // wavefront instructions of latency however few its samples; the
+  // time-parallel path costs about 8 instructions per trajectory step spread
+  // over the whole GPU.  Take the longest candidates while their time-parallel
+  // work stays below that latency.
+  const double budget = (double)cand.front().first * (double)kTpStepsPerLongestStep;
+  double used = 0.0;
+  for (const auto& c : cand) {
+    const double w = (double)specs[c.second].n_samples * (double)c.first;
+    if (used + w > budget) break;
+    used += w;
+    tp[c.second] = true;
+  }
+  return tp;
+}
+
+LevelDesc make_desc(const ItemSpec& s, bool tp) {
   const mlmc_ap_problem& p = *s.prob;
   const bool coarse = !s.single && s.level >= 1;
   const LevelConst F = level_const(p, s.level);
@@ -160,6 +195,10 @@ LevelDesc make_desc(const ItemSpec& s) {
   if (ct > 64) ct = 64;
   d.chunk_tiles = (uint32_t)ct;
   d.n_chunks = (d.n_tiles + d.chunk_tiles - 1) / d.chunk_tiles;
+  if (tp) {  // no persistent-kernel chunks; tp_base and tp_out are set by the caller
+    d.flags |= kFlagTimeParallel;
+    d.n_chunks = 0;
+  }
   d.result_slot = s.result_slot;
   return d;
 }
@@ -255,6 +294,11 @@ mlmc_ap_status Workspace::ensure(size_t n_items, size_t n_tiles, size_t n_groups
   return MLMC_AP_OK;
 }
 
+mlmc_ap_status Workspace::ensure_tp(size_t n_samples) {
+  if (n_samples == 0) return MLMC_AP_OK;
+  return grow_dev(tp_buf, tp_cap, n_samples);
+}
+
 void Workspace::release() {
   if (graph) (void)hipGraphExecDestroy(graph);
   if (graph_def) (void)hipGraphDestroy(graph_def);
@@ -269,6 +313,9 @@ void Workspace::release() {
   if (resident) (void)hipFree(resident);
   if (resident_host) (void)hipHostFree(resident_host);
   if (hist_dev) (void)hipFree(hist_dev);
+  if (tp_buf) (void)hipFree(tp_buf);
+  tp_buf = nullptr;
+  tp_cap = 0;
   items_dev = nullptr; items_host = nullptr; hdr_dev = nullptr; hdr_host = nullptr;
   counter_dev = nullptr; partials = nullptr; groups = nullptr; resident = nullptr;
   resident_host = nullptr; hist_dev = nullptr;
@@ -325,6 +372,7 @@ mlmc_ap_tuning resolve_tuning(const Workspace& ws, const mlmc_ap_tuning* t) {
     if (t->block) r.block = t->block;
     if (t->ppt) r.ppt = t->ppt;
     if (t->waves_per_simd) r.waves_per_simd = t->waves_per_simd;
+    if (t->tp_max_samples) r.tp_max_samples = t->tp_max_samples;
   }
   return r;
 }
@@ -362,9 +410,12 @@ static mlmc_ap_status reduce(Workspace& ws, hipStream_t s) {
 
 // The whole launch as one stream of kernels: stage the table, simulate,
 // reduce (the host mirror of the resident slots is written by the last one).
+static int tp_grid(const Workspace& ws) { return std::max(1, ws.n_cu * 8); }
+
 static mlmc_ap_status record_device_work(Workspace& ws, bool fp64, const mlmc_ap_tuning& t,
-                                         hipStream_t s) {
+                                         bool has_tp, hipStream_t s) {
   MLMC_TRY(stage(ws, s));
+  if (has_tp) MLMC_HIP(launch_tp(fp64, ws.items_dev, ws.hdr_dev, tp_grid(ws), s));
   MLMC_HIP(launch_persistent(fp64, t.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev, ws.partials,
                              t.block, persistent_grid(ws, t), s));
   MLMC_TRY(reduce(ws, s));
@@ -377,7 +428,8 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
   MLMC_TRY(check_tuning(tuning));
   if (specs.empty()) return MLMC_AP_OK;
   std::vector<LevelDesc> d(specs.size());
-  for (size_t i = 0; i < specs.size(); ++i) d[i] = make_desc(specs[i]);
+  const std::vector<bool> tp = choose_time_parallel(specs, tuning.tp_max_samples);
+  for (size_t i = 0; i < specs.size(); ++i) d[i] = make_desc(specs[i], tp[i]);
   const bool fp64 = specs[0].prob->fp64_state != 0;
   for (const auto& s : specs)
     if ((s.prob->fp64_state != 0) != fp64)
@@ -386,7 +438,7 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
   std::stable_sort(d.begin(), d.end(), [](const LevelDesc& a, const LevelDesc& b) {
     return a.n_steps > b.n_steps;
   });
-  uint64_t tiles = 0, groups = 0, chunks = 0;
+  uint64_t tiles = 0, groups = 0, chunks = 0, tp_samples = 0;
   for (auto& x : d) {
     x.tile_base = tiles;
     x.group_base = groups;
@@ -394,30 +446,44 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
     tiles += x.n_tiles;
     groups += x.n_groups;
     chunks += x.n_chunks;
+    if (x.flags & kFlagTimeParallel) tp_samples += x.n_samples;
   }
-  if (chunks >= 0xFFFFFFF0ull || groups >= 0xFFFFFFF0ull)
+  if (chunks >= 0xFFFFFFF0ull || groups >= 0xFFFFFFF0ull || tp_samples >= 0xFFFFFFF0ull)
     return set_error(MLMC_AP_EINVAL, "work table too large for one launch");
   MLMC_TRY(ws.ensure(d.size(), tiles, groups, n_slots, 0));
+  MLMC_TRY(ws.ensure_tp(tp_samples));
+  uint64_t tp_off = 0;
+  for (auto& x : d) {
+    x.tp_base = (uint32_t)tp_off;
+    if (x.flags & kFlagTimeParallel) {
+      x.tp_out = ws.tp_buf + tp_off;
+      tp_off += x.n_samples;
+    }
+  }
+  const bool has_tp = tp_samples > 0;
   std::memcpy(ws.items_host, d.data(), d.size() * sizeof(LevelDesc));
   ws.hdr_host->n_items = (uint32_t)d.size();
   ws.hdr_host->total_chunks = (uint32_t)chunks;
   ws.hdr_host->total_groups = (uint32_t)groups;
-  ws.hdr_host->pad = 0;
+  ws.hdr_host->total_tp = (uint32_t)tp_samples;
 
   MLMC_HIP(hipEventRecord(ws.ev[0], stream));
   bool kernel_timed = false;
   if (mode == 0) {
     MLMC_TRY(stage(ws, stream));
     MLMC_HIP(hipEventRecord(ws.ev[1], stream));
+    if (has_tp) MLMC_HIP(launch_tp(fp64, ws.items_dev, ws.hdr_dev, tp_grid(ws), stream));
     for (size_t i = 0; i < d.size(); ++i)
-      MLMC_HIP(launch_level(fp64, tuning.ppt, d[i].kind, ws.items_dev, (uint32_t)i, d[i].n_tiles,
-                            tuning.block, ws.partials, stream));
+      if (!(d[i].flags & kFlagTimeParallel))
+        MLMC_HIP(launch_level(fp64, tuning.ppt, d[i].kind, ws.items_dev, (uint32_t)i,
+                              d[i].n_tiles, tuning.block, ws.partials, stream));
     MLMC_HIP(hipEventRecord(ws.ev[2], stream));
     MLMC_TRY(reduce(ws, stream));
     kernel_timed = true;
   } else if (mode == 2) {
     MLMC_TRY(stage(ws, stream));
     MLMC_HIP(hipEventRecord(ws.ev[1], stream));
+    if (has_tp) MLMC_HIP(launch_tp(fp64, ws.items_dev, ws.hdr_dev, tp_grid(ws), stream));
     MLMC_HIP(launch_persistent(fp64, tuning.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev,
                                ws.partials, tuning.block, persistent_grid(ws, tuning), stream));
     MLMC_HIP(hipEventRecord(ws.ev[2], stream));
@@ -426,14 +492,14 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
   } else {
     const uint64_t key = ((uint64_t)tuning.block << 48) ^ ((uint64_t)tuning.ppt << 40) ^
                          ((uint64_t)tuning.waves_per_simd << 32) ^ (fp64 ? 1ull : 2ull) ^
-                         ((uint64_t)(uintptr_t)ws.partials << 3);
+                         (has_tp ? 4ull : 0ull) ^ ((uint64_t)(uintptr_t)ws.partials << 3);
     if (!ws.graph || ws.graph_key != key) {
       if (ws.graph) (void)hipGraphExecDestroy(ws.graph);
       if (ws.graph_def) (void)hipGraphDestroy(ws.graph_def);
       ws.graph = nullptr;
       ws.graph_def = nullptr;
       MLMC_HIP(hipStreamBeginCapture(ws.capture_stream, hipStreamCaptureModeRelaxed));
-      mlmc_ap_status st = record_device_work(ws, fp64, tuning, ws.capture_stream);
+      mlmc_ap_status st = record_device_work(ws, fp64, tuning, has_tp, ws.capture_stream);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(ws.capture_stream, &g);
       if (st != MLMC_AP_OK) {
@@ -644,6 +710,17 @@ mlmc_ap_status mlmc_ap_release(void) {
   if (!ws) return MLMC_AP_EDEVICE;
   std::lock_guard<std::mutex> lk(ws->mu);
   ws->release();
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_set_tuning(const mlmc_ap_tuning* tuning_host) {
+  if (!tuning_host) return set_error(MLMC_AP_EINVAL, "tuning is NULL");
+  Workspace* ws = workspace();
+  if (!ws) return MLMC_AP_EDEVICE;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  const mlmc_ap_tuning t = resolve_tuning(*ws, tuning_host);
+  MLMC_TRY(check_tuning(t));
+  ws->tuning = t;
   return MLMC_AP_OK;
 }
 

@@ -56,7 +56,18 @@ struct ItemSpec {
   bool accumulate = true;    // merge into the result slot (else overwrite it)
 };
 
-LevelDesc make_desc(const ItemSpec& s);
+// Time-parallel path (few long trajectories; see the tuning documentation of
+// the C ABI): an item qualifies with at most tp_max_samples samples
+// (0 = kTpDefaultMaxSamples) of >= 64 fine steps; of the qualifying items of a
+// launch the longest are taken while their trajectory steps stay within
+// kTpStepsPerLongestStep times the longest item's step count.  Results do not
+// depend on the choice.
+constexpr int64_t kTpDefaultMaxSamples = 4096;
+constexpr int64_t kTpStepsPerLongestStep = 4096;
+bool time_parallel_candidate(const ItemSpec& s, int32_t tp_max_samples);
+std::vector<bool> choose_time_parallel(const std::vector<ItemSpec>& specs,
+                                       int32_t tp_max_samples);
+LevelDesc make_desc(const ItemSpec& s, bool tp);
 
 // Device workspace of one device: work table, tile partials, group results,
 // resident statistics, histogram counters, pinned staging, captured graph.
@@ -87,6 +98,8 @@ struct Workspace {
   size_t resident_cap = 0;  // slots
   unsigned long long* hist_dev = nullptr;
   size_t hist_cap = 0;      // counters
+  TpSample* tp_buf = nullptr;  // final states of time-parallel samples
+  size_t tp_cap = 0;
 
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_def = nullptr;
@@ -99,6 +112,7 @@ struct Workspace {
 
   mlmc_ap_status ensure(size_t n_items, size_t n_tiles, size_t n_groups, size_t n_slots,
                         size_t n_hist);
+  mlmc_ap_status ensure_tp(size_t n_samples);
   void release();
 };
 

@@ -117,34 +117,70 @@ struct Lane {
     return d.x0_kind == 2 ? 2u : 1u;
   }
 
+  // The arithmetic below is shared with the time-parallel path, which must
+  // round exactly as this loop does.
+
+  // Fine move of trajectory p with velocity v and kick normal xi.
+  __device__ __forceinline__ void move_f(int p, Real v, Real xi) {
+    if constexpr (kCompensate)
+      af[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, v, af[p]));
+    else
+      xf[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, v, xf[p]));
+  }
+
+  // Coarse move of trajectory p with velocity v and coarse kick normal.
+  __device__ __forceinline__ void move_c(int p, Real v, Real kick) {
+    if constexpr (kCompensate)
+      ac[p] = fma_r<Real>(s_c, kick, fma_r<Real>(h_c, v, ac[p]));
+    else
+      xc[p] = fma_r<Real>(s_c, kick, fma_r<Real>(h_c, v, xc[p]));
+  }
+
+  // Coarse-block bookkeeping of one fine step (kick normal xi, decision word
+  // wd, collision hit with new velocity normal vnew).  num accumulates, per
+  // fine move made with an in-block velocity draw, that draw's normal
+  // (-> sum_j n_j nu_j); den accumulates 2u+1 at the u-th further use of a
+  // draw (-> sum_j n_j^2).
+  __device__ __forceinline__ static void book(Real& sxi, Real& nm, Real& dn, Real& ln, Real& us,
+                                              Real& hv, uint32_t& wm, Real xi, uint32_t wd,
+                                              bool hit, Real vnew) {
+    sxi += xi;
+    wm = min(wm, wd);
+    if constexpr (kAgg) {
+      nm += ln;
+      dn = fma_r<Real>(hv, fma_r<Real>(Real(2), us, Real(1)), dn);
+      us += hv;
+      ln = hit ? vnew : ln;
+      us = hit ? Real(0) : us;
+      hv = hit ? Real(1) : hv;
+    }
+  }
+
+  // Coarse kick normal of a block; if the coarse path collides (chit), the
+  // last in-block draw becomes its velocity and leaves the kick.
+  __device__ __forceinline__ Real kick_of(bool chit, Real sxi, Real nm, Real dn, Real ln,
+                                          Real us) const {
+    if constexpr (kAgg) {
+      const Real nn = chit ? fma_r<Real>(-us, ln, nm) : nm;
+      const Real dd = chit ? fma_r<Real>(-us, us, dn) : dn;
+      return fma_r<Real>(h_f, nn, s_f * sxi) * rsqrt_r(fma_r<Real>(h_f2, dd, agg_ms2));
+    } else {
+      return sxi * rsqrt_m;
+    }
+  }
+
   // One fine step of trajectory p: decision word wd, Box-Muller words (wa, wb).
   __device__ __forceinline__ void step(int p, uint32_t wd, uint32_t wa, uint32_t wb) {
     Real xi, g;
     box_muller(wa, wb, xi, g);
     Real vnew = kMaxwell ? g : sign_of(wb);
     keep(vnew);  // computed unconditionally: the select below stays branch-free
-    if constexpr (kCompensate)
-      af[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, vf[p], af[p]));
-    else
-      xf[p] = fma_r<Real>(s_f, xi, fma_r<Real>(h_f, vf[p], xf[p]));
+    move_f(p, vf[p], xi);
     const bool hit = below<WIDE>(wd, thr_f_m1, thr_f);
     vf[p] = hit ? vnew : vf[p];
     cf[p] += hit ? 1u : 0u;
-    if constexpr (kCoarse) {
-      sum_xi[p] += xi;
-      wmin[p] = min(wmin[p], wd);
-      if constexpr (kAgg) {
-        // num accumulates, per fine move made with an in-block velocity draw,
-        // that draw's normal (-> sum_j n_j nu_j); den accumulates 2u+1 at the
-        // u-th further use of a draw (-> sum_j n_j^2)
-        num[p] += lnu[p];
-        den[p] = fma_r<Real>(have[p], fma_r<Real>(Real(2), uses[p], Real(1)), den[p]);
-        uses[p] += have[p];
-        lnu[p] = hit ? vnew : lnu[p];
-        uses[p] = hit ? Real(0) : uses[p];
-        have[p] = hit ? Real(1) : have[p];
-      }
-    }
+    if constexpr (kCoarse)
+      book(sum_xi[p], num[p], den[p], lnu[p], uses[p], have[p], wmin[p], xi, wd, hit, vnew);
   }
 
   // Coarse step of every trajectory at the end of a block of M fine steps.
@@ -153,20 +189,7 @@ struct Lane {
     for (int p = 0; p < P; ++p) {
       // coarse collision: the smallest fine decision word is below thr_c2
       const bool chit = below<WIDE>(wmin[p], thr_c2_m1, thr_c2);
-      Real kick;
-      if constexpr (kAgg) {
-        // if the coarse path collides, the last in-block draw becomes its
-        // velocity and leaves the kick
-        const Real nn = chit ? fma_r<Real>(-uses[p], lnu[p], num[p]) : num[p];
-        const Real dd = chit ? fma_r<Real>(-uses[p], uses[p], den[p]) : den[p];
-        kick = fma_r<Real>(h_f, nn, s_f * sum_xi[p]) * rsqrt_r(fma_r<Real>(h_f2, dd, agg_ms2));
-      } else {
-        kick = sum_xi[p] * rsqrt_m;
-      }
-      if constexpr (kCompensate)
-        ac[p] = fma_r<Real>(s_c, kick, fma_r<Real>(h_c, vc[p], ac[p]));
-      else
-        xc[p] = fma_r<Real>(s_c, kick, fma_r<Real>(h_c, vc[p], xc[p]));
+      move_c(p, vc[p], kick_of(chit, sum_xi[p], num[p], den[p], lnu[p], uses[p]));
       vc[p] = chit ? vf[p] : vc[p];
       cc[p] += chit ? 1u : 0u;
     }
@@ -301,6 +324,106 @@ struct Lane {
   }
 };
 
+// Shifted sums of one tile's samples (shift = the values of the tile's first
+// sample, held by lane 0) and the tile record they give.  The per-lane loop
+// and the time-parallel path build their records with this same code, so
+// both give bitwise identical records for the same samples.
+struct TileSums {
+  double k_dq = 0.0, k_f = 0.0, k_c = 0.0;
+  double s1_dq = 0.0, s2_dq = 0.0, s1_f = 0.0, s2_f = 0.0, s1_c = 0.0, s2_c = 0.0, s_fc = 0.0;
+  uint32_t cnt = 0;
+  unsigned long long col_f = 0, col_c = 0;
+
+  template <bool kCoarse>
+  __device__ __forceinline__ void shift(double dq, double qf, double qc) {
+    k_dq = __shfl(dq, 0, kLanes);
+    if constexpr (kCoarse) {
+      k_f = __shfl(qf, 0, kLanes);
+      k_c = __shfl(qc, 0, kLanes);
+    }
+  }
+
+  template <bool kCoarse>
+  __device__ __forceinline__ void add(double dq, double qf, double qc, uint32_t cf, uint32_t cc) {
+    const double e_dq = dq - k_dq;
+    s1_dq += e_dq;
+    s2_dq = fma(e_dq, e_dq, s2_dq);
+    if constexpr (kCoarse) {
+      const double e_f = qf - k_f, e_c = qc - k_c;
+      s1_f += e_f; s2_f = fma(e_f, e_f, s2_f);
+      s1_c += e_c; s2_c = fma(e_c, e_c, s2_c);
+      s_fc = fma(e_f, e_c, s_fc);
+    }
+    cnt += 1u;
+    col_f += cf;
+    col_c += cc;
+  }
+
+  // Fixed xor-butterfly sums over the wavefront; every lane gets the record.
+  template <bool kCoarse>
+  __device__ __forceinline__ Stats record() const {
+    const double n = (double)wave_sum_u64((unsigned long long)cnt);
+    const double t1_dq = wave_sum(s1_dq), t2_dq = wave_sum(s2_dq);
+    Stats out;
+    out.n = n;
+    out.mean_dq = k_dq + t1_dq / n;
+    out.m2_dq = fmax(fma(-t1_dq, t1_dq / n, t2_dq), 0.0);
+    if constexpr (kCoarse) {
+      const double t1_f = wave_sum(s1_f), t2_f = wave_sum(s2_f);
+      const double t1_c = wave_sum(s1_c), t2_c = wave_sum(s2_c), t_fc = wave_sum(s_fc);
+      out.mean_qf = k_f + t1_f / n;
+      out.m2_qf = fmax(fma(-t1_f, t1_f / n, t2_f), 0.0);
+      out.mean_qc = k_c + t1_c / n;
+      out.m2_qc = fmax(fma(-t1_c, t1_c / n, t2_c), 0.0);
+      out.c_fc = fma(-t1_f, t1_c / n, t_fc);
+    } else {
+      out.mean_qf = out.mean_dq;
+      out.m2_qf = out.m2_dq;
+      out.mean_qc = 0.0;
+      out.m2_qc = 0.0;
+      out.c_fc = 0.0;
+    }
+    out.coll_f = wave_sum_u64(col_f);
+    out.coll_c = wave_sum_u64(col_c);
+    return out;
+  }
+};
+
+// Optional per-sample outputs of one valid sample: trajectory and collision
+// dumps, histogram counters (fine bin, coarse bin, both in the same bin).
+template <typename Real, bool kCoarse>
+__device__ __forceinline__ void sample_outputs(const LevelDesc& d, uint64_t local, Real xf, Real xc,
+                                               uint32_t cf, uint32_t cc) {
+  if (d.traj) {
+    Real* t = (Real*)d.traj;
+    t[local] = xf;
+    t[d.n_samples + local] = kCoarse ? xc : Real(0);
+  }
+  if (d.coll) {
+    d.coll[local] = cf;
+    d.coll[d.n_samples + local] = cc;
+  }
+  if (d.flags & kFlagHist) {
+    const int nb = (int)d.nbins;
+    const double tf = ((double)xf - d.hist_lo) * d.hist_inv_w;
+    const int bf = tf < 0.0 ? -1 : (tf >= (double)nb ? nb : (int)tf);
+    unsigned long long* hst = d.hist;
+    if (bf < 0) atomicAdd(&hst[3 * nb + 0], 1ull);
+    else if (bf >= nb) atomicAdd(&hst[3 * nb + 1], 1ull);
+    else atomicAdd(&hst[3 * bf], 1ull);
+    if (kCoarse) {
+      const double tc = ((double)xc - d.hist_lo) * d.hist_inv_w;
+      const int bc = tc < 0.0 ? -1 : (tc >= (double)nb ? nb : (int)tc);
+      if (bc < 0) atomicAdd(&hst[3 * nb + 2], 1ull);
+      else if (bc >= nb) atomicAdd(&hst[3 * nb + 3], 1ull);
+      else {
+        atomicAdd(&hst[3 * bc + 1], 1ull);
+        if (bc == bf) atomicAdd(&hst[3 * bc + 2], 1ull);
+      }
+    }
+  }
+}
+
 template <typename Real, int P, int KIND, bool WIDE>
 __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
                                               Stats* __restrict__ partials) {
@@ -309,12 +432,7 @@ __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
   const int lane = threadIdx.x & (kLanes - 1);
   const int rounds = (int)d.spl / P;
   const uint64_t tile_samples = (uint64_t)kLanes * d.spl;
-
-  // Shifted sums (shift = the values of the tile's first sample, lane 0).
-  double k_dq = 0.0, k_f = 0.0, k_c = 0.0;
-  double s1_dq = 0.0, s2_dq = 0.0, s1_f = 0.0, s2_f = 0.0, s1_c = 0.0, s2_c = 0.0, s_fc = 0.0;
-  uint32_t cnt = 0;
-  unsigned long long col_f = 0, col_c = 0;
+  TileSums acc;
 
 #pragma unroll 1
   for (int r = 0; r < rounds; ++r) {
@@ -329,116 +447,199 @@ __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
       st.smp[p] = (uint32_t)(d.sample_begin + local[p]);
     }
     st.run(d);
-    Real xf[P], xc[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      xf[p] = st.pos_f(p);
-      xc[p] = st.pos_c(p);
-    }
-    auto& cf = st.cf;
-    auto& cc = st.cc;
-
     // Quantity of interest in FP64 (exact squares of FP32 positions).
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const double qf = (double)xf[p] * (double)xf[p];
-      const double qc = kCoarse ? (double)xc[p] * (double)xc[p] : 0.0;
+      const Real xf = st.pos_f(p), xc = st.pos_c(p);
+      const double qf = (double)xf * (double)xf;
+      const double qc = kCoarse ? (double)xc * (double)xc : 0.0;
       const double dq = qf - qc;
-      if (r == 0 && p == 0) {  // lane 0, sample 0 of the tile always exists
-        k_dq = __shfl(dq, 0, kLanes);
-        if constexpr (kCoarse) {
-          k_f = __shfl(qf, 0, kLanes);
-          k_c = __shfl(qc, 0, kLanes);
-        }
-      }
+      if (r == 0 && p == 0) acc.shift<kCoarse>(dq, qf, qc);  // lane 0, sample 0 always exists
       if (valid[p]) {
-        const double e_dq = dq - k_dq;
-        s1_dq += e_dq;
-        s2_dq += e_dq * e_dq;
-        if constexpr (kCoarse) {
-          const double e_f = qf - k_f, e_c = qc - k_c;
-          s1_f += e_f; s2_f += e_f * e_f;
-          s1_c += e_c; s2_c += e_c * e_c;
-          s_fc += e_f * e_c;
-        }
-        cnt += 1u;
-        col_f += cf[p];
-        col_c += cc[p];
-        if (d.traj) {
-          Real* t = (Real*)d.traj;
-          t[local[p]] = xf[p];
-          t[d.n_samples + local[p]] = kCoarse ? xc[p] : Real(0);
-        }
-        if (d.coll) {
-          d.coll[local[p]] = cf[p];
-          d.coll[d.n_samples + local[p]] = cc[p];
-        }
-        if (d.flags & kFlagHist) {
-          const int nb = (int)d.nbins;
-          const double tf = ((double)xf[p] - d.hist_lo) * d.hist_inv_w;
-          const int bf = tf < 0.0 ? -1 : (tf >= (double)nb ? nb : (int)tf);
-          unsigned long long* hst = d.hist;
-          if (bf < 0) atomicAdd(&hst[3 * nb + 0], 1ull);
-          else if (bf >= nb) atomicAdd(&hst[3 * nb + 1], 1ull);
-          else atomicAdd(&hst[3 * bf], 1ull);
-          if (kCoarse) {
-            const double tc = ((double)xc[p] - d.hist_lo) * d.hist_inv_w;
-            const int bc = tc < 0.0 ? -1 : (tc >= (double)nb ? nb : (int)tc);
-            if (bc < 0) atomicAdd(&hst[3 * nb + 2], 1ull);
-            else if (bc >= nb) atomicAdd(&hst[3 * nb + 3], 1ull);
-            else {
-              atomicAdd(&hst[3 * bc + 1], 1ull);
-              if (bc == bf) atomicAdd(&hst[3 * bc + 2], 1ull);
-            }
-          }
-        }
+        acc.add<kCoarse>(dq, qf, qc, st.cf[p], st.cc[p]);
+        sample_outputs<Real, kCoarse>(d, local[p], xf, xc, st.cf[p], st.cc[p]);
       }
     }
   }
-
-  // Tile statistics: fixed xor-butterfly sums, then lane 0 writes the record.
-  const double n = (double)wave_sum_u64((unsigned long long)cnt);
-  const double t1_dq = wave_sum(s1_dq), t2_dq = wave_sum(s2_dq);
-  Stats out;
-  out.n = n;
-  out.mean_dq = k_dq + t1_dq / n;
-  out.m2_dq = fmax(t2_dq - t1_dq * (t1_dq / n), 0.0);
-  if constexpr (kCoarse) {
-    const double t1_f = wave_sum(s1_f), t2_f = wave_sum(s2_f);
-    const double t1_c = wave_sum(s1_c), t2_c = wave_sum(s2_c), t_fc = wave_sum(s_fc);
-    out.mean_qf = k_f + t1_f / n;
-    out.m2_qf = fmax(t2_f - t1_f * (t1_f / n), 0.0);
-    out.mean_qc = k_c + t1_c / n;
-    out.m2_qc = fmax(t2_c - t1_c * (t1_c / n), 0.0);
-    out.c_fc = t_fc - t1_f * (t1_c / n);
-  } else {
-    out.mean_qf = out.mean_dq;
-    out.m2_qf = out.m2_dq;
-    out.mean_qc = 0.0;
-    out.m2_qc = 0.0;
-    out.c_fc = 0.0;
-  }
-  out.coll_f = wave_sum_u64(col_f);
-  out.coll_c = wave_sum_u64(col_c);
+  const Stats out = acc.record<kCoarse>();
   if (lane == 0) partials[d.tile_base + tile] = out;
 }
 
+// ---------------------------------------------------------------------------
+// Time-parallel trajectory, for items of few long trajectories (the warm-up
+// of the fine levels), where one trajectory per lane would leave most of the
+// GPU idle while a few wavefronts walk thousands of steps.  A wavefront
+// simulates one sample; in chunk c, lane j owns fine step 64 c + j.  What
+// does not depend on the particle state is computed by the lanes in
+// parallel: the chunk's Philox blocks (lane i computes block i; the words go
+// through LDS), the Box-Muller pairs and collision decisions, the velocity
+// each step moves with (the draw of the last colliding step before it: a
+// ballot and a shuffle), and for a pair every coarse block's collision, kick
+// and velocity.  The position increments are then summed in step order on
+// wave-uniform values with the very operations of the per-lane loop
+// (including the compensated folds), so both give bitwise identical results.
+// Needs n_steps >= 1 and, for a pair, M in {2, 4} (coarse blocks inside a
+// chunk).  Writes the sample's final state to d.tp_out; the tile records are
+// built from there by the reduction.
+// ---------------------------------------------------------------------------
+constexpr int kTpBlocks = 49;                 // Philox blocks per 64-step chunk
+constexpr int kTpWords = 4 * kTpBlocks;       // 196 words; step j reads words 3j+2..3j+4
+constexpr int kTpWavesPerBlock = 4;           // kernels here run <= 256 threads
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float lane_value(float v, uint32_t j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)j));
+}
+__device__ __forceinline__ double lane_value(double v, uint32_t j) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, (int)j);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), (int)j);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Word exchange area of the time-parallel path (one row per wavefront).
+__shared__ uint32_t tp_words[kTpWavesPerBlock][kTpWords];
+
+template <typename Real, int KIND, bool WIDE, int MS>
+__device__ __forceinline__ void run_tp(const LevelDesc& d, uint32_t local) {
+  using S = Lane<Real, 1, KIND, WIDE>;
+  constexpr bool kCoarse = S::kCoarse;
+  uint32_t* wl = tp_words[threadIdx.x / kLanes];
+  const uint32_t lane = threadIdx.x & (kLanes - 1);
+  const unsigned long long lanes_below = (1ull << lane) - 1ull;
+
+  S st(d);
+  st.smp[0] = (uint32_t)(d.sample_begin + local);
+  const uint32_t first_block = st.init(d) - 1u;  // block of the two carried words
+  const uint32_t n = d.n_steps;
+  Real vf = st.vf[0], vc = st.vc[0];
+  uint32_t cf = 0, cc = 0;
+
+#pragma unroll 1
+  for (uint32_t c0 = 0; c0 < n; c0 += kLanes) {
+    // words 2 + 3 (c0 + j) .. 4 + 3 (c0 + j) of the stream, from block
+    // first_block + 48 (c0 / 64) on (every chunk starts at word 2 of a block)
+    wave_sync();
+    if (lane < (uint32_t)kTpBlocks) {
+      const Words w = st.block(first_block + (c0 / kLanes) * 48u + lane, 0);
+      wl[4 * lane + 0] = w.w0;
+      wl[4 * lane + 1] = w.w1;
+      wl[4 * lane + 2] = w.w2;
+      wl[4 * lane + 3] = w.w3;
+    }
+    wave_sync();
+    const uint32_t wd = wl[3 * lane + 2], wa = wl[3 * lane + 3], wb = wl[3 * lane + 4];
+    const bool active = c0 + lane < n;
+    Real xi, g;
+    box_muller(wa, wb, xi, g);
+    Real vnew = S::kMaxwell ? g : S::sign_of(wb);
+    const bool hit = active && below<WIDE>(wd, st.thr_f_m1, st.thr_f);
+    const unsigned long long mask = __ballot(hit);
+    const unsigned long long before = mask & lanes_below;
+    const int src = before ? 63 - __clzll((long long)before) : (int)lane;
+    const Real v_last = __shfl(vnew, src, kLanes);
+    const Real vpre = before ? v_last : vf;     // velocity of this step's move
+    const Real vpost = hit ? vnew : vpre;       // velocity after its collision
+
+    Real kick = Real(0), vcpre = Real(0);
+    unsigned long long cmask = 0;
+    if constexpr (kCoarse) {
+      // the coarse block of this lane: steps lb .. lb + MS - 1 of the chunk,
+      // its bookkeeping replayed in step order exactly as the per-lane loop
+      const int lb = (int)(lane & ~(uint32_t)(MS - 1));
+      Real sum_xi = Real(0), num = Real(0), den = Real(0), lnu = Real(0), uses = Real(0),
+           have = Real(0);
+      uint32_t wmin = 0xFFFFFFFFu;
+#pragma unroll
+      for (int i = 0; i < MS; ++i) {
+        const Real xi_i = __shfl(xi, lb + i, kLanes);
+        const uint32_t wd_i = (uint32_t)__shfl((int)wd, lb + i, kLanes);
+        const Real vn_i = __shfl(vnew, lb + i, kLanes);
+        const bool hit_i = (mask >> (lb + i)) & 1ull;
+        S::book(sum_xi, num, den, lnu, uses, have, wmin, xi_i, wd_i, hit_i, vn_i);
+      }
+      const bool chit = below<WIDE>(wmin, st.thr_c2_m1, st.thr_c2);
+      kick = st.kick_of(chit, sum_xi, num, den, lnu, uses);
+      const bool last = (lane & (uint32_t)(MS - 1)) == (uint32_t)(MS - 1);
+      cmask = __ballot(last && active && chit);
+      const unsigned long long cbefore = cmask & lanes_below;
+      const int csrc = cbefore ? 63 - __clzll((long long)cbefore) : (int)lane;
+      const Real vc_last = __shfl(vpost, csrc, kLanes);
+      vcpre = cbefore ? vc_last : vc;
+    }
+
+    // position increments in step order (wave-uniform values)
+    const uint32_t cnt = min((uint32_t)kLanes, n - c0);
+#pragma unroll 1
+    for (uint32_t j = 0; j < cnt; ++j) {
+      st.move_f(0, lane_value(vpre, j), lane_value(xi, j));
+      if constexpr (kCoarse) {
+        if ((j & (uint32_t)(MS - 1)) == (uint32_t)(MS - 1))
+          st.move_c(0, lane_value(vcpre, j), lane_value(kick, j));
+      }
+      if ((j & 15u) == 15u) st.fold_all();
+    }
+    cf += (uint32_t)__popcll(mask);
+    if (mask) vf = lane_value(vnew, 63u - (uint32_t)__clzll((long long)mask));
+    if constexpr (kCoarse) {
+      cc += (uint32_t)__popcll(cmask);
+      if (cmask) vc = lane_value(vpost, 63u - (uint32_t)__clzll((long long)cmask));
+    }
+  }
+  st.fold_all();
+  const Real xf = st.pos_f(0), xc = st.pos_c(0);
+  if (lane == 0) {
+    TpSample r;
+    r.xf = (double)xf;
+    r.xc = kCoarse ? (double)xc : 0.0;
+    r.cf = cf;
+    r.cc = cc;
+    d.tp_out[local] = r;
+    sample_outputs<Real, kCoarse>(d, local, xf, xc, cf, cc);
+  }
+}
+
+// Tile record of a time-parallel item from its samples' final states: the
+// same arithmetic as run_tile_impl on a 64-sample tile.
+template <bool kCoarse>
+__device__ __forceinline__ Stats tp_tile_record(const LevelDesc& d, uint32_t tile) {
+  const uint32_t lane = threadIdx.x & (kLanes - 1);
+  const uint64_t local = (uint64_t)tile * kLanes + lane;
+  const bool valid = local < d.n_samples;
+  TpSample r{0.0, 0.0, 0u, 0u};
+  if (valid) r = d.tp_out[local];
+  const double qf = r.xf * r.xf;
+  const double qc = kCoarse ? r.xc * r.xc : 0.0;
+  const double dq = qf - qc;
+  TileSums acc;
+  acc.shift<kCoarse>(dq, qf, qc);
+  if (valid) acc.add<kCoarse>(dq, qf, qc, r.cf, r.cc);
+  return acc.record<kCoarse>();
+}
+
+// One tile of an item (per-lane loop).
 template <typename Real, int P, int KIND>
-__device__ __forceinline__ void run_tile(const LevelDesc& d, uint32_t tile,
+__device__ __forceinline__ void run_unit(const LevelDesc& d, uint32_t unit,
                                          Stats* __restrict__ partials) {
+  const bool wide = (d.flags & kFlagWide) != 0;
   // one trajectory per lane on the long levels (64-sample tiles)
   constexpr int P1 = 1;
   if (d.spl == 1) {
-    if (d.flags & kFlagWide) run_tile_impl<Real, P1, KIND, true>(d, tile, partials);
-    else run_tile_impl<Real, P1, KIND, false>(d, tile, partials);
+    if (wide) run_tile_impl<Real, P1, KIND, true>(d, unit, partials);
+    else run_tile_impl<Real, P1, KIND, false>(d, unit, partials);
   } else {
-    if (d.flags & kFlagWide) run_tile_impl<Real, P, KIND, true>(d, tile, partials);
-    else run_tile_impl<Real, P, KIND, false>(d, tile, partials);
+    if (wide) run_tile_impl<Real, P, KIND, true>(d, unit, partials);
+    else run_tile_impl<Real, P, KIND, false>(d, unit, partials);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Plain launch: one tile per wavefront over one work item.
+// Plain launch: one unit per wavefront over one work item.
 // ---------------------------------------------------------------------------
 template <typename Real, int P, int KIND>
 __global__ void __launch_bounds__(256) level_kernel(const LevelDesc* __restrict__ items,
@@ -446,7 +647,52 @@ __global__ void __launch_bounds__(256) level_kernel(const LevelDesc* __restrict_
   const LevelDesc d = items[item];
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
   if (wave >= d.n_tiles) return;  // the whole wavefront leaves together
-  run_tile<Real, P, KIND>(d, wave, partials);
+  run_unit<Real, P, KIND>(d, wave, partials);
+}
+
+// ---------------------------------------------------------------------------
+// Time-parallel items of a work table (their chunks are absent from the
+// persistent kernel's chunk space).  Wavefront w of the grid takes
+// trajectories w, w + W, ... of the table's time-parallel space.
+// ---------------------------------------------------------------------------
+template <typename Real, int KIND>
+__device__ __forceinline__ void run_tp_kind(const LevelDesc& d, uint32_t local) {
+  constexpr bool kCoarse = KIND >= kKindPairTwoPointSum;
+  const bool wide = (d.flags & kFlagWide) != 0;
+  if constexpr (!kCoarse) {
+    if (wide) run_tp<Real, KIND, true, 1>(d, local);
+    else run_tp<Real, KIND, false, 1>(d, local);
+  } else if (d.M == 2) {
+    if (wide) run_tp<Real, KIND, true, 2>(d, local);
+    else run_tp<Real, KIND, false, 2>(d, local);
+  } else {
+    if (wide) run_tp<Real, KIND, true, 4>(d, local);
+    else run_tp<Real, KIND, false, 4>(d, local);
+  }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(256) tp_kernel(const LevelDesc* __restrict__ items,
+                                                  const WorkHeader* __restrict__ hdr) {
+  const uint32_t n_items = hdr->n_items;
+  const uint32_t total = hdr->total_tp;
+  const uint32_t waves = gridDim.x * (blockDim.x / kLanes);
+  for (uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; g < total; g += waves) {
+    uint32_t lo = 0, hi = n_items;  // last item whose time-parallel range starts at or before g
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (items[mid].tp_base <= g) lo = mid; else hi = mid;
+    }
+    const LevelDesc d = items[lo];
+    const uint32_t local = g - d.tp_base;
+    switch (d.kind) {
+      case kKindFineTwoPoint: run_tp_kind<Real, kKindFineTwoPoint>(d, local); break;
+      case kKindFineMaxwell: run_tp_kind<Real, kKindFineMaxwell>(d, local); break;
+      case kKindPairTwoPointSum: run_tp_kind<Real, kKindPairTwoPointSum>(d, local); break;
+      case kKindPairMaxwellSum: run_tp_kind<Real, kKindPairMaxwellSum>(d, local); break;
+      default: run_tp_kind<Real, kKindPairMaxwellAggregate>(d, local); break;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -472,26 +718,26 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
       const uint32_t mid = (lo + hi) >> 1;
       if (items[mid].chunk_base <= g) lo = mid; else hi = mid;
     }
-    const LevelDesc d = items[lo];
+    const LevelDesc d = items[lo];  // (time-parallel items hold no chunks)
     const uint32_t c = g - (uint32_t)d.chunk_base;
     const uint32_t t0 = c * d.chunk_tiles;
     const uint32_t t1 = min(t0 + d.chunk_tiles, d.n_tiles);
     switch (d.kind) {
       case kKindFineTwoPoint:
-        for (uint32_t t = t0; t < t1; ++t) run_tile<Real, P, kKindFineTwoPoint>(d, t, partials);
+        for (uint32_t t = t0; t < t1; ++t) run_unit<Real, P, kKindFineTwoPoint>(d, t, partials);
         break;
       case kKindFineMaxwell:
-        for (uint32_t t = t0; t < t1; ++t) run_tile<Real, P, kKindFineMaxwell>(d, t, partials);
+        for (uint32_t t = t0; t < t1; ++t) run_unit<Real, P, kKindFineMaxwell>(d, t, partials);
         break;
       case kKindPairTwoPointSum:
-        for (uint32_t t = t0; t < t1; ++t) run_tile<Real, P, kKindPairTwoPointSum>(d, t, partials);
+        for (uint32_t t = t0; t < t1; ++t) run_unit<Real, P, kKindPairTwoPointSum>(d, t, partials);
         break;
       case kKindPairMaxwellSum:
-        for (uint32_t t = t0; t < t1; ++t) run_tile<Real, P, kKindPairMaxwellSum>(d, t, partials);
+        for (uint32_t t = t0; t < t1; ++t) run_unit<Real, P, kKindPairMaxwellSum>(d, t, partials);
         break;
       default:
         for (uint32_t t = t0; t < t1; ++t)
-          run_tile<Real, P, kKindPairMaxwellAggregate>(d, t, partials);
+          run_unit<Real, P, kKindPairMaxwellAggregate>(d, t, partials);
         break;
     }
   }
@@ -518,7 +764,7 @@ __device__ __forceinline__ void block_tree(const Stats& acc, Stats* sh) {
 
 __global__ void __launch_bounds__(kReduceThreads) reduce_groups_kernel(
     const LevelDesc* __restrict__ items, const WorkHeader* __restrict__ hdr,
-    const Stats* __restrict__ partials, Stats* __restrict__ groups) {
+    Stats* __restrict__ partials, Stats* __restrict__ groups) {
   __shared__ Stats sh[kReduceThreads];
   const uint32_t n_items = hdr->n_items;
   const uint32_t total = hdr->total_groups;
@@ -531,6 +777,18 @@ __global__ void __launch_bounds__(kReduceThreads) reduce_groups_kernel(
     const uint64_t tile_base = items[lo].tile_base;
     const uint32_t n_tiles = items[lo].n_tiles;
     const uint32_t g = vb - (uint32_t)items[lo].group_base;
+    if (items[lo].flags & kFlagTimeParallel) {
+      // tile records of a time-parallel item, from its samples' final states
+      const LevelDesc d = items[lo];
+      const uint32_t t_end = min((g + 1) * (uint32_t)kGroupTiles, n_tiles);
+      for (uint32_t t = g * kGroupTiles + threadIdx.x / kLanes; t < t_end;
+           t += kReduceThreads / kLanes) {
+        const Stats r = (d.flags & kFlagCoarse) ? tp_tile_record<true>(d, t)
+                                                : tp_tile_record<false>(d, t);
+        if ((threadIdx.x & (kLanes - 1)) == 0) partials[tile_base + t] = r;
+      }
+      __syncthreads();
+    }
     Stats acc = stats_empty();
     const uint32_t first = g * kGroupTiles + threadIdx.x * kReducePerThread;
     for (int k = 0; k < kReducePerThread; ++k) {
@@ -707,7 +965,7 @@ hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
 }
 
 hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev,
-                         const Stats* partials, Stats* groups, Stats* resident, Stats* mirror,
+                         Stats* partials, Stats* groups, Stats* resident, Stats* mirror,
                          int grid_groups, int grid_items, hipStream_t s) {
   hipLaunchKernelGGL(reduce_groups_kernel, dim3(grid_groups), dim3(kReduceThreads), 0, s,
                      items_dev, hdr_dev, partials, groups);
@@ -715,6 +973,15 @@ hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reduce_items_kernel, dim3(grid_items), dim3(kReduceThreads), 0, s,
                      items_dev, hdr_dev, groups, resident, mirror);
+  return hipGetLastError();
+}
+
+hipError_t launch_tp(bool fp64, const LevelDesc* items_dev, const WorkHeader* hdr_dev, int grid,
+                     hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(tp_kernel<double>, dim3(grid), dim3(256), 0, s, items_dev, hdr_dev);
+  else
+    hipLaunchKernelGGL(tp_kernel<float>, dim3(grid), dim3(256), 0, s, items_dev, hdr_dev);
   return hipGetLastError();
 }
 

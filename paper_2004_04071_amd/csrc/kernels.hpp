@@ -11,9 +11,9 @@ namespace mlmc {
 // replay picks up whatever table the host uploaded last).
 struct alignas(16) WorkHeader {
   uint32_t n_items;
-  uint32_t total_chunks;
+  uint32_t total_chunks;  // persistent kernel chunks
   uint32_t total_groups;
-  uint32_t pad;
+  uint32_t total_tp;      // trajectories of the time-parallel items
 };
 
 hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev, uint32_t item,
@@ -21,11 +21,15 @@ hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev
 hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
                              const WorkHeader* hdr_dev, unsigned int* counter, Stats* partials,
                              int block, int grid, hipStream_t s);
-// Tile records -> group records -> resident slots; `mirror` (host-mapped
+// Tile records -> group records -> resident slots (the tile records of a
+// time-parallel item are first built from its samples); `mirror` (host-mapped
 // pinned memory, or null) receives a copy of every slot written.
 hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev,
-                         const Stats* partials, Stats* groups, Stats* resident, Stats* mirror,
+                         Stats* partials, Stats* groups, Stats* resident, Stats* mirror,
                          int grid_groups, int grid_items, hipStream_t s);
+// Time-parallel items of the table (one wavefront per trajectory, grid-stride).
+hipError_t launch_tp(bool fp64, const LevelDesc* items_dev, const WorkHeader* hdr_dev, int grid,
+                     hipStream_t s);
 // Work table and header from host-mapped pinned memory to the device; clears
 // the persistent kernel's chunk counter.
 hipError_t launch_stage(const WorkHeader* hdr_src, const LevelDesc* items_src, uint32_t cap,

@@ -358,7 +358,7 @@ static bool read_cache(const char* path, const std::string& dev, mlmc_ap_tuning*
   t->block = b;
   t->ppt = pp;
   t->waves_per_simd = w;
-  t->reserved = 0;
+  t->tp_max_samples = 0;
   return (b == 64 || b == 128 || b == 256) && (pp == 1 || pp == 2 || pp == 4) && w >= 1 && w <= 8;
 }
 

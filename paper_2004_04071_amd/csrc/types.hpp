@@ -43,6 +43,13 @@ enum : uint32_t {
   kFlagHist = 1u << 3,        // histogram QoI
   kFlagWide = 1u << 4,        // a decision threshold is 0: 64-bit compares
   kFlagAccumulate = 1u << 6,  // merge into the resident statistics (else overwrite)
+  kFlagTimeParallel = 1u << 7,  // one trajectory per wavefront, steps across lanes
+};
+
+// Final state of one sample of a time-parallel item.
+struct alignas(8) TpSample {
+  double xf, xc;
+  uint32_t cf, cc;
 };
 
 // Trajectory kinds (the compile-time specialisations of the particle loop).
@@ -85,8 +92,12 @@ struct alignas(16) LevelDesc {
   uint32_t n_chunks;
   uint32_t result_slot;         // resident statistics slot
   uint32_t spl;                 // samples per lane of a tile (tile = 64 spl samples)
-  uint32_t pad1, pad2;
+  uint32_t tp_base;             // first trajectory in the table's time-parallel space
+  uint32_t pad;
+  TpSample* tp_out;             // time-parallel item: final state of every sample
 };
+
+static_assert(sizeof(LevelDesc) == 256, "LevelDesc layout");
 
 // Mergeable statistics of a set of samples (FP64 means and centred sums).
 struct alignas(16) Stats {

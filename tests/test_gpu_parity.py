@@ -1,6 +1,6 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
-Bars ("Parity bars"):
+Bars:
   * Philox words, uniforms, collision decisions and counts: bit-exact;
   * FP32 positions: |x_gpu - x_oracle| <= 1e-5 max(|x_oracle|, rms(x_oracle));
     FP64 positions: 1e-12 relative to the same scale;

@@ -1,0 +1,112 @@
+"""Time-parallel path (one trajectory per wavefront, its fine steps across the
+lanes) against the one-trajectory-per-lane loop, through the C ABI.
+
+Both forms apply the same floating-point operations in the same order, so
+trajectories, collision counts, histograms and statistics must be bitwise
+equal; the library picks the form per launch (few long trajectories run
+time-parallel), and mlmc_ap_set_tuning(tp_max_samples=-1) switches it off.
+The oracle parity of the time-parallel form itself is covered by the
+trajectory cases of the parity tests, whose small long-level runs take it."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2004_04071_amd")
+
+pytestmark = pytest.mark.gpu
+
+DEFAULT_TP = 4096
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    pkg.mlmc_ap_init()
+    yield
+    pkg.mlmc_ap_set_tuning(tp_max_samples=DEFAULT_TP)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run(prob, level, begin, n, single, tp):
+    pkg.mlmc_ap_set_tuning(tp_max_samples=DEFAULT_TP if tp else -1)
+    P = pkg.as_problem(prob)
+    dt = torch.float64 if P.fp64_state else torch.float32
+    traj = torch.full((2 * n,), float("nan"), dtype=dt, device="cuda")
+    coll = torch.full((2 * n,), -1, dtype=torch.int32, device="cuda")
+    hist = P.qoi == pkg.QOI_X2_HIST
+    out = pkg.mlmc_ap_simulate_level(P, level, begin, n, single=single, traj=traj, coll=coll,
+                                     hist=bool(hist))
+    torch.cuda.synchronize()
+    st, h = out if hist else (out, None)
+    return st, traj.cpu(), coll.cpu(), h
+
+
+CASES = [
+    ("agg_m2_l6", W.cfg2(eps=0.01, stream_id=71), 6, 17, 300, False),
+    ("agg_m2_l5_one_tile", W.cfg2(eps=1.0, stream_id=72), 5, 0, 64, False),
+    ("agg_m2_l7_ragged", W.cfg2(eps=1e-4, stream_id=73), 7, 5, 129, False),
+    ("kicksum_l6", W.cfg2(eps=0.1, coupling=W.COUPLING_KICK_SUM, stream_id=74), 6, 3, 200, False),
+    ("twopoint_l6", dict(W.cfg1(), M=2, L=8, dt0=0.125, T=1.0, fp64_state=0), 6, 0, 150, False),
+    ("twopoint_fp64_l6", dict(W.cfg1(), M=2, L=8, dt0=0.125, T=1.0), 6, 9, 70, False),
+    ("m4_l3", dict(W.cfg2(eps=0.05, stream_id=75), M=4, L=4), 3, 11, 200, False),
+    ("cosine_hist_fp32_l6", W.cfg4(0), 6, 0, 100, False),
+    ("cosine_hist_fp64_l6", W.cfg4(1), 6, 0, 100, False),
+    ("single_l6", W.cfg2(eps=0.02, stream_id=76), 6, 40, 150, True),
+    ("wide_threshold_l6", W.cfg2(eps=1e6, stream_id=77), 6, 0, 100, False),
+    ("steps_96_l5", dict(W.cfg2(eps=0.3, stream_id=78), T=1.5, dt0=0.5), 5, 2, 77, False),
+    ("agg_fp64_l6", dict(W.cfg2(eps=0.3, stream_id=79), fp64_state=1), 6, 0, 100, False),
+]
+
+
+@pytest.mark.parametrize("name,prob,level,begin,n,single", CASES, ids=[c[0] for c in CASES])
+def test_time_parallel_equals_per_lane(name, prob, level, begin, n, single):
+    say("case", name)
+    a = run(prob, level, begin, n, single, tp=True)
+    b = run(prob, level, begin, n, single, tp=False)
+    assert a[0] == b[0], "statistics differ"
+    assert torch.equal(a[1], b[1]), "positions differ"
+    assert torch.equal(a[2], b[2]), "collision counts differ"
+    assert a[3] == b[3], "histograms differ"
+    assert a[0]["n"] == n and not torch.isnan(a[1]).any()
+
+
+def test_time_parallel_case_matches_oracle():
+    """A time-parallel run against the oracle directly (positions to the
+    FP32 bar, collision counts exactly)."""
+    prob = W.cfg2(eps=0.01, stream_id=80)
+    st, traj, coll, _ = run(prob, 8, 123, 40, False, tp=True)
+    ref = O.simulate(prob, 8, 123, 40)
+    x = traj.double().numpy()
+    c = coll.numpy().astype(np.int64)
+    assert np.array_equal(c[:40], ref["cf"].astype(np.int64))
+    assert np.array_equal(c[40:], ref["cc"].astype(np.int64))
+    for got, want in ((x[:40], ref["xf"]), (x[40:], ref["xc"])):
+        scale = np.maximum(np.abs(want), np.sqrt(np.mean(want ** 2)))
+        assert np.max(np.abs(got - want) / scale) <= 1e-5
+
+
+def key(r):
+    return (r["estimate"], r["var_estimator"], tuple(r["N"]),
+            tuple(tuple(sorted(l.items())) for l in r["levels"]))
+
+
+@pytest.mark.parametrize("batched", [0, 1, 2])
+def test_estimates_equal_with_and_without_time_parallel(batched):
+    """The warm-up of an L = 8 estimate runs its long levels time-parallel;
+    the estimate is bitwise the same with the path switched off."""
+    pkg.mlmc_ap_set_tuning(tp_max_samples=DEFAULT_TP)
+    prob = W.cfg2(eps=0.01, stream_id=81)
+    on = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=batched))
+    off = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=batched, tp_max_samples=-1))
+    assert key(on) == key(off)
