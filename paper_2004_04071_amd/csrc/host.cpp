@@ -25,6 +25,7 @@ constexpr double kTwo32 = 4294967296.0;
 // work-counter traffic); chunks never exceed 64 tiles, and on the long levels
 // a chunk is a single tile so that the slowest chunks end early.
 constexpr uint64_t kChunkLaneSteps = 256;
+constexpr uint64_t kMinChunksPerItem = 64;
 }  // namespace
 
 mlmc_ap_status set_error(mlmc_ap_status s, const std::string& msg) {
@@ -186,11 +187,18 @@ LevelDesc make_desc(const ItemSpec& s, bool tp) {
                              : kKindPairTwoPointSum)
                   : (maxwell ? kKindFineMaxwell : kKindFineTwoPoint);
   d.x0_kind = (uint32_t)p.x0_kind;
+  // wide tiles (several samples per lane) only where they still give the
+  // item at least one wavefront per SIMD; a few samples of short
+  // trajectories are spread over one per lane instead
   d.spl = samples_per_lane((uint32_t)F.n_steps);
+  while (d.spl > 1 && s.n_samples < kMinWideTiles * (uint64_t)kLanes * d.spl) d.spl /= 4;
   const uint64_t tile_samples = (uint64_t)kLanes * d.spl;
   d.n_tiles = (uint32_t)((s.n_samples + tile_samples - 1) / tile_samples);
   d.n_groups = (d.n_tiles + kGroupTiles - 1) / kGroupTiles;
+  // a chunk is about kChunkLaneSteps lane-steps of work, but an item keeps at
+  // least kMinChunksPerItem chunks so that a small one is not serialised
   uint64_t ct = kChunkLaneSteps / ((uint64_t)d.spl * (F.n_steps + 1));
+  ct = std::min<uint64_t>(ct, std::max<uint64_t>(1, d.n_tiles / kMinChunksPerItem));
   if (ct < 1) ct = 1;
   if (ct > 64) ct = 64;
   d.chunk_tiles = (uint32_t)ct;
@@ -278,7 +286,7 @@ mlmc_ap_status Workspace::ensure(size_t n_items, size_t n_tiles, size_t n_groups
   }
   if (!hdr_dev) {
     MLMC_HIP(hipMalloc((void**)&hdr_dev, sizeof(WorkHeader)));
-    MLMC_HIP(hipMalloc((void**)&counter_dev, 64));
+    MLMC_HIP(hipMalloc((void**)&counter_dev, sizeof(unsigned int) * kChunkStreams * kCounterStride));
   }
   if (!hdr_host) MLMC_TRY(grow_pinned(hdr_host, hdr_host_dev, 0, 1));
   MLMC_TRY(grow_dev(partials, partials_cap, std::max<size_t>(n_tiles, 1)));
@@ -290,7 +298,7 @@ mlmc_ap_status Workspace::ensure(size_t n_items, size_t n_tiles, size_t n_groups
   MLMC_TRY(grow_dev(hist_dev, hist_cap, std::max<size_t>(n_hist, 1)));
   const void* after[7] = {items_dev, partials, groups, resident, hist_dev, items_host_dev,
                           resident_host_dev};
-  if (std::memcmp(before, after, sizeof(before)) != 0) graph_key = 0;  // recapture
+  if (std::memcmp(before, after, sizeof(before)) != 0) drop_graphs();  // recapture
   return MLMC_AP_OK;
 }
 
@@ -299,10 +307,16 @@ mlmc_ap_status Workspace::ensure_tp(size_t n_samples) {
   return grow_dev(tp_buf, tp_cap, n_samples);
 }
 
+void Workspace::drop_graphs() {
+  for (auto& e : graphs) {
+    if (e.second.exec) (void)hipGraphExecDestroy(e.second.exec);
+    if (e.second.def) (void)hipGraphDestroy(e.second.def);
+  }
+  graphs.clear();
+}
+
 void Workspace::release() {
-  if (graph) (void)hipGraphExecDestroy(graph);
-  if (graph_def) (void)hipGraphDestroy(graph_def);
-  graph = nullptr; graph_def = nullptr; graph_key = 0;
+  drop_graphs();
   if (items_dev) (void)hipFree(items_dev);
   if (items_host) (void)hipHostFree(items_host);
   if (hdr_dev) (void)hipFree(hdr_dev);
@@ -380,7 +394,8 @@ mlmc_ap_tuning resolve_tuning(const Workspace& ws, const mlmc_ap_tuning* t) {
 int persistent_grid(const Workspace& ws, const mlmc_ap_tuning& t) {
   const int waves_per_block = t.block / kLanes;
   const int waves = ws.n_cu * 4 * t.waves_per_simd;
-  return std::max(1, (waves + waves_per_block - 1) / waves_per_block);
+  // every chunk stream needs blocks
+  return std::max((int)kChunkStreams, (waves + waves_per_block - 1) / waves_per_block);
 }
 
 static mlmc_ap_status check_tuning(const mlmc_ap_tuning& t) {
@@ -493,11 +508,9 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
     const uint64_t key = ((uint64_t)tuning.block << 48) ^ ((uint64_t)tuning.ppt << 40) ^
                          ((uint64_t)tuning.waves_per_simd << 32) ^ (fp64 ? 1ull : 2ull) ^
                          (has_tp ? 4ull : 0ull) ^ ((uint64_t)(uintptr_t)ws.partials << 3);
-    if (!ws.graph || ws.graph_key != key) {
-      if (ws.graph) (void)hipGraphExecDestroy(ws.graph);
-      if (ws.graph_def) (void)hipGraphDestroy(ws.graph_def);
-      ws.graph = nullptr;
-      ws.graph_def = nullptr;
+    auto it = ws.graphs.find(key);
+    if (it == ws.graphs.end()) {
+      if (ws.graphs.size() >= 16) ws.drop_graphs();  // bound the cache
       MLMC_HIP(hipStreamBeginCapture(ws.capture_stream, hipStreamCaptureModeRelaxed));
       mlmc_ap_status st = record_device_work(ws, fp64, tuning, has_tp, ws.capture_stream);
       hipGraph_t g = nullptr;
@@ -507,11 +520,16 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
         return st;
       }
       if (e != hipSuccess) return set_error(MLMC_AP_EDEVICE, "hipStreamEndCapture failed");
-      ws.graph_def = g;
-      MLMC_HIP(hipGraphInstantiate(&ws.graph, g, nullptr, nullptr, 0));
-      ws.graph_key = key;
+      Workspace::Graph entry;
+      entry.def = g;
+      if (hipGraphInstantiate(&entry.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(g);
+        return set_error(MLMC_AP_EDEVICE, "hipGraphInstantiate failed");
+      }
+      it = ws.graphs.emplace(key, entry).first;
     }
-    MLMC_HIP(hipGraphLaunch(ws.graph, stream));
+    MLMC_HIP(hipGraphLaunch(it->second.exec, stream));
   }
   MLMC_HIP(hipEventRecord(ws.ev[3], stream));
   MLMC_HIP(hipStreamSynchronize(stream));

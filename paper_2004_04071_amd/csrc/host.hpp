@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -101,9 +102,14 @@ struct Workspace {
   TpSample* tp_buf = nullptr;  // final states of time-parallel samples
   size_t tp_cap = 0;
 
-  hipGraphExec_t graph = nullptr;
-  hipGraph_t graph_def = nullptr;
-  uint64_t graph_key = 0;
+  // Captured launches by shape (tuning, precision, time-parallel node); every
+  // buffer they name is in the workspace, so any reallocation drops them all.
+  struct Graph {
+    hipGraph_t def = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::map<uint64_t, Graph> graphs;
+  void drop_graphs();
 
   mlmc_ap_tuning tuning{};      // current default (autotuned or built-in)
   bool tuned = false;

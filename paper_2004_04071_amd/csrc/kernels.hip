@@ -505,6 +505,19 @@ __device__ __forceinline__ double lane_value(double v, uint32_t j) {
 // Word exchange area of the time-parallel path (one row per wavefront).
 __shared__ uint32_t tp_words[kTpWavesPerBlock][kTpWords];
 
+// Step j of a chunk in the serial order of the per-lane loop: fine move,
+// coarse move at the end of a coarse block, compensated fold every 16 steps.
+template <int MS, typename S, typename Real>
+__device__ __forceinline__ void tp_serial_step(S& st, uint32_t j, Real vpre, Real xi, Real vcpre,
+                                               Real kick) {
+  st.move_f(0, lane_value(vpre, j), lane_value(xi, j));
+  if constexpr (S::kCoarse) {
+    if ((j & (uint32_t)(MS - 1)) == (uint32_t)(MS - 1))
+      st.move_c(0, lane_value(vcpre, j), lane_value(kick, j));
+  }
+  if ((j & 15u) == 15u) st.fold_all();
+}
+
 template <typename Real, int KIND, bool WIDE, int MS>
 __device__ __forceinline__ void run_tp(const LevelDesc& d, uint32_t local) {
   using S = Lane<Real, 1, KIND, WIDE>;
@@ -573,16 +586,15 @@ __device__ __forceinline__ void run_tp(const LevelDesc& d, uint32_t local) {
       vcpre = cbefore ? vc_last : vc;
     }
 
-    // position increments in step order (wave-uniform values)
+    // position increments in step order (wave-uniform values); a full chunk
+    // is unrolled so that the lane reads run ahead of the dependent chain
     const uint32_t cnt = min((uint32_t)kLanes, n - c0);
+    if (cnt == (uint32_t)kLanes) {
+#pragma unroll
+      for (uint32_t j = 0; j < (uint32_t)kLanes; ++j) tp_serial_step<MS>(st, j, vpre, xi, vcpre, kick);
+    } else {
 #pragma unroll 1
-    for (uint32_t j = 0; j < cnt; ++j) {
-      st.move_f(0, lane_value(vpre, j), lane_value(xi, j));
-      if constexpr (kCoarse) {
-        if ((j & (uint32_t)(MS - 1)) == (uint32_t)(MS - 1))
-          st.move_c(0, lane_value(vcpre, j), lane_value(kick, j));
-      }
-      if ((j & 15u) == 15u) st.fold_all();
+      for (uint32_t j = 0; j < cnt; ++j) tp_serial_step<MS>(st, j, vpre, xi, vcpre, kick);
     }
     cf += (uint32_t)__popcll(mask);
     if (mask) vf = lane_value(vnew, 63u - (uint32_t)__clzll((long long)mask));
@@ -645,7 +657,7 @@ template <typename Real, int P, int KIND>
 __global__ void __launch_bounds__(256) level_kernel(const LevelDesc* __restrict__ items,
                                                      uint32_t item, Stats* __restrict__ partials) {
   const LevelDesc d = items[item];
-  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kLanes);
   if (wave >= d.n_tiles) return;  // the whole wavefront leaves together
   run_unit<Real, P, KIND>(d, wave, partials);
 }
@@ -677,7 +689,8 @@ __global__ void __launch_bounds__(256) tp_kernel(const LevelDesc* __restrict__ i
   const uint32_t n_items = hdr->n_items;
   const uint32_t total = hdr->total_tp;
   const uint32_t waves = gridDim.x * (blockDim.x / kLanes);
-  for (uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; g < total; g += waves) {
+  const uint32_t first = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kLanes);
+  for (uint32_t g = first; g < total; g += waves) {
     uint32_t lo = 0, hi = n_items;  // last item whose time-parallel range starts at or before g
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
@@ -696,9 +709,15 @@ __global__ void __launch_bounds__(256) tp_kernel(const LevelDesc* __restrict__ i
 }
 
 // ---------------------------------------------------------------------------
-// Persistent launch over a work table.  Each wavefront takes the next chunk
-// (a run of tiles of one item) from an integer work counter until the table
-// is drained; items are ordered most expensive first.
+// Persistent launch over a work table; items are ordered most expensive
+// first.  The chunk space (runs of tiles of one item) is dealt out as
+// kChunkStreams interleaved streams, chunks x, x + 8, x + 16, ... to the
+// blocks with blockIdx % 8 == x (the blocks of one XCD under round-robin
+// dispatch), each stream with its own work counter on its own cache line:
+// the wavefronts that arrive first take the first (longest) chunks.  When one
+// round covers the whole table (a small launch such as a warm-up), a
+// wavefront takes the chunk of its own index instead and touches no counter.
+// The grid must have at least kChunkStreams blocks (every stream needs waves).
 // ---------------------------------------------------------------------------
 template <typename Real, int P>
 __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __restrict__ items,
@@ -708,11 +727,23 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
   const uint32_t n_items = hdr->n_items;
   const uint32_t total = hdr->total_chunks;
   const int lane = threadIdx.x & (kLanes - 1);
+  const uint32_t wpb = blockDim.x / kLanes;
+  const uint32_t x = blockIdx.x % kChunkStreams;
+  const uint32_t stream_waves = wpb * ((gridDim.x - x + kChunkStreams - 1) / kChunkStreams);
+  const bool one_round = (uint64_t)x + (uint64_t)kChunkStreams * stream_waves >= total;
+  // (wave-uniform; readfirstlane tells the compiler so, which keeps the
+  // descriptor of the chunk's item in scalar registers)
+  uint32_t k = __builtin_amdgcn_readfirstlane((blockIdx.x / kChunkStreams) * wpb +
+                                              threadIdx.x / kLanes);  // static index
+  if (!one_round) {
+    unsigned int first = 0;
+    if (lane == 0) first = atomicAdd(&counter[x * kCounterStride], 1u);
+    k = __builtin_amdgcn_readfirstlane(__shfl(first, 0, kLanes));
+  }
   for (;;) {
-    unsigned int g = 0;
-    if (lane == 0) g = atomicAdd(counter, 1u);
-    g = __builtin_amdgcn_readfirstlane(__shfl(g, 0, kLanes));
-    if (g >= total) break;
+    const uint64_t g64 = (uint64_t)x + (uint64_t)kChunkStreams * k;
+    if (g64 >= total) break;
+    const uint32_t g = (uint32_t)g64;
     uint32_t lo = 0, hi = n_items;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
@@ -740,6 +771,10 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
           run_unit<Real, P, kKindPairMaxwellAggregate>(d, t, partials);
         break;
     }
+    if (one_round) break;
+    unsigned int next = 0;
+    if (lane == 0) next = atomicAdd(&counter[x * kCounterStride], 1u);
+    k = __builtin_amdgcn_readfirstlane(__shfl(next, 0, kLanes));
   }
 }
 
@@ -828,7 +863,7 @@ __global__ void __launch_bounds__(kReduceThreads) reduce_items_kernel(
 
 // First node of every launch: copies the work table and its header from
 // host-mapped pinned memory (written by the host before the launch) into
-// device memory and clears the chunk counter, so one launch needs no copy
+// device memory and clears the chunk counters, so one launch needs no copy
 // commands.  At most `cap` descriptors are copied.
 __global__ void stage_kernel(const WorkHeader* __restrict__ hdr_src,
                              const LevelDesc* __restrict__ items_src, uint32_t cap,
@@ -842,11 +877,11 @@ __global__ void stage_kernel(const WorkHeader* __restrict__ hdr_src,
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words;
        i += (uint64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
+  if (blockIdx.x == 0 && threadIdx.x < kChunkStreams) counter[threadIdx.x * kCounterStride] = 0u;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     WorkHeader h = *hdr_src;
     h.n_items = n_items;
     *hdr_dst = h;
-    *counter = 0u;
   }
 }
 

@@ -16,6 +16,11 @@ struct alignas(16) WorkHeader {
   uint32_t total_tp;      // trajectories of the time-parallel items
 };
 
+// Persistent-kernel work counters: one per chunk stream, each on its own
+// 128-byte line (kChunkStreams * kCounterStride unsigned ints).
+constexpr uint32_t kChunkStreams = 8;
+constexpr uint32_t kCounterStride = 32;
+
 hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev, uint32_t item,
                         uint32_t n_tiles, int block, Stats* partials, hipStream_t s);
 hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
@@ -31,7 +36,7 @@ hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev,
 hipError_t launch_tp(bool fp64, const LevelDesc* items_dev, const WorkHeader* hdr_dev, int grid,
                      hipStream_t s);
 // Work table and header from host-mapped pinned memory to the device; clears
-// the persistent kernel's chunk counter.
+// the persistent kernel's chunk counters.
 hipError_t launch_stage(const WorkHeader* hdr_src, const LevelDesc* items_src, uint32_t cap,
                         WorkHeader* hdr_dst, LevelDesc* items_dst, unsigned int* counter,
                         hipStream_t s);

@@ -22,7 +22,10 @@ constexpr uint32_t kLongLevelSteps = 64;         // from here on: 64-sample tile
 
 // Samples per lane of a tile of a level with n_steps fine steps: the tile's
 // closing wave reduction is spread over more samples where trajectories are
-// short, and long trajectories keep one sample per lane.
+// short, and long trajectories keep one sample per lane.  An item with fewer
+// than kMinWideTiles tiles of that size uses a quarter of it (repeatedly, down
+// to one sample per lane).
+constexpr uint64_t kMinWideTiles = 1024;
 __host__ __device__ inline uint32_t samples_per_lane(uint32_t n_steps) {
   return n_steps >= kLongLevelSteps ? 1u : (n_steps >= kShortLevelSteps ? 4u : 16u);
 }

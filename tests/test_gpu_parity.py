@@ -166,12 +166,13 @@ def test_wide_thresholds_used():
     assert c["thr_f"] == 0
 
 
-@pytest.mark.parametrize("level,n", [(0, 1), (0, 1023), (0, 1024), (0, 1025), (0, 1025 * 1024 + 3),
-                                     (4, 255), (4, 257), (4, 1025 * 256 + 3),
-                                     (5, 63), (5, 65), (5, 1025 * 64 + 3)])
+@pytest.mark.parametrize("level,n", [(0, 1), (0, 63), (0, 65), (0, 1024 * 1024 - 1),
+                                     (0, 1024 * 1024 + 1), (0, 1025 * 1024 + 3),
+                                     (4, 1024 * 256 + 255), (5, 63), (5, 65), (5, 1025 * 64 + 3)])
 def test_tile_and_group_boundaries(level, n):
-    """Ragged tiles (1024 samples below 16 fine steps, 256 below 64, 64 from
-    there on) and more than one 1024-tile reduction group."""
+    """Ragged tiles of every width (1024 samples below 16 fine steps, 256 below
+    64, 64 from there on, narrowed for items of fewer than 1024 such tiles)
+    and more than one 1024-tile reduction group."""
     prob = W.cfg2(eps=0.3)
     st = pkg.mlmc_ap_simulate_level(prob, level, 5, n)
     ref = O.simulate(prob, level, 5, n)
