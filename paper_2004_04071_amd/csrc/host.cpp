@@ -278,11 +278,15 @@ static mlmc_ap_status grow_pinned(T*& p, T*& dp, size_t cap_old, size_t cap_new)
 
 mlmc_ap_status Workspace::ensure(size_t n_items, size_t n_tiles, size_t n_groups,
                                  size_t n_slots, size_t n_hist) {
-  const void* before[7] = {items_dev, partials, groups, resident, hist_dev, items_host_dev,
-                           resident_host_dev};
-  if (n_items > items_cap || !items_dev || !items_host) {
+  const void* before[8] = {items_dev, partials, groups, resident, hist_dev, items_host_dev,
+                           resident_host_dev, item_done};
+  if (n_items > items_cap || !items_dev || !items_host || !item_done) {
     MLMC_TRY(grow_dev(items_dev, items_cap, n_items));
     MLMC_TRY(grow_pinned(items_host, items_host_dev, 0, items_cap));
+    size_t done_cap = 0;
+    if (item_done) (void)hipFree(item_done);
+    item_done = nullptr;
+    MLMC_TRY(grow_dev(item_done, done_cap, items_cap));
   }
   if (!hdr_dev) {
     MLMC_HIP(hipMalloc((void**)&hdr_dev, sizeof(WorkHeader)));
@@ -296,8 +300,8 @@ mlmc_ap_status Workspace::ensure(size_t n_items, size_t n_tiles, size_t n_groups
     MLMC_TRY(grow_pinned(resident_host, resident_host_dev, 0, resident_cap));
   }
   MLMC_TRY(grow_dev(hist_dev, hist_cap, std::max<size_t>(n_hist, 1)));
-  const void* after[7] = {items_dev, partials, groups, resident, hist_dev, items_host_dev,
-                          resident_host_dev};
+  const void* after[8] = {items_dev, partials, groups, resident, hist_dev, items_host_dev,
+                          resident_host_dev, item_done};
   if (std::memcmp(before, after, sizeof(before)) != 0) drop_graphs();  // recapture
   return MLMC_AP_OK;
 }
@@ -329,6 +333,8 @@ void Workspace::release() {
   if (hist_dev) (void)hipFree(hist_dev);
   if (tp_buf) (void)hipFree(tp_buf);
   tp_buf = nullptr;
+  if (item_done) (void)hipFree(item_done);
+  item_done = nullptr;
   tp_cap = 0;
   items_dev = nullptr; items_host = nullptr; hdr_dev = nullptr; hdr_host = nullptr;
   counter_dev = nullptr; partials = nullptr; groups = nullptr; resident = nullptr;
@@ -408,29 +414,29 @@ static mlmc_ap_status check_tuning(const mlmc_ap_tuning& t) {
   return MLMC_AP_OK;
 }
 
-static const int kReduceGridGroups = 1024;
-static const int kReduceGridItems = 256;
+static const int kReduceGrid = 1024;
 
 static mlmc_ap_status stage(Workspace& ws, hipStream_t s) {
   MLMC_HIP(launch_stage(ws.hdr_host_dev, ws.items_host_dev, (uint32_t)ws.items_cap, ws.hdr_dev,
-                        ws.items_dev, ws.counter_dev, s));
+                        ws.items_dev, ws.counter_dev, ws.item_done, s));
   return MLMC_AP_OK;
 }
 
 static mlmc_ap_status reduce(Workspace& ws, hipStream_t s) {
-  MLMC_HIP(launch_reduce(ws.items_dev, ws.hdr_dev, ws.partials, ws.groups, ws.resident,
-                         ws.resident_host_dev, kReduceGridGroups, kReduceGridItems, s));
+  MLMC_HIP(launch_reduce(ws.items_dev, ws.hdr_dev, ws.partials, ws.groups, ws.item_done,
+                         ws.resident, ws.resident_host_dev, kReduceGrid, s));
   return MLMC_AP_OK;
 }
 
-// The whole launch as one stream of kernels: stage the table, simulate,
-// reduce (the host mirror of the resident slots is written by the last one).
+// Grid of the per-level form's time-parallel launch.
 static int tp_grid(const Workspace& ws) { return std::max(1, ws.n_cu * 8); }
 
+// The whole launch as three kernels: stage the table, simulate (the
+// persistent kernel also runs the time-parallel trajectories), reduce (which
+// also writes the host mirror of the resident slots).
 static mlmc_ap_status record_device_work(Workspace& ws, bool fp64, const mlmc_ap_tuning& t,
-                                         bool has_tp, hipStream_t s) {
+                                         hipStream_t s) {
   MLMC_TRY(stage(ws, s));
-  if (has_tp) MLMC_HIP(launch_tp(fp64, ws.items_dev, ws.hdr_dev, tp_grid(ws), s));
   MLMC_HIP(launch_persistent(fp64, t.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev, ws.partials,
                              t.block, persistent_grid(ws, t), s));
   MLMC_TRY(reduce(ws, s));
@@ -442,6 +448,8 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
                          LaunchTiming* timing) {
   MLMC_TRY(check_tuning(tuning));
   if (specs.empty()) return MLMC_AP_OK;
+  for (const auto& sp : specs)
+    if (sp.n_samples == 0) return set_error(MLMC_AP_EINVAL, "work item without samples");
   std::vector<LevelDesc> d(specs.size());
   const std::vector<bool> tp = choose_time_parallel(specs, tuning.tp_max_samples);
   for (size_t i = 0; i < specs.size(); ++i) d[i] = make_desc(specs[i], tp[i]);
@@ -498,7 +506,6 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
   } else if (mode == 2) {
     MLMC_TRY(stage(ws, stream));
     MLMC_HIP(hipEventRecord(ws.ev[1], stream));
-    if (has_tp) MLMC_HIP(launch_tp(fp64, ws.items_dev, ws.hdr_dev, tp_grid(ws), stream));
     MLMC_HIP(launch_persistent(fp64, tuning.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev,
                                ws.partials, tuning.block, persistent_grid(ws, tuning), stream));
     MLMC_HIP(hipEventRecord(ws.ev[2], stream));
@@ -507,12 +514,12 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
   } else {
     const uint64_t key = ((uint64_t)tuning.block << 48) ^ ((uint64_t)tuning.ppt << 40) ^
                          ((uint64_t)tuning.waves_per_simd << 32) ^ (fp64 ? 1ull : 2ull) ^
-                         (has_tp ? 4ull : 0ull) ^ ((uint64_t)(uintptr_t)ws.partials << 3);
+                         ((uint64_t)(uintptr_t)ws.partials << 3);
     auto it = ws.graphs.find(key);
     if (it == ws.graphs.end()) {
       if (ws.graphs.size() >= 16) ws.drop_graphs();  // bound the cache
       MLMC_HIP(hipStreamBeginCapture(ws.capture_stream, hipStreamCaptureModeRelaxed));
-      mlmc_ap_status st = record_device_work(ws, fp64, tuning, has_tp, ws.capture_stream);
+      mlmc_ap_status st = record_device_work(ws, fp64, tuning, ws.capture_stream);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(ws.capture_stream, &g);
       if (st != MLMC_AP_OK) {
@@ -532,7 +539,16 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
     MLMC_HIP(hipGraphLaunch(it->second.exec, stream));
   }
   MLMC_HIP(hipEventRecord(ws.ev[3], stream));
-  MLMC_HIP(hipStreamSynchronize(stream));
+  // Poll the launch's last event instead of a blocking wait: the MLMC loop
+  // plans its next launch from these statistics, so the wake-up latency of a
+  // blocking wait would sit on the critical path of every iteration.
+  hipError_t q;
+  while ((q = hipEventQuery(ws.ev[3])) == hipErrorNotReady) {
+  }
+  if (q != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(MLMC_AP_EDEVICE, std::string("launch failed: ") + hipGetErrorString(q));
+  }
   if (timing) {
     float ms = 0.f;
     MLMC_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[3]));

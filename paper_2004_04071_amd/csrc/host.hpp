@@ -99,6 +99,7 @@ struct Workspace {
   size_t resident_cap = 0;  // slots
   unsigned long long* hist_dev = nullptr;
   size_t hist_cap = 0;      // counters
+  unsigned int* item_done = nullptr;  // reduction: finished groups per item (items_cap)
   TpSample* tp_buf = nullptr;  // final states of time-parallel samples
   size_t tp_cap = 0;
 

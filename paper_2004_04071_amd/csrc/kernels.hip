@@ -683,6 +683,27 @@ __device__ __forceinline__ void run_tp_kind(const LevelDesc& d, uint32_t local) 
   }
 }
 
+// Trajectory g of the table's time-parallel space.
+template <typename Real>
+__device__ __forceinline__ void run_tp_index(const LevelDesc* __restrict__ items, uint32_t n_items,
+                                             uint32_t g) {
+  uint32_t lo = 0, hi = n_items;  // last item whose time-parallel range starts at or before g
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (items[mid].tp_base <= g) lo = mid; else hi = mid;
+  }
+  const LevelDesc d = items[lo];
+  const uint32_t local = g - d.tp_base;
+  switch (d.kind) {
+    case kKindFineTwoPoint: run_tp_kind<Real, kKindFineTwoPoint>(d, local); break;
+    case kKindFineMaxwell: run_tp_kind<Real, kKindFineMaxwell>(d, local); break;
+    case kKindPairTwoPointSum: run_tp_kind<Real, kKindPairTwoPointSum>(d, local); break;
+    case kKindPairMaxwellSum: run_tp_kind<Real, kKindPairMaxwellSum>(d, local); break;
+    default: run_tp_kind<Real, kKindPairMaxwellAggregate>(d, local); break;
+  }
+}
+
+// The time-parallel items alone (the per-level launch form).
 template <typename Real>
 __global__ void __launch_bounds__(256) tp_kernel(const LevelDesc* __restrict__ items,
                                                   const WorkHeader* __restrict__ hdr) {
@@ -690,22 +711,7 @@ __global__ void __launch_bounds__(256) tp_kernel(const LevelDesc* __restrict__ i
   const uint32_t total = hdr->total_tp;
   const uint32_t waves = gridDim.x * (blockDim.x / kLanes);
   const uint32_t first = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kLanes);
-  for (uint32_t g = first; g < total; g += waves) {
-    uint32_t lo = 0, hi = n_items;  // last item whose time-parallel range starts at or before g
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (items[mid].tp_base <= g) lo = mid; else hi = mid;
-    }
-    const LevelDesc d = items[lo];
-    const uint32_t local = g - d.tp_base;
-    switch (d.kind) {
-      case kKindFineTwoPoint: run_tp_kind<Real, kKindFineTwoPoint>(d, local); break;
-      case kKindFineMaxwell: run_tp_kind<Real, kKindFineMaxwell>(d, local); break;
-      case kKindPairTwoPointSum: run_tp_kind<Real, kKindPairTwoPointSum>(d, local); break;
-      case kKindPairMaxwellSum: run_tp_kind<Real, kKindPairMaxwellSum>(d, local); break;
-      default: run_tp_kind<Real, kKindPairMaxwellAggregate>(d, local); break;
-    }
-  }
+  for (uint32_t g = first; g < total; g += waves) run_tp_index<Real>(items, n_items, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -735,6 +741,14 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
   // descriptor of the chunk's item in scalar registers)
   uint32_t k = __builtin_amdgcn_readfirstlane((blockIdx.x / kChunkStreams) * wpb +
                                               threadIdx.x / kLanes);  // static index
+  // Time-parallel trajectories first, dealt from the last wavefront down (the
+  // chunk streams hand out their first chunks to the first wavefronts).
+  const uint32_t total_tp = hdr->total_tp;
+  if (total_tp) {
+    const uint32_t waves = gridDim.x * wpb;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + threadIdx.x / kLanes);
+    for (uint32_t t = waves - 1u - wave; t < total_tp; t += waves) run_tp_index<Real>(items, n_items, t);
+  }
   if (!one_round) {
     unsigned int first = 0;
     if (lane == 0) first = atomicAdd(&counter[x * kCounterStride], 1u);
@@ -781,9 +795,9 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
 // ---------------------------------------------------------------------------
 // Reductions.  Stage 1: group g of an item merges tiles [1024 g, 1024 g +
 // 1024): thread t merges its 4 consecutive tiles in order, then a fixed LDS
-// tree.  Stage 2: one block per item merges the item's group results the
-// same way (thread t merges groups [t q, t q + q), q = ceil(n_groups / 256))
-// and folds the result into the item's resident statistics slot.
+// tree.  Stage 2 merges an item's group results the same way (thread t merges
+// groups [t q, t q + q), q = ceil(n_groups / 256)) and folds the result into
+// the item's resident statistics slot.
 // ---------------------------------------------------------------------------
 // Fixed LDS tree over the block's 256 records; the result is left in sh[0].
 __device__ __forceinline__ void block_tree(const Stats& acc, Stats* sh) {
@@ -797,10 +811,37 @@ __device__ __forceinline__ void block_tree(const Stats& acc, Stats* sh) {
   }
 }
 
-__global__ void __launch_bounds__(kReduceThreads) reduce_groups_kernel(
+// Merge of one item's group records into its resident slot (stage 2).
+__device__ __forceinline__ void merge_item(const LevelDesc& d, const Stats* __restrict__ groups,
+                                           Stats* __restrict__ resident, Stats* __restrict__ mirror,
+                                           Stats* sh) {
+  const uint64_t gbase = d.group_base;
+  const uint32_t n_groups = d.n_groups;
+  Stats acc = stats_empty();
+  const uint32_t q = (n_groups + kReduceThreads - 1) / kReduceThreads;
+  const uint32_t first = threadIdx.x * q;
+  for (uint32_t idx = first; idx < n_groups && idx < first + q; ++idx)
+    acc = stats_merge(acc, groups[gbase + idx]);
+  block_tree(acc, sh);
+  if (threadIdx.x == 0) {
+    const uint32_t slot = d.result_slot;
+    const Stats r = (d.flags & kFlagAccumulate) ? stats_merge(resident[slot], sh[0]) : sh[0];
+    resident[slot] = r;
+    if (mirror) mirror[slot] = r;  // host-mapped copy, read after the stream syncs
+  }
+  __syncthreads();
+}
+
+// Both stages in one launch: blocks take groups in grid-stride order; each
+// item counts its finished groups, and the block that finishes an item's last
+// group merges that item at once (release/acquire through device-scope fences
+// around the count).  Every item has at least one group.
+__global__ void __launch_bounds__(kReduceThreads) reduce_kernel(
     const LevelDesc* __restrict__ items, const WorkHeader* __restrict__ hdr,
-    Stats* __restrict__ partials, Stats* __restrict__ groups) {
+    Stats* __restrict__ partials, Stats* __restrict__ groups, unsigned int* __restrict__ item_done,
+    Stats* __restrict__ resident, Stats* __restrict__ mirror) {
   __shared__ Stats sh[kReduceThreads];
+  __shared__ unsigned int item_complete;
   const uint32_t n_items = hdr->n_items;
   const uint32_t total = hdr->total_groups;
   for (uint32_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
@@ -809,15 +850,15 @@ __global__ void __launch_bounds__(kReduceThreads) reduce_groups_kernel(
       const uint32_t mid = (lo + hi) >> 1;
       if (items[mid].group_base <= vb) lo = mid; else hi = mid;
     }
-    const uint64_t tile_base = items[lo].tile_base;
-    const uint32_t n_tiles = items[lo].n_tiles;
-    const uint32_t g = vb - (uint32_t)items[lo].group_base;
-    if (items[lo].flags & kFlagTimeParallel) {
+    const LevelDesc d = items[lo];
+    const uint64_t tile_base = d.tile_base;
+    const uint32_t n_tiles = d.n_tiles;
+    const uint32_t g = vb - (uint32_t)d.group_base;
+    if (d.flags & kFlagTimeParallel) {
       // tile records of a time-parallel item, from its samples' final states
-      const LevelDesc d = items[lo];
       const uint32_t t_end = min((g + 1) * (uint32_t)kGroupTiles, n_tiles);
-      for (uint32_t t = g * kGroupTiles + threadIdx.x / kLanes; t < t_end;
-           t += kReduceThreads / kLanes) {
+      const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+      for (uint32_t t = g * kGroupTiles + wave; t < t_end; t += kReduceThreads / kLanes) {
         const Stats r = (d.flags & kFlagCoarse) ? tp_tile_record<true>(d, t)
                                                 : tp_tile_record<false>(d, t);
         if ((threadIdx.x & (kLanes - 1)) == 0) partials[tile_base + t] = r;
@@ -831,31 +872,16 @@ __global__ void __launch_bounds__(kReduceThreads) reduce_groups_kernel(
       if (idx < n_tiles) acc = stats_merge(acc, partials[tile_base + idx]);
     }
     block_tree(acc, sh);
-    if (threadIdx.x == 0) groups[vb] = sh[0];
-    __syncthreads();
-  }
-}
-
-__global__ void __launch_bounds__(kReduceThreads) reduce_items_kernel(
-    const LevelDesc* __restrict__ items, const WorkHeader* __restrict__ hdr,
-    const Stats* __restrict__ groups, Stats* __restrict__ resident, Stats* __restrict__ mirror) {
-  __shared__ Stats sh[kReduceThreads];
-  const uint32_t n_items = hdr->n_items;
-  for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const uint64_t gbase = items[it].group_base;
-    const uint32_t n_groups = items[it].n_groups;
-    Stats acc = stats_empty();
-    const uint32_t q = (n_groups + kReduceThreads - 1) / kReduceThreads;
-    const uint32_t first = threadIdx.x * q;
-    for (uint32_t idx = first; idx < n_groups && idx < first + q; ++idx)
-      acc = stats_merge(acc, groups[gbase + idx]);
-    block_tree(acc, sh);
     if (threadIdx.x == 0) {
-      const uint32_t slot = items[it].result_slot;
-      const Stats r = (items[it].flags & kFlagAccumulate) ? stats_merge(resident[slot], sh[0])
-                                                          : sh[0];
-      resident[slot] = r;
-      if (mirror) mirror[slot] = r;  // host-mapped copy, read after the stream syncs
+      groups[vb] = sh[0];
+      __threadfence();  // the group record is visible before it is counted
+      const unsigned int prev = atomicAdd(&item_done[lo], 1u);
+      item_complete = (prev + 1u == d.n_groups) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (item_complete) {
+      __threadfence();  // the other blocks' group records of this item
+      merge_item(d, groups, resident, mirror, sh);
     }
     __syncthreads();
   }
@@ -863,12 +889,13 @@ __global__ void __launch_bounds__(kReduceThreads) reduce_items_kernel(
 
 // First node of every launch: copies the work table and its header from
 // host-mapped pinned memory (written by the host before the launch) into
-// device memory and clears the chunk counters, so one launch needs no copy
-// commands.  At most `cap` descriptors are copied.
+// device memory and clears the chunk and item counters, so one launch needs no
+// copy commands.  At most `cap` descriptors are copied.
 __global__ void stage_kernel(const WorkHeader* __restrict__ hdr_src,
                              const LevelDesc* __restrict__ items_src, uint32_t cap,
                              WorkHeader* __restrict__ hdr_dst, LevelDesc* __restrict__ items_dst,
-                             unsigned int* __restrict__ counter) {
+                             unsigned int* __restrict__ counter,
+                             unsigned int* __restrict__ item_done) {
   static_assert(sizeof(LevelDesc) % sizeof(uint4) == 0, "descriptor copy granularity");
   const uint32_t n_items = min(hdr_src->n_items, cap);
   const uint64_t words = (uint64_t)n_items * (sizeof(LevelDesc) / sizeof(uint4));
@@ -877,6 +904,8 @@ __global__ void stage_kernel(const WorkHeader* __restrict__ hdr_src,
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words;
        i += (uint64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x)
+    item_done[i] = 0u;
   if (blockIdx.x == 0 && threadIdx.x < kChunkStreams) counter[threadIdx.x * kCounterStride] = 0u;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     WorkHeader h = *hdr_src;
@@ -999,15 +1028,11 @@ hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev,
-                         Stats* partials, Stats* groups, Stats* resident, Stats* mirror,
-                         int grid_groups, int grid_items, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_groups_kernel, dim3(grid_groups), dim3(kReduceThreads), 0, s,
-                     items_dev, hdr_dev, partials, groups);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reduce_items_kernel, dim3(grid_items), dim3(kReduceThreads), 0, s,
-                     items_dev, hdr_dev, groups, resident, mirror);
+hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev, Stats* partials,
+                         Stats* groups, unsigned int* item_done, Stats* resident, Stats* mirror,
+                         int grid, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(kReduceThreads), 0, s, items_dev, hdr_dev,
+                     partials, groups, item_done, resident, mirror);
   return hipGetLastError();
 }
 
@@ -1022,9 +1047,9 @@ hipError_t launch_tp(bool fp64, const LevelDesc* items_dev, const WorkHeader* hd
 
 hipError_t launch_stage(const WorkHeader* hdr_src, const LevelDesc* items_src, uint32_t cap,
                         WorkHeader* hdr_dst, LevelDesc* items_dst, unsigned int* counter,
-                        hipStream_t s) {
+                        unsigned int* item_done, hipStream_t s) {
   hipLaunchKernelGGL(stage_kernel, dim3(16), dim3(256), 0, s, hdr_src, items_src, cap, hdr_dst,
-                     items_dst, counter);
+                     items_dst, counter, item_done);
   return hipGetLastError();
 }
 

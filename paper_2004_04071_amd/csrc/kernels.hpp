@@ -26,20 +26,21 @@ hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev
 hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
                              const WorkHeader* hdr_dev, unsigned int* counter, Stats* partials,
                              int block, int grid, hipStream_t s);
-// Tile records -> group records -> resident slots (the tile records of a
-// time-parallel item are first built from its samples); `mirror` (host-mapped
-// pinned memory, or null) receives a copy of every slot written.
-hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev,
-                         Stats* partials, Stats* groups, Stats* resident, Stats* mirror,
-                         int grid_groups, int grid_items, hipStream_t s);
+// Tile records -> group records -> resident slots in one launch (the tile
+// records of a time-parallel item are first built from its samples);
+// item_done holds one counter per item, zeroed by the stage kernel; `mirror`
+// (host-mapped pinned memory, or null) receives a copy of every slot written.
+hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev, Stats* partials,
+                         Stats* groups, unsigned int* item_done, Stats* resident, Stats* mirror,
+                         int grid, hipStream_t s);
 // Time-parallel items of the table (one wavefront per trajectory, grid-stride).
 hipError_t launch_tp(bool fp64, const LevelDesc* items_dev, const WorkHeader* hdr_dev, int grid,
                      hipStream_t s);
 // Work table and header from host-mapped pinned memory to the device; clears
-// the persistent kernel's chunk counters.
+// the persistent kernel's chunk counters and the reduction's item counters.
 hipError_t launch_stage(const WorkHeader* hdr_src, const LevelDesc* items_src, uint32_t cap,
                         WorkHeader* hdr_dst, LevelDesc* items_dst, unsigned int* counter,
-                        hipStream_t s);
+                        unsigned int* item_done, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, uint64_t n, unsigned int v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_words(uint32_t key0, uint32_t key1, uint32_t strm, uint32_t tag,
