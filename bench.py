@@ -189,10 +189,9 @@ def main():
     log("estimate %.6f exact %.6f sd %.2e N %s" % (last["estimate"], exact,
                                                    math.sqrt(last["var_estimator"]), last["N"]))
 
-    # Dominant kernel: the particle kernels of each launch (the persistent
-    # kernel, preceded in a warm-up launch by the time-parallel kernel for
-    # its few long trajectories), launched directly so that HIP events on the
-    # launch stream time them.
+    # Dominant kernel: the persistent particle kernel (which also runs a
+    # warm-up launch's few long trajectories time-parallel), launched directly
+    # so that HIP events on the launch stream time it.
     direct = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=2, **tk))
     kern_s = direct["kernel_seconds"]
     launches = direct["launches"]
@@ -201,8 +200,7 @@ def main():
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12,
                     unit="TOP/s (full-rate VALU lane-slots)", frac=achieved / PEAK_SLOTS,
                     traffic=recorded_traffic(tuning),
-                    kernel="persistent_kernel<float,%d> (+ tp_kernel<float> in warm-up launches)"
-                    % tuning["ppt"],
+                    kernel="persistent_kernel<float,%d>" % tuning["ppt"],
                     avg_launch_ms=kern_s / launches * 1e3, launches=launches)
     out = {
         "metric": "particle-steps/s; MLMC time-to-RMSE 1e-3 vs plain MC; p50/p99 request latency",

@@ -793,9 +793,8 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Reductions.  Stage 1: group g of an item merges tiles [1024 g, 1024 g +
-// 1024): thread t merges its 4 consecutive tiles in order, then a fixed LDS
-// tree.  Stage 2 merges an item's group results the same way (thread t merges
+// Reductions.  Stage 1: group g of an item merges tiles [256 g, 256 g +
+// 256): thread t takes tile 256 g + t, then a fixed LDS tree.  Stage 2 merges an item's group results the same way (thread t merges
 // groups [t q, t q + q), q = ceil(n_groups / 256)) and folds the result into
 // the item's resident statistics slot.
 // ---------------------------------------------------------------------------
@@ -817,12 +816,17 @@ __device__ __forceinline__ void merge_item(const LevelDesc& d, const Stats* __re
                                            Stats* sh) {
   const uint64_t gbase = d.group_base;
   const uint32_t n_groups = d.n_groups;
-  Stats acc = stats_empty();
-  const uint32_t q = (n_groups + kReduceThreads - 1) / kReduceThreads;
-  const uint32_t first = threadIdx.x * q;
-  for (uint32_t idx = first; idx < n_groups && idx < first + q; ++idx)
-    acc = stats_merge(acc, groups[gbase + idx]);
-  block_tree(acc, sh);
+  if (n_groups > 1) {
+    Stats acc = stats_empty();
+    const uint32_t q = (n_groups + kReduceThreads - 1) / kReduceThreads;
+    const uint32_t first = threadIdx.x * q;
+    for (uint32_t idx = first; idx < n_groups && idx < first + q; ++idx)
+      acc = stats_merge(acc, groups[gbase + idx]);
+    block_tree(acc, sh);
+  } else if (threadIdx.x == 0) {
+    // the tree over one record and empties returns that record unchanged
+    sh[0] = groups[gbase];
+  }
   if (threadIdx.x == 0) {
     const uint32_t slot = d.result_slot;
     const Stats r = (d.flags & kFlagAccumulate) ? stats_merge(resident[slot], sh[0]) : sh[0];

@@ -5,7 +5,7 @@
 // with spl = 4 for levels of fewer than 64 fine steps and spl = 1 above (so
 // that one wavefront's serial work per tile stays short on the long levels).
 // Every tile is reduced by one wavefront into a Stats record, and the records
-// of an item are merged by a fixed tree (groups of 1024 tiles, then one group
+// of an item are merged by a fixed tree (groups of 256 tiles, then one group
 // result per item).  The tile size is a function of the level and the tree a
 // function of the item's sample count, so the statistics are bitwise
 // independent of launch shape, tuning, and of other items sharing a launch.
@@ -29,12 +29,12 @@ constexpr uint64_t kMinWideTiles = 1024;
 __host__ __device__ inline uint32_t samples_per_lane(uint32_t n_steps) {
   return n_steps >= kLongLevelSteps ? 1u : (n_steps >= kShortLevelSteps ? 4u : 16u);
 }
-constexpr int kGroupTiles = 1024;                // tiles per first-stage group
+constexpr int kGroupTiles = 256;                 // tiles per first-stage group
 constexpr int kReduceThreads = 256;
-constexpr int kReducePerThread = kGroupTiles / kReduceThreads;  // 4
+constexpr int kReducePerThread = kGroupTiles / kReduceThreads;  // 1
 // An item holds at most 2^32 samples (the sample counter word), so at most
-// 2^26 tiles and 2^16 groups.
-constexpr uint64_t kMaxGroupsPerItem = 1ull << 16;
+// 2^26 tiles and 2^18 groups.
+constexpr uint64_t kMaxGroupsPerItem = 1ull << 18;
 static_assert((uint64_t)kGroupTiles * kMaxGroupsPerItem * kLanes >= (1ull << 32),
               "an item of 2^32 samples must fit the two-stage reduction");
 
