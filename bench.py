@@ -7,13 +7,14 @@ workload (x0 ~ N(0,1), Maxwellian equilibrium, eps = 0.01, T = 1, dt0 = 0.5,
 M = 2, levels 0..8, RMSE 1e-3, FP32 particle state with FP64 statistics):
 warm-up samples on every level, optimal sample numbers, top-ups until the
 statistical constraint holds -- every level of an iteration in one persistent
-kernel launch replayed from a captured hipGraph.
+kernel launch (issued directly, the library's default).
 
 Printed: one JSON line.  ``value`` = particle-steps (fine + coarse) per
-second over the K timed estimates.  Extra fields: time-to-RMSE of the batched
-path, of plain per-level launches and of plain Monte Carlo at level 8; the
-eps-sweep batch; serving latency; the roofline of the particle kernel; the
-FP64 oracle timed on the host cores on a bounded sample.
+second over the K timed estimates.  Extra fields: time-to-RMSE of the same
+launches replayed from captured hipGraphs, of plain per-level launches and of
+plain Monte Carlo at level 8; the eps-sweep batch; serving latency; the
+roofline of the particle kernel; the FP64 oracle timed on the host cores on a
+bounded sample.
 """
 import argparse
 import json
@@ -173,7 +174,7 @@ def main():
     log("tuning", tuning)
     tk = dict(block=tuning["block"], ppt=tuning["ppt"], waves_per_simd=tuning["waves_per_simd"])
 
-    opt = pkg.options(batched=1, **tk)
+    opt = pkg.options(batched=0, **tk)
     for _ in range(args.warmup):
         pkg.mlmc_ap_estimate(prob, tol, opt)
     torch.cuda.synchronize()
@@ -230,18 +231,25 @@ def main():
         t0 = time.perf_counter()
         reps = 3
         for _ in range(reps):
-            pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=0, **tk))
+            pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=-1, **tk))
         per_level_ms = (time.perf_counter() - t0) / reps * 1e3
         # plain Monte Carlo at level 8
         t0 = time.perf_counter()
         mc = pkg.mlmc_ap_plain_mc(prob, tol)
         plain_ms = (time.perf_counter() - t0) * 1e3
+        # the same persistent launches replayed from captured hipGraphs
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=1, **tk))
+        graph_ms = (time.perf_counter() - t0) / reps * 1e3
+        out["graph_replay_time_to_rmse_ms"] = graph_ms
         out["per_level_launch_time_to_rmse_ms"] = per_level_ms
         out["plain_mc_time_to_rmse_ms"] = plain_ms
         out["plain_mc_particle_steps"] = mc["particle_steps"]
         out["mlmc_speedup_vs_plain_mc"] = plain_ms / ms_per
         out["batched_speedup_vs_per_level"] = per_level_ms / ms_per
-        log("per-level %.2f ms, batched %.2f ms, plain MC %.2f ms" % (per_level_ms, ms_per, plain_ms))
+        log("per-level %.2f ms, batched %.2f ms (graph replay %.2f ms), plain MC %.2f ms"
+            % (per_level_ms, ms_per, graph_ms, plain_ms))
 
         # eps sweep: 15 requests in one batched launch per iteration vs one by one
         probs, tols = W.cfg3()
@@ -251,7 +259,7 @@ def main():
         batch_ms = (time.perf_counter() - t0) * 1e3
         t0 = time.perf_counter()
         for p, t in zip(probs, tols):
-            pkg.mlmc_ap_estimate(p, t, pkg.options(batched=0))
+            pkg.mlmc_ap_estimate(p, t, pkg.options(batched=-1))
         seq_ms = (time.perf_counter() - t0) * 1e3
         out["eps_sweep"] = dict(requests=len(probs), batched_ms=batch_ms,
                                 per_level_sequential_ms=seq_ms,

@@ -155,11 +155,15 @@ typedef struct mlmc_ap_tuning {
 } mlmc_ap_tuning;
 
 typedef struct mlmc_ap_options {
-    int32_t batched;        /* 1: all levels of an iteration in one persistent
-                               launch replayed from a captured hipGraph (default);
-                               0: one plain launch per level;
-                               2: the persistent launch issued directly (no graph),
-                                  so kernel_seconds is measured */
+    int32_t batched;        /* 0 = 3 (default): all levels of an iteration in one
+                                  persistent launch (stage, persistent, reduce
+                                  kernels) issued directly;
+                               1: the same launch replayed from a captured hipGraph
+                                  (one graph per launch shape, kept by the library);
+                               2: as 3, with HIP events around the particle kernel,
+                                  so kernel_seconds is measured;
+                               -1: one plain launch per level.
+                               All four give bitwise identical results. */
     int32_t max_iter;       /* MLMC top-up iterations after warm-up (0 = 10) */
     uint64_t n_warmup;      /* warm-up samples per level (0 = 1000) */
     mlmc_ap_tuning tuning;

@@ -492,7 +492,7 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
 
   MLMC_HIP(hipEventRecord(ws.ev[0], stream));
   bool kernel_timed = false;
-  if (mode == 0) {
+  if (mode == kModePerLevel) {
     MLMC_TRY(stage(ws, stream));
     MLMC_HIP(hipEventRecord(ws.ev[1], stream));
     if (has_tp) MLMC_HIP(launch_tp(fp64, ws.items_dev, ws.hdr_dev, tp_grid(ws), stream));
@@ -503,15 +503,15 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
     MLMC_HIP(hipEventRecord(ws.ev[2], stream));
     MLMC_TRY(reduce(ws, stream));
     kernel_timed = true;
-  } else if (mode == 2) {
+  } else if (mode == kModeTimed || mode == kModeDirect) {
+    kernel_timed = mode == kModeTimed;
     MLMC_TRY(stage(ws, stream));
-    MLMC_HIP(hipEventRecord(ws.ev[1], stream));
+    if (kernel_timed) MLMC_HIP(hipEventRecord(ws.ev[1], stream));
     MLMC_HIP(launch_persistent(fp64, tuning.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev,
                                ws.partials, tuning.block, persistent_grid(ws, tuning), stream));
-    MLMC_HIP(hipEventRecord(ws.ev[2], stream));
+    if (kernel_timed) MLMC_HIP(hipEventRecord(ws.ev[2], stream));
     MLMC_TRY(reduce(ws, stream));
-    kernel_timed = true;
-  } else {
+  } else if (mode == kModeGraph) {
     const uint64_t key = ((uint64_t)tuning.block << 48) ^ ((uint64_t)tuning.ppt << 40) ^
                          ((uint64_t)tuning.waves_per_simd << 32) ^ (fp64 ? 1ull : 2ull) ^
                          ((uint64_t)(uintptr_t)ws.partials << 3);
@@ -537,6 +537,8 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
       it = ws.graphs.emplace(key, entry).first;
     }
     MLMC_HIP(hipGraphLaunch(it->second.exec, stream));
+  } else {
+    return set_error(MLMC_AP_EINVAL, "unknown launch mode");
   }
   MLMC_HIP(hipEventRecord(ws.ev[3], stream));
   // Poll the launch's last event instead of a blocking wait: the MLMC loop
@@ -560,6 +562,17 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
     }
   }
   return MLMC_AP_OK;
+}
+
+int launch_mode(int32_t batched) {
+  switch (batched) {
+    case -1: return kModePerLevel;
+    case 0: return kModeDirect;
+    case 1: return kModeGraph;
+    case 2: return kModeTimed;
+    case 3: return kModeDirect;
+    default: return -1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -691,7 +704,6 @@ double now_s() {
 mlmc_ap_options default_options(const mlmc_ap_options* opt) {
   mlmc_ap_options o;
   std::memset(&o, 0, sizeof(o));
-  o.batched = 1;
   if (opt) o = *opt;
   if (o.max_iter <= 0) o.max_iter = 10;
   if (o.n_warmup == 0) o.n_warmup = 1000;
@@ -857,7 +869,7 @@ mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, i
   it.coll = coll_dev;
   it.accumulate = false;
   const mlmc_ap_tuning t = resolve_tuning(*ws, nullptr);
-  MLMC_TRY(run_table(*ws, std::vector<ItemSpec>{it}, 1, 0, t, s, nullptr));
+  MLMC_TRY(run_table(*ws, std::vector<ItemSpec>{it}, 1, kModePerLevel, t, s, nullptr));
   *out_host = stats_to_api(ws->resident_host[0]);
   if (hist) {
     MLMC_HIP(hipMemcpy(hist_host, ws->hist_dev, hist_n * sizeof(uint64_t), hipMemcpyDeviceToHost));
@@ -877,7 +889,8 @@ static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* to
       return set_error(MLMC_AP_EINVAL, "a batch cannot mix FP32 and FP64 particle state");
   }
   const mlmc_ap_options o = default_options(opt);
-  if (o.batched < 0 || o.batched > 2) return set_error(MLMC_AP_EINVAL, "options.batched must be 0, 1 or 2");
+  const int mode = launch_mode(o.batched);
+  if (mode < 0) return set_error(MLMC_AP_EINVAL, "options.batched must be -1, 0, 1, 2 or 3");
   Workspace* ws = workspace();
   if (!ws) return MLMC_AP_EDEVICE;
   std::lock_guard<std::mutex> lk(ws->mu);
@@ -896,7 +909,7 @@ static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* to
     MLMC_HIP(launch_fill_u64(ws->hist_dev, hist_stride * MLMC_AP_MAX_LEVELS, 0ull, s));
     hist_dev = ws->hist_dev;
   }
-  MLMC_TRY(run_requests(*ws, reqs, o.batched, t, s, hist_dev, hist_stride));
+  MLMC_TRY(run_requests(*ws, reqs, mode, t, s, hist_dev, hist_stride));
   const double el = now_s() - t0;
   for (int i = 0; i < n_req; ++i) {
     reqs[i].fill_result(&out[i]);

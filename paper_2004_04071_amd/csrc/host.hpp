@@ -132,14 +132,22 @@ int persistent_grid(const Workspace& ws, const mlmc_ap_tuning& t);
 // Device time measured by one launch of a table.
 struct LaunchTiming {
   double total_s = 0.0;   // table upload to statistics read-back
-  double kernel_s = 0.0;  // particle kernel(s) only (0 when replayed from a graph)
+  double kernel_s = 0.0;  // particle kernel(s) only (kModeTimed and kModePerLevel, else 0)
 };
 
+// Launch forms of a work table (all give bitwise identical results).
+enum LaunchMode : int {
+  kModePerLevel = 0,  // one plain launch per item
+  kModeGraph = 1,     // stage, persistent, reduce replayed from a captured graph
+  kModeTimed = 2,     // the three kernels issued directly, HIP events around the particle kernel
+  kModeDirect = 3,    // the three kernels issued directly
+};
+// Maps mlmc_ap_options.batched to a launch mode (-1 if invalid).
+int launch_mode(int32_t batched);
+
 // Builds the work table of `items` (assigning tile, group and chunk bases),
-// launches it in the given mode and reads the resident statistics slots
-// [0, n_slots) back into ws.resident_host.  Mode: 0 plain per-item launches,
-// 1 persistent kernel replayed from a captured graph, 2 persistent kernel
-// launched directly (timed with events).
+// launches it in the given mode and leaves the updated resident statistics
+// slots in ws.resident_host (written by the reduction).
 mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& items, size_t n_slots,
                          int mode, const mlmc_ap_tuning& tuning, hipStream_t stream,
                          LaunchTiming* timing);

@@ -131,7 +131,7 @@ mlmc_ap_status mlmc_ap_server::tick(int32_t* n_completed, std::vector<uint64_t>*
   stats.bytes_peak = std::max(stats.bytes_peak, used);
   if (!items.empty()) {
     LaunchTiming t;
-    MLMC_TRY(run_table(ws, items, (size_t)cfg.max_active * MLMC_AP_MAX_LEVELS, 1, tuning, stream,
+    MLMC_TRY(run_table(ws, items, (size_t)cfg.max_active * MLMC_AP_MAX_LEVELS, kModeDirect, tuning, stream,
                        &t));
     stats.ticks++;
     const double tnow = now_s();

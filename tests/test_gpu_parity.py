@@ -245,10 +245,11 @@ def test_estimate_bitwise_across_modes_and_tunings():
     prob = W.cfg2(eps=0.05)
     base = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=1))
     say("estimate", base["estimate"], "N", base["N"])
-    for opt in (pkg.options(batched=0), pkg.options(batched=2),
+    for opt in (pkg.options(batched=-1), pkg.options(batched=2), pkg.options(batched=0),
+                pkg.options(batched=3),
                 pkg.options(batched=1, block=64, ppt=1, waves_per_simd=2),
                 pkg.options(batched=2, block=128, ppt=2, waves_per_simd=8),
-                pkg.options(batched=0, block=256, ppt=1)):
+                pkg.options(batched=-1, block=256, ppt=1)):
         r = pkg.mlmc_ap_estimate(prob, 1e-2, opt)
         assert _key(r) == _key(base)
 

@@ -101,7 +101,7 @@ def key(r):
             tuple(tuple(sorted(l.items())) for l in r["levels"]))
 
 
-@pytest.mark.parametrize("batched", [0, 1, 2])
+@pytest.mark.parametrize("batched", [-1, 0, 1, 2])
 def test_estimates_equal_with_and_without_time_parallel(batched):
     """The warm-up of an L = 8 estimate runs its long levels time-parallel;
     the estimate is bitwise the same with the path switched off."""
