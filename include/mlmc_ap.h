@@ -148,7 +148,8 @@ typedef struct mlmc_ap_level_info {
 typedef struct mlmc_ap_tuning {
     int32_t block;          /* threads per block: 64, 128 or 256 */
     int32_t ppt;            /* trajectories in flight per thread: 1, 2 or 4 */
-    int32_t waves_per_simd; /* persistent grid occupancy target, 1..8 */
+    int32_t waves_per_simd; /* persistent grid occupancy target, 1..8 (capped at
+                               what the kernel's registers allow) */
     int32_t tp_max_samples; /* time-parallel path for work items of at most this
                                many samples with >= 64 fine steps (pairs: M = 2
                                or 4); 0 = 4096, < 0 = never */

@@ -397,11 +397,20 @@ mlmc_ap_tuning resolve_tuning(const Workspace& ws, const mlmc_ap_tuning* t) {
   return r;
 }
 
-int persistent_grid(const Workspace& ws, const mlmc_ap_tuning& t) {
+int persistent_grid(Workspace& ws, const mlmc_ap_tuning& t, bool fp64) {
   const int waves_per_block = t.block / kLanes;
   const int waves = ws.n_cu * 4 * t.waves_per_simd;
+  int grid = (waves + waves_per_block - 1) / waves_per_block;
+  // no more blocks than fit the GPU at once: a block that waits for a free
+  // slot would start its statically assigned work (one-round launches,
+  // time-parallel trajectories) only after the others finish
+  const int key = (fp64 ? 1 : 0) | (t.ppt << 1) | (t.block << 4);
+  auto it = ws.blocks_per_cu.find(key);
+  if (it == ws.blocks_per_cu.end())
+    it = ws.blocks_per_cu.emplace(key, persistent_blocks_per_cu(fp64, t.ppt, t.block)).first;
+  if (it->second > 0) grid = std::min(grid, ws.n_cu * it->second);
   // every chunk stream needs blocks
-  return std::max((int)kChunkStreams, (waves + waves_per_block - 1) / waves_per_block);
+  return std::max((int)kChunkStreams, grid);
 }
 
 static mlmc_ap_status check_tuning(const mlmc_ap_tuning& t) {
@@ -438,7 +447,7 @@ static mlmc_ap_status record_device_work(Workspace& ws, bool fp64, const mlmc_ap
                                          hipStream_t s) {
   MLMC_TRY(stage(ws, s));
   MLMC_HIP(launch_persistent(fp64, t.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev, ws.partials,
-                             t.block, persistent_grid(ws, t), s));
+                             t.block, persistent_grid(ws, t, fp64), s));
   MLMC_TRY(reduce(ws, s));
   return MLMC_AP_OK;
 }
@@ -508,7 +517,7 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
     MLMC_TRY(stage(ws, stream));
     if (kernel_timed) MLMC_HIP(hipEventRecord(ws.ev[1], stream));
     MLMC_HIP(launch_persistent(fp64, tuning.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev,
-                               ws.partials, tuning.block, persistent_grid(ws, tuning), stream));
+                               ws.partials, tuning.block, persistent_grid(ws, tuning, fp64), stream));
     if (kernel_timed) MLMC_HIP(hipEventRecord(ws.ev[2], stream));
     MLMC_TRY(reduce(ws, stream));
   } else if (mode == kModeGraph) {

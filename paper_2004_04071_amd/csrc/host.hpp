@@ -110,6 +110,7 @@ struct Workspace {
     hipGraphExec_t exec = nullptr;
   };
   std::map<uint64_t, Graph> graphs;
+  std::map<int, int> blocks_per_cu;  // persistent-kernel occupancy by (precision, ppt, block)
   void drop_graphs();
 
   mlmc_ap_tuning tuning{};      // current default (autotuned or built-in)
@@ -127,7 +128,7 @@ Workspace* workspace();  // of the current device (created on first use)
 // Sets up a private workspace on the current device (the serving loop owns one).
 mlmc_ap_status init_workspace(Workspace& ws);
 mlmc_ap_tuning resolve_tuning(const Workspace& ws, const mlmc_ap_tuning* t);
-int persistent_grid(const Workspace& ws, const mlmc_ap_tuning& t);
+int persistent_grid(Workspace& ws, const mlmc_ap_tuning& t, bool fp64);
 
 // Device time measured by one launch of a table.
 struct LaunchTiming {

@@ -1013,6 +1013,25 @@ hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev
   return launch_level_p<float, 4>(kind, items_dev, item, n_tiles, block, partials, s);
 }
 
+int persistent_blocks_per_cu(bool fp64, int ppt, int block) {
+  int nb = 0;
+  hipError_t e;
+  if (fp64) {
+    if (ppt == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<double, 1>, block, 0);
+    else if (ppt == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<double, 2>, block, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<double, 4>, block, 0);
+  } else {
+    if (ppt == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<float, 1>, block, 0);
+    else if (ppt == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<float, 2>, block, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<float, 4>, block, 0);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
 hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
                              const WorkHeader* hdr_dev, unsigned int* counter, Stats* partials,
                              int block, int grid, hipStream_t s) {

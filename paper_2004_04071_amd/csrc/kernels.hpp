@@ -23,6 +23,9 @@ constexpr uint32_t kCounterStride = 32;
 
 hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev, uint32_t item,
                         uint32_t n_tiles, int block, Stats* partials, hipStream_t s);
+// Blocks of `block` threads of the persistent kernel that fit one CU at once
+// (0 if the runtime cannot say).
+int persistent_blocks_per_cu(bool fp64, int ppt, int block);
 hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
                              const WorkHeader* hdr_dev, unsigned int* counter, Stats* partials,
                              int block, int grid, hipStream_t s);
