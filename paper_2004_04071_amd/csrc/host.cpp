@@ -24,7 +24,7 @@ constexpr double kTwo32 = 4294967296.0;
 // Fine steps per lane a persistent-kernel chunk aims at (load balance versus
 // work-counter traffic); chunks never exceed 64 tiles, and on the long levels
 // a chunk is a single tile so that the slowest chunks end early.
-constexpr uint64_t kChunkLaneSteps = 256;
+constexpr uint64_t kChunkLaneSteps = 128;
 constexpr uint64_t kMinChunksPerItem = 64;
 }  // namespace
 
@@ -181,7 +181,8 @@ LevelDesc make_desc(const ItemSpec& s, bool tp) {
   d.key1 = (uint32_t)(p.seed >> 32);
   d.flags = (coarse ? kFlagCoarse : 0u) | (maxwell ? kFlagMaxwell : 0u) |
             (agg ? kFlagAggregate : 0u) | (s.hist ? kFlagHist : 0u) |
-            (s.accumulate ? kFlagAccumulate : 0u);
+            (s.accumulate ? kFlagAccumulate : 0u) |
+            ((s.hist || s.traj || s.coll) ? kFlagSampleOutputs : 0u);
   if (d.thr_f == 0 || d.thr_c2 == 0) d.flags |= kFlagWide;
   d.kind = coarse ? (maxwell ? (agg ? kKindPairMaxwellAggregate : kKindPairMaxwellSum)
                              : kKindPairTwoPointSum)

@@ -457,7 +457,8 @@ __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
       if (r == 0 && p == 0) acc.shift<kCoarse>(dq, qf, qc);  // lane 0, sample 0 always exists
       if (valid[p]) {
         acc.add<kCoarse>(dq, qf, qc, st.cf[p], st.cc[p]);
-        sample_outputs<Real, kCoarse>(d, local[p], xf, xc, st.cf[p], st.cc[p]);
+        if (d.flags & kFlagSampleOutputs)  // one test on the common path
+          sample_outputs<Real, kCoarse>(d, local[p], xf, xc, st.cf[p], st.cc[p]);
       }
     }
   }
@@ -612,7 +613,7 @@ __device__ __forceinline__ void run_tp(const LevelDesc& d, uint32_t local) {
     r.cf = cf;
     r.cc = cc;
     d.tp_out[local] = r;
-    sample_outputs<Real, kCoarse>(d, local, xf, xc, cf, cc);
+    if (d.flags & kFlagSampleOutputs) sample_outputs<Real, kCoarse>(d, local, xf, xc, cf, cc);
   }
 }
 

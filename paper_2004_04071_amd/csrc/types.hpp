@@ -47,6 +47,7 @@ enum : uint32_t {
   kFlagWide = 1u << 4,        // a decision threshold is 0: 64-bit compares
   kFlagAccumulate = 1u << 6,  // merge into the resident statistics (else overwrite)
   kFlagTimeParallel = 1u << 7,  // one trajectory per wavefront, steps across lanes
+  kFlagSampleOutputs = 1u << 8, // a dump or a histogram is requested
 };
 
 // Final state of one sample of a time-parallel item.
