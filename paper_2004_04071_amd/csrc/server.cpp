@@ -44,15 +44,26 @@ struct ServerReq {
   double t_done = 0.0;
 };
 
-// Device bytes a request can need in one tick: its resident statistics and
-// the tile partials and group results of at most max_per_tick samples on
-// every level.
-uint64_t tick_bytes(const McRequest& mc) {
+// Device bytes a request can need in one tick besides its resident
+// statistics: per level, the tile partials and group results of at most
+// max_per_tick samples, the final states of a time-parallel item (at most
+// kTpDefaultMaxSamples samples; a server that raises the limit through its
+// tuning is charged for that limit), the descriptor and the item counter.
+uint64_t tick_bytes(const McRequest& mc, int32_t tp_max_samples) {
   const uint64_t levels = (uint64_t)(mc.prob.L + 1);
   const uint64_t per_level = std::max<uint64_t>(mc.n_warmup, mc.max_per_tick);
   const uint64_t tiles = (per_level + kLanes - 1) / kLanes;  // 64-sample tiles at worst
   const uint64_t groups = (tiles + kGroupTiles - 1) / kGroupTiles;
-  return levels * (tiles + groups) * sizeof(Stats) + levels * sizeof(LevelDesc);
+  const uint64_t tp_limit =
+      tp_max_samples < 0 ? 0 : (tp_max_samples == 0 ? (uint64_t)kTpDefaultMaxSamples
+                                                      : (uint64_t)tp_max_samples);
+  uint64_t tp_levels = 0;  // levels that can run time-parallel
+  for (int l = 0; l <= mc.prob.L; ++l)
+    if (level_const(mc.prob, l).n_steps >= (int64_t)kLongLevelSteps &&
+        (l == 0 || mc.prob.M == 2 || mc.prob.M == 4))
+      ++tp_levels;
+  return levels * ((tiles + groups) * sizeof(Stats) + sizeof(LevelDesc) + sizeof(unsigned int)) +
+         tp_levels * std::min(per_level, tp_limit) * sizeof(TpSample);
 }
 
 uint64_t state_bytes() { return (uint64_t)MLMC_AP_MAX_LEVELS * sizeof(Stats); }
@@ -97,7 +108,7 @@ mlmc_ap_status mlmc_ap_server::tick(int32_t* n_completed, std::vector<uint64_t>*
   for (ServerReq* r : active) {
     std::vector<ItemSpec> mine;
     if (!r->mc.plan(mine, (uint32_t)(r->region * MLMC_AP_MAX_LEVELS), nullptr, 0)) continue;
-    const uint64_t b = tick_bytes(r->mc);
+    const uint64_t b = tick_bytes(r->mc, tuning.tp_max_samples);
     if (used + b > budget) continue;  // deferred to a later tick
     used += b;
     items.insert(items.end(), mine.begin(), mine.end());
@@ -109,7 +120,7 @@ mlmc_ap_status mlmc_ap_server::tick(int32_t* n_completed, std::vector<uint64_t>*
       queue.pop_front();
       continue;
     }
-    const uint64_t b = tick_bytes(r->mc) + state_bytes();
+    const uint64_t b = tick_bytes(r->mc, tuning.tp_max_samples) + state_bytes();
     if (used + b > budget) break;  // FIFO: wait for memory
     queue.pop_front();
     r->region = free_regions.back();
@@ -205,7 +216,7 @@ mlmc_ap_status mlmc_ap_server_submit(mlmc_ap_server* srv, const mlmc_ap_problem*
   std::unique_ptr<ServerReq> r(new ServerReq());
   r->mc.init(*p, rmse_tol, false, srv->cfg.options.n_warmup, srv->cfg.options.max_iter,
              srv->cfg.max_samples_per_tick);
-  if (tick_bytes(r->mc) + state_bytes() > srv->cfg.hbm_budget_bytes) {
+  if (tick_bytes(r->mc, srv->tuning.tp_max_samples) + state_bytes() > srv->cfg.hbm_budget_bytes) {
     srv->stats.rejected++;
     return set_error(MLMC_AP_EBUSY, "request can never fit the server's memory budget");
   }

@@ -76,9 +76,11 @@ def test_alone_equals_mix_equals_estimate():
 def test_tight_budget_queues_and_keeps_results():
     cap = 4096
     ref, _ = serve(REQS, max_samples_per_tick=cap)
-    # each request needs about 9 levels x 65 tiles x 80 B per tick: two fit at once
+    # with the time-parallel path off, each request needs about 9 levels x 65
+    # tiles x 80 B per tick: two fit at once (results do not depend on the path)
     budget = 120 * 1024
-    tight, st = serve(REQS, hbm_budget_bytes=budget, max_samples_per_tick=cap)
+    tight, st = serve(REQS, hbm_budget_bytes=budget, max_samples_per_tick=cap,
+                      opt=pkg.options(tp_max_samples=-1))
     assert st["bytes_peak"] <= budget
     assert st["completed"] == len(REQS)
     for a, b in zip(ref, tight):
