@@ -365,7 +365,7 @@ mlmc_ap_status init_workspace(Workspace& ws) {
   MLMC_HIP(hipStreamCreateWithFlags(&ws.capture_stream, hipStreamNonBlocking));
   for (auto& e : ws.ev) MLMC_HIP(hipEventCreate(&e));
   ws.tuning.block = 256;
-  ws.tuning.ppt = 4;
+  ws.tuning.ppt = 1;  // measured best on every level (one sample in flight per lane)
   ws.tuning.waves_per_simd = 4;
   return MLMC_AP_OK;
 }
