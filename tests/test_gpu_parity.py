@@ -151,6 +151,12 @@ CASES = {
     "cfg4_cos_l2_fp32": (dict(W.cfg4(0), qoi=0), 2, 900, 0, False),
     "cfg4_cos_l2_fp64": (dict(W.cfg4(1), qoi=0), 2, 900, 0, False),
     "cfg2_fp64_l3": (dict(W.cfg2(), fp64_state=1), 3, 500, 0, False),
+    # M = 3: coarse blocks at run-time positions, groups of four steps with a tail
+    "maxwell_M3_agg_l2": (dict(W.cfg2(eps=0.05), M=3, L=3, T=1.5, dt0=0.5), 2, 600, 7, False),
+    "twopoint_M3_l2": (dict(W.cfg1(), fp64_state=0, M=3, L=3, T=0.3, dt0=0.1), 2, 600, 0, False),
+    "maxwell_M3_single_l3": (dict(W.cfg2(eps=0.3), M=3, L=3, T=1.5, dt0=0.5), 3, 300, 0, True),
+    # an odd step count at level 0 (tail of three steps, then 6 and 12 at levels 1, 2)
+    "maxwell_n0_3_l1": (dict(W.cfg2(eps=0.2), T=1.5, dt0=0.5), 1, 600, 0, False),
 }
 
 
