@@ -6,8 +6,10 @@ it imports nothing from the product package.
 
 Contents
 --------
-``oracle.c``           particle scheme, fine/coarse correlation, Philox4x32-10
-                       (plain C, double precision, one trajectory at a time)
+``oracle.c``           particle schemes (asymptotic-preserving splitting and the
+                       kinetic-diffusion scheme), fine/coarse correlation,
+                       Philox4x32-10 (plain C, double precision, one
+                       trajectory at a time)
 ``closed_form.py``     exact second moment of the discrete scheme and its
                        kinetic and diffusive limits
 ``mlmc.py``            two-pass level statistics, optimal sample numbers
@@ -27,6 +29,7 @@ _lib = None
 X0_DELTA, X0_NORMAL, X0_COSINE = 0, 1, 2
 EQ_TWO_POINT, EQ_MAXWELLIAN = 0, 1
 COUPLING_KICK_SUM, COUPLING_AGGREGATE = 0, 1
+SCHEME_SPLITTING, SCHEME_KD = 0, 1
 
 
 def lib():
@@ -63,6 +66,15 @@ def lib():
         L.oracle_words.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, u32p]
         L.oracle_words.restype = None
+        L.oracle_simulate_kd.argtypes = L.oracle_simulate.argtypes
+        L.oracle_simulate_kd.restype = ctypes.c_int
+        L.oracle_kd_coeffs.argtypes = [ctypes.c_double] * 5 + [dp]
+        L.oracle_kd_coeffs.restype = None
+        L.oracle_kd_coarse_numbers.argtypes = [
+            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+            ctypes.c_uint64, dp, ctypes.c_uint64, dp]
+        L.oracle_kd_coarse_numbers.restype = ctypes.c_uint64
         _lib = L
     return _lib
 
@@ -117,10 +129,15 @@ def simulate(prob, level, sample_begin=0, n=None, samples=None, single=False, th
     """Final positions and collision counts of fine/coarse pairs.
 
     ``prob`` is a dict with keys eps, T, dt0, M, x0_kind, x0_a, x0_b, eq_kind,
-    coupling, seed, stream_id.  Either a contiguous range
-    [sample_begin, sample_begin+n) or an explicit index array ``samples``.
-    Returns dict(xf, xc, cf, cc) of numpy arrays.
+    coupling, seed, stream_id and optionally scheme (SCHEME_SPLITTING, the
+    default, or SCHEME_KD: the kinetic-diffusion scheme, Maxwellian only;
+    its counts are KD steps, i.e. collisions before T).  Either a contiguous
+    range [sample_begin, sample_begin+n) or an explicit index array
+    ``samples``.  Returns dict(xf, xc, cf, cc) of numpy arrays.
     """
+    kd = int(prob.get("scheme", SCHEME_SPLITTING)) == SCHEME_KD
+    if kd and int(prob["eq_kind"]) != EQ_MAXWELLIAN:
+        raise ValueError("the KD scheme needs the Maxwellian equilibrium")
     if samples is not None:
         idx = np.ascontiguousarray(samples, dtype=np.uint64)
         count = idx.size
@@ -134,7 +151,8 @@ def simulate(prob, level, sample_begin=0, n=None, samples=None, single=False, th
     cf = np.zeros(count, dtype=np.uint32)
     cc = np.zeros(count, dtype=np.uint32)
     if count:
-        lib().oracle_simulate(*_common_args(prob, level, single), int(sample_begin), idx_p,
+        fn = lib().oracle_simulate_kd if kd else lib().oracle_simulate
+        fn(*_common_args(prob, level, single), int(sample_begin), idx_p,
                               count, _ptr(xf, ctypes.c_double), _ptr(xc, ctypes.c_double),
                               _ptr(cf, ctypes.c_uint32), _ptr(cc, ctypes.c_uint32),
                               int(threads or default_threads()))
@@ -163,3 +181,29 @@ def words(seed, stream_id, tag, sample_begin, n_samples, n_steps):
     lib().oracle_words(int(seed), int(stream_id), int(tag), int(sample_begin), int(n_samples),
                        int(n_steps), _ptr(out, ctypes.c_uint32))
     return out
+
+
+def kd_coeffs(theta, R, mu, sigma, v_next):
+    """(a, d): advection and diffusion coefficient of a KD diffusive phase of
+    length theta ending with velocity v_next (eqs. advection and diffusion,
+    homogeneous background with collision rate R and Maxwellian N(mu,
+    sigma^2))."""
+    out = np.zeros(2)
+    lib().oracle_kd_coeffs(float(theta), float(R), float(mu), float(sigma), float(v_next),
+                           _ptr(out, ctypes.c_double))
+    return float(out[0]), float(out[1])
+
+
+def kd_coarse_numbers(prob, level, sample, cap=None):
+    """Coarse numbers of one KD pair, one row per coarse KD step:
+    (chi~, nu~, E~, fine KD steps aggregated), and the final (x_f, x_c)."""
+    if cap is None:
+        cap = int(round(prob["T"] / prob["dt0"])) * int(prob["M"]) ** level + 2
+    rows = np.zeros((cap, 4))
+    fin = np.zeros(2)
+    used = lib().oracle_kd_coarse_numbers(
+        float(prob["eps"]), float(prob["T"]), float(prob["dt0"]), int(prob["M"]), int(level),
+        int(prob["x0_kind"]), float(prob.get("x0_a", 0.0)), float(prob.get("x0_b", 0.0)),
+        int(prob.get("seed", 42)), int(prob.get("stream_id", 0)), int(sample),
+        _ptr(rows, ctypes.c_double), cap, _ptr(fin, ctypes.c_double))
+    return rows[:used], fin

@@ -399,3 +399,308 @@ void oracle_words(uint64_t seed, uint32_t stream, uint32_t tag,
         }
     }
 }
+
+/* ================================================================== */
+/* Kinetic-diffusion (KD) scheme, homogeneous background              */
+/* ================================================================== */
+/*
+ * The paper's own simulation scheme (Section 2, Algorithm "KD algorithm")
+ * and its correlated fine/coarse form (Section 3, Algorithm "Correlated KD
+ * algorithm"), in the diffusive scaling of the BGK equation above: constant
+ * collision rate R = 1/eps^2, post-collision velocities drawn from the
+ * Maxwellian with mean mu = 0 and standard deviation sigma = 1/eps.
+ *
+ * A KD step of a path with time step dt starts on the time grid at t with
+ * velocity v and a pending collision at c = t + tau (tau = E/R, E ~ Exp(1)).
+ * If c < T: the path moves kinetically to c, then diffusively to the end
+ * of the grid step that contains c (length theta), with the advection a
+ * (eq. advection) and diffusion d (eq. diffusion) conditioned on the next
+ * velocity, and a new flight is drawn (eq. position-update, eq.
+ * time-update).  Once the pending collision is at or after T the path
+ * moves kinetically to T.
+ *
+ * Random numbers of one trajectory: Philox block 0 holds the initial
+ * condition (W0, W1: Box-Muller pair, cosine branch -> x0 for the normal
+ * law, sine branch -> nu_0; W2 -> E_0 = -log u; W3 -> u of the cosine
+ * law); block k+1 holds the numbers of KD step k (W0, W1: Box-Muller pair,
+ * cosine branch -> nu_{k+1}, sine branch -> chi_k; W2 -> E_{k+1}).
+ * Counter (block, sample, level tag, stream) as for the splitting scheme.
+ *
+ * Correlated pair (level l >= 1): the coarse path (step dt_{l-1} = M dt_l)
+ * takes its numbers from the fine path (Section 3.1 mapping by the time at
+ * which they act; Section 3.2 aggregation):
+ *   - its flight k uses the fine flight kappa_k: the same velocity number
+ *     (eq. nu-update), and the exponential number reduced by the part of
+ *     the flight the fine path has already used (eq. epsilon-update); in a
+ *     homogeneous background the coarse collision therefore falls at the
+ *     same time as the fine one;
+ *   - its diffusive phase k aggregates, by eq. chi-update, the fine
+ *     diffusive numbers chi_m and the fine velocity numbers nu_m of the
+ *     fine phases that follow flight kappa_k up to the first fine flight
+ *     whose collision lies after the end of the coarse grid step; the
+ *     weights are alpha_m = sigma tau'_m and beta_m = the unconditioned
+ *     diffusive standard deviation over theta'_m (eq. weights-beta), with
+ *     the expected time zeta_m = (1 - e^{-R theta_m})/R moved from each
+ *     diffusive phase to the next flight.
+ *
+ * PARITY: pinned by the CPU tests (the second moment of x(T), which the KD
+ * construction keeps exact at every dt; the conditional moments of a
+ * diffusive phase against a brute-force velocity-jump simulation; the laws
+ * of the aggregated coarse numbers; the coarse path against the fine path
+ * of the level below).
+ */
+
+/* Stable evaluations of three functions of y = R theta >= 0 that lose
+ * all their digits to cancellation when written with exp for small y
+ * (exact up to rounding; the series are their Taylor expansions):
+ *   kd_h(y) = e^{-y} - 1 + y                  = sum_{m>=2} (-y)^m/m!
+ *   kd_f(y) = 2(e^{-y} - 1) + y(e^{-y} + 1)   = sum_{m>=3} (-1)^{m+1} (m-2) y^m/m!
+ *   kd_g(y) = 1 - 2y e^{-y} - e^{-2y}         = sum_{m>=3} (-1)^{m+1} (2^m - 2m) y^m/m!
+ */
+#define KD_SERIES_Y 0.05
+#define KD_SERIES_TERMS 16
+
+static double kd_h(double y)
+{
+    if (y >= KD_SERIES_Y) return expm1(-y) + y;
+    double s = 0.0, term = 1.0;
+    for (int m = 1; m <= KD_SERIES_TERMS; ++m) {
+        term *= -y / (double)m;           /* (-y)^m / m! */
+        if (m >= 2) s += term;
+    }
+    return s;
+}
+
+static double kd_f(double y)
+{
+    if (y >= KD_SERIES_Y) {
+        double e = exp(-y);
+        return 2.0 * (e - 1.0) + y * (e + 1.0);
+    }
+    double s = 0.0, pw = 1.0;
+    for (int m = 1; m <= KD_SERIES_TERMS; ++m) {
+        pw *= y / (double)m;              /* y^m / m! */
+        if (m >= 3) s += ((m % 2) ? 1.0 : -1.0) * (double)(m - 2) * pw;
+    }
+    return s;
+}
+
+static double kd_g(double y)
+{
+    if (y >= KD_SERIES_Y) {
+        double e = exp(-y);
+        return 1.0 - 2.0 * y * e - e * e;
+    }
+    double s = 0.0, pw = 1.0;
+    for (int m = 1; m <= KD_SERIES_TERMS; ++m) {
+        pw *= y / (double)m;
+        if (m >= 3) s += ((m % 2) ? 1.0 : -1.0) * (ldexp(1.0, m) - 2.0 * (double)m) * pw;
+    }
+    return s;
+}
+
+/* eq. advection and eq. diffusion (homogeneous background): advection a and
+ * diffusion coefficient d of a diffusive phase of length theta that ends
+ * with velocity vnext. */
+void oracle_kd_coeffs(double theta, double R, double mu, double sigma, double vnext,
+                      double out[2])
+{
+    double y = R * theta;
+    double dv = vnext - mu;
+    double a = mu * theta + dv * (-expm1(-y)) / R;
+    double d2 = 2.0 * sigma * sigma / (R * R) * kd_f(y) + dv * dv / (R * R) * kd_g(y);
+    out[0] = a;
+    out[1] = sqrt(d2 > 0.0 ? d2 : 0.0);
+}
+
+/* Numbers of one KD step from its Philox block. */
+static void kd_draws(const uint32_t w[4], double *nu_next, double *chi, double *E_next)
+{
+    box_muller(w[0], w[1], nu_next, chi);
+    *E_next = -log(oracle_uniform(w[2]));
+}
+
+static void kd_block(const problem_t *P, uint32_t sample, uint32_t tag, uint32_t b,
+                     uint32_t w[4])
+{
+    uint32_t ctr[4] = {b, sample, tag, P->stream};
+    oracle_philox4x32_10(ctr, P->key, w);
+}
+
+/* Index of the grid step that contains time c: the step [q dt, (q+1) dt). */
+static double kd_step_of(double c, double dt)
+{
+    return floor(c / dt);
+}
+
+/* Optional record of the coarse numbers of a pair, 4 doubles per coarse
+ * step: (chi~, nu~, E~, number of fine KD steps aggregated). */
+typedef struct {
+    double *rows;
+    uint64_t cap, used;
+} kd_trace_t;
+
+static void simulate_kd_one(const problem_t *P, uint64_t sample,
+                            double *xf_out, double *xc_out,
+                            uint32_t *cf_out, uint32_t *cc_out, kd_trace_t *tr)
+{
+    const int l = P->level;
+    const int coarse = (!P->single && l >= 1);
+    const uint32_t tag = (uint32_t)l + (P->single ? 64u : 0u);
+    const uint32_t smp = (uint32_t)sample;
+    const double R = 1.0 / (P->eps * P->eps);     /* collision rate */
+    const double mu = 0.0;                        /* Maxwellian mean */
+    const double sigma = 1.0 / P->eps;            /* Maxwellian standard deviation */
+    const double T = P->T;
+    const double dtf = P->dt0 / pow((double)P->M, (double)l);
+    const double dtc = coarse ? P->dt0 / pow((double)P->M, (double)(l - 1)) : 0.0;
+
+    /* Initial condition, shared by both paths. */
+    uint32_t w[4];
+    kd_block(P, smp, tag, 0, w);
+    double nc, ns;
+    box_muller(w[0], w[1], &nc, &ns);
+    double x0;
+    if (P->x0_kind == X0_DELTA) x0 = P->x0_a;
+    else if (P->x0_kind == X0_NORMAL) x0 = P->x0_a + P->x0_b * nc;
+    else x0 = oracle_cosine_icdf(oracle_uniform(w[3]));
+    double nu = ns;                               /* nu_0 */
+    double E = -log(oracle_uniform(w[2]));        /* E_0 */
+
+    /* Fine path: position, velocity, grid time, flight, pending collision. */
+    double xf = x0, vf = mu + sigma * nu, tf = 0.0, tauf = E / R;
+    double cfine = tf + tauf;
+    uint32_t cf = 0, cc = 0, b = 1;
+
+    if (!coarse) {
+        /* Algorithm "KD algorithm". */
+        while (cfine < T) {
+            double nu_next, chi, E_next;
+            kd_block(P, smp, tag, b++, w);
+            kd_draws(w, &nu_next, &chi, &E_next);
+            double t_next = (kd_step_of(cfine, dtf) + 1.0) * dtf;
+            double theta = t_next - cfine;                /* eq. diffusive-time */
+            double v_next = mu + sigma * nu_next;
+            double ad[2];
+            oracle_kd_coeffs(theta, R, mu, sigma, v_next, ad);
+            xf = xf + vf * tauf + (ad[0] + ad[1] * chi);  /* eq. position-update */
+            tf = t_next;                                  /* eq. time-update */
+            tauf = E_next / R;
+            cfine = tf + tauf;
+            vf = v_next;
+            cf++;
+        }
+        if (tf < T) xf = xf + vf * (T - tf);
+        *xf_out = xf; *xc_out = 0.0; *cf_out = cf; *cc_out = 0;
+        return;
+    }
+
+    /* Algorithm "Correlated KD algorithm".  The coarse path starts with the
+     * fine path's first flight (same velocity number and exponential
+     * number), so the same collision time. */
+    double xc = x0, vc = vf, tc = 0.0, ccoarse = cfine;
+    double nu_f = nu;   /* velocity number of the fine path's pending flight */
+    while (ccoarse < T || cfine < T) {
+        /* end of the coarse grid step containing the coarse collision, in
+         * fine steps */
+        const double end_c = kd_step_of(ccoarse, dtc) + 1.0;
+        const double end_c_fine = end_c * (double)P->M;
+        double num = 0.0, den = 0.0, zeta_prev = 0.0;
+        int first = 1;
+        uint32_t used = 0;
+        do {
+            /* one fine KD step (phase m) */
+            double nu_next, chi, E_next;
+            kd_block(P, smp, tag, b++, w);
+            kd_draws(w, &nu_next, &chi, &E_next);
+            double t_next = (kd_step_of(cfine, dtf) + 1.0) * dtf;
+            double theta = t_next - cfine;
+            double v_next = mu + sigma * nu_next;
+            double ad[2];
+            oracle_kd_coeffs(theta, R, mu, sigma, v_next, ad);
+            xf = xf + vf * tauf + (ad[0] + ad[1] * chi);
+
+            /* aggregation weights of phase m (Section 3.2) */
+            double y = R * theta;
+            double zeta = -expm1(-y) / R;                 /* expected time of nu_{m+1} */
+            double theta_p = kd_h(y) / R;                 /* theta'_m = theta_m - zeta_m */
+            double beta = sqrt(2.0 * sigma * sigma / (R * R) * kd_h(R * theta_p));
+            if (!first) {
+                double alpha = (tauf + zeta_prev) * sigma;   /* sigma tau'_m */
+                num += alpha * nu_f;
+                den += alpha * alpha;
+            }
+            num += beta * chi;
+            den += beta * beta;
+            zeta_prev = zeta;
+            first = 0;
+            used++;
+
+            tf = t_next;
+            tauf = E_next / R;
+            cfine = tf + tauf;
+            vf = v_next;
+            nu_f = nu_next;
+            cf++;
+        } while (!(kd_step_of(cfine, dtf) + 1.0 > end_c_fine));
+
+        if (ccoarse < T) {
+            double nu_c = nu_f;                               /* eq. nu-update */
+            double chi_c = den > 0.0 ? num / sqrt(den) : 0.0; /* eq. chi-update */
+            double t_next = end_c * dtc;
+            double theta = t_next - ccoarse;
+            double v_next = mu + sigma * nu_c;
+            double ad[2];
+            oracle_kd_coeffs(theta, R, mu, sigma, v_next, ad);
+            xc = xc + vc * (ccoarse - tc) + (ad[0] + ad[1] * chi_c);
+            tc = t_next;
+            /* eq. epsilon-update: E~ = E_kappa - R (t_c - t_f,kappa), so the
+             * coarse collision is the fine one */
+            double E_c = R * (cfine - tc);
+            ccoarse = cfine;
+            vc = v_next;
+            cc++;
+            if (tr && tr->rows && tr->used < tr->cap) {
+                double *r = tr->rows + 4 * tr->used++;
+                r[0] = chi_c; r[1] = nu_c; r[2] = E_c; r[3] = (double)used;
+            }
+        }
+    }
+    if (tf < T) xf = xf + vf * (T - tf);
+    if (tc < T) xc = xc + vc * (T - tc);
+    *xf_out = xf; *xc_out = xc; *cf_out = cf; *cc_out = cc;
+}
+
+/* As oracle_simulate, for the KD scheme. */
+int oracle_simulate_kd(double eps, double T, double dt0, int M, int level, int single,
+                       int x0_kind, double x0_a, double x0_b, int eq_kind, int coupling,
+                       uint64_t seed, uint32_t stream,
+                       uint64_t sample_begin, const uint64_t *idx, uint64_t n,
+                       double *xf, double *xc, uint32_t *cf, uint32_t *cc, int nthreads)
+{
+    problem_t P = make_problem(eps, T, dt0, M, level, single, x0_kind, x0_a, x0_b,
+                               eq_kind, coupling, seed, stream);
+    (void)nthreads;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+        uint64_t s = idx ? idx[i] : sample_begin + (uint64_t)i;
+        simulate_kd_one(&P, s, &xf[i], &xc[i], &cf[i], &cc[i], NULL);
+    }
+    return 0;
+}
+
+/* Coarse numbers of one pair (rows of 4 doubles, see kd_trace_t); returns
+ * the number of rows written.  out_final = (x_f, x_c). */
+uint64_t oracle_kd_coarse_numbers(double eps, double T, double dt0, int M, int level,
+                                  int x0_kind, double x0_a, double x0_b,
+                                  uint64_t seed, uint32_t stream, uint64_t sample,
+                                  double *rows, uint64_t cap, double out_final[2])
+{
+    problem_t P = make_problem(eps, T, dt0, M, level, 0, x0_kind, x0_a, x0_b,
+                               EQ_MAXWELLIAN, 0, seed, stream);
+    kd_trace_t tr = {rows, cap, 0};
+    double xf, xc; uint32_t cf, cc;
+    simulate_kd_one(&P, sample, &xf, &xc, &cf, &cc, &tr);
+    out_final[0] = xf; out_final[1] = xc;
+    return tr.used;
+}

@@ -312,16 +312,143 @@ def pin_mlmc_unbiased():
     assert res["var_estimator"] <= 0.5 * 2e-2 ** 2 * 1.0000001
 
 
+# --------------------------------------------------------------------------
+# Kinetic-diffusion (KD) scheme
+# --------------------------------------------------------------------------
+def kd_problem(eps, T=1.0, dt0=0.5, M=2, x0_kind=0, seed=42, stream=0):
+    return dict(eps=eps, T=T, dt0=dt0, M=M, x0_kind=x0_kind, x0_a=0.0, x0_b=1.0,
+                eq_kind=1, coupling=1, seed=seed, stream_id=stream, scheme=O.SCHEME_KD)
+
+
+def pin_kd_second_moment_exact():
+    """The KD step keeps the mean and variance of the kinetic motion given the
+    next velocity, so in a homogeneous background E[x(T)^2] is the kinetic
+    value 2 (T - eps^2 (1 - e^{-T/eps^2})) (x0 = 0) at every time step, for
+    single paths and for both paths of a pair."""
+    cases = [(1.0, 0.5, 0, False), (0.3, 0.5, 0, False), (0.3, 0.25, 2, False),
+             (0.1, 0.5, 1, False), (0.3, 0.5, 2, True), (2.0, 0.5, 1, False)]
+    for k, (eps, dt0, level, single) in enumerate(cases):
+        prob = kd_problem(eps, dt0=dt0, stream=300 + k)
+        r = O.simulate(prob, level, 0, 100000, single=single)
+        exact = CF.kinetic_limit(eps, prob["T"], 0.0)
+        assert abs(_z(r["xf"] ** 2, exact)) < Z_MAX, (eps, dt0, level, "fine")
+        if level >= 1 and not single:
+            assert abs(_z(r["xc"] ** 2, exact)) < Z_MAX, (eps, dt0, level, "coarse")
+            assert abs(_z(r["xf"] ** 2 - r["xc"] ** 2, 0.0)) < Z_MAX
+
+
+def _velocity_jump(theta, R, mu, sigma, n, rng):
+    """Exact velocity-jump motion over [0, theta] right after a collision:
+    velocities N(mu, sigma^2), redrawn at rate R.  Returns (dx, v_end)."""
+    v = mu + sigma * rng.standard_normal(n)
+    t = np.zeros(n)
+    dx = np.zeros(n)
+    live = np.ones(n, dtype=bool)
+    while live.any():
+        idx = np.nonzero(live)[0]
+        tau = rng.exponential(1.0 / R, size=idx.size)
+        end = t[idx] + tau >= theta
+        stop = idx[end]
+        dx[stop] += v[stop] * (theta - t[stop])
+        live[stop] = False
+        go = idx[~end]
+        dx[go] += v[go] * tau[~end]
+        t[go] += tau[~end]
+        v[go] = mu + sigma * rng.standard_normal(go.size)
+    return dx, v
+
+
+def pin_kd_diffusive_phase_bruteforce():
+    """eqs. advection and diffusion are the conditional mean and variance of
+    the kinetic displacement over theta given the final velocity: checked
+    against a brute-force velocity-jump simulation (moments weighted by 1
+    and by the velocity)."""
+    rng = np.random.default_rng(7)
+    R, mu, sigma = 2.0, 0.3, 1.5
+    for theta in (0.02, 0.2, 1.0, 2.5):   # y = R theta on both sides of the series switch
+        # a(v) is affine and d(v)^2 quadratic in v - mu: read them off the
+        # oracle at a few velocities and check that structure
+        vs = mu + sigma * np.array([-2.0, 0.0, 1.0, 3.0])
+        ad = np.array([O.kd_coeffs(theta, R, mu, sigma, v) for v in vs])
+        a0, a1 = ad[1, 0], ad[2, 0] - ad[1, 0]
+        D0, D1 = ad[1, 1] ** 2, (ad[2, 1] ** 2 - ad[1, 1] ** 2) / sigma ** 2
+        assert np.allclose(ad[:, 0], a0 + a1 * (vs - mu) / sigma, rtol=1e-12, atol=1e-14)
+        assert np.allclose(ad[:, 1] ** 2, D0 + D1 * (vs - mu) ** 2, rtol=1e-10, atol=1e-14)
+        dx, v = _velocity_jump(theta, R, mu, sigma, 400000, rng)
+        w = v - mu
+        r = dx - (a0 + a1 * w / sigma)
+        s2 = r * r - (D0 + D1 * w * w)
+        for sample in (r, r * w, s2, s2 * w * w / sigma ** 2):
+            assert abs(_z(sample, 0.0)) < Z_MAX, theta
+
+
+def _kd_coarse_rows(prob, level, nsamp):
+    rows = [O.kd_coarse_numbers(prob, level, s)[0] for s in range(nsamp)]
+    return np.concatenate(rows)
+
+
+def pin_kd_coarse_number_laws():
+    """The aggregated coarse numbers have the laws of the coarse path's own
+    numbers (Section 3.2): chi~ ~ N(0,1) (eq. chi-update), nu~ ~ N(0,1) (eq.
+    nu-update), E~ ~ Exp(1) by memorylessness (eq. epsilon-update), and
+    chi~ is uncorrelated with nu~."""
+    for k, (eps, level, nsamp) in enumerate(((0.3, 3, 3000), (1.0, 2, 6000), (0.05, 2, 1500))):
+        rows = _kd_coarse_rows(kd_problem(eps, stream=320 + k), level, nsamp)
+        assert rows.shape[0] > 5000
+        assert anderson_darling(rows[:, 0], stats.norm.cdf) < AD_MAX, (eps, "chi")
+        assert anderson_darling(rows[:, 1], stats.norm.cdf) < AD_MAX, (eps, "nu")
+        assert anderson_darling(rows[:, 2], stats.expon.cdf) < AD_MAX, (eps, "E")
+        assert abs(_z(rows[:, 0] * rows[:, 1], 0.0)) < Z_MAX
+        assert np.all(rows[:, 3] >= 1)
+
+
+def pin_kd_coarse_matches_level_below():
+    """The coarse path of a level-l pair has the law of the KD path of level
+    l-1 (the telescoping requirement): two-sample tests of x and of x^4."""
+    for k, (eps, level) in enumerate(((0.3, 2), (1.0, 1), (0.1, 3))):
+        pair = O.simulate(kd_problem(eps, x0_kind=1, stream=340 + k), level, 0, 100000)
+        below = O.simulate(kd_problem(eps, x0_kind=1, stream=360 + k), level - 1, 0, 100000)
+        a, b = pair["xc"], below["xf"]
+        assert stats.ks_2samp(a, b).pvalue > P_MIN, (eps, level)
+        d = np.mean(a ** 4) - np.mean(b ** 4)
+        se = math.sqrt((np.var(a ** 4) + np.var(b ** 4)) / a.size)
+        assert abs(d / se) < Z_MAX, (eps, level)
+
+
+def pin_kd_invariants():
+    """Paths without a collision before T stream freely with the shared
+    initial velocity, so both paths of such a pair end at the same point;
+    coarse collisions are fine collisions; in the diffusive regime every
+    time step holds a collision and the two paths stay close (the
+    aggregated diffusive number follows the fine diffusive motion)."""
+    r = O.simulate(kd_problem(5.0, stream=380), 2, 0, 20000)
+    free = r["cf"] == 0
+    assert free.sum() > 10000
+    assert np.array_equal(r["xf"][free], r["xc"][free])
+    assert np.all(r["cc"] <= r["cf"])
+    assert not np.array_equal(r["xf"][~free], r["xc"][~free])
+    r0 = O.simulate(kd_problem(0.3, stream=381), 0, 0, 1000)
+    assert np.all(r0["cc"] == 0) and np.all(r0["xc"] == 0.0)
+    prob = kd_problem(1e-3, stream=382)
+    r = O.simulate(prob, 3, 0, 20000)
+    assert np.all(r["cf"] == 16) and np.all(r["cc"] == 8)
+    dq = r["xf"] ** 2 - r["xc"] ** 2
+    assert np.var(dq) < 1e-6 * np.var(r["xf"] ** 2)
+
+
+KD_PINS = [pin_kd_second_moment_exact, pin_kd_diffusive_phase_bruteforce,
+           pin_kd_coarse_number_laws, pin_kd_coarse_matches_level_below, pin_kd_invariants]
+
 ALL_PINS = [pin_philox_kat, pin_word_layout, pin_uniform, pin_normals, pin_second_moment_cfg1,
             pin_second_moment_levels, pin_cosine_initial, pin_heat_limit, pin_kinetic_limit,
             pin_two_point_bruteforce, pin_telescoping, pin_coupling_laws, pin_coarse_threshold,
             pin_symmetry, pin_optimal_samples, pin_mlmc_unbiased]
 
 
-def run_all(stop_at_first=False):
-    """Runs every pin, returns the names of the failing ones."""
+def run_all(stop_at_first=False, pins=None):
+    """Runs every pin (or those given), returns the names of the failing ones."""
     failed = []
-    for f in ALL_PINS:
+    for f in (ALL_PINS + KD_PINS if pins is None else pins):
         try:
             f()
         except Exception as e:       # a mutant may also crash or produce NaN
@@ -334,4 +461,5 @@ def run_all(stop_at_first=False):
 if __name__ == "__main__":
     import json
     import sys
-    print(json.dumps(run_all(stop_at_first="--first" in sys.argv)))
+    print(json.dumps(run_all(stop_at_first="--first" in sys.argv,
+                             pins=KD_PINS if "--kd" in sys.argv else None)))

@@ -47,14 +47,38 @@ MUTANTS = [
 ]
 
 
+# Mistakes in the kinetic-diffusion scheme; these run the KD pins only.
+KD_MUTANTS = [
+    ("kd_diffusion_missing_2", "double d2 = 2.0 * sigma * sigma / (R * R) * kd_f(y)",
+     "double d2 = sigma * sigma / (R * R) * kd_f(y)"),
+    ("kd_advection_mean_dropped", "double a = mu * theta + dv", "double a = dv"),
+    ("kd_advection_rate_inverted", "double a = mu * theta + dv * (-expm1(-y)) / R;",
+     "double a = mu * theta + dv * (-expm1(-y)) * R;"),
+    ("kd_f_sign", "return 2.0 * (e - 1.0) + y * (e + 1.0);", "return 2.0 * (e - 1.0) + y * (e - 1.0);"),
+    ("kd_g_series_coefficient", "(ldexp(1.0, m) - 2.0 * (double)m)", "(ldexp(1.0, m) - (double)m)"),
+    ("kd_g_direct_sign", "return 1.0 - 2.0 * y * e - e * e;", "return 1.0 - 2.0 * y * e + e * e;"),
+    ("kd_flight_rate_inverted", "tf = 0.0, tauf = E / R;", "tf = 0.0, tauf = E * R;"),
+    ("kd_theta_full_step", "double theta = t_next - cfine;                /* eq. diffusive-time */",
+     "double theta = dtf;"),
+    ("kd_step_grid_ceil", "return floor(c / dt);", "return ceil(c / dt);"),
+    ("kd_chi_not_normalised", "double chi_c = den > 0.0 ? num / sqrt(den) : 0.0;",
+     "double chi_c = den > 0.0 ? num / den : 0.0;"),
+    ("kd_nu_update_initial", "double nu_c = nu_f;", "double nu_c = nu;"),
+    ("kd_one_fine_step_per_window", "} while (!(kd_step_of(cfine, dtf) + 1.0 > end_c_fine));",
+     "} while (0);"),
+    ("kd_alpha_includes_own_flight", "if (!first) {", "if (1) {"),
+    ("kd_exponential_from_wrong_word", "*E_next = -log(oracle_uniform(w[2]));",
+     "*E_next = -log(oracle_uniform(w[0]));"),
+]
+
+
 @pytest.fixture(scope="module")
 def source():
     with open(os.path.join(ROOT, "oracle", "oracle.c")) as f:
         return f.read()
 
 
-@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_mutant_is_caught(source, tmp_path, name, old, new):
+def _run_mutant(source, tmp_path, name, old, new, extra):
     assert source.count(old) == 1, "mutation anchor must occur exactly once: %r" % old
     src = tmp_path / "oracle_mut.c"
     src.write_text(source.replace(old, new))
@@ -63,8 +87,19 @@ def test_mutant_is_caught(source, tmp_path, name, old, new):
                            "-w", str(src), "-o", str(lib), "-lm"])
     env = dict(os.environ, ORACLE_LIB_PATH=str(lib),
                PYTHONPATH=os.pathsep.join([ROOT, os.environ.get("PYTHONPATH", "")]))
-    out = subprocess.run([sys.executable, os.path.join(ROOT, "tests", "oracle_pins.py"), "--first"],
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "tests", "oracle_pins.py"), "--first"]
+                         + extra,
                          env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert out.returncode == 0, out.stderr[-2000:]
     failed = json.loads(out.stdout.strip().splitlines()[-1])
     assert failed, "mutant %s passed every pin" % name
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(source, tmp_path, name, old, new):
+    _run_mutant(source, tmp_path, name, old, new, [])
+
+
+@pytest.mark.parametrize("name,old,new", KD_MUTANTS, ids=[m[0] for m in KD_MUTANTS])
+def test_kd_mutant_is_caught(source, tmp_path, name, old, new):
+    _run_mutant(source, tmp_path, name, old, new, ["--kd"])
