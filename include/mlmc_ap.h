@@ -84,6 +84,23 @@ enum { MLMC_AP_COUPLING_KICK_SUM = 0,  /* normalised sum of the M fine kick norm
 enum { MLMC_AP_QOI_X2 = 0,        /* Q = x(T)^2 */
        MLMC_AP_QOI_X2_HIST = 1 }; /* x(T)^2 plus a position histogram */
 
+/* Particle scheme (Section 2).  SPLITTING: the asymptotic-preserving
+ * splitting scheme at fixed dt (transport-diffusion step with the
+ * eps- and dt-dependent drift and Gaussian kick, then a collision with
+ * probability dt/(eps^2+dt)); fine/coarse pairs as in Section 3 with the
+ * fixed-step mapping.  KD: the kinetic-diffusion scheme (Algorithm "KD
+ * algorithm") in a homogeneous background, collision rate R = 1/eps^2 and
+ * Maxwellian velocities N(0, 1/eps^2); pairs by Algorithm "Correlated KD
+ * algorithm" (eqs. nu-update, epsilon-update, chi-update with the weights
+ * alpha and beta of Section 3.2).  KD needs eps > 0, the Maxwellian
+ * equilibrium and fp64_state = 1 (its step decisions are taken on FP64
+ * times); coupling is ignored; its collision counts are KD steps, i.e.
+ * collisions before T; random numbers: Philox block 0 = initial condition,
+ * block k+1 = KD step k (Box-Muller pair nu_{k+1}, chi_k and E_{k+1} =
+ * -log u). */
+enum { MLMC_AP_SCHEME_SPLITTING = 0,
+       MLMC_AP_SCHEME_KD = 1 };
+
 #define MLMC_AP_MAX_LEVELS 31   /* levels 0..30 */
 #define MLMC_AP_MAX_BINS 1024
 
@@ -105,7 +122,7 @@ typedef struct mlmc_ap_problem {
     double hist_hi;
     uint64_t seed;       /* Philox key */
     uint32_t stream_id;  /* fourth counter word (request / stream id) */
-    uint32_t reserved;   /* must be 0 */
+    uint32_t scheme;     /* MLMC_AP_SCHEME_* (0 = splitting) */
 } mlmc_ap_problem;
 
 /* Per-level statistics, mergeable (Chan et al. pairwise update) in FP64.
@@ -248,7 +265,9 @@ mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, i
 /* MLMC estimate of E[Q_L] to RMSE tolerance rmse_tol (Section 4.1): warm-up
  * samples on every level 0..L, then eqs. Nopt1/Noptj with sample variances
  * and the deterministic cost C_0 = n_0, C_l = n_l + n_{l-1} (particle steps
- * per sample), topped up until the statistical constraint
+ * per sample; for the KD scheme the expected KD steps,
+ * C = sum over the paths of n (1 - e^{-R dt}), rounded up), topped up until
+ * the statistical constraint
  * sum_l V_l/N_l <= rmse_tol^2/2 holds.  Level l uses samples [0, N_l).
  * opt may be NULL (defaults).  With qoi = QOI_X2_HIST, hist_host (nullable)
  * receives (L+1) per-level histograms of 3*nbins+4 counts each. */

@@ -562,7 +562,7 @@ static void simulate_kd_one(const problem_t *P, uint64_t sample,
     box_muller(w[0], w[1], &nc, &ns);
     double x0;
     if (P->x0_kind == X0_DELTA) x0 = P->x0_a;
-    else if (P->x0_kind == X0_NORMAL) x0 = P->x0_a + P->x0_b * nc;
+    else if (P->x0_kind == X0_NORMAL) x0 = P->x0_a + nc * P->x0_b;
     else x0 = oracle_cosine_icdf(oracle_uniform(w[3]));
     double nu = ns;                               /* nu_0 */
     double E = -log(oracle_uniform(w[2]));        /* E_0 */

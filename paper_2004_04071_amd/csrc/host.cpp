@@ -61,7 +61,21 @@ uint64_t coarse_threshold(uint64_t thr_f, uint64_t thr_c, int M) {
   return r > thr_f ? thr_f : r;
 }
 
+// Expected KD steps of one path of a level: a KD step runs from a grid point
+// to the end of the grid step holding the next collision, which advances
+// 1/(1 - e^{-R dt}) steps on average, so n (1 - e^{-R dt}) steps per path.
+static double kd_path_cost(const mlmc_ap_problem& p, int level) {
+  const LevelConst c = level_const(p, level);
+  const double R = 1.0 / (p.eps * p.eps);
+  return (double)c.n_steps * -std::expm1(-R * c.dt);
+}
+
 uint64_t sample_cost(const mlmc_ap_problem& p, int level, bool single) {
+  if (p.scheme == MLMC_AP_SCHEME_KD) {
+    double c = kd_path_cost(p, level);
+    if (!single && level > 0) c += kd_path_cost(p, level - 1);
+    return std::max<uint64_t>(1, (uint64_t)std::ceil(c));
+  }
   const uint64_t n = level_const(p, level).n_steps;
   if (single || level == 0) return n;
   return n + level_const(p, level - 1).n_steps;
@@ -104,12 +118,21 @@ mlmc_ap_status validate_problem(const mlmc_ap_problem* p) {
   }
   if (p->fp64_state != 0 && p->fp64_state != 1)
     return set_error(MLMC_AP_EINVAL, "fp64_state must be 0 or 1");
-  if (p->reserved != 0) return set_error(MLMC_AP_EINVAL, "reserved must be 0");
+  if (p->scheme != MLMC_AP_SCHEME_SPLITTING && p->scheme != MLMC_AP_SCHEME_KD)
+    return set_error(MLMC_AP_EINVAL, "unknown scheme");
+  if (p->scheme == MLMC_AP_SCHEME_KD) {
+    if (!(p->eps > 0.0)) return set_error(MLMC_AP_EINVAL, "the KD scheme needs eps > 0");
+    if (p->eq_kind != MLMC_AP_EQ_MAXWELLIAN)
+      return set_error(MLMC_AP_EINVAL, "the KD scheme needs the Maxwellian equilibrium");
+    if (p->fp64_state != 1)
+      return set_error(MLMC_AP_EINVAL, "the KD scheme runs with FP64 state (fp64_state = 1)");
+  }
   return MLMC_AP_OK;
 }
 
 bool time_parallel_candidate(const ItemSpec& s, int32_t tp_max_samples) {
   const mlmc_ap_problem& p = *s.prob;
+  if (p.scheme == MLMC_AP_SCHEME_KD) return false;  // KD steps depend on the previous ones
   const int64_t limit = tp_max_samples == 0 ? kTpDefaultMaxSamples : tp_max_samples;
   if (limit <= 0 || s.n_samples == 0 || s.n_samples > (uint64_t)limit) return false;
   const bool coarse = !s.single && s.level >= 1;
@@ -188,6 +211,20 @@ LevelDesc make_desc(const ItemSpec& s, bool tp) {
                              : kKindPairTwoPointSum)
                   : (maxwell ? kKindFineMaxwell : kKindFineTwoPoint);
   d.x0_kind = (uint32_t)p.x0_kind;
+  if (p.scheme == MLMC_AP_SCHEME_KD) {
+    // the KD kinds read their constants from the coefficient slots
+    d.h_f = F.dt;
+    d.h_c = coarse ? C.dt : 0.0;
+    d.s_f = 1.0 / (p.eps * p.eps);  // collision rate R
+    d.s_c = 1.0 / p.eps;            // Maxwellian standard deviation sigma
+    d.agg_ms2 = p.T;
+    d.h_f2 = 0.0;                   // Maxwellian mean mu
+    d.rsqrt_m = 0.0;
+    d.thr_f = d.thr_c2 = 0;
+    d.thr_f_m1 = d.thr_c2_m1 = 0u;
+    d.flags &= ~(kFlagWide | kFlagAggregate);
+    d.kind = coarse ? kKindKdPair : kKindKdFine;
+  }
   // wide tiles (several samples per lane) only where they still give the
   // item at least one wavefront per SIMD; a few samples of short
   // trajectories are spread over one per lane instead
@@ -398,17 +435,17 @@ mlmc_ap_tuning resolve_tuning(const Workspace& ws, const mlmc_ap_tuning* t) {
   return r;
 }
 
-int persistent_grid(Workspace& ws, const mlmc_ap_tuning& t, bool fp64) {
+int persistent_grid(Workspace& ws, const mlmc_ap_tuning& t, bool fp64, bool kd) {
   const int waves_per_block = t.block / kLanes;
   const int waves = ws.n_cu * 4 * t.waves_per_simd;
   int grid = (waves + waves_per_block - 1) / waves_per_block;
   // no more blocks than fit the GPU at once: a block that waits for a free
   // slot would start its statically assigned work (one-round launches,
   // time-parallel trajectories) only after the others finish
-  const int key = (fp64 ? 1 : 0) | (t.ppt << 1) | (t.block << 4);
+  const int key = (fp64 ? 1 : 0) | (kd ? 2 : 0) | (t.ppt << 2) | (t.block << 5);
   auto it = ws.blocks_per_cu.find(key);
   if (it == ws.blocks_per_cu.end())
-    it = ws.blocks_per_cu.emplace(key, persistent_blocks_per_cu(fp64, t.ppt, t.block)).first;
+    it = ws.blocks_per_cu.emplace(key, persistent_blocks_per_cu(fp64, t.ppt, t.block, kd)).first;
   if (it->second > 0) grid = std::min(grid, ws.n_cu * it->second);
   // every chunk stream needs blocks
   return std::max((int)kChunkStreams, grid);
@@ -444,11 +481,11 @@ static int tp_grid(const Workspace& ws) { return std::max(1, ws.n_cu * 8); }
 // The whole launch as three kernels: stage the table, simulate (the
 // persistent kernel also runs the time-parallel trajectories), reduce (which
 // also writes the host mirror of the resident slots).
-static mlmc_ap_status record_device_work(Workspace& ws, bool fp64, const mlmc_ap_tuning& t,
-                                         hipStream_t s) {
+static mlmc_ap_status record_device_work(Workspace& ws, bool fp64, bool kd,
+                                         const mlmc_ap_tuning& t, hipStream_t s) {
   MLMC_TRY(stage(ws, s));
   MLMC_HIP(launch_persistent(fp64, t.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev, ws.partials,
-                             t.block, persistent_grid(ws, t, fp64), s));
+                             t.block, persistent_grid(ws, t, fp64, kd), s, kd));
   MLMC_TRY(reduce(ws, s));
   return MLMC_AP_OK;
 }
@@ -467,6 +504,10 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
   for (const auto& s : specs)
     if ((s.prob->fp64_state != 0) != fp64)
       return set_error(MLMC_AP_EINVAL, "one launch cannot mix FP32 and FP64 particle state");
+  const bool kd = specs[0].prob->scheme == MLMC_AP_SCHEME_KD;
+  for (const auto& s : specs)
+    if ((s.prob->scheme == MLMC_AP_SCHEME_KD) != kd)
+      return set_error(MLMC_AP_EINVAL, "one launch cannot mix particle schemes");
   // most expensive chunks first (persistent kernel load balance)
   std::stable_sort(d.begin(), d.end(), [](const LevelDesc& a, const LevelDesc& b) {
     return a.n_steps > b.n_steps;
@@ -518,18 +559,20 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
     MLMC_TRY(stage(ws, stream));
     if (kernel_timed) MLMC_HIP(hipEventRecord(ws.ev[1], stream));
     MLMC_HIP(launch_persistent(fp64, tuning.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev,
-                               ws.partials, tuning.block, persistent_grid(ws, tuning, fp64), stream));
+                               ws.partials, tuning.block, persistent_grid(ws, tuning, fp64, kd),
+                               stream, kd));
     if (kernel_timed) MLMC_HIP(hipEventRecord(ws.ev[2], stream));
     MLMC_TRY(reduce(ws, stream));
   } else if (mode == kModeGraph) {
     const uint64_t key = ((uint64_t)tuning.block << 48) ^ ((uint64_t)tuning.ppt << 40) ^
                          ((uint64_t)tuning.waves_per_simd << 32) ^ (fp64 ? 1ull : 2ull) ^
+                         (kd ? 4ull : 0ull) ^
                          ((uint64_t)(uintptr_t)ws.partials << 3);
     auto it = ws.graphs.find(key);
     if (it == ws.graphs.end()) {
       if (ws.graphs.size() >= 16) ws.drop_graphs();  // bound the cache
       MLMC_HIP(hipStreamBeginCapture(ws.capture_stream, hipStreamCaptureModeRelaxed));
-      mlmc_ap_status st = record_device_work(ws, fp64, tuning, ws.capture_stream);
+      mlmc_ap_status st = record_device_work(ws, fp64, kd, tuning, ws.capture_stream);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(ws.capture_stream, &g);
       if (st != MLMC_AP_OK) {
@@ -897,6 +940,8 @@ static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* to
       return set_error(MLMC_AP_EINVAL, "rmse_tol must be > 0");
     if ((p[i].fp64_state != 0) != (p[0].fp64_state != 0))
       return set_error(MLMC_AP_EINVAL, "a batch cannot mix FP32 and FP64 particle state");
+    if (p[i].scheme != p[0].scheme)
+      return set_error(MLMC_AP_EINVAL, "a batch cannot mix particle schemes");
   }
   const mlmc_ap_options o = default_options(opt);
   const int mode = launch_mode(o.batched);

@@ -128,7 +128,7 @@ Workspace* workspace();  // of the current device (created on first use)
 // Sets up a private workspace on the current device (the serving loop owns one).
 mlmc_ap_status init_workspace(Workspace& ws);
 mlmc_ap_tuning resolve_tuning(const Workspace& ws, const mlmc_ap_tuning* t);
-int persistent_grid(Workspace& ws, const mlmc_ap_tuning& t, bool fp64);
+int persistent_grid(Workspace& ws, const mlmc_ap_tuning& t, bool fp64, bool kd);
 
 // Device time measured by one launch of a table.
 struct LaunchTiming {

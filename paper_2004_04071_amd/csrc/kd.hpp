@@ -1,0 +1,243 @@
+// Kinetic-diffusion (KD) scheme on the device: one path or one correlated
+// fine/coarse pair per lane, FP64 state.
+//
+// Homogeneous background in the diffusive scaling: collision rate R =
+// 1/eps^2, post-collision velocities N(mu, sigma^2) with mu = 0 and sigma =
+// 1/eps.  A KD step (Section 2, Algorithm "KD algorithm") starts on the time
+// grid at t with velocity v and a pending collision at c = t + E/R: the path
+// flies to c, then moves diffusively to the end of the grid step holding c
+// (length theta) with the advection a and diffusion d of eqs. advection and
+// diffusion, conditioned on the next velocity.  Once the pending collision
+// is at or after T the path flies to T.
+//
+// Pair (Section 3, Algorithm "Correlated KD algorithm"): the coarse path's
+// flight mirrors the fine flight kappa_k (eq. nu-update; eq.
+// epsilon-update, which in a homogeneous background puts the coarse
+// collision at the fine collision time), and its diffusive phase takes the
+// normalised weighted sum (eq. chi-update) of the fine diffusive numbers and
+// of the velocity numbers of the fine flights in between, weights alpha_m =
+// sigma tau'_m and beta_m (eq. weights-beta) after moving zeta_m =
+// (1 - e^{-R theta_m})/R from each diffusive phase to the next flight.  The
+// fine path steps until its pending collision lies after the end of the
+// coarse grid step; step indices are compared as integers of the fine grid.
+//
+// Random numbers: Philox block 0 = initial condition (Box-Muller pair of
+// words 0, 1: cosine branch -> normal x0, sine branch -> nu_0; word 2 ->
+// E_0 = -log u; word 3 -> u of the cosine law), block k+1 = KD step k (pair
+// of words 0, 1: nu_{k+1}, chi_k; word 2 -> E_{k+1}).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace mlmc {
+
+// Three functions of y = R theta >= 0 that cancel catastrophically when
+// written with exp for small y; below y = 0.05 they are summed from their
+// Taylor series (terms up to y^16, Horner form), above from exp/expm1:
+//   kd_h(y) = e^{-y} - 1 + y                 (the unconditioned variance shape)
+//   kd_f(y) = 2(e^{-y} - 1) + y(e^{-y} + 1)  (first term of eq. diffusion)
+//   kd_g(y) = 1 - 2y e^{-y} - e^{-2y}        (second term of eq. diffusion)
+constexpr double kKdSeriesY = 0.05;
+constexpr int kKdTerms = 16;
+
+// Taylor coefficients of y^m, m <= kKdTerms, of the three functions
+struct KdCoefs {
+  double h[kKdTerms + 1], f[kKdTerms + 1], g[kKdTerms + 1];
+};
+
+constexpr KdCoefs kd_make_coefs() {
+  KdCoefs c{};
+  double inv_fact = 1.0, pow2 = 1.0;
+  for (int m = 0; m <= kKdTerms; ++m) {
+    if (m > 0) {
+      inv_fact /= (double)m;
+      pow2 *= 2.0;
+    }
+    const double sign_odd = (m % 2) ? 1.0 : -1.0;  // (-1)^(m+1)
+    c.h[m] = m >= 2 ? -sign_odd * inv_fact : 0.0;
+    c.f[m] = m >= 3 ? sign_odd * (double)(m - 2) * inv_fact : 0.0;
+    c.g[m] = m >= 3 ? sign_odd * (pow2 - 2.0 * (double)m) * inv_fact : 0.0;
+  }
+  return c;
+}
+
+// sum_{m=LO}^{kKdTerms} c[m] y^m by Horner's rule
+template <int LO>
+__device__ __forceinline__ double kd_series(const double (&c)[kKdTerms + 1], double y) {
+  double s = c[kKdTerms];
+#pragma unroll
+  for (int m = kKdTerms - 1; m >= LO; --m) s = s * y + c[m];
+  double p = 1.0;
+#pragma unroll
+  for (int m = 0; m < LO; ++m) p *= y;
+  return s * p;
+}
+
+__device__ __forceinline__ double kd_h(double y) {
+  constexpr KdCoefs C = kd_make_coefs();
+  return y < kKdSeriesY ? kd_series<2>(C.h, y) : expm1(-y) + y;
+}
+
+__device__ __forceinline__ double kd_f(double y) {
+  constexpr KdCoefs C = kd_make_coefs();
+  if (y < kKdSeriesY) return kd_series<3>(C.f, y);
+  const double e = exp(-y);
+  return 2.0 * (e - 1.0) + y * (e + 1.0);
+}
+
+__device__ __forceinline__ double kd_g(double y) {
+  constexpr KdCoefs C = kd_make_coefs();
+  if (y < kKdSeriesY) return kd_series<3>(C.g, y);
+  const double e = exp(-y);
+  return 1.0 - 2.0 * y * e - e * e;
+}
+
+struct KdParams {
+  double dtf, dtc, R, sigma, mu, T;
+  uint32_t M, tag, strm, key0, key1;
+  uint32_t guard;  // bound on fine KD steps (a step advances at least one grid step)
+};
+
+__device__ __forceinline__ KdParams kd_params(const LevelDesc& d) {
+  KdParams k;
+  k.dtf = d.h_f;
+  k.dtc = d.h_c;
+  k.R = d.s_f;
+  k.sigma = d.s_c;
+  k.mu = d.h_f2;
+  k.T = d.agg_ms2;
+  k.M = d.M;
+  k.tag = d.tag;
+  k.strm = d.stream;
+  k.key0 = d.key0;
+  k.key1 = d.key1;
+  k.guard = d.n_steps + 2u;
+  return k;
+}
+
+// eq. advection and eq. diffusion: a and d of a diffusive phase of length
+// theta that ends with velocity v_next.
+__device__ __forceinline__ void kd_coeffs(const KdParams& k, double theta, double v_next,
+                                          double& a, double& dd) {
+  const double y = k.R * theta;
+  const double dv = v_next - k.mu;
+  a = k.mu * theta + dv * (-expm1(-y)) / k.R;
+  const double d2 = 2.0 * k.sigma * k.sigma / (k.R * k.R) * kd_f(y) + dv * dv / (k.R * k.R) * kd_g(y);
+  dd = sqrt(d2 > 0.0 ? d2 : 0.0);
+}
+
+// Numbers of KD step b - 1 from Philox block b.
+__device__ __forceinline__ void kd_draws(const KdParams& k, uint32_t smp, uint32_t b,
+                                         double& nu_next, double& chi, double& E_next) {
+  const Words w = philox4x32_10(b, smp, k.tag, k.strm, k.key0, k.key1);
+  box_muller(w.w0, w.w1, nu_next, chi);
+  E_next = -log(uniform_f64(w.w2));
+}
+
+// One path (COARSE = false) or a correlated pair of sample smp: final
+// positions and KD step counts (collisions before T).
+template <bool COARSE>
+__device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, double& xf_out,
+                                          double& xc_out, uint32_t& cf_out, uint32_t& cc_out) {
+  const KdParams k = kd_params(d);
+  // initial condition, shared by both paths
+  const Words w0 = philox4x32_10(0u, smp, k.tag, k.strm, k.key0, k.key1);
+  double nc, ns;
+  box_muller(w0.w0, w0.w1, nc, ns);
+  double x0;
+  if (d.x0_kind == 0) x0 = d.x0_a;
+  else if (d.x0_kind == 1) x0 = d.x0_a + d.x0_b * nc;
+  else x0 = cosine_icdf(uniform_f64(w0.w3));
+  const double E0 = -log(uniform_f64(w0.w2));
+
+  double xf = x0, vf = k.mu + k.sigma * ns, tf = 0.0, tauf = E0 / k.R;
+  double cfine = tf + tauf;
+  uint32_t cf = 0, cc = 0, b = 1;
+
+  if constexpr (!COARSE) {
+    while (cfine < k.T && cf < k.guard) {
+      double nu_next, chi, E_next;
+      kd_draws(k, smp, b++, nu_next, chi, E_next);
+      const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
+      const double theta = t_next - cfine;
+      const double v_next = k.mu + k.sigma * nu_next;
+      double a, dd;
+      kd_coeffs(k, theta, v_next, a, dd);
+      xf = xf + vf * tauf + (a + dd * chi);
+      tf = t_next;
+      tauf = E_next / k.R;
+      cfine = tf + tauf;
+      vf = v_next;
+      ++cf;
+    }
+    if (tf < k.T) xf = xf + vf * (k.T - tf);
+    xf_out = xf;
+    xc_out = 0.0;
+    cf_out = cf;
+    cc_out = 0u;
+  } else {
+    double xc = x0, vc = vf, tc = 0.0, ccoarse = cfine;
+    double nu_f = ns;  // velocity number of the fine path's pending flight
+    while ((ccoarse < k.T || cfine < k.T) && cf < k.guard) {
+      // end of the coarse grid step holding the coarse collision, as an
+      // index of the fine grid
+      const double end_c = floor(ccoarse / k.dtc) + 1.0;
+      const double end_c_fine = end_c * (double)k.M;
+      double num = 0.0, den = 0.0, zeta_prev = 0.0;
+      bool first = true;
+      do {
+        double nu_next, chi, E_next;
+        kd_draws(k, smp, b++, nu_next, chi, E_next);
+        const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
+        const double theta = t_next - cfine;
+        const double v_next = k.mu + k.sigma * nu_next;
+        double a, dd;
+        kd_coeffs(k, theta, v_next, a, dd);
+        xf = xf + vf * tauf + (a + dd * chi);
+        // aggregation weights of this fine phase
+        const double y = k.R * theta;
+        const double zeta = -expm1(-y) / k.R;
+        const double theta_p = kd_h(y) / k.R;
+        const double beta = sqrt(2.0 * k.sigma * k.sigma / (k.R * k.R) * kd_h(k.R * theta_p));
+        if (!first) {
+          const double alpha = (tauf + zeta_prev) * k.sigma;
+          num += alpha * nu_f;
+          den += alpha * alpha;
+        }
+        num += beta * chi;
+        den += beta * beta;
+        zeta_prev = zeta;
+        first = false;
+        tf = t_next;
+        tauf = E_next / k.R;
+        cfine = tf + tauf;
+        vf = v_next;
+        nu_f = nu_next;
+        ++cf;
+      } while (!(floor(cfine / k.dtf) + 1.0 > end_c_fine) && cf < k.guard);
+      if (ccoarse < k.T) {
+        const double chi_c = den > 0.0 ? num / sqrt(den) : 0.0;
+        const double t_next = end_c * k.dtc;
+        const double theta = t_next - ccoarse;
+        const double v_next = k.mu + k.sigma * nu_f;
+        double a, dd;
+        kd_coeffs(k, theta, v_next, a, dd);
+        xc = xc + vc * (ccoarse - tc) + (a + dd * chi_c);
+        tc = t_next;
+        ccoarse = cfine;
+        vc = v_next;
+        ++cc;
+      }
+    }
+    if (tf < k.T) xf = xf + vf * (k.T - tf);
+    if (tc < k.T) xc = xc + vc * (k.T - tc);
+    xf_out = xf;
+    xc_out = xc;
+    cf_out = cf;
+    cc_out = cc;
+  }
+}
+
+}  // namespace mlmc

@@ -29,6 +29,7 @@
 #include <stdint.h>
 
 #include "device.hpp"
+#include "kd.hpp"
 #include "kernels.hpp"
 
 namespace mlmc {
@@ -466,6 +467,40 @@ __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
   if (lane == 0) partials[d.tile_base + tile] = out;
 }
 
+// One tile of a kinetic-diffusion item: lane i simulates samples
+// tile*64*spl + 64 j + i, j < spl, with the same record arithmetic as above.
+template <bool kCoarse>
+__device__ __forceinline__ void run_kd_tile(const LevelDesc& d, uint32_t tile,
+                                            Stats* __restrict__ partials) {
+  const int lane = threadIdx.x & (kLanes - 1);
+  const uint64_t tile_samples = (uint64_t)kLanes * d.spl;
+  TileSums acc;
+#pragma unroll 1
+  for (uint32_t j = 0; j < d.spl; ++j) {
+    const uint64_t local = (uint64_t)tile * tile_samples + (uint64_t)(j * kLanes + lane);
+    const bool valid = local < d.n_samples;
+    double xf = 0.0, xc = 0.0;
+    uint32_t cf = 0, cc = 0;
+    if (valid) kd_sample<kCoarse>(d, (uint32_t)(d.sample_begin + local), xf, xc, cf, cc);
+    const double qf = xf * xf;
+    const double qc = kCoarse ? xc * xc : 0.0;
+    const double dq = qf - qc;
+    if (j == 0) acc.shift<kCoarse>(dq, qf, qc);  // lane 0, sample 0 always exists
+    if (valid) {
+      acc.add<kCoarse>(dq, qf, qc, cf, cc);
+      if (d.flags & kFlagSampleOutputs) sample_outputs<double, kCoarse>(d, local, xf, xc, cf, cc);
+    }
+  }
+  const Stats out = acc.record<kCoarse>();
+  if (lane == 0) partials[d.tile_base + tile] = out;
+}
+
+__device__ __forceinline__ void run_kd_unit(const LevelDesc& d, uint32_t unit,
+                                            Stats* __restrict__ partials) {
+  if (d.kind == kKindKdPair) run_kd_tile<true>(d, unit, partials);
+  else run_kd_tile<false>(d, unit, partials);
+}
+
 // ---------------------------------------------------------------------------
 // Time-parallel trajectory, for items of few long trajectories (the warm-up
 // of the fine levels), where one trajectory per lane would leave most of the
@@ -663,6 +698,15 @@ __global__ void __launch_bounds__(256) level_kernel(const LevelDesc* __restrict_
   run_unit<Real, P, KIND>(d, wave, partials);
 }
 
+// The same for a kinetic-diffusion item.
+__global__ void __launch_bounds__(256) kd_level_kernel(const LevelDesc* __restrict__ items,
+                                                        uint32_t item, Stats* __restrict__ partials) {
+  const LevelDesc d = items[item];
+  const uint32_t wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kLanes);
+  if (wave >= d.n_tiles) return;
+  run_kd_unit(d, wave, partials);
+}
+
 // ---------------------------------------------------------------------------
 // Time-parallel items of a work table (their chunks are absent from the
 // persistent kernel's chunk space).  Wavefront w of the grid takes
@@ -756,8 +800,10 @@ __global__ void __launch_bounds__(256) tp_kernel(const LevelDesc* __restrict__ i
 // round covers the whole table (a small launch such as a warm-up), a
 // wavefront takes the chunk of its own index instead and touches no counter.
 // The grid must have at least kChunkStreams blocks (every stream needs waves).
+// KD = true: the kinetic-diffusion instantiation (FP64; its tables hold KD
+// items only and no time-parallel items).
 // ---------------------------------------------------------------------------
-template <typename Real, int P>
+template <typename Real, int P, bool KD>
 __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __restrict__ items,
                                                           const WorkHeader* __restrict__ hdr,
                                                           unsigned int* __restrict__ counter,
@@ -782,7 +828,7 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
                                               threadIdx.x / kLanes);  // static index
   // Time-parallel trajectories first, dealt from the last wavefront down (the
   // chunk streams hand out their first chunks to the first wavefronts).
-  const uint32_t total_tp = hdr->total_tp;
+  const uint32_t total_tp = KD ? 0u : hdr->total_tp;
   if (total_tp) {
     const uint32_t waves = gridDim.x * wpb;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + threadIdx.x / kLanes);
@@ -813,7 +859,9 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
     const uint32_t c = g - (uint32_t)d.chunk_base;
     const uint32_t t0 = c * d.chunk_tiles;
     const uint32_t t1 = min(t0 + d.chunk_tiles, d.n_tiles);
-    switch (d.kind) {
+    if constexpr (KD) {
+      for (uint32_t t = t0; t < t1; ++t) run_kd_unit(d, t, partials);
+    } else switch (d.kind) {
       case kKindFineTwoPoint:
         for (uint32_t t = t0; t < t1; ++t) run_unit<Real, P, kKindFineTwoPoint>(d, t, partials);
         break;
@@ -1058,6 +1106,12 @@ static hipError_t launch_level_p(int kind, const LevelDesc* items, uint32_t item
 hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev, uint32_t item,
                         uint32_t n_tiles, int block, Stats* partials, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
+  if (is_kd_kind(kind)) {
+    const uint64_t threads = (uint64_t)n_tiles * kLanes;
+    const dim3 grid((unsigned)((threads + block - 1) / block));
+    hipLaunchKernelGGL(kd_level_kernel, grid, dim3(block), 0, s, items_dev, item, partials);
+    return hipGetLastError();
+  }
   if (fp64) {
     if (ppt == 1) return launch_level_p<double, 1>(kind, items_dev, item, n_tiles, block, partials, s);
     if (ppt == 2) return launch_level_p<double, 2>(kind, items_dev, item, n_tiles, block, partials, s);
@@ -1068,18 +1122,23 @@ hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev
   return launch_level_p<float, 4>(kind, items_dev, item, n_tiles, block, partials, s);
 }
 
-int persistent_blocks_per_cu(bool fp64, int ppt, int block) {
+int persistent_blocks_per_cu(bool fp64, int ppt, int block, bool kd) {
   int nb = 0;
   hipError_t e;
-  if (fp64) {
-    if (ppt == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<double, 1>, block, 0);
-    else if (ppt == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<double, 2>, block, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<double, 4>, block, 0);
+#define MLMC_OCC(R, PP, K) \
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<R, PP, K>, block, 0)
+  if (kd) {
+    e = MLMC_OCC(double, 1, true);
+  } else if (fp64) {
+    if (ppt == 1) e = MLMC_OCC(double, 1, false);
+    else if (ppt == 2) e = MLMC_OCC(double, 2, false);
+    else e = MLMC_OCC(double, 4, false);
   } else {
-    if (ppt == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<float, 1>, block, 0);
-    else if (ppt == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<float, 2>, block, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel<float, 4>, block, 0);
+    if (ppt == 1) e = MLMC_OCC(float, 1, false);
+    else if (ppt == 2) e = MLMC_OCC(float, 2, false);
+    else e = MLMC_OCC(float, 4, false);
   }
+#undef MLMC_OCC
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;
@@ -1089,18 +1148,20 @@ int persistent_blocks_per_cu(bool fp64, int ppt, int block) {
 
 hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
                              const WorkHeader* hdr_dev, unsigned int* counter, Stats* partials,
-                             int block, int grid, hipStream_t s) {
+                             int block, int grid, hipStream_t s, bool kd) {
   const dim3 g(grid), b(block);
-#define MLMC_PERSIST(R, PP) \
-  hipLaunchKernelGGL((persistent_kernel<R, PP>), g, b, 0, s, items_dev, hdr_dev, counter, partials)
-  if (fp64) {
-    if (ppt == 1) MLMC_PERSIST(double, 1);
-    else if (ppt == 2) MLMC_PERSIST(double, 2);
-    else MLMC_PERSIST(double, 4);
+#define MLMC_PERSIST(R, PP, K) \
+  hipLaunchKernelGGL((persistent_kernel<R, PP, K>), g, b, 0, s, items_dev, hdr_dev, counter, partials)
+  if (kd) {
+    MLMC_PERSIST(double, 1, true);
+  } else if (fp64) {
+    if (ppt == 1) MLMC_PERSIST(double, 1, false);
+    else if (ppt == 2) MLMC_PERSIST(double, 2, false);
+    else MLMC_PERSIST(double, 4, false);
   } else {
-    if (ppt == 1) MLMC_PERSIST(float, 1);
-    else if (ppt == 2) MLMC_PERSIST(float, 2);
-    else MLMC_PERSIST(float, 4);
+    if (ppt == 1) MLMC_PERSIST(float, 1, false);
+    else if (ppt == 2) MLMC_PERSIST(float, 2, false);
+    else MLMC_PERSIST(float, 4, false);
   }
 #undef MLMC_PERSIST
   return hipGetLastError();

@@ -21,14 +21,17 @@ struct alignas(16) WorkHeader {
 constexpr uint32_t kChunkStreams = 8;
 constexpr uint32_t kCounterStride = 32;
 
+// One plain launch over one item (any kind; KD kinds ignore fp64 and ppt).
 hipError_t launch_level(bool fp64, int ppt, int kind, const LevelDesc* items_dev, uint32_t item,
                         uint32_t n_tiles, int block, Stats* partials, hipStream_t s);
 // Blocks of `block` threads of the persistent kernel that fit one CU at once
 // (0 if the runtime cannot say).
-int persistent_blocks_per_cu(bool fp64, int ppt, int block);
+// kd: the kinetic-diffusion instantiation (FP64, one path or pair per lane;
+// fp64 and ppt are then ignored).
+int persistent_blocks_per_cu(bool fp64, int ppt, int block, bool kd);
 hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
                              const WorkHeader* hdr_dev, unsigned int* counter, Stats* partials,
-                             int block, int grid, hipStream_t s);
+                             int block, int grid, hipStream_t s, bool kd);
 // Tile records -> group records -> resident slots in one launch (the tile
 // records of a time-parallel item are first built from its samples);
 // item_done holds one counter per item, zeroed by the stage kernel; `mirror`

@@ -63,7 +63,15 @@ enum : int {
   kKindPairTwoPointSum = 2,
   kKindPairMaxwellSum = 3,
   kKindPairMaxwellAggregate = 4,
+  kKindKdFine = 5,   // kinetic-diffusion scheme: one path (FP64 state)
+  kKindKdPair = 6,   // kinetic-diffusion scheme: correlated fine/coarse pair
 };
+
+// The KD kinds use the coefficient slots of LevelDesc as
+//   h_f = fine step dt_l, h_c = coarse step dt_{l-1}, s_f = collision rate R,
+//   s_c = Maxwellian standard deviation sigma, agg_ms2 = end time T,
+//   h_f2 = Maxwellian mean mu.
+__host__ __device__ inline bool is_kd_kind(int kind) { return kind >= kKindKdFine; }
 
 struct alignas(16) LevelDesc {
   double h_f, s_f, h_c, s_c;    // scheme coefficients, fine and coarse

@@ -115,7 +115,7 @@ def test_merge_stats_equals_two_pass(lib):
 @pytest.mark.parametrize("field,value", [
     ("eps", -1.0), ("eps", float("nan")), ("T", 0.0), ("dt0", -0.5), ("M", 1), ("M", 65),
     ("L", -1), ("L", 31), ("dt0", 0.3), ("x0_kind", 3), ("eq_kind", 2), ("x0_b", -1.0),
-    ("coupling", 2), ("qoi", 2), ("fp64_state", 2), ("reserved", 1)])
+    ("coupling", 2), ("qoi", 2), ("fp64_state", 2), ("scheme", 2)])
 def test_validation_rejects(lib, field, value):
     p = pkg.problem(eps=0.1, T=1.0, dt0=0.5, L=3)
     setattr(p, field, value)
@@ -137,6 +137,13 @@ def test_validation_special_cases(lib):
     p = pkg.problem(eps=0.1, T=1.0, dt0=0.5, qoi=pkg.QOI_X2_HIST, hist_lo=1.0, hist_hi=1.0)
     assert pkg.mlmc_ap_validate(p) == -1
     assert pkg.mlmc_ap_validate(pkg.problem(eps=0.0, T=1.0, dt0=0.5)) == 0
+    # the KD scheme: Maxwellian, eps > 0, FP64 state
+    kd = dict(eps=0.1, T=1.0, dt0=0.5, L=3, fp64_state=1, scheme=pkg.SCHEME_KD)
+    assert pkg.mlmc_ap_validate(pkg.problem(**kd)) == 0
+    assert pkg.mlmc_ap_validate(pkg.problem(**dict(kd, eps=0.0))) == -1
+    assert pkg.mlmc_ap_validate(pkg.problem(**dict(kd, fp64_state=0))) == -1
+    assert pkg.mlmc_ap_validate(pkg.problem(**dict(kd, eq_kind=pkg.EQ_TWO_POINT,
+                                                   coupling=pkg.COUPLING_KICK_SUM))) == -1
 
 
 def test_entry_points_report_errors_without_a_device(lib):

@@ -14,6 +14,9 @@ asymptotic-preserving Monte Carlo study in plain numbers:
 * ``cfg4``  precision study: x0 with density 1 + cos(2 pi x) on [0,1],
             eps = 1e-3, T = 1, dt0 = 0.5, M = 2, L = 10; x^2 and a 64-bin
             histogram on [-4, 5).
+* ``cfg_kd`` the cfg2 estimate with the kinetic-diffusion scheme (homogeneous
+            background: collision rate 1/eps^2, Maxwellian velocities of
+            standard deviation 1/eps), FP64 state.
 * ``cfg5``  serving stream: Poisson arrivals at 200/s, eps log-uniform in
             [1e-4, 1], T uniform in [0.1, 1] (dt0 = T/2, L = 8), RMSE
             log-uniform in [1e-3, 1e-2], Maxwellian, x0 ~ N(0,1).
@@ -23,6 +26,7 @@ import numpy as np
 X0_DELTA, X0_NORMAL, X0_COSINE = 0, 1, 2
 EQ_TWO_POINT, EQ_MAXWELLIAN = 0, 1
 COUPLING_KICK_SUM, COUPLING_AGGREGATE = 0, 1
+SCHEME_SPLITTING, SCHEME_KD = 0, 1
 
 
 def cfg1():
@@ -44,6 +48,12 @@ CFG2_TOL = 1e-3
 
 CFG3_EPS = (1e-4, 1e-3, 1e-2, 1e-1, 1.0)
 CFG3_TOL = (1e-2, 3e-3, 1e-3)
+
+
+def cfg_kd(eps=0.01, stream_id=6):
+    """The cfg2 estimate with the kinetic-diffusion scheme instead of the
+    splitting scheme (homogeneous background, FP64 state)."""
+    return dict(cfg2(eps=eps, stream_id=stream_id), fp64_state=1, scheme=SCHEME_KD)
 
 
 def cfg3():
