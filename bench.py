@@ -12,9 +12,9 @@ kernel launch (issued directly, the library's default).
 Printed: one JSON line.  ``value`` = particle-steps (fine + coarse) per
 second over the K timed estimates.  Extra fields: time-to-RMSE of the same
 launches replayed from captured hipGraphs, of plain per-level launches and of
-plain Monte Carlo at level 8; the eps-sweep batch; serving latency; the
-roofline of the particle kernel; the FP64 oracle timed on the host cores on a
-bounded sample.
+plain Monte Carlo at level 8; the eps-sweep batch; serving latency; the same
+estimate with the kinetic-diffusion scheme; the roofline of the particle
+kernel; the FP64 oracle timed on the host cores on a bounded sample.
 """
 import argparse
 import json
@@ -65,6 +65,28 @@ def algorithmic_slots(prob, N):
 
 KERNEL_SOURCES = ("kernels.hip", "kernels.hpp", "device.hpp", "types.hpp", "stats.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "persistent_kernel_hbm_traffic.json")
+
+
+def exact_second_moment(prob, level):
+    """Exact E[x(T)^2] of the splitting scheme at `level` (reported beside the
+    estimate; x0 ~ N(a, b^2)): with n steps of the level and its h, s, p, the
+    velocity chain has correlation q^d (q = 1 - p) at lag d, so
+    E[x^2] = E[x0^2] + n s^2 + h^2 (n + 2 sum_{d=1}^{n-1} (n - d) q^d)."""
+    dt = prob["dt0"] / float(prob["M"]) ** level
+    n = int(round(prob["T"] / prob["dt0"])) * int(prob["M"]) ** level
+    eps = prob["eps"]
+    den = eps * eps + dt
+    h, s2, q = dt * eps / den, 2.0 * dt * dt / den, 1.0 - dt / den
+    lag = sum((n - d) * q ** d for d in range(1, n))
+    return prob["x0_a"] ** 2 + prob["x0_b"] ** 2 + n * s2 + h * h * (n + 2.0 * lag)
+
+
+def kd_exact_second_moment(prob):
+    """Exact E[x(T)^2] of the kinetic-diffusion scheme in a homogeneous
+    background at every time step: the kinetic value E[x0^2] +
+    2 (T - eps^2 (1 - e^{-T/eps^2}))."""
+    eps, T = prob["eps"], prob["T"]
+    return prob["x0_a"] ** 2 + prob["x0_b"] ** 2 + 2.0 * (T + eps * eps * math.expm1(-T / (eps * eps)))
 
 
 def kernel_source_hash():
@@ -158,7 +180,6 @@ def main():
     import torch
     import paper_2004_04071_amd as pkg
     import workloads as W
-    from oracle import closed_form as CF
 
     torch.cuda.set_device(0)
     pkg.mlmc_ap_init()
@@ -188,7 +209,7 @@ def main():
     value = steps_total / elapsed
     ms_per = elapsed / args.steps * 1e3
     last = results[-1]
-    exact = CF.level_second_moment(prob, prob["L"])
+    exact = exact_second_moment(prob, prob["L"])
     log("estimate %.6f exact %.6f sd %.2e N %s" % (last["estimate"], exact,
                                                    math.sqrt(last["var_estimator"]), last["N"]))
 
@@ -284,6 +305,28 @@ def main():
                               particle_steps_per_s=sstats["particle_steps"] / (span + lat[-1]),
                               ticks=sstats["ticks"])
         log("serving", out["serving"])
+
+        # the paper's kinetic-diffusion scheme on the same estimate (FP64 state)
+        kprob = W.cfg_kd()
+        KP = pkg.as_problem(kprob)
+        kopt = pkg.options(batched=2, **tk)
+        pkg.mlmc_ap_estimate(KP, tol, kopt, stream=hs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kres = [pkg.mlmc_ap_estimate(KP, tol, kopt, stream=hs) for _ in range(reps)]
+        torch.cuda.synchronize()
+        kd_ms = (time.perf_counter() - t0) / reps * 1e3
+        kr = kres[-1]
+        kd_steps = sum(int(l["coll_f"]) + int(l["coll_c"]) for l in kr["levels"])
+        out["kd"] = dict(
+            workload="MLMC-KD eps=0.01 T=1 dt0=0.5 M=2 L=0..8 RMSE=1e-3 x0~N(0,1), "
+                     "homogeneous background, FP64 state",
+            time_to_rmse_ms=kd_ms, kernel_ms=kr["kernel_seconds"] * 1e3,
+            kd_steps=kd_steps, kd_steps_per_s=kd_steps / (kd_ms * 1e-3),
+            N=kr["N"], estimate=kr["estimate"],
+            estimate_exact=kd_exact_second_moment(kprob),
+            sd=math.sqrt(kr["var_estimator"]))
+        log("kd", out["kd"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, last["N"], args.cpu_seconds)
     print(json.dumps(out), flush=True)
