@@ -63,7 +63,7 @@ def algorithmic_slots(prob, N):
     return tot
 
 
-KERNEL_SOURCES = ("kernels.hip", "kernels.hpp", "device.hpp", "types.hpp", "stats.hpp")
+KERNEL_SOURCES = ("kernels.hip", "kernels.hpp", "kd.hpp", "device.hpp", "types.hpp", "stats.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "persistent_kernel_hbm_traffic.json")
 
 
@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=400)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("ap", "kd"), default="ap",
+                    help="kd: time the same estimate with the kinetic-diffusion scheme instead "
+                         "(FP64 state; value = KD steps per second; for profiling its kernel)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed estimates (for profiler runs)")
     ap.add_argument("--tuning", default=None,
@@ -183,7 +186,8 @@ def main():
 
     torch.cuda.set_device(0)
     pkg.mlmc_ap_init()
-    prob = W.cfg2()
+    kd_mode = args.workload == "kd"
+    prob = W.cfg_kd() if kd_mode else W.cfg2()
     tol = W.CFG2_TOL
     stream = torch.cuda.current_stream()
 
@@ -205,11 +209,14 @@ def main():
     results = [pkg.mlmc_ap_estimate(P, tol, opt, stream=hs) for _ in range(args.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    steps_total = sum(r["particle_steps"] for r in results)
+    if kd_mode:   # KD steps actually taken (fine + coarse)
+        steps_total = sum(int(l["coll_f"]) + int(l["coll_c"]) for r in results for l in r["levels"])
+    else:
+        steps_total = sum(r["particle_steps"] for r in results)
     value = steps_total / elapsed
     ms_per = elapsed / args.steps * 1e3
     last = results[-1]
-    exact = exact_second_moment(prob, prob["L"])
+    exact = kd_exact_second_moment(prob) if kd_mode else exact_second_moment(prob, prob["L"])
     log("estimate %.6f exact %.6f sd %.2e N %s" % (last["estimate"], exact,
                                                    math.sqrt(last["var_estimator"]), last["N"]))
 
@@ -219,17 +226,22 @@ def main():
     direct = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=2, **tk))
     kern_s = direct["kernel_seconds"]
     launches = direct["launches"]
-    slots = algorithmic_slots(prob, direct["N"])
-    achieved = slots / kern_s
-    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12,
-                    unit="TOP/s (full-rate VALU lane-slots)", frac=achieved / PEAK_SLOTS,
-                    traffic=recorded_traffic(tuning),
-                    kernel="persistent_kernel<float,%d>" % tuning["ppt"],
-                    avg_launch_ms=kern_s / launches * 1e3, launches=launches)
+    if kd_mode:
+        # no algorithmic operation count for the FP64 library transcendentals
+        # of a KD step: its kernel is characterised by counters instead
+        roofline = None
+    else:
+        slots = algorithmic_slots(prob, direct["N"])
+        achieved = slots / kern_s
+        roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12,
+                        unit="TOP/s (full-rate VALU lane-slots)", frac=achieved / PEAK_SLOTS,
+                        traffic=recorded_traffic(tuning),
+                        kernel="persistent_kernel<float,%d,false>" % tuning["ppt"],
+                        avg_launch_ms=kern_s / launches * 1e3, launches=launches)
     out = {
         "metric": "particle-steps/s; MLMC time-to-RMSE 1e-3 vs plain MC; p50/p99 request latency",
         "value": value,
-        "unit": "particle-steps/s",
+        "unit": "KD steps/s" if kd_mode else "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -237,10 +249,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if kd_mode else "f32",
         "data": "synthetic",
-        "config": {"workload": "MLMC-AP eps=0.01 T=1 dt0=0.5 M=2 L=0..8 RMSE=1e-3 "
-                               "x0~N(0,1) Maxwellian, FP32 state / FP64 statistics",
+        "config": {"workload": ("MLMC-KD eps=0.01 T=1 dt0=0.5 M=2 L=0..8 RMSE=1e-3 x0~N(0,1), "
+                                "homogeneous background, FP64 state") if kd_mode else
+                               ("MLMC-AP eps=0.01 T=1 dt0=0.5 M=2 L=0..8 RMSE=1e-3 "
+                                "x0~N(0,1) Maxwellian, FP32 state / FP64 statistics"),
                    "rmse_tol": tol, "levels": prob["L"] + 1,
                    "particle_steps_per_estimate": last["particle_steps"],
                    "N": last["N"], "tuning": tuning},
@@ -249,7 +263,9 @@ def main():
         "estimate_exact": exact,
         "roofline": roofline,
     }
-    if not args.no_extras:
+    if kd_mode:
+        out["kernel_ms_per_estimate"] = kern_s * 1e3
+    if not args.no_extras and not kd_mode:
         # plain per-level launches (same estimator, one kernel launch per level)
         t0 = time.perf_counter()
         reps = 3
@@ -327,7 +343,7 @@ def main():
             estimate_exact=kd_exact_second_moment(kprob),
             sd=math.sqrt(kr["var_estimator"]))
         log("kd", out["kd"])
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not kd_mode:
         out["cpu_baseline"] = cpu_baseline(prob, last["N"], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -75,27 +75,31 @@ __device__ __forceinline__ double kd_series(const double (&c)[kKdTerms + 1], dou
   return s * p;
 }
 
-__device__ __forceinline__ double kd_h(double y) {
+// With em = e^{-y} - 1 (expm1: accurate for small y) the exp forms above
+// are, exactly,
+//   kd_h = em + y,   kd_f = 2 em + y (2 + em),   kd_g = -(em (2 + em) + 2 y (1 + em)),
+// so one expm1 per diffusive phase serves eqs. advection and diffusion and
+// the aggregation weights.
+__device__ __forceinline__ double kd_h(double y, double em) {
   constexpr KdCoefs C = kd_make_coefs();
-  return y < kKdSeriesY ? kd_series<2>(C.h, y) : expm1(-y) + y;
+  return y < kKdSeriesY ? kd_series<2>(C.h, y) : em + y;
 }
 
-__device__ __forceinline__ double kd_f(double y) {
+__device__ __forceinline__ double kd_f(double y, double em) {
   constexpr KdCoefs C = kd_make_coefs();
-  if (y < kKdSeriesY) return kd_series<3>(C.f, y);
-  const double e = exp(-y);
-  return 2.0 * (e - 1.0) + y * (e + 1.0);
+  return y < kKdSeriesY ? kd_series<3>(C.f, y) : 2.0 * em + y * (2.0 + em);
 }
 
-__device__ __forceinline__ double kd_g(double y) {
+__device__ __forceinline__ double kd_g(double y, double em) {
   constexpr KdCoefs C = kd_make_coefs();
-  if (y < kKdSeriesY) return kd_series<3>(C.g, y);
-  const double e = exp(-y);
-  return 1.0 - 2.0 * y * e - e * e;
+  return y < kKdSeriesY ? kd_series<3>(C.g, y) : -(em * (2.0 + em) + 2.0 * y * (1.0 + em));
 }
 
 struct KdParams {
   double dtf, dtc, R, sigma, mu, T;
+  double inv_r;   // 1/R
+  double inv_r2;  // 1/R^2
+  double c2;      // 2 sigma^2 / R^2
   uint32_t M, tag, strm, key0, key1;
   uint32_t guard;  // bound on fine KD steps (a step advances at least one grid step)
 };
@@ -114,17 +118,19 @@ __device__ __forceinline__ KdParams kd_params(const LevelDesc& d) {
   k.key0 = d.key0;
   k.key1 = d.key1;
   k.guard = d.n_steps + 2u;
+  k.inv_r = 1.0 / k.R;
+  k.inv_r2 = k.inv_r * k.inv_r;
+  k.c2 = 2.0 * k.sigma * k.sigma * k.inv_r2;
   return k;
 }
 
 // eq. advection and eq. diffusion: a and d of a diffusive phase of length
-// theta that ends with velocity v_next.
-__device__ __forceinline__ void kd_coeffs(const KdParams& k, double theta, double v_next,
-                                          double& a, double& dd) {
-  const double y = k.R * theta;
+// theta that ends with velocity v_next; y = R theta, em = e^{-y} - 1.
+__device__ __forceinline__ void kd_coeffs(const KdParams& k, double theta, double y, double em,
+                                          double v_next, double& a, double& dd) {
   const double dv = v_next - k.mu;
-  a = k.mu * theta + dv * (-expm1(-y)) / k.R;
-  const double d2 = 2.0 * k.sigma * k.sigma / (k.R * k.R) * kd_f(y) + dv * dv / (k.R * k.R) * kd_g(y);
+  a = k.mu * theta + dv * (-em) * k.inv_r;
+  const double d2 = k.c2 * kd_f(y, em) + dv * dv * k.inv_r2 * kd_g(y, em);
   dd = sqrt(d2 > 0.0 ? d2 : 0.0);
 }
 
@@ -152,7 +158,7 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
   else x0 = cosine_icdf(uniform_f64(w0.w3));
   const double E0 = -log(uniform_f64(w0.w2));
 
-  double xf = x0, vf = k.mu + k.sigma * ns, tf = 0.0, tauf = E0 / k.R;
+  double xf = x0, vf = k.mu + k.sigma * ns, tf = 0.0, tauf = E0 * k.inv_r;
   double cfine = tf + tauf;
   uint32_t cf = 0, cc = 0, b = 1;
 
@@ -162,12 +168,14 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
       kd_draws(k, smp, b++, nu_next, chi, E_next);
       const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
       const double theta = t_next - cfine;
+      const double y = k.R * theta;
+      const double em = expm1(-y);
       const double v_next = k.mu + k.sigma * nu_next;
       double a, dd;
-      kd_coeffs(k, theta, v_next, a, dd);
+      kd_coeffs(k, theta, y, em, v_next, a, dd);
       xf = xf + vf * tauf + (a + dd * chi);
       tf = t_next;
-      tauf = E_next / k.R;
+      tauf = E_next * k.inv_r;
       cfine = tf + tauf;
       vf = v_next;
       ++cf;
@@ -192,15 +200,17 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
         kd_draws(k, smp, b++, nu_next, chi, E_next);
         const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
         const double theta = t_next - cfine;
+        const double y = k.R * theta;
+        const double em = expm1(-y);
         const double v_next = k.mu + k.sigma * nu_next;
         double a, dd;
-        kd_coeffs(k, theta, v_next, a, dd);
+        kd_coeffs(k, theta, y, em, v_next, a, dd);
         xf = xf + vf * tauf + (a + dd * chi);
-        // aggregation weights of this fine phase
-        const double y = k.R * theta;
-        const double zeta = -expm1(-y) / k.R;
-        const double theta_p = kd_h(y) / k.R;
-        const double beta = sqrt(2.0 * k.sigma * k.sigma / (k.R * k.R) * kd_h(k.R * theta_p));
+        // aggregation weights of this fine phase: zeta = (1 - e^{-y})/R, and
+        // beta over theta' = theta - zeta, i.e. R theta' = kd_h(y)
+        const double zeta = -em * k.inv_r;
+        const double yp = kd_h(y, em);
+        const double beta = sqrt(k.c2 * kd_h(yp, yp < kKdSeriesY ? 0.0 : expm1(-yp)));
         if (!first) {
           const double alpha = (tauf + zeta_prev) * k.sigma;
           num += alpha * nu_f;
@@ -211,7 +221,7 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
         zeta_prev = zeta;
         first = false;
         tf = t_next;
-        tauf = E_next / k.R;
+        tauf = E_next * k.inv_r;
         cfine = tf + tauf;
         vf = v_next;
         nu_f = nu_next;
@@ -221,9 +231,10 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
         const double chi_c = den > 0.0 ? num / sqrt(den) : 0.0;
         const double t_next = end_c * k.dtc;
         const double theta = t_next - ccoarse;
+        const double y = k.R * theta;
         const double v_next = k.mu + k.sigma * nu_f;
         double a, dd;
-        kd_coeffs(k, theta, v_next, a, dd);
+        kd_coeffs(k, theta, y, expm1(-y), v_next, a, dd);
         xc = xc + vc * (ccoarse - tc) + (a + dd * chi_c);
         tc = t_next;
         ccoarse = cfine;

@@ -7,7 +7,7 @@ Bars (derivation in the design notes):
     rms(x_oracle)) -- both sides take the same FP64 operations, and differ only
     by the last-bit differences of exp, log, sin/cos and sqrt between the two
     math libraries, a few units of 1e-16 per KD step over at most a few
-    hundred steps (measured: at most 1.1e-14);
+    hundred steps (measured: at most 2.5e-14);
   * statistics: the device reduction against two-pass FP64 statistics of the
     device's own dump;
   * estimates: within 4.5 standard errors of the exact E[x(T)^2], which the
