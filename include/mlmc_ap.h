@@ -185,7 +185,16 @@ typedef struct mlmc_ap_options {
     int32_t max_iter;       /* MLMC top-up iterations after warm-up (0 = 10) */
     uint64_t n_warmup;      /* warm-up samples per level (0 = 1000) */
     mlmc_ap_tuning tuning;
+    int32_t level_select;   /* MLMC_AP_LEVELS_ALL (0, default): levels 0..L;
+                               MLMC_AP_LEVELS_HEURISTIC: the level set of
+                               mlmc_ap_select_levels_heuristic from the warm-up's
+                               V_l and V_{l,l-1}; the pairs of the set that are not
+                               adjacent levels get a warm-up of their own, adjacent
+                               ones keep their warm-up samples */
+    int32_t reserved;       /* must be 0 */
 } mlmc_ap_options;
+
+enum { MLMC_AP_LEVELS_ALL = 0, MLMC_AP_LEVELS_HEURISTIC = 1 };
 
 typedef struct mlmc_ap_result {
     double estimate;         /* eq. mlmc-compact: sum_l mean(dQ_l) */
@@ -202,6 +211,9 @@ typedef struct mlmc_ap_result {
     double gpu_seconds;      /* device time from table upload to statistics read-back */
     double kernel_seconds;   /* device time of the particle kernels alone (plain and
                                 direct persistent launches; 0 for graph replays) */
+    uint64_t level_mask;     /* bit l set for every level of the hierarchy used; N[l]
+                                and lv[l] of a level l_j of the set hold the samples of
+                                Q_{l_j} - Q_{l_{j-1}} (of Q_{l_1} for the first) */
 } mlmc_ap_result;
 
 /* Library and device set-up.  mlmc_ap_init is optional (every entry point
@@ -236,6 +248,29 @@ mlmc_ap_status mlmc_ap_level_constants(const mlmc_ap_problem* p, int32_t level,
 mlmc_ap_status mlmc_ap_optimal_samples(const double* V_host, const double* C_host, int32_t n,
                                        double tol, uint64_t* N_out_host);
 
+/* Level selection (host only).  Heuristic of Section 5.2 (Algorithm
+ * "Heuristic level selection approach"): from V_l = Var[Q_l] (l = 0..L) and
+ * Vdiff_l = Var[Q_l - Q_{l-1}] (l = 1..L; Vdiff_host[0] is ignored), start
+ * with the first l whose Vdiff_l < V_l and l - 1, then add every later level
+ * whose Vdiff_l is below half the last one added.  Readings: the scan starts
+ * after that first pair (the printed loop from l = 0 would read Vdiff_0);
+ * if no level qualifies the set is {L} (plain Monte Carlo at L); L is always
+ * added, since the estimator targets E[Q_L].  *mask_out: bit l set for each
+ * selected level. */
+mlmc_ap_status mlmc_ap_select_levels_heuristic(const double* V_host, const double* Vdiff_host,
+                                               int32_t L, uint64_t* mask_out);
+
+/* eq. level_selection (host only): the set {l_1 < ... < l_J = L} that
+ * minimises sqrt(V_{l_1} C_{l_1}) + sum_{j>=2} sqrt(V_{l_j,l_{j-1}} C_{l_j,l_{j-1}}),
+ * found exactly as a shortest path over the levels (the problem the paper
+ * writes as an integer linear programme).  V_host, C_host: L+1 values of
+ * the single levels; Vpair_host, Cpair_host: (L+1) x (L+1) row-major, entry
+ * [i][j] (i > j) for the pair (i, j).  All >= 0 (C > 0).  *cost_out
+ * (nullable) receives the minimum. */
+mlmc_ap_status mlmc_ap_select_levels_optimal(const double* V_host, const double* C_host,
+                                             const double* Vpair_host, const double* Cpair_host,
+                                             int32_t L, uint64_t* mask_out, double* cost_out);
+
 /* Pairwise merge of two statistics records (host only; the same update the
  * device reductions apply): out = a (+) b.  out may alias a or b. */
 mlmc_ap_status mlmc_ap_merge_stats(const mlmc_ap_level_stats* a, const mlmc_ap_level_stats* b,
@@ -261,6 +296,18 @@ mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, i
                                       uint64_t sample_begin, uint64_t n_samples,
                                       mlmc_ap_level_stats* out_host, void* traj_dev,
                                       uint32_t* coll_dev, uint64_t* hist_host, void* stream);
+
+/* As mlmc_ap_simulate_level (single = 0) for the pair of levels
+ * (level, coarse_level) of a non-contiguous hierarchy (Section 4.2): the
+ * coarse path is the scheme at level coarse_level (0 <= coarse_level <
+ * level), one coarse step per M^(level - coarse_level) fine steps, built from
+ * the fine random numbers as for adjacent levels; coarse_level = level - 1
+ * is mlmc_ap_simulate_level.  Samples use the fine level's counter tag.
+ * EINVAL for coarse_level outside [0, level). */
+mlmc_ap_status mlmc_ap_simulate_pair(const mlmc_ap_problem* p, int32_t level, int32_t coarse_level,
+                                     uint64_t sample_begin, uint64_t n_samples,
+                                     mlmc_ap_level_stats* out_host, void* traj_dev,
+                                     uint32_t* coll_dev, uint64_t* hist_host, void* stream);
 
 /* MLMC estimate of E[Q_L] to RMSE tolerance rmse_tol (Section 4.1): warm-up
  * samples on every level 0..L, then eqs. Nopt1/Noptj with sample variances

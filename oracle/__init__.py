@@ -68,6 +68,12 @@ def lib():
         L.oracle_words.restype = None
         L.oracle_simulate_kd.argtypes = L.oracle_simulate.argtypes
         L.oracle_simulate_kd.restype = ctypes.c_int
+        L.oracle_simulate_pair.argtypes = [
+            ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+            ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, u64p,
+            ctypes.c_uint64, dp, dp, u32p, u32p, ctypes.c_int]
+        L.oracle_simulate_pair.restype = ctypes.c_int
         L.oracle_kd_coeffs.argtypes = [ctypes.c_double] * 5 + [dp]
         L.oracle_kd_coeffs.restype = None
         L.oracle_kd_coarse_numbers.argtypes = [
@@ -125,7 +131,8 @@ def _common_args(prob, level, single):
             int(prob.get("seed", 42)), int(prob.get("stream_id", 0)))
 
 
-def simulate(prob, level, sample_begin=0, n=None, samples=None, single=False, threads=None):
+def simulate(prob, level, sample_begin=0, n=None, samples=None, single=False, threads=None,
+             coarse_level=None):
     """Final positions and collision counts of fine/coarse pairs.
 
     ``prob`` is a dict with keys eps, T, dt0, M, x0_kind, x0_a, x0_b, eq_kind,
@@ -133,7 +140,10 @@ def simulate(prob, level, sample_begin=0, n=None, samples=None, single=False, th
     default, or SCHEME_KD: the kinetic-diffusion scheme, Maxwellian only;
     its counts are KD steps, i.e. collisions before T).  Either a contiguous
     range [sample_begin, sample_begin+n) or an explicit index array
-    ``samples``.  Returns dict(xf, xc, cf, cc) of numpy arrays.
+    ``samples``.  ``coarse_level`` (pairs only; default level - 1) puts the
+    coarse path of the pair at that level (one coarse step per
+    M^(level - coarse_level) fine steps).  Returns dict(xf, xc, cf, cc) of
+    numpy arrays.
     """
     kd = int(prob.get("scheme", SCHEME_SPLITTING)) == SCHEME_KD
     if kd and int(prob["eq_kind"]) != EQ_MAXWELLIAN:
@@ -151,6 +161,16 @@ def simulate(prob, level, sample_begin=0, n=None, samples=None, single=False, th
     cf = np.zeros(count, dtype=np.uint32)
     cc = np.zeros(count, dtype=np.uint32)
     if count:
+        if coarse_level is not None and not single and int(coarse_level) != int(level) - 1:
+            a = _common_args(prob, level, single)
+            st = lib().oracle_simulate_pair(
+                int(kd), *a[:5], int(coarse_level), *a[6:], int(sample_begin), idx_p, count,
+                _ptr(xf, ctypes.c_double), _ptr(xc, ctypes.c_double),
+                _ptr(cf, ctypes.c_uint32), _ptr(cc, ctypes.c_uint32),
+                int(threads or default_threads()))
+            if st != 0:
+                raise ValueError("coarse_level must be in [0, level)")
+            return dict(xf=xf, xc=xc, cf=cf, cc=cc)
         fn = lib().oracle_simulate_kd if kd else lib().oracle_simulate
         fn(*_common_args(prob, level, single), int(sample_begin), idx_p,
                               count, _ptr(xf, ctypes.c_double), _ptr(xc, ctypes.c_double),

@@ -212,6 +212,7 @@ enum { COUPLING_KICK_SUM = 0, COUPLING_AGGREGATE = 1 };
 typedef struct {
     double eps, T, dt0;
     int M, level, single;
+    int coarse_level;    /* level of the coarse path of a pair (level - 1 unless set) */
     int x0_kind; double x0_a, x0_b;
     int eq_kind, coupling;
     uint32_t key[2];
@@ -240,9 +241,11 @@ static void simulate_one(const problem_t *P, uint64_t sample,
     const int l = P->level;
     const int coarse = (!P->single && l >= 1);
     const uint32_t tag = (uint32_t)l + (P->single ? 64u : 0u);
+    /* fine steps per coarse step: M^(l - coarse level) (M for adjacent levels) */
+    const int Mb = coarse ? (int)llround(pow((double)P->M, (double)(l - P->coarse_level))) : 1;
     level_consts F = make_level(P->eps, P->T, P->dt0, P->M, l);
-    level_consts C = coarse ? make_level(P->eps, P->T, P->dt0, P->M, l - 1) : F;
-    uint64_t thr_c2 = coarse ? oracle_coarse_threshold(F.thr, C.thr, P->M) : 0;
+    level_consts C = coarse ? make_level(P->eps, P->T, P->dt0, P->M, P->coarse_level) : F;
+    uint64_t thr_c2 = coarse ? oracle_coarse_threshold(F.thr, C.thr, Mb) : 0;
 
     words_t ws;
     words_init(&ws, P->key, (uint32_t)sample, tag, P->stream);
@@ -303,11 +306,11 @@ static void simulate_one(const problem_t *P, uint64_t sample,
                           oracle_uniform(wa), oracle_uniform(wb), xi, g, (double)hit,
                           xf, vf, 0, 0, 0, 0};
 
-        if (coarse && (n % (uint64_t)P->M) == (uint64_t)(P->M - 1)) {
+        if (coarse && (n % (uint64_t)Mb) == (uint64_t)(Mb - 1)) {
             int chit = ((uint64_t)min_word < thr_c2);
             double kick;
             if (P->coupling == COUPLING_KICK_SUM) {
-                kick = sum_xi / sqrt((double)P->M);
+                kick = sum_xi / sqrt((double)Mb);
             } else {
                 /* the last in-block draw becomes the coarse velocity when the
                  * coarse path collides; otherwise it joins the kick */
@@ -317,7 +320,7 @@ static void simulate_one(const problem_t *P, uint64_t sample,
                     den += last_uses * last_uses;
                 }
                 kick = (F.s * sum_xi + F.h * num) /
-                       sqrt((double)P->M * F.s * F.s + F.h * F.h * den);
+                       sqrt((double)Mb * F.s * F.s + F.h * F.h * den);
             }
             xc = xc + C.h * vc + C.s * kick;
             if (chit) { vc = vf; cc++; }
@@ -338,6 +341,7 @@ static problem_t make_problem(double eps, double T, double dt0, int M, int level
 {
     problem_t P;
     P.eps = eps; P.T = T; P.dt0 = dt0; P.M = M; P.level = level; P.single = single;
+    P.coarse_level = level - 1;
     P.x0_kind = x0_kind; P.x0_a = x0_a; P.x0_b = x0_b;
     P.eq_kind = eq_kind; P.coupling = coupling;
     P.key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
@@ -553,7 +557,8 @@ static void simulate_kd_one(const problem_t *P, uint64_t sample,
     const double sigma = 1.0 / P->eps;            /* Maxwellian standard deviation */
     const double T = P->T;
     const double dtf = P->dt0 / pow((double)P->M, (double)l);
-    const double dtc = coarse ? P->dt0 / pow((double)P->M, (double)(l - 1)) : 0.0;
+    const double dtc = coarse ? P->dt0 / pow((double)P->M, (double)P->coarse_level) : 0.0;
+    const double Mb = coarse ? (double)llround(pow((double)P->M, (double)(l - P->coarse_level))) : 1.0;
 
     /* Initial condition, shared by both paths. */
     uint32_t w[4];
@@ -604,7 +609,7 @@ static void simulate_kd_one(const problem_t *P, uint64_t sample,
         /* end of the coarse grid step containing the coarse collision, in
          * fine steps */
         const double end_c = kd_step_of(ccoarse, dtc) + 1.0;
-        const double end_c_fine = end_c * (double)P->M;
+        const double end_c_fine = end_c * Mb;
         double num = 0.0, den = 0.0, zeta_prev = 0.0;
         int first = 1;
         uint32_t used = 0;
@@ -703,4 +708,27 @@ uint64_t oracle_kd_coarse_numbers(double eps, double T, double dt0, int M, int l
     simulate_kd_one(&P, sample, &xf, &xc, &cf, &cc, &tr);
     out_final[0] = xf; out_final[1] = xc;
     return tr.used;
+}
+
+/* As oracle_simulate / oracle_simulate_kd for a pair whose coarse path is at
+ * level coarse_level < level (the level pairs of a non-contiguous hierarchy,
+ * Section 4.2): one coarse step per M^(level - coarse_level) fine steps. */
+int oracle_simulate_pair(int kd, double eps, double T, double dt0, int M, int level,
+                         int coarse_level, int x0_kind, double x0_a, double x0_b, int eq_kind,
+                         int coupling, uint64_t seed, uint32_t stream,
+                         uint64_t sample_begin, const uint64_t *idx, uint64_t n,
+                         double *xf, double *xc, uint32_t *cf, uint32_t *cc, int nthreads)
+{
+    problem_t P = make_problem(eps, T, dt0, M, level, 0, x0_kind, x0_a, x0_b,
+                               eq_kind, coupling, seed, stream);
+    if (coarse_level < 0 || coarse_level >= level) return -1;
+    P.coarse_level = coarse_level;
+    (void)nthreads;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+        uint64_t s = idx ? idx[i] : sample_begin + (uint64_t)i;
+        if (kd) simulate_kd_one(&P, s, &xf[i], &xc[i], &cf[i], &cc[i], NULL);
+        else simulate_one(&P, s, &xf[i], &xc[i], &cf[i], &cc[i], NULL);
+    }
+    return 0;
 }

@@ -64,7 +64,8 @@ class Tuning(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("batched", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-                ("n_warmup", ctypes.c_uint64), ("tuning", Tuning)]
+                ("n_warmup", ctypes.c_uint64), ("tuning", Tuning),
+                ("level_select", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -74,7 +75,7 @@ class Result(ctypes.Structure):
                 ("N", ctypes.c_uint64 * MAX_LEVELS), ("lv", LevelStats * MAX_LEVELS),
                 ("particle_steps", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("seconds", ctypes.c_double), ("gpu_seconds", ctypes.c_double),
-                ("kernel_seconds", ctypes.c_double)]
+                ("kernel_seconds", ctypes.c_double), ("level_mask", ctypes.c_uint64)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -107,6 +108,13 @@ _SIGNATURES = {
     "mlmc_ap_merge_stats": [_P(LevelStats), _P(LevelStats), _P(LevelStats)],
     "mlmc_ap_simulate_level": [_P(Problem), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                ctypes.c_uint64, _P(LevelStats), _vp, _vp, _P(ctypes.c_uint64), _vp],
+    "mlmc_ap_simulate_pair": [_P(Problem), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                              ctypes.c_uint64, _P(LevelStats), _vp, _vp, _P(ctypes.c_uint64), _vp],
+    "mlmc_ap_select_levels_heuristic": [_P(ctypes.c_double), _P(ctypes.c_double), ctypes.c_int32,
+                                        _P(ctypes.c_uint64)],
+    "mlmc_ap_select_levels_optimal": [_P(ctypes.c_double), _P(ctypes.c_double),
+                                      _P(ctypes.c_double), _P(ctypes.c_double), ctypes.c_int32,
+                                      _P(ctypes.c_uint64), _P(ctypes.c_double)],
     "mlmc_ap_estimate": [_P(Problem), ctypes.c_double, _P(Options), _P(Result),
                          _P(ctypes.c_uint64), _vp],
     "mlmc_ap_plain_mc": [_P(Problem), ctypes.c_double, _P(Options), _P(Result), _vp],
@@ -220,19 +228,26 @@ def result_dict(r):
                 N=list(r.N[:L + 1]),
                 levels=[dict(zip(_STATS_NAMES, t)) for t in struct.iter_unpack(_STATS_FORMAT, raw)],
                 particle_steps=int(r.particle_steps), launches=int(r.launches),
-                seconds=r.seconds, gpu_seconds=r.gpu_seconds, kernel_seconds=r.kernel_seconds)
+                seconds=r.seconds, gpu_seconds=r.gpu_seconds, kernel_seconds=r.kernel_seconds,
+                level_mask=int(r.level_mask),
+                level_set=[l for l in range(L + 1) if (int(r.level_mask) >> l) & 1])
 
 
 BATCHED_DIRECT, BATCHED_GRAPH, BATCHED_TIMED, BATCHED_PER_LEVEL = 0, 1, 2, -1
 
 
+LEVELS_ALL, LEVELS_HEURISTIC = 0, 1
+
+
 def options(batched=BATCHED_DIRECT, max_iter=0, n_warmup=0, block=0, ppt=0, waves_per_simd=0,
-            tp_max_samples=0):
+            tp_max_samples=0, level_select=LEVELS_ALL):
     """mlmc_ap_options: batched = 0 (direct persistent launch, default), 1 (hipGraph
-    replay), 2 (direct, particle kernel timed), -1 (one launch per level)."""
+    replay), 2 (direct, particle kernel timed), -1 (one launch per level);
+    level_select = LEVELS_ALL (levels 0..L) or LEVELS_HEURISTIC."""
     return Options(batched=batched, max_iter=max_iter, n_warmup=n_warmup,
                    tuning=Tuning(block=block, ppt=ppt, waves_per_simd=waves_per_simd,
-                                 tp_max_samples=tp_max_samples))
+                                 tp_max_samples=tp_max_samples),
+                   level_select=level_select, reserved=0)
 
 
 # ---------------------------------------------------------------------------
@@ -306,6 +321,51 @@ def mlmc_ap_simulate_level(p, level, sample_begin, n_samples, single=False, traj
     if hist:
         return stats_dict(out), [int(x) for x in hbuf]
     return stats_dict(out)
+
+
+def mlmc_ap_simulate_pair(p, level, coarse_level, sample_begin, n_samples, traj=None, coll=None,
+                          hist=False, stream=None):
+    """As mlmc_ap_simulate_level for the pair (level, coarse_level)."""
+    P = as_problem(p)
+    out = LevelStats()
+    hbuf = None
+    if hist:
+        hbuf = (ctypes.c_uint64 * (3 * P.nbins + 4))()
+    _check(lib().mlmc_ap_simulate_pair(ctypes.byref(P), int(level), int(coarse_level),
+                                       int(sample_begin), int(n_samples), ctypes.byref(out),
+                                       _dev_ptr(traj), _dev_ptr(coll), hbuf, _stream(stream)),
+           "mlmc_ap_simulate_pair")
+    if hist:
+        return stats_dict(out), [int(x) for x in hbuf]
+    return stats_dict(out)
+
+
+def _doubles(v):
+    v = [float(x) for x in v]
+    return (ctypes.c_double * max(1, len(v)))(*v)
+
+
+def mlmc_ap_select_levels_heuristic(V, Vdiff):
+    """Selected levels (sorted list) from V_l and V_{l,l-1} (Vdiff[0] ignored)."""
+    L = len(V) - 1
+    m = ctypes.c_uint64()
+    _check(lib().mlmc_ap_select_levels_heuristic(_doubles(V), _doubles(Vdiff), L, ctypes.byref(m)),
+           "mlmc_ap_select_levels_heuristic")
+    return [l for l in range(L + 1) if (m.value >> l) & 1]
+
+
+def mlmc_ap_select_levels_optimal(V, C, Vpair, Cpair):
+    """(levels, cost) minimising eq. level_selection; Vpair/Cpair are
+    (L+1) x (L+1) nested lists or arrays, entry [i][j] for i > j."""
+    L = len(V) - 1
+    flat = lambda a: [float(a[i][j]) for i in range(L + 1) for j in range(L + 1)]
+    m = ctypes.c_uint64()
+    c = ctypes.c_double()
+    _check(lib().mlmc_ap_select_levels_optimal(_doubles(V), _doubles(C), _doubles(flat(Vpair)),
+                                               _doubles(flat(Cpair)), L, ctypes.byref(m),
+                                               ctypes.byref(c)),
+           "mlmc_ap_select_levels_optimal")
+    return [l for l in range(L + 1) if (m.value >> l) & 1], c.value
 
 
 def mlmc_ap_estimate(p, rmse_tol, opt=None, hist=False, stream=None):

@@ -70,15 +70,24 @@ static double kd_path_cost(const mlmc_ap_problem& p, int level) {
   return (double)c.n_steps * -std::expm1(-R * c.dt);
 }
 
-uint64_t sample_cost(const mlmc_ap_problem& p, int level, bool single) {
+uint64_t pair_cost(const mlmc_ap_problem& p, int level, int coarse_level) {
   if (p.scheme == MLMC_AP_SCHEME_KD) {
     double c = kd_path_cost(p, level);
-    if (!single && level > 0) c += kd_path_cost(p, level - 1);
+    if (coarse_level >= 0) c += kd_path_cost(p, coarse_level);
     return std::max<uint64_t>(1, (uint64_t)std::ceil(c));
   }
   const uint64_t n = level_const(p, level).n_steps;
-  if (single || level == 0) return n;
-  return n + level_const(p, level - 1).n_steps;
+  return coarse_level >= 0 ? n + level_const(p, coarse_level).n_steps : n;
+}
+
+uint64_t sample_cost(const mlmc_ap_problem& p, int level, bool single) {
+  return pair_cost(p, level, (single || level == 0) ? -1 : level - 1);
+}
+
+uint64_t block_factor(const mlmc_ap_problem& p, int level, int coarse_level) {
+  uint64_t b = 1;
+  for (int i = coarse_level; i < level; ++i) b *= (uint64_t)p.M;
+  return b;
 }
 
 mlmc_ap_status validate_problem(const mlmc_ap_problem* p) {
@@ -136,7 +145,10 @@ bool time_parallel_candidate(const ItemSpec& s, int32_t tp_max_samples) {
   const int64_t limit = tp_max_samples == 0 ? kTpDefaultMaxSamples : tp_max_samples;
   if (limit <= 0 || s.n_samples == 0 || s.n_samples > (uint64_t)limit) return false;
   const bool coarse = !s.single && s.level >= 1;
-  if (coarse && p.M != 2 && p.M != 4) return false;  // coarse blocks inside a 64-step chunk
+  const uint64_t mb = coarse ? block_factor(p, s.level, s.coarse_level >= 0 ? s.coarse_level
+                                                                              : s.level - 1)
+                             : 1;
+  if (coarse && mb != 2 && mb != 4) return false;  // coarse blocks inside a 64-step chunk
   return level_const(p, s.level).n_steps >= (int64_t)kLongLevelSteps;
 }
 
@@ -169,8 +181,11 @@ std::vector<bool> choose_time_parallel(const std::vector<ItemSpec>& specs,
 LevelDesc make_desc(const ItemSpec& s, bool tp) {
   const mlmc_ap_problem& p = *s.prob;
   const bool coarse = !s.single && s.level >= 1;
+  const int lc = s.coarse_level >= 0 ? s.coarse_level : s.level - 1;
   const LevelConst F = level_const(p, s.level);
-  const LevelConst C = coarse ? level_const(p, s.level - 1) : F;
+  const LevelConst C = coarse ? level_const(p, lc) : F;
+  // fine steps per coarse step (M for adjacent levels)
+  const uint64_t mb = coarse ? block_factor(p, s.level, lc) : (uint64_t)p.M;
   const bool maxwell = p.eq_kind == MLMC_AP_EQ_MAXWELLIAN;
   const bool agg = coarse && p.coupling == MLMC_AP_COUPLING_AGGREGATE;
   LevelDesc d;
@@ -178,9 +193,9 @@ LevelDesc make_desc(const ItemSpec& s, bool tp) {
   d.h_f = F.h; d.s_f = F.s;
   d.h_c = coarse ? C.h : 0.0;
   d.s_c = coarse ? C.s : 0.0;
-  d.agg_ms2 = (double)p.M * F.s * F.s;
+  d.agg_ms2 = (double)mb * F.s * F.s;
   d.h_f2 = F.h * F.h;
-  d.rsqrt_m = 1.0 / std::sqrt((double)p.M);
+  d.rsqrt_m = 1.0 / std::sqrt((double)mb);
   d.x0_a = p.x0_a; d.x0_b = p.x0_b;
   if (p.qoi == MLMC_AP_QOI_X2_HIST) {
     d.hist_lo = p.hist_lo;
@@ -193,11 +208,11 @@ LevelDesc make_desc(const ItemSpec& s, bool tp) {
   d.traj = s.traj;
   d.coll = s.coll;
   d.thr_f = F.thr;
-  d.thr_c2 = coarse ? coarse_threshold(F.thr, C.thr, p.M) : 1;
+  d.thr_c2 = coarse ? coarse_threshold(F.thr, C.thr, (int)mb) : 1;
   d.thr_f_m1 = d.thr_f >= 1 ? (uint32_t)(d.thr_f - 1) : 0u;
   d.thr_c2_m1 = d.thr_c2 >= 1 ? (uint32_t)(d.thr_c2 - 1) : 0u;
   d.n_steps = (uint32_t)F.n_steps;
-  d.M = (uint32_t)p.M;
+  d.M = (uint32_t)mb;
   d.tag = (uint32_t)s.level + (s.single ? 64u : 0u);
   d.stream = p.stream_id;
   d.key0 = (uint32_t)(p.seed & 0xFFFFFFFFull);
@@ -629,6 +644,47 @@ int launch_mode(int32_t batched) {
 }
 
 // ---------------------------------------------------------------------------
+// Level selection (Section 4.2, Section 5.2).
+// ---------------------------------------------------------------------------
+uint64_t select_levels_heuristic(const double* V, const double* Vdiff, int L) {
+  if (L <= 0) return 1ull;
+  int l = 1;
+  while (l <= L && Vdiff[l] > V[l]) ++l;  // first level whose difference beats the level
+  if (l > L) return 1ull << L;
+  uint64_t mask = (1ull << (l - 1)) | (1ull << l);
+  double vmin = Vdiff[l];
+  for (int k = l + 1; k <= L; ++k)
+    if (Vdiff[k] < 0.5 * vmin) {          // enough variance decay to pay for level k
+      mask |= 1ull << k;
+      vmin = Vdiff[k];
+    }
+  return mask | (1ull << L);
+}
+
+// best[i]: least cost of a hierarchy ending at level i; a hierarchy is a path
+// (first level) -> ... -> i, so the levels are taken in increasing order.
+double select_levels_optimal(const double* V, const double* C, const double* Vpair,
+                             const double* Cpair, int L, uint64_t* mask) {
+  const int n = L + 1;
+  std::vector<double> best(n);
+  std::vector<int> prev(n, -1);
+  for (int i = 0; i < n; ++i) {
+    best[i] = std::sqrt(V[i] * C[i]);
+    for (int j = 0; j < i; ++j) {
+      const double c = best[j] + std::sqrt(Vpair[i * n + j] * Cpair[i * n + j]);
+      if (c < best[i]) {
+        best[i] = c;
+        prev[i] = j;
+      }
+    }
+  }
+  uint64_t m = 0;
+  for (int i = L; i >= 0; i = prev[i]) m |= 1ull << i;
+  *mask = m;
+  return best[L];
+}
+
+// ---------------------------------------------------------------------------
 // MLMC control of one request.
 // ---------------------------------------------------------------------------
 void McRequest::init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, uint64_t warmup,
@@ -646,7 +702,14 @@ void McRequest::init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, u
   done.assign(p.L + 1, 0);
   target.assign(p.L + 1, 0);
   st.assign(p.L + 1, stats_empty());
-  for (int l = first_level(); l <= p.L; ++l) target[l] = n_warmup;
+  coarse_of.assign(p.L + 1, -1);
+  in_set.assign(p.L + 1, 0);
+  selected = false;
+  for (int l = first_level(); l <= p.L; ++l) {
+    target[l] = n_warmup;
+    in_set[l] = 1;
+    coarse_of[l] = (plain || l == 0) ? -1 : l - 1;
+  }
   particle_steps = 0;
   launches = 0;
   gpu_seconds = kernel_seconds = 0.0;
@@ -657,13 +720,16 @@ bool McRequest::plan(std::vector<ItemSpec>& items, uint32_t slot_base,
   if (phase == 2) return false;
   bool any = false;
   for (int l = first_level(); l <= prob.L; ++l) {
-    if (done[l] >= target[l]) continue;
+    if (!in_set[l] || done[l] >= target[l]) continue;
     uint64_t n = target[l] - done[l];
     if (max_per_tick && n > max_per_tick) n = max_per_tick;
     ItemSpec s;
     s.prob = &prob;
     s.level = l;
-    s.single = plain;
+    // the first level of a hierarchy that does not start at 0 runs single
+    // trajectories (the plain-MC counter tag, independent of the pairs)
+    s.single = plain || (l > 0 && coarse_of[l] < 0);
+    s.coarse_level = coarse_of[l];
     s.sample_begin = done[l];
     s.n_samples = n;
     s.result_slot = slot_base + (uint32_t)l;
@@ -679,23 +745,66 @@ bool McRequest::plan(std::vector<ItemSpec>& items, uint32_t slot_base,
 
 static double sample_var(const Stats& s) { return s.n > 1.0 ? s.m2_dq / (s.n - 1.0) : 0.0; }
 
+uint64_t McRequest::item_cost(int l) const {
+  if (plain) return sample_cost(prob, l, true);
+  return pair_cost(prob, l, coarse_of[l]);
+}
+
+// After the warm-up of adjacent pairs on every level: V_l from the fine
+// paths (Q_l), V_{l,l-1} from the differences; the new set's pairs that are
+// not the warm-up's adjacent pairs start over with a warm-up of their own.
+void McRequest::select_levels() {
+  const int L = prob.L;
+  std::vector<double> V(L + 1, 0.0), Vd(L + 1, 0.0);
+  for (int l = 0; l <= L; ++l) {
+    const Stats& s = st[l];
+    const double n1 = s.n > 1.0 ? s.n - 1.0 : 1.0;
+    V[l] = (l == 0 ? s.m2_dq : s.m2_qf) / n1;
+    Vd[l] = s.m2_dq / n1;
+  }
+  const uint64_t mask = select_levels_heuristic(V.data(), Vd.data(), L);
+  int prev = -1;
+  for (int l = 0; l <= L; ++l) {
+    if (!((mask >> l) & 1ull)) {
+      in_set[l] = 0;
+      target[l] = done[l];
+      continue;
+    }
+    const int keep = coarse_of[l];
+    coarse_of[l] = prev;
+    if (prev != keep) {  // a different item than the warm-up's
+      done[l] = 0;
+      st[l] = stats_empty();
+      target[l] = n_warmup;
+    }
+    prev = l;
+  }
+  selected = true;
+}
+
 void McRequest::absorb(const Stats* slots) {
   for (int l = first_level(); l <= prob.L; ++l) {
+    if (!in_set[l]) continue;
     const uint64_t n_new = (uint64_t)slots[l].n;
     if (n_new > done[l]) {
-      particle_steps += (n_new - done[l]) * sample_cost(prob, l, plain);
+      particle_steps += (n_new - done[l]) * item_cost(l);
       done[l] = n_new;
     }
     st[l] = slots[l];
   }
   for (;;) {
     for (int l = first_level(); l <= prob.L; ++l)
-      if (done[l] < target[l]) return;  // the current round is not complete
+      if (in_set[l] && done[l] < target[l]) return;  // the current round is not complete
     if (phase == 0) {
+      if (level_select != MLMC_AP_LEVELS_ALL && !plain && !selected) {
+        select_levels();
+        continue;  // warm-up of the set's new pairs, if any
+      }
       phase = 1;
     } else {
       double v = 0.0;
-      for (int l = first_level(); l <= prob.L; ++l) v += sample_var(st[l]) / (double)done[l];
+      for (int l = first_level(); l <= prob.L; ++l)
+        if (in_set[l]) v += sample_var(st[l]) / (double)done[l];
       if (v <= 0.5 * tol * tol) {
         converged = true;
         phase = 2;
@@ -709,9 +818,10 @@ void McRequest::absorb(const Stats* slots) {
     // eqs. Nopt1/Noptj with sample variances and the deterministic costs
     double S = 0.0;
     for (int l = first_level(); l <= prob.L; ++l)
-      S += std::sqrt(sample_var(st[l]) * (double)sample_cost(prob, l, plain));
+      if (in_set[l]) S += std::sqrt(sample_var(st[l]) * (double)item_cost(l));
     for (int l = first_level(); l <= prob.L; ++l) {
-      const double c = (double)sample_cost(prob, l, plain);
+      if (!in_set[l]) continue;
+      const double c = (double)item_cost(l);
       const double N = std::ceil(2.0 / (tol * tol) * std::sqrt(sample_var(st[l]) / c) * S);
       const uint64_t Ni = N >= 4294967295.0 ? 4294967295ull : (uint64_t)N;
       target[l] = std::max<uint64_t>(Ni, done[l]);
@@ -728,10 +838,12 @@ void McRequest::fill_result(mlmc_ap_result* out) const {
   out->status = MLMC_AP_OK;
   double est = 0.0, var = 0.0;
   for (int l = first_level(); l <= prob.L; ++l) {
+    if (!in_set[l]) continue;
     est += st[l].mean_dq;
     if (done[l]) var += sample_var(st[l]) / (double)done[l];
     out->N[l] = done[l];
     out->lv[l] = stats_to_api(st[l]);
+    out->level_mask |= 1ull << l;
   }
   out->estimate = est;
   out->var_estimator = var;
@@ -862,6 +974,36 @@ mlmc_ap_status mlmc_ap_level_constants(const mlmc_ap_problem* p, int32_t level,
   return MLMC_AP_OK;
 }
 
+mlmc_ap_status mlmc_ap_select_levels_heuristic(const double* V_host, const double* Vdiff_host,
+                                               int32_t L, uint64_t* mask_out) {
+  if (!V_host || !Vdiff_host || !mask_out) return set_error(MLMC_AP_EINVAL, "NULL argument");
+  if (L < 0 || L >= MLMC_AP_MAX_LEVELS) return set_error(MLMC_AP_EINVAL, "L must be in [0, 30]");
+  for (int l = 0; l <= L; ++l)
+    if (!(V_host[l] >= 0.0) || (l > 0 && !(Vdiff_host[l] >= 0.0)))
+      return set_error(MLMC_AP_EINVAL, "variances must be >= 0");
+  *mask_out = select_levels_heuristic(V_host, Vdiff_host, L);
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_select_levels_optimal(const double* V_host, const double* C_host,
+                                             const double* Vpair_host, const double* Cpair_host,
+                                             int32_t L, uint64_t* mask_out, double* cost_out) {
+  if (!V_host || !C_host || !Vpair_host || !Cpair_host || !mask_out)
+    return set_error(MLMC_AP_EINVAL, "NULL argument");
+  if (L < 0 || L >= MLMC_AP_MAX_LEVELS) return set_error(MLMC_AP_EINVAL, "L must be in [0, 30]");
+  const int n = L + 1;
+  for (int i = 0; i < n; ++i) {
+    if (!(V_host[i] >= 0.0) || !(C_host[i] > 0.0))
+      return set_error(MLMC_AP_EINVAL, "V must be >= 0 and C > 0");
+    for (int j = 0; j < i; ++j)
+      if (!(Vpair_host[i * n + j] >= 0.0) || !(Cpair_host[i * n + j] > 0.0))
+        return set_error(MLMC_AP_EINVAL, "V must be >= 0 and C > 0");
+  }
+  const double c = select_levels_optimal(V_host, C_host, Vpair_host, Cpair_host, L, mask_out);
+  if (cost_out) *cost_out = c;
+  return MLMC_AP_OK;
+}
+
 mlmc_ap_status mlmc_ap_optimal_samples(const double* V, const double* C, int32_t n, double tol,
                                        uint64_t* N) {
   if (!V || !C || !N || n < 1) return set_error(MLMC_AP_EINVAL, "bad arrays");
@@ -885,10 +1027,11 @@ mlmc_ap_status mlmc_ap_merge_stats(const mlmc_ap_level_stats* a, const mlmc_ap_l
   return MLMC_AP_OK;
 }
 
-mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, int32_t single,
-                                      uint64_t sample_begin, uint64_t n_samples,
-                                      mlmc_ap_level_stats* out_host, void* traj_dev,
-                                      uint32_t* coll_dev, uint64_t* hist_host, void* stream) {
+static mlmc_ap_status simulate_common(const mlmc_ap_problem* p, int32_t level, int32_t single,
+                                      int32_t coarse_level, uint64_t sample_begin,
+                                      uint64_t n_samples, mlmc_ap_level_stats* out_host,
+                                      void* traj_dev, uint32_t* coll_dev, uint64_t* hist_host,
+                                      void* stream) {
   MLMC_TRY(validate_problem(p));
   if (!out_host) return set_error(MLMC_AP_EINVAL, "out_host is NULL");
   if (level < 0 || level > p->L) return set_error(MLMC_AP_EINVAL, "level must be in [0, L]");
@@ -914,6 +1057,7 @@ mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, i
   it.prob = p;
   it.level = level;
   it.single = single != 0;
+  it.coarse_level = coarse_level;
   it.sample_begin = sample_begin;
   it.n_samples = n_samples;
   it.result_slot = 0;
@@ -928,6 +1072,25 @@ mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, i
     MLMC_HIP(hipMemcpy(hist_host, ws->hist_dev, hist_n * sizeof(uint64_t), hipMemcpyDeviceToHost));
   }
   return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, int32_t single,
+                                      uint64_t sample_begin, uint64_t n_samples,
+                                      mlmc_ap_level_stats* out_host, void* traj_dev,
+                                      uint32_t* coll_dev, uint64_t* hist_host, void* stream) {
+  return simulate_common(p, level, single, -1, sample_begin, n_samples, out_host, traj_dev,
+                         coll_dev, hist_host, stream);
+}
+
+mlmc_ap_status mlmc_ap_simulate_pair(const mlmc_ap_problem* p, int32_t level, int32_t coarse_level,
+                                     uint64_t sample_begin, uint64_t n_samples,
+                                     mlmc_ap_level_stats* out_host, void* traj_dev,
+                                     uint32_t* coll_dev, uint64_t* hist_host, void* stream) {
+  if (!p) return set_error(MLMC_AP_EINVAL, "problem is NULL");
+  if (level < 1 || coarse_level < 0 || coarse_level >= level)
+    return set_error(MLMC_AP_EINVAL, "a pair needs 0 <= coarse_level < level");
+  return simulate_common(p, level, 0, coarse_level, sample_begin, n_samples, out_host, traj_dev,
+                         coll_dev, hist_host, stream);
 }
 
 static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* tols, int32_t n_req,
@@ -946,6 +1109,11 @@ static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* to
   const mlmc_ap_options o = default_options(opt);
   const int mode = launch_mode(o.batched);
   if (mode < 0) return set_error(MLMC_AP_EINVAL, "options.batched must be -1, 0, 1, 2 or 3");
+  if (o.level_select != MLMC_AP_LEVELS_ALL && o.level_select != MLMC_AP_LEVELS_HEURISTIC)
+    return set_error(MLMC_AP_EINVAL, "options.level_select must be 0 or 1");
+  if (o.reserved != 0) return set_error(MLMC_AP_EINVAL, "options.reserved must be 0");
+  if (o.level_select != MLMC_AP_LEVELS_ALL && hist_host)
+    return set_error(MLMC_AP_EINVAL, "level selection does not support per-level histograms");
   Workspace* ws = workspace();
   if (!ws) return MLMC_AP_EDEVICE;
   std::lock_guard<std::mutex> lk(ws->mu);
@@ -953,7 +1121,10 @@ static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* to
   MLMC_TRY(check_tuning(t));
   const double t0 = now_s();
   std::vector<McRequest> reqs(n_req);
-  for (int i = 0; i < n_req; ++i) reqs[i].init(p[i], tols[i], plain, o.n_warmup, o.max_iter, 0);
+  for (int i = 0; i < n_req; ++i) {
+    reqs[i].init(p[i], tols[i], plain, o.n_warmup, o.max_iter, 0);
+    reqs[i].level_select = o.level_select;
+  }
   // histogram counters (single request with QOI_X2_HIST)
   size_t hist_stride = 0;
   unsigned long long* hist_dev = nullptr;

@@ -43,12 +43,21 @@ uint64_t coarse_threshold(uint64_t thr_f, uint64_t thr_c, int M);
 mlmc_ap_status validate_problem(const mlmc_ap_problem* p);
 // Particle steps of one sample: n_l (+ n_{l-1} for a pair at l >= 1).
 uint64_t sample_cost(const mlmc_ap_problem& p, int level, bool single);
+// The same for a pair whose coarse path is at level coarse_level (< level).
+uint64_t pair_cost(const mlmc_ap_problem& p, int level, int coarse_level);
+// Fine steps per coarse step of a pair (level, coarse_level): M^(level - coarse_level).
+uint64_t block_factor(const mlmc_ap_problem& p, int level, int coarse_level);
+// Level selection (see the C ABI): bit masks of the selected levels.
+uint64_t select_levels_heuristic(const double* V, const double* Vdiff, int L);
+double select_levels_optimal(const double* V, const double* C, const double* Vpair,
+                             const double* Cpair, int L, uint64_t* mask);
 
 // One work item request: a sample range of one level of one problem.
 struct ItemSpec {
   const mlmc_ap_problem* prob;
   int level;
   bool single;
+  int coarse_level = -1;     // coarse path of a pair: this level (< level), or -1 for level - 1
   uint64_t sample_begin, n_samples;
   uint32_t result_slot;
   unsigned long long* hist;  // device histogram counters or null
@@ -172,6 +181,10 @@ struct McRequest {
   bool need_check = false;     // statistics changed since the last constraint check
   std::vector<uint64_t> done, target;
   std::vector<Stats> st;       // host copy of the resident statistics per level
+  int level_select = 0;        // MLMC_AP_LEVELS_*
+  bool selected = false;       // the level set has been chosen
+  std::vector<int> coarse_of;  // coarse level of level l's pair; -1: single level
+  std::vector<char> in_set;    // level l is part of the hierarchy
   uint64_t particle_steps = 0;
   uint64_t launches = 0;
   double gpu_seconds = 0.0, kernel_seconds = 0.0;
@@ -179,6 +192,10 @@ struct McRequest {
   void init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, uint64_t warmup,
             int iters, uint64_t cap);
   int first_level() const { return plain ? prob.L : 0; }
+  // Particle steps of one sample of level l's item.
+  uint64_t item_cost(int l) const;
+  // Chooses the level set after the warm-up (level_select != 0).
+  void select_levels();
   // Appends this request's work for the next launch; returns false if it has
   // none (finished).  Slots are slot_base + level.
   bool plan(std::vector<ItemSpec>& items, uint32_t slot_base, unsigned long long* hist_base,

@@ -436,13 +436,41 @@ def pin_kd_invariants():
     assert np.var(dq) < 1e-6 * np.var(r["xf"] ** 2)
 
 
+def pin_kd_nonadjacent_pairs():
+    """The coarse path of a KD pair (l, l') with l' < l - 1 has the law of the
+    KD path of level l' (two-sample KS and x^4 tests) and the exact second
+    moment."""
+    for k, (eps, l, lc, M) in enumerate(((0.3, 4, 1, 2), (1.0, 3, 0, 2), (0.1, 2, 0, 3))):
+        prob = kd_problem(eps, x0_kind=1, M=M, T=1.5 if M == 3 else 1.0, stream=420 + k)
+        pair = O.simulate(prob, l, 0, 100000, coarse_level=lc)
+        below = O.simulate(dict(prob, stream_id=440 + k), lc, 0, 100000)
+        a, b = pair["xc"], below["xf"]
+        assert stats.ks_2samp(a, b).pvalue > P_MIN, (eps, l, lc)
+        assert abs(_z(a ** 2, CF.kinetic_limit(eps, prob["T"], 1.0))) < Z_MAX
+
+
 KD_PINS = [pin_kd_second_moment_exact, pin_kd_diffusive_phase_bruteforce,
-           pin_kd_coarse_number_laws, pin_kd_coarse_matches_level_below, pin_kd_invariants]
+           pin_kd_coarse_number_laws, pin_kd_coarse_matches_level_below, pin_kd_invariants,
+           pin_kd_nonadjacent_pairs]
+
+def pin_nonadjacent_pairs():
+    """A pair of levels (l, l') with l' < l - 1 (a non-contiguous hierarchy,
+    Section 4.2): its coarse path is the scheme at level l' (exact second
+    moment of the discrete scheme, P1), for both couplings and M = 2, 3."""
+    for k, (M, coupling, l, lc) in enumerate(((2, 1, 4, 1), (2, 0, 5, 2), (3, 1, 3, 1))):
+        prob = maxwell_problem(0.2, T=1.5 if M == 3 else 1.0, M=M, coupling=coupling,
+                               stream=400 + k)
+        r = O.simulate(prob, l, 0, 100000, coarse_level=lc)
+        assert abs(_z(r["xc"] ** 2, CF.level_second_moment(prob, lc))) < Z_MAX, (M, l, lc)
+        assert abs(_z(r["xf"] ** 2, CF.level_second_moment(prob, l))) < Z_MAX, (M, l, lc)
+        n_c = int(round(prob["T"] / prob["dt0"])) * M ** lc
+        assert np.all(r["cc"] <= n_c)
+
 
 ALL_PINS = [pin_philox_kat, pin_word_layout, pin_uniform, pin_normals, pin_second_moment_cfg1,
             pin_second_moment_levels, pin_cosine_initial, pin_heat_limit, pin_kinetic_limit,
             pin_two_point_bruteforce, pin_telescoping, pin_coupling_laws, pin_coarse_threshold,
-            pin_symmetry, pin_optimal_samples, pin_mlmc_unbiased]
+            pin_symmetry, pin_optimal_samples, pin_mlmc_unbiased, pin_nonadjacent_pairs]
 
 
 def run_all(stop_at_first=False, pins=None):

@@ -1,0 +1,180 @@
+"""Non-contiguous level hierarchies on the GPU (Section 4.2), through the C
+ABI: pairs of levels (l, l') with l' < l - 1 against the oracle, and MLMC
+estimates on the level set the heuristic of Section 5.2 selects.
+
+Bars: as for adjacent pairs (collision / KD-step counts bit-exact; FP32
+positions 1e-5, FP64 positions 1e-12 of max(|x|, rms x)); the selected
+level set equals the heuristic applied to the same warm-up statistics; the
+estimate within 4.5 standard errors of the exact E[Q_L].
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import closed_form as CF
+from oracle import levels as OL
+from oracle import mlmc as OM
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2004_04071_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    pkg.mlmc_ap_init()
+    yield
+    pkg.mlmc_ap_set_tuning(tp_max_samples=4096)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def kd(eps, **kw):
+    return dict(W.cfg_kd(eps=eps, stream_id=kw.pop("stream_id", 600)), **kw)
+
+
+def scaled_error(got, want):
+    scale = np.maximum(np.abs(want), math.sqrt(np.mean(want ** 2)))
+    return float(np.max(np.abs(got - want) / scale))
+
+
+PAIRS = [
+    # name, problem, level, coarse level, begin, n
+    ("ap_fp32_l5_c3", W.cfg2(eps=0.05, stream_id=601), 5, 3, 7, 3000),
+    ("ap_fp32_l6_c0", W.cfg2(eps=0.2, stream_id=602), 6, 0, 0, 1500),
+    ("ap_fp64_l4_c1", dict(W.cfg2(eps=0.1, stream_id=603), fp64_state=1), 4, 1, 0, 2000),
+    ("ap_kicksum_l4_c2", W.cfg2(eps=0.1, coupling=W.COUPLING_KICK_SUM, stream_id=604), 4, 2, 3, 1000),
+    ("ap_M3_l3_c1", dict(W.cfg2(eps=0.1, stream_id=605), M=3, T=1.5, L=4), 3, 1, 0, 1000),
+    ("ap_twopoint_l5_c2", dict(W.cfg1(), M=2, L=6, dt0=0.125, T=1.0, fp64_state=0,
+                               stream_id=606), 5, 2, 0, 1000),
+    ("kd_l5_c2", kd(0.1, stream_id=607), 5, 2, 0, 2000),
+    ("kd_l8_c1", kd(0.01, stream_id=608), 8, 1, 11, 1000),
+    ("kd_eps1_l3_c0", kd(1.0, stream_id=609), 3, 0, 0, 2000),
+]
+
+
+@pytest.mark.parametrize("name,prob,level,lc,begin,n", PAIRS, ids=[c[0] for c in PAIRS])
+def test_nonadjacent_pair_matches_oracle(name, prob, level, lc, begin, n):
+    say("case", name)
+    P = pkg.as_problem(prob)
+    dt = torch.float64 if P.fp64_state else torch.float32
+    traj = torch.full((2 * n,), float("nan"), dtype=dt, device="cuda")
+    coll = torch.full((2 * n,), -1, dtype=torch.int32, device="cuda")
+    st = pkg.mlmc_ap_simulate_pair(P, level, lc, begin, n, traj=traj, coll=coll)
+    torch.cuda.synchronize()
+    ref = O.simulate(prob, level, begin, n, coarse_level=lc)
+    x = traj.cpu().double().numpy()
+    c = coll.cpu().numpy().astype(np.int64)
+    assert np.array_equal(c[:n], ref["cf"].astype(np.int64)), "fine counts differ"
+    assert np.array_equal(c[n:], ref["cc"].astype(np.int64)), "coarse counts differ"
+    rel = 1e-12 if P.fp64_state else 1e-5
+    ef, ec = scaled_error(x[:n], ref["xf"]), scaled_error(x[n:], ref["xc"])
+    say("  max scaled error fine %.3e coarse %.3e" % (ef, ec))
+    assert ef <= rel and ec <= rel
+    dev = OM.stats_of(x[:n], x[n:], level)
+    assert st["n"] == n
+    sd = math.sqrt(dev["m2_dq"] / max(n - 1, 1))
+    assert abs(st["mean_dq"] - dev["mean_dq"]) <= 1e-12 * (abs(dev["mean_dq"]) + sd)
+
+
+def test_adjacent_pair_entry_equals_simulate_level():
+    prob = W.cfg2(eps=0.05, stream_id=610)
+    a = pkg.mlmc_ap_simulate_pair(prob, 4, 3, 0, 5000)
+    b = pkg.mlmc_ap_simulate_level(prob, 4, 0, 5000)
+    assert a == b
+
+
+def test_nonadjacent_time_parallel_equals_per_lane():
+    """Block factor 4 (levels 6 and 4, M = 2) takes the time-parallel path for
+    a few long trajectories; it must agree bitwise with the per-lane loop."""
+    prob = W.cfg2(eps=0.02, stream_id=611)
+    res = []
+    for tp in (4096, -1):
+        pkg.mlmc_ap_set_tuning(tp_max_samples=tp)
+        traj = torch.zeros(2 * 300, dtype=torch.float32, device="cuda")
+        st = pkg.mlmc_ap_simulate_pair(prob, 6, 4, 0, 300, traj=traj)
+        torch.cuda.synchronize()
+        res.append((st, traj.cpu()))
+    pkg.mlmc_ap_set_tuning(tp_max_samples=4096)
+    assert res[0][0] == res[1][0]
+    assert torch.equal(res[0][1], res[1][1])
+
+
+def test_pair_entry_rejects_bad_levels():
+    prob = W.cfg2()
+    for level, lc in ((3, 3), (3, -1), (0, 0), (3, 5)):
+        with pytest.raises(pkg.MlmcApError):
+            pkg.mlmc_ap_simulate_pair(prob, level, lc, 0, 10)
+
+
+def warmup_variances(prob, n_w):
+    """V_l and V_{l,l-1} from the same warm-up samples the estimator takes
+    (adjacent pairs, samples [0, n_w) of every level)."""
+    V, Vd = [], [0.0]
+    for l in range(prob["L"] + 1):
+        st = pkg.mlmc_ap_simulate_level(prob, l, 0, n_w)
+        V.append((st["m2_dq"] if l == 0 else st["m2_qf"]) / (n_w - 1))
+        if l:
+            Vd.append(st["m2_dq"] / (n_w - 1))
+    return V, Vd
+
+
+SELECT = [
+    ("kd_eps0.01", kd(0.01, stream_id=620), 1e-3),
+    ("kd_eps0.3", kd(0.3, stream_id=621, L=6), 5e-3),
+    ("ap_eps0.01", W.cfg2(stream_id=622), 1e-3),
+    ("ap_eps1", W.cfg2(eps=1.0, stream_id=623), 3e-3),
+]
+
+
+@pytest.mark.parametrize("name,prob,tol", SELECT, ids=[c[0] for c in SELECT])
+def test_estimate_on_selected_levels(name, prob, tol):
+    n_w = 1000
+    V, Vd = warmup_variances(prob, n_w)
+    want = OL.heuristic(V, Vd)
+    r = pkg.mlmc_ap_estimate(prob, tol, pkg.options(level_select=pkg.LEVELS_HEURISTIC))
+    kd_scheme = prob.get("scheme", 0) == W.SCHEME_KD
+    exact = (CF.kinetic_limit(prob["eps"], prob["T"], 1.0) if kd_scheme
+             else CF.level_second_moment(prob, prob["L"]))
+    sd = math.sqrt(r["var_estimator"])
+    say("%s: levels %s (heuristic on the warm-up %s), N %s, estimate %.6f exact %.6f sd %.2e"
+        % (name, r["level_set"], want, [r["N"][l] for l in r["level_set"]], r["estimate"],
+           exact, sd))
+    assert r["level_set"] == want
+    assert r["converged"]
+    assert abs(r["estimate"] - exact) <= 4.5 * sd
+    assert all(r["N"][l] == 0 for l in range(prob["L"] + 1) if l not in want)
+    # the same estimate on every launch form
+    for batched in (-1, 1):
+        o = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=batched,
+                                                        level_select=pkg.LEVELS_HEURISTIC))
+        assert (o["estimate"], o["N"], o["level_mask"]) == (r["estimate"], r["N"], r["level_mask"])
+
+
+def test_selected_levels_terms_match_pair_entry():
+    """Each term of a selected-level estimate equals mlmc_ap_simulate_pair (or
+    the single level for the first) on the same sample range."""
+    prob = kd(0.01, stream_id=630)
+    r = pkg.mlmc_ap_estimate(prob, 2e-3, pkg.options(level_select=pkg.LEVELS_HEURISTIC))
+    levels = r["level_set"]
+    for j, l in enumerate(levels):
+        n = r["N"][l]
+        if j == 0:
+            st = pkg.mlmc_ap_simulate_level(prob, l, 0, n, single=(l > 0))
+        else:
+            st = pkg.mlmc_ap_simulate_pair(prob, l, levels[j - 1], 0, n)
+        lv = r["levels"][l]
+        assert st["n"] == lv["n"] == n
+        sd = math.sqrt(st["m2_dq"] / max(n - 1, 1))
+        assert abs(st["mean_dq"] - lv["mean_dq"]) <= 1e-9 * (abs(st["mean_dq"]) + sd)

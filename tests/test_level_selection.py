@@ -1,0 +1,96 @@
+"""Level selection of the C ABI (host-only entry points) against the
+oracle: the heuristic of Section 5.2 on hand-derived cases and random
+variance profiles, and the cost-optimal set of eq. level_selection against
+plain enumeration (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import levels as OL
+
+pkg = pytest.importorskip("paper_2004_04071_amd")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    try:
+        return pkg.lib()
+    except Exception as e:  # pragma: no cover
+        pytest.skip("library not built: %s" % e)
+
+
+# Hand-derived from the algorithm's steps: the first level whose difference
+# variance is below its own variance starts the set with the level before it;
+# a later level joins when its difference variance is below half of the last
+# one taken.
+HAND = [
+    # V, Vdiff (index 0 unused), selected
+    ([1.0] * 9, [0, 1.5, 1.2, 0.8, 0.5, 0.3, 0.1, 0.03, 0.004], [2, 3, 5, 6, 7, 8]),
+    ([1.0] * 5, [0, 0.5, 0.2, 0.09, 0.04], [0, 1, 2, 3, 4]),
+    ([1.0] * 5, [0, 0.5, 0.4, 0.3, 0.3], [0, 1, 4]),          # L added at the end
+    ([1.0] * 4, [0, 2.0, 3.0, 1.5], [3]),                    # no pair pays: level L alone
+    ([2.0], [0], [0]),                                       # L = 0
+    ([1.0, 1.0, 1.0], [0, 1.0, 0.2], [0, 1, 2]),             # V_{l,l-1} = V_l ends the search
+]
+
+
+@pytest.mark.parametrize("V,Vd,want", HAND)
+def test_heuristic_hand_cases(lib, V, Vd, want):
+    assert OL.heuristic(V, Vd) == want
+    assert pkg.mlmc_ap_select_levels_heuristic(V, Vd) == want
+
+
+def test_heuristic_random_profiles(lib):
+    rng = np.random.default_rng(5)
+    for _ in range(300):
+        L = int(rng.integers(0, 12))
+        V = list(rng.uniform(0.5, 2.0, L + 1))
+        # a bump then a decay, as for the kinetic-diffusion levels
+        Vd = [0.0] + list(np.exp(rng.normal(0, 1.5, L)) * np.geomspace(2, 1e-3, L))
+        assert pkg.mlmc_ap_select_levels_heuristic(V, Vd) == OL.heuristic(V, Vd)
+
+
+def _random_instance(rng, L):
+    V = rng.uniform(0.1, 2.0, L + 1)
+    C = np.array([2.0 ** l for l in range(L + 1)])
+    Vp = np.zeros((L + 1, L + 1))
+    Cp = np.zeros((L + 1, L + 1))
+    for i in range(L + 1):
+        for j in range(i):
+            Vp[i, j] = V[i] * rng.uniform(1e-3, 1.5) * 0.5 ** (i - j > 1)
+            Cp[i, j] = C[i] + C[j]
+    return V, C, Vp, Cp
+
+
+def test_optimal_against_enumeration(lib):
+    rng = np.random.default_rng(11)
+    for _ in range(150):
+        L = int(rng.integers(0, 9))
+        V, C, Vp, Cp = _random_instance(rng, L)
+        best, args = OL.optimal(V, C, Vp, Cp)
+        got, cost = pkg.mlmc_ap_select_levels_optimal(V, C, Vp, Cp)
+        assert cost == pytest.approx(best, rel=1e-12)
+        assert got in args
+        assert OL.hierarchy_cost(got, V, C, Vp, Cp) == pytest.approx(best, rel=1e-12)
+
+
+def test_optimal_special_cases(lib):
+    # all pairs useless: level L alone
+    V = [1.0, 1.0, 1.0]
+    C = [1.0, 2.0, 4.0]
+    big = [[0, 0, 0], [9.0, 0, 0], [9.0, 9.0, 0]]
+    Cp = [[1, 1, 1], [3.0, 1, 1], [5.0, 6.0, 1]]
+    assert pkg.mlmc_ap_select_levels_optimal(V, C, big, Cp)[0] == [2]
+    # free corrections: every level pays
+    tiny = [[0, 0, 0], [1e-30, 0, 0], [1e-30, 1e-30, 0]]
+    levels, cost = pkg.mlmc_ap_select_levels_optimal(V, C, tiny, Cp)
+    assert levels[0] == 0 and levels[-1] == 2 and cost == pytest.approx(1.0, rel=1e-9)
+
+
+def test_selectors_reject_bad_input(lib):
+    with pytest.raises(pkg.MlmcApError):
+        pkg.mlmc_ap_select_levels_heuristic([1.0, -1.0], [0.0, 0.5])
+    with pytest.raises(pkg.MlmcApError):
+        pkg.mlmc_ap_select_levels_optimal([1.0, 1.0], [1.0, 0.0], [[0, 0], [1, 0]],
+                                          [[1, 1], [1, 1]])

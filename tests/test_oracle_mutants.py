@@ -29,13 +29,13 @@ MUTANTS = [
      "int chit = ((uint64_t)min_word < F.thr);"),
     ("coarse_threshold_unadjusted", "int chit = ((uint64_t)min_word < thr_c2);",
      "int chit = ((uint64_t)min_word < C.thr);"),
-    ("kick_sum_unnormalised", "kick = sum_xi / sqrt((double)P->M);", "kick = sum_xi;"),
-    ("aggregate_norm_wrong", "sqrt((double)P->M * F.s * F.s + F.h * F.h * den)",
-     "sqrt((double)P->M * F.s * F.s + F.h * den)"),
+    ("kick_sum_unnormalised", "kick = sum_xi / sqrt((double)Mb);", "kick = sum_xi;"),
+    ("aggregate_norm_wrong", "sqrt((double)Mb * F.s * F.s + F.h * F.h * den)",
+     "sqrt((double)Mb * F.s * F.s + F.h * den)"),
     ("coarse_uses_fine_drift", "xc = xc + C.h * vc + C.s * kick;", "xc = xc + F.h * vc + C.s * kick;"),
     ("coarse_uses_fine_kick_std", "xc = xc + C.h * vc + C.s * kick;", "xc = xc + C.h * vc + F.s * kick;"),
-    ("block_boundary_misaligned", "(n % (uint64_t)P->M) == (uint64_t)(P->M - 1)",
-     "(n % (uint64_t)P->M) == 0"),
+    ("block_boundary_misaligned", "(n % (uint64_t)Mb) == (uint64_t)(Mb - 1)",
+     "(n % (uint64_t)Mb) == 0"),
     ("block_sum_not_reset", "sum_xi = 0.0; vel_num = 0.0;", "vel_num = 0.0;"),
     ("coarse_velocity_not_updated", "if (chit) { vc = vf; cc++; }", "if (chit) { cc++; }"),
     ("cosine_icdf_sign", "double F = mid + sin(2.0 * M_PI * mid) / (2.0 * M_PI);",
@@ -44,6 +44,9 @@ MUTANTS = [
     ("velocity_not_resampled", "vf = v_new;", "vf = vf;"),
     ("coarse_threshold_linearised", "-expm1(log1p(-pc) / (double)M)", "(pc / (double)M)"),
     ("block_min_not_reset", "            min_word = 0xFFFFFFFFu;\n", "\n"),
+    ("nonadjacent_block_is_M",
+     "const int Mb = coarse ? (int)llround(pow((double)P->M, (double)(l - P->coarse_level))) : 1;",
+     "const int Mb = coarse ? P->M : 1;"),
 ]
 
 
@@ -67,6 +70,9 @@ KD_MUTANTS = [
     ("kd_one_fine_step_per_window", "} while (!(kd_step_of(cfine, dtf) + 1.0 > end_c_fine));",
      "} while (0);"),
     ("kd_alpha_includes_own_flight", "if (!first) {", "if (1) {"),
+    ("kd_nonadjacent_block_is_M",
+     "const double Mb = coarse ? (double)llround(pow((double)P->M, (double)(l - P->coarse_level))) : 1.0;",
+     "const double Mb = coarse ? (double)P->M : 1.0;"),
     ("kd_exponential_from_wrong_word", "*E_next = -log(oracle_uniform(w[2]));",
      "*E_next = -log(oracle_uniform(w[0]));"),
 ]
