@@ -12,9 +12,11 @@ kernel launch (issued directly, the library's default).
 Printed: one JSON line.  ``value`` = particle-steps (fine + coarse) per
 second over the K timed estimates.  Extra fields: time-to-RMSE of the same
 launches replayed from captured hipGraphs, of plain per-level launches and of
-plain Monte Carlo at level 8; the eps-sweep batch; serving latency; the same
-estimate with the kinetic-diffusion scheme; the roofline of the particle
-kernel; the FP64 oracle timed on the host cores on a bounded sample.
+plain Monte Carlo at level 8; the estimate on the level set the heuristic
+level selection picks; the eps-sweep batch; serving latency; the same
+estimate with the kinetic-diffusion scheme (all levels and selected levels);
+the roofline of the particle kernel; the FP64 oracle timed on the host cores
+on a bounded sample.
 """
 import argparse
 import json
@@ -290,6 +292,22 @@ def main():
         log("per-level %.2f ms, batched %.2f ms (graph replay %.2f ms), plain MC %.2f ms"
             % (per_level_ms, ms_per, graph_ms, plain_ms))
 
+        # the same estimate on the level set the heuristic of Section 5.2 picks
+        sopt = pkg.options(batched=0, level_select=pkg.LEVELS_HEURISTIC, **tk)
+        pkg.mlmc_ap_estimate(P, tol, sopt, stream=hs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sel = pkg.mlmc_ap_estimate(P, tol, sopt, stream=hs)
+        torch.cuda.synchronize()
+        sel_ms = (time.perf_counter() - t0) / reps * 1e3
+        out["level_selection"] = dict(levels=sel["level_set"], time_to_rmse_ms=sel_ms,
+                                      particle_steps=sel["particle_steps"],
+                                      N=[sel["N"][l] for l in sel["level_set"]],
+                                      estimate=sel["estimate"],
+                                      sd=math.sqrt(sel["var_estimator"]))
+        log("level selection", out["level_selection"])
+
         # eps sweep: 15 requests in one batched launch per iteration vs one by one
         probs, tols = W.cfg3()
         pkg.mlmc_ap_estimate_batch(probs, tols)
@@ -334,6 +352,14 @@ def main():
         kd_ms = (time.perf_counter() - t0) / reps * 1e3
         kr = kres[-1]
         kd_steps = sum(int(l["coll_f"]) + int(l["coll_c"]) for l in kr["levels"])
+        ksopt = pkg.options(batched=2, level_select=pkg.LEVELS_HEURISTIC, **tk)
+        pkg.mlmc_ap_estimate(KP, tol, ksopt, stream=hs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ks = pkg.mlmc_ap_estimate(KP, tol, ksopt, stream=hs)
+        torch.cuda.synchronize()
+        kd_sel_ms = (time.perf_counter() - t0) / reps * 1e3
         out["kd"] = dict(
             workload="MLMC-KD eps=0.01 T=1 dt0=0.5 M=2 L=0..8 RMSE=1e-3 x0~N(0,1), "
                      "homogeneous background, FP64 state",
@@ -341,7 +367,10 @@ def main():
             kd_steps=kd_steps, kd_steps_per_s=kd_steps / (kd_ms * 1e-3),
             N=kr["N"], estimate=kr["estimate"],
             estimate_exact=kd_exact_second_moment(kprob),
-            sd=math.sqrt(kr["var_estimator"]))
+            sd=math.sqrt(kr["var_estimator"]),
+            level_selection=dict(levels=ks["level_set"], time_to_rmse_ms=kd_sel_ms,
+                                 N=[ks["N"][l] for l in ks["level_set"]],
+                                 estimate=ks["estimate"], sd=math.sqrt(ks["var_estimator"])))
         log("kd", out["kd"])
     if not args.no_cpu_baseline and not kd_mode:
         out["cpu_baseline"] = cpu_baseline(prob, last["N"], args.cpu_seconds)
