@@ -190,11 +190,17 @@ typedef struct mlmc_ap_options {
                                mlmc_ap_select_levels_heuristic from the warm-up's
                                V_l and V_{l,l-1}; the pairs of the set that are not
                                adjacent levels get a warm-up of their own, adjacent
-                               ones keep their warm-up samples */
+                               ones keep their warm-up samples;
+                               MLMC_AP_LEVELS_OPTIMAL: the set of
+                               mlmc_ap_select_levels_optimal, with the warm-up also
+                               running pilot pairs (L, i), i <= L-2: the variances of
+                               the pairs (i, i-1) and (L, i) are measured, the others
+                               taken from eq. V_approx with the correlations
+                               rho_{L,i}; costs n_i (+ n_j) */
     int32_t reserved;       /* must be 0 */
 } mlmc_ap_options;
 
-enum { MLMC_AP_LEVELS_ALL = 0, MLMC_AP_LEVELS_HEURISTIC = 1 };
+enum { MLMC_AP_LEVELS_ALL = 0, MLMC_AP_LEVELS_HEURISTIC = 1, MLMC_AP_LEVELS_OPTIMAL = 2 };
 
 typedef struct mlmc_ap_result {
     double estimate;         /* eq. mlmc-compact: sum_l mean(dQ_l) */

@@ -78,8 +78,8 @@ def lib():
         L.oracle_kd_coeffs.restype = None
         L.oracle_kd_coarse_numbers.argtypes = [
             ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-            ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
-            ctypes.c_uint64, dp, ctypes.c_uint64, dp]
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+            ctypes.c_uint32, ctypes.c_uint64, dp, ctypes.c_uint64, dp]
         L.oracle_kd_coarse_numbers.restype = ctypes.c_uint64
         _lib = L
     return _lib
@@ -214,16 +214,17 @@ def kd_coeffs(theta, R, mu, sigma, v_next):
     return float(out[0]), float(out[1])
 
 
-def kd_coarse_numbers(prob, level, sample, cap=None):
-    """Coarse numbers of one KD pair, one row per coarse KD step:
-    (chi~, nu~, E~, fine KD steps aggregated), and the final (x_f, x_c)."""
+def kd_coarse_numbers(prob, level, sample, cap=None, coarse_level=None):
+    """Coarse numbers of one KD pair (coarse path at coarse_level, default
+    level - 1), one row per coarse KD step: (chi~, nu~, E~, fine KD steps
+    aggregated), and the final (x_f, x_c)."""
     if cap is None:
         cap = int(round(prob["T"] / prob["dt0"])) * int(prob["M"]) ** level + 2
     rows = np.zeros((cap, 4))
     fin = np.zeros(2)
     used = lib().oracle_kd_coarse_numbers(
         float(prob["eps"]), float(prob["T"]), float(prob["dt0"]), int(prob["M"]), int(level),
-        int(prob["x0_kind"]), float(prob.get("x0_a", 0.0)), float(prob.get("x0_b", 0.0)),
+        int(level - 1 if coarse_level is None else coarse_level), int(prob["x0_kind"]), float(prob.get("x0_a", 0.0)), float(prob.get("x0_b", 0.0)),
         int(prob.get("seed", 42)), int(prob.get("stream_id", 0)), int(sample),
         _ptr(rows, ctypes.c_double), cap, _ptr(fin, ctypes.c_double))
     return rows[:used], fin

@@ -697,12 +697,13 @@ int oracle_simulate_kd(double eps, double T, double dt0, int M, int level, int s
 /* Coarse numbers of one pair (rows of 4 doubles, see kd_trace_t); returns
  * the number of rows written.  out_final = (x_f, x_c). */
 uint64_t oracle_kd_coarse_numbers(double eps, double T, double dt0, int M, int level,
-                                  int x0_kind, double x0_a, double x0_b,
+                                  int coarse_level, int x0_kind, double x0_a, double x0_b,
                                   uint64_t seed, uint32_t stream, uint64_t sample,
                                   double *rows, uint64_t cap, double out_final[2])
 {
     problem_t P = make_problem(eps, T, dt0, M, level, 0, x0_kind, x0_a, x0_b,
                                EQ_MAXWELLIAN, 0, seed, stream);
+    if (coarse_level >= 0 && coarse_level < level) P.coarse_level = coarse_level;
     kd_trace_t tr = {rows, cap, 0};
     double xf, xc; uint32_t cf, cc;
     simulate_kd_one(&P, sample, &xf, &xc, &cf, &cc, &tr);

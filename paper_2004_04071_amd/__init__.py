@@ -236,14 +236,14 @@ def result_dict(r):
 BATCHED_DIRECT, BATCHED_GRAPH, BATCHED_TIMED, BATCHED_PER_LEVEL = 0, 1, 2, -1
 
 
-LEVELS_ALL, LEVELS_HEURISTIC = 0, 1
+LEVELS_ALL, LEVELS_HEURISTIC, LEVELS_OPTIMAL = 0, 1, 2
 
 
 def options(batched=BATCHED_DIRECT, max_iter=0, n_warmup=0, block=0, ppt=0, waves_per_simd=0,
             tp_max_samples=0, level_select=LEVELS_ALL):
     """mlmc_ap_options: batched = 0 (direct persistent launch, default), 1 (hipGraph
     replay), 2 (direct, particle kernel timed), -1 (one launch per level);
-    level_select = LEVELS_ALL (levels 0..L) or LEVELS_HEURISTIC."""
+    level_select = LEVELS_ALL (levels 0..L), LEVELS_HEURISTIC or LEVELS_OPTIMAL."""
     return Options(batched=batched, max_iter=max_iter, n_warmup=n_warmup,
                    tuning=Tuning(block=block, ppt=ppt, waves_per_simd=waves_per_simd,
                                  tp_max_samples=tp_max_samples),

@@ -704,6 +704,8 @@ void McRequest::init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, u
   st.assign(p.L + 1, stats_empty());
   coarse_of.assign(p.L + 1, -1);
   in_set.assign(p.L + 1, 0);
+  pilot_done.assign(p.L + 1, 0);
+  pilot_st.assign(p.L + 1, stats_empty());
   selected = false;
   for (int l = first_level(); l <= p.L; ++l) {
     target[l] = n_warmup;
@@ -715,10 +717,34 @@ void McRequest::init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, u
   gpu_seconds = kernel_seconds = 0.0;
 }
 
+bool McRequest::pilots_active() const {
+  return level_select == MLMC_AP_LEVELS_OPTIMAL && !plain && !selected && prob.L >= 2;
+}
+
 bool McRequest::plan(std::vector<ItemSpec>& items, uint32_t slot_base,
                      unsigned long long* hist_base, size_t hist_stride) {
   if (phase == 2) return false;
   bool any = false;
+  if (pilots_active()) {
+    for (int i = 0; i + 2 <= prob.L; ++i) {
+      if (pilot_done[i] >= n_warmup) continue;
+      ItemSpec s;
+      s.prob = &prob;
+      s.level = prob.L;
+      s.single = false;
+      s.coarse_level = i;
+      s.sample_begin = pilot_done[i];
+      s.n_samples = n_warmup - pilot_done[i];
+      if (max_per_tick && s.n_samples > max_per_tick) s.n_samples = max_per_tick;
+      s.result_slot = slot_base + kPilotSlot + (uint32_t)i;
+      s.hist = nullptr;
+      s.traj = nullptr;
+      s.coll = nullptr;
+      s.accumulate = pilot_done[i] > 0;
+      items.push_back(s);
+      any = true;
+    }
+  }
   for (int l = first_level(); l <= prob.L; ++l) {
     if (!in_set[l] || done[l] >= target[l]) continue;
     uint64_t n = target[l] - done[l];
@@ -762,7 +788,39 @@ void McRequest::select_levels() {
     V[l] = (l == 0 ? s.m2_dq : s.m2_qf) / n1;
     Vd[l] = s.m2_dq / n1;
   }
-  const uint64_t mask = select_levels_heuristic(V.data(), Vd.data(), L);
+  uint64_t mask;
+  if (level_select == MLMC_AP_LEVELS_OPTIMAL && L >= 1) {
+    // eq. level_selection over every pair: measured variances where a
+    // warm-up or pilot pair exists ((i, i-1) and (L, i)), eq. V_approx from
+    // the correlations rho_{L,i} elsewhere
+    const int n = L + 1;
+    std::vector<double> C(n), rho(n, 1.0), Vp(n * n, 0.0), Cp(n * n, 1.0);
+    for (int i = 0; i <= L; ++i) C[i] = (double)pair_cost(prob, i, -1);
+    auto corr = [](const Stats& s) {
+      const double d = std::sqrt(s.m2_qf * s.m2_qc);
+      return d > 0.0 ? s.c_fc / d : 0.0;
+    };
+    for (int i = 0; i + 2 <= L; ++i) rho[i] = corr(pilot_st[i]);
+    rho[L - 1] = corr(st[L]);
+    for (int i = 1; i <= L; ++i)
+      for (int j = 0; j < i; ++j) {
+        double v;
+        if (j == i - 1) {
+          v = Vd[i];
+        } else if (i == L) {
+          const Stats& ps = pilot_st[j];
+          v = ps.m2_dq / (ps.n > 1.0 ? ps.n - 1.0 : 1.0);
+        } else {
+          const double r2 = rho[i] * rho[i] + rho[j] * rho[j] - 1.0;
+          v = V[i] + V[j] - 2.0 * std::sqrt(std::max(0.0, r2) * V[i] * V[j]);
+        }
+        Vp[i * n + j] = std::max(0.0, v);
+        Cp[i * n + j] = (double)pair_cost(prob, i, j);
+      }
+    select_levels_optimal(V.data(), C.data(), Vp.data(), Cp.data(), L, &mask);
+  } else {
+    mask = select_levels_heuristic(V.data(), Vd.data(), L);
+  }
   int prev = -1;
   for (int l = 0; l <= L; ++l) {
     if (!((mask >> l) & 1ull)) {
@@ -792,9 +850,23 @@ void McRequest::absorb(const Stats* slots) {
     }
     st[l] = slots[l];
   }
+  if (pilots_active()) {
+    for (int i = 0; i + 2 <= prob.L; ++i) {
+      const Stats& ps = slots[kPilotSlot + i];
+      const uint64_t n_new = (uint64_t)ps.n;
+      if (n_new > pilot_done[i]) {
+        particle_steps += (n_new - pilot_done[i]) * pair_cost(prob, prob.L, i);
+        pilot_done[i] = n_new;
+      }
+      pilot_st[i] = ps;
+    }
+  }
   for (;;) {
     for (int l = first_level(); l <= prob.L; ++l)
       if (in_set[l] && done[l] < target[l]) return;  // the current round is not complete
+    if (pilots_active())
+      for (int i = 0; i + 2 <= prob.L; ++i)
+        if (pilot_done[i] < n_warmup) return;
     if (phase == 0) {
       if (level_select != MLMC_AP_LEVELS_ALL && !plain && !selected) {
         select_levels();
@@ -880,7 +952,9 @@ mlmc_ap_options default_options(const mlmc_ap_options* opt) {
 mlmc_ap_status run_requests(Workspace& ws, std::vector<McRequest>& reqs, int mode,
                             const mlmc_ap_tuning& tuning, hipStream_t stream,
                             unsigned long long* hist_dev, size_t hist_stride) {
-  const size_t n_slots = reqs.size() * MLMC_AP_MAX_LEVELS;
+  // per request: one statistics slot per level, then the pilot pairs' slots
+  const size_t kStride = 2 * MLMC_AP_MAX_LEVELS + 2;
+  const size_t n_slots = reqs.size() * kStride;
   MLMC_TRY(ws.ensure(1, 1, 1, n_slots, 0));
   // A slot's first launch overwrites it on the device; the host mirror of the
   // slots no launch has written yet reads as empty.
@@ -891,7 +965,7 @@ mlmc_ap_status run_requests(Workspace& ws, std::vector<McRequest>& reqs, int mod
     for (size_t r = 0; r < reqs.size(); ++r) {
       const size_t before = items.size();
       unsigned long long* hb = hist_dev ? hist_dev + r * (MLMC_AP_MAX_LEVELS * hist_stride) : nullptr;
-      reqs[r].plan(items, (uint32_t)(r * MLMC_AP_MAX_LEVELS), hb, hist_stride);
+      reqs[r].plan(items, (uint32_t)(r * kStride), hb, hist_stride);
       if (items.size() > before) owners.push_back(r);
     }
     if (items.empty()) return MLMC_AP_OK;
@@ -901,7 +975,7 @@ mlmc_ap_status run_requests(Workspace& ws, std::vector<McRequest>& reqs, int mod
       reqs[r].launches += 1;
       reqs[r].gpu_seconds += t.total_s;
       reqs[r].kernel_seconds += t.kernel_s;
-      reqs[r].absorb(ws.resident_host + r * MLMC_AP_MAX_LEVELS);
+      reqs[r].absorb(ws.resident_host + r * kStride);
     }
   }
   return set_error(MLMC_AP_EDEVICE, "MLMC loop did not terminate");
@@ -1109,8 +1183,9 @@ static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* to
   const mlmc_ap_options o = default_options(opt);
   const int mode = launch_mode(o.batched);
   if (mode < 0) return set_error(MLMC_AP_EINVAL, "options.batched must be -1, 0, 1, 2 or 3");
-  if (o.level_select != MLMC_AP_LEVELS_ALL && o.level_select != MLMC_AP_LEVELS_HEURISTIC)
-    return set_error(MLMC_AP_EINVAL, "options.level_select must be 0 or 1");
+  if (o.level_select != MLMC_AP_LEVELS_ALL && o.level_select != MLMC_AP_LEVELS_HEURISTIC &&
+      o.level_select != MLMC_AP_LEVELS_OPTIMAL)
+    return set_error(MLMC_AP_EINVAL, "options.level_select must be 0, 1 or 2");
   if (o.reserved != 0) return set_error(MLMC_AP_EINVAL, "options.reserved must be 0");
   if (o.level_select != MLMC_AP_LEVELS_ALL && hist_host)
     return set_error(MLMC_AP_EINVAL, "level selection does not support per-level histograms");

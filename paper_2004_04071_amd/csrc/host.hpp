@@ -185,6 +185,12 @@ struct McRequest {
   bool selected = false;       // the level set has been chosen
   std::vector<int> coarse_of;  // coarse level of level l's pair; -1: single level
   std::vector<char> in_set;    // level l is part of the hierarchy
+  // Pilot pairs (L, i), i <= L - 2, of the cost-optimal selection: their
+  // statistics give the correlations rho_{L,i} (slot slot_base + kPilotSlot + i).
+  static constexpr uint32_t kPilotSlot = MLMC_AP_MAX_LEVELS + 1;
+  std::vector<uint64_t> pilot_done;
+  std::vector<Stats> pilot_st;
+  bool pilots_active() const;
   uint64_t particle_steps = 0;
   uint64_t launches = 0;
   double gpu_seconds = 0.0, kernel_seconds = 0.0;

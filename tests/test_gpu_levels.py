@@ -178,3 +178,59 @@ def test_selected_levels_terms_match_pair_entry():
         assert st["n"] == lv["n"] == n
         sd = math.sqrt(st["m2_dq"] / max(n - 1, 1))
         assert abs(st["mean_dq"] - lv["mean_dq"]) <= 1e-9 * (abs(st["mean_dq"]) + sd)
+
+
+def path_cost(prob, l):
+    """Particle steps of one path of level l (KD: expected KD steps)."""
+    n = int(round(prob["T"] / prob["dt0"])) * prob["M"] ** l
+    if prob.get("scheme", 0) == W.SCHEME_KD:
+        dt = prob["dt0"] / prob["M"] ** l
+        return n * -math.expm1(-dt / prob["eps"] ** 2)
+    return float(n)
+
+
+def item_cost(prob, l, lc):
+    c = path_cost(prob, l) + (path_cost(prob, lc) if lc >= 0 else 0.0)
+    return float(max(1, math.ceil(c))) if prob.get("scheme", 0) == W.SCHEME_KD else c
+
+
+@pytest.mark.parametrize("name,prob,tol", [
+    ("ap_eps0.3_L6", dict(W.cfg2(eps=0.3, stream_id=640), L=6), 3e-3),
+    ("kd_eps0.1_L6", kd(0.1, stream_id=641, L=6), 5e-3),
+])
+def test_estimate_on_cost_optimal_levels(name, prob, tol):
+    """The cost-optimal set from the warm-up and pilot statistics: measured
+    variances of the pairs (i, i-1) and (L, i), eq. V_approx for the rest."""
+    L, n_w = prob["L"], 1000
+    adj = [pkg.mlmc_ap_simulate_level(prob, l, 0, n_w) for l in range(L + 1)]
+    pil = {i: pkg.mlmc_ap_simulate_pair(prob, L, i, 0, n_w) for i in range(L - 1)}
+    var = lambda s, k: s[k] / (n_w - 1)
+    V = [var(adj[0], "m2_dq")] + [var(adj[l], "m2_qf") for l in range(1, L + 1)]
+    rho = {i: pil[i]["c_fc"] / math.sqrt(pil[i]["m2_qf"] * pil[i]["m2_qc"]) for i in pil}
+    rho[L - 1] = adj[L]["c_fc"] / math.sqrt(adj[L]["m2_qf"] * adj[L]["m2_qc"])
+    Vp = [[0.0] * (L + 1) for _ in range(L + 1)]
+    Cp = [[1.0] * (L + 1) for _ in range(L + 1)]
+    for i in range(1, L + 1):
+        for j in range(i):
+            if j == i - 1:
+                v = var(adj[i], "m2_dq")
+            elif i == L:
+                v = var(pil[j], "m2_dq")
+            else:   # eq. V_approx
+                r2 = rho[i] ** 2 + rho[j] ** 2 - 1.0
+                v = V[i] + V[j] - 2.0 * math.sqrt(max(0.0, r2) * V[i] * V[j])
+            Vp[i][j] = max(0.0, v)
+            Cp[i][j] = item_cost(prob, i, j)
+    C = [item_cost(prob, l, -1) for l in range(L + 1)]
+    best, sets = OL.optimal(V, C, Vp, Cp)
+    r = pkg.mlmc_ap_estimate(prob, tol, pkg.options(level_select=pkg.LEVELS_OPTIMAL))
+    kd_scheme = prob.get("scheme", 0) == W.SCHEME_KD
+    exact = (CF.kinetic_limit(prob["eps"], prob["T"], 1.0) if kd_scheme
+             else CF.level_second_moment(prob, L))
+    sd = math.sqrt(r["var_estimator"])
+    say("%s: levels %s (enumeration: %s, cost %.4g), N %s, estimate %.6f exact %.6f sd %.2e"
+        % (name, r["level_set"], sets, best, [r["N"][l] for l in r["level_set"]],
+           r["estimate"], exact, sd))
+    assert r["level_set"] in sets
+    assert r["converged"]
+    assert abs(r["estimate"] - exact) <= 4.5 * sd
