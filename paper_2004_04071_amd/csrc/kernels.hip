@@ -893,15 +893,30 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
 // the item's resident statistics slot.
 // ---------------------------------------------------------------------------
 // Fixed LDS tree over the block's 256 records; the result is left in sh[0].
-__device__ __forceinline__ void block_tree(const Stats& acc, Stats* sh) {
+// Records from index n_live on are empty, and a merge with an empty record
+// returns the other one unchanged, so the levels whose stride is at least
+// n_live are skipped (block-uniform) without changing the result.
+__device__ __forceinline__ void block_tree(const Stats& acc, Stats* sh, uint32_t n_live) {
   const int t = threadIdx.x;
   sh[t] = acc;
   __syncthreads();
 #pragma unroll 1
   for (int stride = kReduceThreads / 2; stride > 0; stride >>= 1) {
+    if ((uint32_t)stride >= n_live) continue;
     if (t < stride) sh[t] = stats_merge(sh[t], sh[t + stride]);
     __syncthreads();
   }
+}
+
+// Folds an item's final record into its resident statistics slot (and the
+// host-mapped mirror).
+__device__ __forceinline__ void store_item(const LevelDesc& d, const Stats& rec,
+                                           Stats* __restrict__ resident,
+                                           Stats* __restrict__ mirror) {
+  const uint32_t slot = d.result_slot;
+  const Stats r = (d.flags & kFlagAccumulate) ? stats_merge(resident[slot], rec) : rec;
+  resident[slot] = r;
+  if (mirror) mirror[slot] = r;  // host-mapped copy, read after the stream syncs
 }
 
 // Merge of one item's group records into its resident slot (stage 2).
@@ -916,17 +931,12 @@ __device__ __forceinline__ void merge_item(const LevelDesc& d, const Stats* __re
     const uint32_t first = threadIdx.x * q;
     for (uint32_t idx = first; idx < n_groups && idx < first + q; ++idx)
       acc = stats_merge(acc, groups[gbase + idx]);
-    block_tree(acc, sh);
+    block_tree(acc, sh, (n_groups + q - 1) / q);
   } else if (threadIdx.x == 0) {
     // the tree over one record and empties returns that record unchanged
     sh[0] = groups[gbase];
   }
-  if (threadIdx.x == 0) {
-    const uint32_t slot = d.result_slot;
-    const Stats r = (d.flags & kFlagAccumulate) ? stats_merge(resident[slot], sh[0]) : sh[0];
-    resident[slot] = r;
-    if (mirror) mirror[slot] = r;  // host-mapped copy, read after the stream syncs
-  }
+  if (threadIdx.x == 0) store_item(d, sh[0], resident, mirror);
   __syncthreads();
 }
 
@@ -978,7 +988,14 @@ __global__ void __launch_bounds__(kReduceThreads) reduce_kernel(
       const uint32_t idx = first + k;
       if (idx < n_tiles) acc = stats_merge(acc, partials[tile_base + idx]);
     }
-    block_tree(acc, sh);
+    block_tree(acc, sh, min((uint32_t)kGroupTiles, n_tiles - g * (uint32_t)kGroupTiles));
+    if (d.n_groups == 1) {
+      // the item's only group: its record is the item's (what the second
+      // stage would merge from the one group record), no count needed
+      if (threadIdx.x == 0) store_item(d, sh[0], resident, mirror);
+      __syncthreads();
+      continue;
+    }
     if (threadIdx.x == 0) {
       groups[vb] = sh[0];
       __threadfence();  // the group record is visible before it is counted
