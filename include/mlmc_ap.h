@@ -382,14 +382,16 @@ typedef struct mlmc_ap_server_stats {
 
 mlmc_ap_status mlmc_ap_server_create(const mlmc_ap_server_config* cfg, mlmc_ap_server** out);
 mlmc_ap_status mlmc_ap_server_destroy(mlmc_ap_server* srv);
-/* Queues a request; it is admitted at a later tick once its device memory
- * (per-level state and per-tick tile partials) fits the budget.  EBUSY if it
- * can never fit; EINVAL for an invalid problem or tolerance. */
+/* Queues a request (QOI_X2; either scheme, FP32 or FP64 state); it is
+ * admitted at a later tick once its device memory (per-level state and
+ * per-tick tile partials) fits the budget.  EBUSY if it can never fit; EINVAL
+ * for an invalid problem or tolerance, or a histogram QoI. */
 mlmc_ap_status mlmc_ap_server_submit(mlmc_ap_server* srv, const mlmc_ap_problem* p,
                                      double rmse_tol, uint64_t* ticket_out);
 /* One tick: admit queued requests that fit, run one top-up iteration of every
- * active request in one persistent launch (graph replay), update their level
- * state and complete those whose statistical constraint holds.
+ * active request in one persistent launch per particle kernel in use (FP32
+ * splitting, FP64 splitting, KD; launches issued directly), update their
+ * level state and complete those whose statistical constraint holds.
  * n_completed_out (nullable) receives the number completed in this tick. */
 mlmc_ap_status mlmc_ap_server_step(mlmc_ap_server* srv, int32_t* n_completed_out);
 /* OK with the result, EAGAIN while pending, ECANCELLED, ENOTFOUND.  A

@@ -141,9 +141,22 @@ mlmc_ap_status mlmc_ap_server::tick(int32_t* n_completed, std::vector<uint64_t>*
   }
   stats.bytes_peak = std::max(stats.bytes_peak, used);
   if (!items.empty()) {
+    // one launch per particle kernel: FP32 and FP64 state and the KD scheme
+    // have kernels of their own (splitting FP32, splitting FP64, KD)
     LaunchTiming t;
-    MLMC_TRY(run_table(ws, items, (size_t)cfg.max_active * MLMC_AP_MAX_LEVELS, kModeDirect, tuning, stream,
-                       &t));
+    t.total_s = 0.0;
+    for (int cls = 0; cls < 3; ++cls) {
+      std::vector<ItemSpec> part;
+      for (const ItemSpec& it : items) {
+        const int c = it.prob->scheme == MLMC_AP_SCHEME_KD ? 2 : (it.prob->fp64_state ? 1 : 0);
+        if (c == cls) part.push_back(it);
+      }
+      if (part.empty()) continue;
+      LaunchTiming tc;
+      MLMC_TRY(run_table(ws, part, (size_t)cfg.max_active * MLMC_AP_MAX_LEVELS, kModeDirect,
+                         tuning, stream, &tc));
+      t.total_s += tc.total_s;
+    }
     stats.ticks++;
     const double tnow = now_s();
     for (ServerReq* r : in_tick) {
@@ -211,8 +224,8 @@ mlmc_ap_status mlmc_ap_server_submit(mlmc_ap_server* srv, const mlmc_ap_problem*
   MLMC_TRY(validate_problem(p));
   if (!(rmse_tol > 0.0) || !std::isfinite(rmse_tol))
     return set_error(MLMC_AP_EINVAL, "rmse_tol must be > 0");
-  if (p->fp64_state != 0 || p->qoi != MLMC_AP_QOI_X2)
-    return set_error(MLMC_AP_EINVAL, "the server runs FP32-state requests with QOI_X2");
+  if (p->qoi != MLMC_AP_QOI_X2)
+    return set_error(MLMC_AP_EINVAL, "the server runs requests with QOI_X2");
   std::unique_ptr<ServerReq> r(new ServerReq());
   r->mc.init(*p, rmse_tol, false, srv->cfg.options.n_warmup, srv->cfg.options.max_iter,
              srv->cfg.max_samples_per_tick);

@@ -98,6 +98,28 @@ def test_oversized_request_is_rejected():
         pkg.mlmc_ap_server_destroy(srv)
 
 
+MIXED = [(W.cfg2(eps=0.1, stream_id=55), 1e-2),
+         (dict(W.cfg2(eps=0.05, stream_id=56), fp64_state=1), 1e-2),
+         (W.cfg_kd(eps=0.05, stream_id=57), 1e-2),
+         (dict(W.cfg_kd(eps=0.3, stream_id=58), L=5), 1e-2)]
+
+
+def test_mixed_precisions_and_schemes_in_one_server():
+    """FP32 and FP64 splitting requests and KD requests served together (one
+    launch per particle kernel and tick): each result equals the request
+    served alone and is close to its exact value."""
+    mixed, st = serve(MIXED)
+    assert st["completed"] == len(MIXED)
+    for (p, t), m in zip(MIXED, mixed):
+        alone, _ = serve([(p, t)])
+        assert key(alone[0]) == key(m)
+        kd = p.get("scheme", 0) == W.SCHEME_KD
+        exact = (CF.kinetic_limit(p["eps"], p["T"], 1.0) if kd
+                 else CF.level_second_moment(p, p["L"]))
+        assert m["converged"]
+        assert abs(m["estimate"] - exact) <= 4.5 * math.sqrt(m["var_estimator"])
+
+
 def test_invalid_requests_are_refused():
     srv = pkg.mlmc_ap_server_create()
     try:
@@ -105,6 +127,8 @@ def test_invalid_requests_are_refused():
             pkg.mlmc_ap_server_submit(srv, W.cfg2(), 0.0)
         with pytest.raises(pkg.MlmcApError):
             pkg.mlmc_ap_server_submit(srv, dict(W.cfg2(), M=1), 1e-2)
+        with pytest.raises(pkg.MlmcApError):   # histograms are not served
+            pkg.mlmc_ap_server_submit(srv, W.cfg4(), 1e-2)
         with pytest.raises(pkg.MlmcApError) as e:
             pkg.mlmc_ap_server_poll(srv, 12345)
         assert e.value.name == "ENOTFOUND"
