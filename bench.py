@@ -308,6 +308,28 @@ def main():
                                       sd=math.sqrt(sel["var_estimator"]))
         log("level selection", out["level_selection"])
 
+        # the epsilon-adaptive on-line phase of Section 5.3: tolerances
+        # tol0 / sqrt(2^r), r = 0..20, ending at the same RMSE target
+        R = 20
+        sq_opt = pkg.options(batched=0, **tk)
+        pkg.mlmc_ap_estimate_sequence(P, tol * 2.0 ** (R / 2), R, sq_opt, stream=hs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sq = pkg.mlmc_ap_estimate_sequence(P, tol * 2.0 ** (R / 2), R, sq_opt, stream=hs)
+        torch.cuda.synchronize()
+        sq_ms = (time.perf_counter() - t0) * 1e3
+        out["tolerance_sequence"] = dict(
+            stages=R + 1, tol_first=tol * 2.0 ** (R / 2), tol_last=tol, time_ms=sq_ms,
+            particle_steps=sq[-1]["particle_steps"],
+            last_stage_particle_steps=sq[-1]["particle_steps"] - sq[-2]["particle_steps"],
+            launches=sq[-1]["launches"], estimate=sq[-1]["estimate"],
+            sd=math.sqrt(sq[-1]["var_estimator"]),
+            level_correction=sq[-1]["levels"][prob["L"]]["mean_dq"],
+            level_correction_sd=math.sqrt(sq[-1]["levels"][prob["L"]]["m2_dq"]
+                                          / max(sq[-1]["N"][prob["L"]] - 1, 1)
+                                          / max(sq[-1]["N"][prob["L"]], 1)))
+        log("tolerance sequence", out["tolerance_sequence"])
+
         # eps sweep: 15 requests in one batched launch per iteration vs one by one
         probs, tols = W.cfg3()
         pkg.mlmc_ap_estimate_batch(probs, tols)

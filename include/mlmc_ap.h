@@ -328,6 +328,27 @@ mlmc_ap_status mlmc_ap_estimate(const mlmc_ap_problem* p, double rmse_tol,
                                 const mlmc_ap_options* opt, mlmc_ap_result* out_host,
                                 uint64_t* hist_host, void* stream);
 
+/* The epsilon-adaptive on-line phase of Section 5.3: the MLMC estimate of
+ * mlmc_ap_estimate run through the decreasing tolerances
+ * tol_r = rmse_tol0 / sqrt(2^r), r = 0..R (the paper takes rmse_tol0 = 1), so
+ * that each stage costs about twice the previous one.  Reading of the paper's
+ * "repeatedly": the stages continue one estimate.  The warm-up (and the level
+ * selection of opt->level_select) happens once; stage r computes eqs.
+ * Nopt1/Noptj at tol_r from the statistics so far, tops up (samples are never
+ * discarded: level l keeps using samples [0, N_l)) and ends when
+ * sum_l V_l/N_l <= tol_r^2/2 or after opt->max_iter top-ups.
+ *   out_host  R + 1 results (caller-owned), out_host[r] the state at the end
+ *             of stage r: estimate, variance, N, per-level statistics, and the
+ *             work, launches and times spent since the call began.  The
+ *             statistics of the finest level, lv[L].mean_dq and its sample
+ *             variance, estimate the level-L correction that the paper's
+ *             bias estimates rest on, with more samples at every stage.
+ * Stage 0 equals mlmc_ap_estimate at rmse_tol0 (bitwise, except for times).
+ * EINVAL for R outside [0, 40]; per-level histograms are not produced. */
+mlmc_ap_status mlmc_ap_estimate_sequence(const mlmc_ap_problem* p, double rmse_tol0,
+                                         int32_t R, const mlmc_ap_options* opt,
+                                         mlmc_ap_result* out_host, void* stream);
+
 /* Plain Monte Carlo at level L (single-level trajectories, level tag
  * L + 64): N = ceil(2 V_L / rmse_tol^2) samples after the warm-up,
  * iterated like mlmc_ap_estimate.  Reported in out_host->N[L] / lv[L]. */

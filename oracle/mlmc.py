@@ -105,3 +105,44 @@ def estimate(prob, tol, L, n_warmup=1000, max_iter=8, threads=None):
     st = [stats_of(xs[l][0], xs[l][1], l) for l in range(L + 1)]
     return dict(estimate=sum(s["mean_dq"] for s in st), N=list(done), levels=st,
                 var_estimator=sum(sample_variance(s) / d for s, d in zip(st, done)))
+
+
+def estimate_sequence(prob, tol0, R, L, n_warmup=1000, max_iter=10, threads=None):
+    """The epsilon-adaptive on-line phase of Section 5.3: the loop of
+    ``estimate`` run through the tolerances tol_r = tol0 / sqrt(2^r),
+    r = 0..R.  One warm-up; each stage then computes the optimal sample
+    numbers at tol_r from all samples so far, tops up, and checks the
+    statistical constraint at tol_r (at most max_iter times).  Samples are
+    never discarded, so stage r goes on from stage r - 1.  Returns one result
+    per stage (the state when the stage ended)."""
+    C = [level_cost(prob, l) for l in range(L + 1)]
+    done = [0] * (L + 1)
+    xs = [(np.zeros(0), np.zeros(0)) for _ in range(L + 1)]
+
+    def run(l, upto):
+        if upto <= done[l]:
+            return
+        r = simulate(prob, l, done[l], upto - done[l], threads=threads)
+        xs[l] = (np.concatenate([xs[l][0], r["xf"]]), np.concatenate([xs[l][1], r["xc"]]))
+        done[l] = upto
+
+    def state(tol):
+        st = [stats_of(xs[l][0], xs[l][1], l) for l in range(L + 1)]
+        var = sum(sample_variance(s) / d for s, d in zip(st, done))
+        return dict(estimate=sum(s["mean_dq"] for s in st), N=list(done), levels=st,
+                    var_estimator=var, converged=var <= 0.5 * tol * tol, tol=tol)
+
+    for l in range(L + 1):
+        run(l, n_warmup)
+    out = []
+    for r in range(R + 1):
+        tol = tol0 / math.sqrt(2.0 ** r)
+        for _ in range(max_iter):
+            V = [sample_variance(s) for s in state(tol)["levels"]]
+            N = optimal_samples(V, C, tol)
+            for l in range(L + 1):
+                run(l, max(N[l], done[l]))
+            if state(tol)["converged"]:
+                break
+        out.append(state(tol))
+    return out

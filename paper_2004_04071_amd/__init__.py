@@ -117,6 +117,8 @@ _SIGNATURES = {
                                       _P(ctypes.c_uint64), _P(ctypes.c_double)],
     "mlmc_ap_estimate": [_P(Problem), ctypes.c_double, _P(Options), _P(Result),
                          _P(ctypes.c_uint64), _vp],
+    "mlmc_ap_estimate_sequence": [_P(Problem), ctypes.c_double, ctypes.c_int32, _P(Options),
+                                  _P(Result), _vp],
     "mlmc_ap_plain_mc": [_P(Problem), ctypes.c_double, _P(Options), _P(Result), _vp],
     "mlmc_ap_estimate_batch": [_P(Problem), _P(ctypes.c_double), ctypes.c_int32, _P(Options),
                                _P(Result), _vp],
@@ -384,6 +386,17 @@ def mlmc_ap_estimate(p, rmse_tol, opt=None, hist=False, stream=None):
         w = 3 * P.nbins + 4
         d["hist"] = [[int(x) for x in hbuf[l * w:(l + 1) * w]] for l in range(P.L + 1)]
     return d
+
+
+def mlmc_ap_estimate_sequence(p, rmse_tol0, R, opt=None, stream=None):
+    """The estimate through the tolerances rmse_tol0 / sqrt(2^r), r = 0..R,
+    continuing from the same samples: a list of R + 1 result dicts."""
+    P = as_problem(p)
+    res = (Result * max(int(R) + 1, 1))()
+    _check(lib().mlmc_ap_estimate_sequence(ctypes.byref(P), float(rmse_tol0), int(R),
+                                           ctypes.byref(opt) if opt is not None else None,
+                                           res, _stream(stream)), "mlmc_ap_estimate_sequence")
+    return [result_dict(r) for r in res]
 
 
 def mlmc_ap_plain_mc(p, rmse_tol, opt=None, stream=None):

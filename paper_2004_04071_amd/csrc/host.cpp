@@ -687,6 +687,10 @@ double select_levels_optimal(const double* V, const double* C, const double* Vpa
 // ---------------------------------------------------------------------------
 // MLMC control of one request.
 // ---------------------------------------------------------------------------
+static double wall_now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 void McRequest::init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, uint64_t warmup,
                      int iters, uint64_t cap) {
   prob = p;
@@ -715,6 +719,17 @@ void McRequest::init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, u
   particle_steps = 0;
   launches = 0;
   gpu_seconds = kernel_seconds = 0.0;
+  tols.assign(1, rmse_tol);
+  stage = 0;
+  stage_iter = 0;
+  t_start = wall_now();
+  snaps.clear();
+}
+
+void McRequest::set_sequence(const std::vector<double>& seq) {
+  tols = seq;
+  stage = 0;
+  tol = tols[0];
 }
 
 bool McRequest::pilots_active() const {
@@ -877,14 +892,21 @@ void McRequest::absorb(const Stats* slots) {
       double v = 0.0;
       for (int l = first_level(); l <= prob.L; ++l)
         if (in_set[l]) v += sample_var(st[l]) / (double)done[l];
-      if (v <= 0.5 * tol * tol) {
-        converged = true;
-        phase = 2;
-        return;
-      }
-      if (iterations >= max_iter) {
-        phase = 2;
-        return;
+      const bool met = v <= 0.5 * tol * tol;
+      if (met || stage_iter >= max_iter) {
+        converged = met;
+        if (stage + 1 >= tols.size()) {
+          phase = 2;
+          return;
+        }
+        // the next tolerance of the sequence starts from these samples
+        snaps.emplace_back();
+        fill_result(&snaps.back());
+        snaps.back().seconds = wall_now() - t_start;
+        ++stage;
+        tol = tols[stage];
+        stage_iter = 0;
+        converged = false;
       }
     }
     // eqs. Nopt1/Noptj with sample variances and the deterministic costs
@@ -899,6 +921,7 @@ void McRequest::absorb(const Stats* slots) {
       target[l] = std::max<uint64_t>(Ni, done[l]);
     }
     ++iterations;
+    ++stage_iter;
   }
 }
 
@@ -934,9 +957,7 @@ using namespace mlmc;
 
 namespace {
 
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
+double now_s() { return wall_now(); }
 
 mlmc_ap_options default_options(const mlmc_ap_options* opt) {
   mlmc_ap_options o;
@@ -1167,9 +1188,12 @@ mlmc_ap_status mlmc_ap_simulate_pair(const mlmc_ap_problem* p, int32_t level, in
                          coll_dev, hist_host, stream);
 }
 
+// stages > 0: one request run through the tolerance sequence
+// tols[0] 2^(-r/2), r = 0..stages-1; out receives one result per stage.
 static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* tols, int32_t n_req,
                                       bool plain, const mlmc_ap_options* opt,
-                                      mlmc_ap_result* out, uint64_t* hist_host, void* stream) {
+                                      mlmc_ap_result* out, uint64_t* hist_host, void* stream,
+                                      int32_t stages = 0) {
   if (n_req < 1 || !p || !tols || !out) return set_error(MLMC_AP_EINVAL, "bad arguments");
   for (int i = 0; i < n_req; ++i) {
     MLMC_TRY(validate_problem(&p[i]));
@@ -1200,6 +1224,11 @@ static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* to
     reqs[i].init(p[i], tols[i], plain, o.n_warmup, o.max_iter, 0);
     reqs[i].level_select = o.level_select;
   }
+  if (stages > 0) {
+    std::vector<double> seq(stages);
+    for (int r = 0; r < stages; ++r) seq[r] = tols[0] / std::sqrt(std::ldexp(1.0, r));
+    reqs[0].set_sequence(seq);
+  }
   // histogram counters (single request with QOI_X2_HIST)
   size_t hist_stride = 0;
   unsigned long long* hist_dev = nullptr;
@@ -1212,6 +1241,15 @@ static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* to
   }
   MLMC_TRY(run_requests(*ws, reqs, mode, t, s, hist_dev, hist_stride));
   const double el = now_s() - t0;
+  if (stages > 0) {
+    const McRequest& q = reqs[0];
+    if (q.snaps.size() + 1 != (size_t)stages)
+      return set_error(MLMC_AP_EDEVICE, "tolerance sequence ended early");
+    for (int r = 0; r + 1 < stages; ++r) out[r] = q.snaps[r];
+    q.fill_result(&out[stages - 1]);
+    out[stages - 1].seconds = el;
+    return MLMC_AP_OK;
+  }
   for (int i = 0; i < n_req; ++i) {
     reqs[i].fill_result(&out[i]);
     out[i].seconds = el;
@@ -1227,6 +1265,13 @@ mlmc_ap_status mlmc_ap_estimate(const mlmc_ap_problem* p, double rmse_tol,
                                 const mlmc_ap_options* opt, mlmc_ap_result* out_host,
                                 uint64_t* hist_host, void* stream) {
   return estimate_common(p, &rmse_tol, 1, false, opt, out_host, hist_host, stream);
+}
+
+mlmc_ap_status mlmc_ap_estimate_sequence(const mlmc_ap_problem* p, double rmse_tol0,
+                                         int32_t R, const mlmc_ap_options* opt,
+                                         mlmc_ap_result* out_host, void* stream) {
+  if (R < 0 || R > 40) return set_error(MLMC_AP_EINVAL, "R must be in [0, 40]");
+  return estimate_common(p, &rmse_tol0, 1, false, opt, out_host, nullptr, stream, R + 1);
 }
 
 mlmc_ap_status mlmc_ap_plain_mc(const mlmc_ap_problem* p, double rmse_tol,

@@ -194,6 +194,15 @@ struct McRequest {
   uint64_t particle_steps = 0;
   uint64_t launches = 0;
   double gpu_seconds = 0.0, kernel_seconds = 0.0;
+  // Tolerance sequence of the epsilon-adaptive on-line phase (Section 5.3):
+  // stage r ends when the statistical constraint holds at tols[r] (or after
+  // max_iter top-ups), its result is kept in snaps, and stage r + 1 goes on
+  // from the same samples.  A plain estimate is the one-stage sequence.
+  std::vector<double> tols;
+  size_t stage = 0;
+  int stage_iter = 0;
+  double t_start = 0.0;        // host clock of the call (for snapshot times)
+  std::vector<mlmc_ap_result> snaps;
 
   void init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, uint64_t warmup,
             int iters, uint64_t cap);
@@ -209,6 +218,8 @@ struct McRequest {
   // Takes the statistics of the launch and advances the state machine.
   void absorb(const Stats* resident_slots);
   void fill_result(mlmc_ap_result* out) const;
+  // Replaces the tolerance by a sequence (before the first launch).
+  void set_sequence(const std::vector<double>& seq);
 };
 
 }  // namespace mlmc

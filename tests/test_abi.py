@@ -161,6 +161,17 @@ def test_entry_points_report_errors_without_a_device(lib):
     assert e.value.name == "EDEVICE"
     with pytest.raises(pkg.MlmcApError):
         pkg.mlmc_ap_estimate(p, 1e-2)
+    with pytest.raises(pkg.MlmcApError) as e:
+        pkg.mlmc_ap_estimate_sequence(p, 1e-1, 2)
+    assert e.value.name == "EDEVICE"
+
+
+def test_sequence_rejects_bad_stage_counts(lib):
+    p = pkg.problem(eps=0.1, T=1.0, dt0=0.5, L=2)
+    for R in (-1, 41):
+        with pytest.raises(pkg.MlmcApError) as e:
+            pkg.mlmc_ap_estimate_sequence(p, 1e-1, R)
+        assert e.value.name == "EINVAL"
 
 
 def test_optimal_samples_rejects_bad_input(lib):

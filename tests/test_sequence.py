@@ -1,0 +1,155 @@
+"""The epsilon-adaptive on-line phase (Section 5.3): the MLMC estimate run
+through the tolerances tol0 / sqrt(2^r), r = 0..R, each stage going on from
+the samples of the previous ones.
+
+CPU: the oracle's sequence against what fixes it independently of its own
+loop: the closed-form E[Q_L] (exact discrete second moment) at every stage,
+the statistical constraint at each stage's tolerance (and not far below it:
+a wrong tolerance schedule would show), sample numbers that never shrink,
+and every stage's statistics recomputed from scratch on its sample ranges.
+GPU: the library's sequence against the oracle's (same sample numbers at
+every stage, FP64 particle state), the first stage against a plain
+estimate, launch-mode independence, and a KD sequence on a selected level
+set."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import closed_form as CF
+from oracle import mlmc as OM
+
+Z_MAX = 4.5
+
+
+def problem(eps, stream, fp64=1, L=3, **kw):
+    p = dict(eps=eps, T=1.0, dt0=0.5, M=2, L=L, x0_kind=1, x0_a=0.0, x0_b=1.0, eq_kind=1,
+             coupling=1, seed=42, stream_id=stream, fp64_state=fp64)
+    p.update(kw)
+    return p
+
+
+SEQ = dict(prob=problem(0.3, 900), tol0=0.12, R=3)
+
+
+@pytest.fixture(scope="module")
+def oracle_seq():
+    c = SEQ
+    return OM.estimate_sequence(c["prob"], c["tol0"], c["R"], c["prob"]["L"], n_warmup=1000)
+
+
+def test_oracle_sequence_pins(oracle_seq):
+    prob, tol0, R = SEQ["prob"], SEQ["tol0"], SEQ["R"]
+    L = prob["L"]
+    exact = CF.level_second_moment(prob, L)
+    assert len(oracle_seq) == R + 1
+    prev = [0] * (L + 1)
+    for r, st in enumerate(oracle_seq):
+        tol = tol0 / math.sqrt(2.0 ** r)
+        assert st["converged"]
+        v = st["var_estimator"]
+        assert v <= 0.5 * tol * tol
+        # the stage's own top-up put the variance near its tolerance (the
+        # optimal numbers meet the constraint with equality for the warm-up
+        # variances; the updated variances move it by a few per cent)
+        assert v >= 0.3 * 0.5 * tol * tol, (r, v, tol)
+        assert abs(st["estimate"] - exact) <= Z_MAX * math.sqrt(v), (r, st["estimate"], exact)
+        assert all(n >= p for n, p in zip(st["N"], prev))
+        assert any(n > p for n, p in zip(st["N"], prev))
+        prev = st["N"]
+
+
+def test_oracle_sequence_stages_equal_fresh_runs(oracle_seq):
+    """Stage r's statistics are those of samples [0, N_l) computed afresh:
+    no sample is lost or counted twice across stages."""
+    for st in oracle_seq:
+        est, levels = OM.estimate_fixed(SEQ["prob"], st["N"])
+        assert est == st["estimate"]
+        for a, b in zip(levels, st["levels"]):
+            assert a["n"] == b["n"] and a["m2_dq"] == b["m2_dq"]
+
+
+def test_oracle_sequence_first_stage_is_the_plain_estimate(oracle_seq):
+    prob = SEQ["prob"]
+    ref = OM.estimate(prob, SEQ["tol0"], prob["L"], n_warmup=1000, max_iter=10)
+    assert ref["N"] == oracle_seq[0]["N"] and ref["estimate"] == oracle_seq[0]["estimate"]
+
+
+# ---------------------------------------------------------------------------
+# GPU
+# ---------------------------------------------------------------------------
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pkg = pytest.importorskip("paper_2004_04071_amd")
+    torch.cuda.set_device(0)
+    pkg.mlmc_ap_init()
+    return pkg
+
+
+def key(r):
+    return (r["estimate"], r["var_estimator"], tuple(r["N"]), r["converged"], r["level_mask"],
+            r["particle_steps"], tuple(tuple(sorted(l.items())) for l in r["levels"]))
+
+
+@pytest.mark.gpu
+def test_gpu_sequence_matches_oracle(oracle_seq):
+    """FP64 particle state: the device statistics agree with the oracle's to
+    about 1e-15, so every stage takes the same sample numbers (a ceil that
+    such a difference could flip would need a value within 1e-10 of an
+    integer)."""
+    pkg = _gpu()
+    prob, tol0, R = SEQ["prob"], SEQ["tol0"], SEQ["R"]
+    got = pkg.mlmc_ap_estimate_sequence(prob, tol0, R)
+    assert len(got) == R + 1
+    for r, (g, o) in enumerate(zip(got, oracle_seq)):
+        print("stage %d tol %.4f N %s estimate %.6f" % (r, o["tol"], g["N"], g["estimate"]),
+              flush=True)
+        assert list(g["N"][:prob["L"] + 1]) == o["N"], r
+        assert g["converged"] == 1
+        assert abs(g["estimate"] - o["estimate"]) <= 1e-10 * (abs(o["estimate"]) + 1.0)
+        assert g["var_estimator"] == pytest.approx(o["var_estimator"], rel=1e-9)
+        if r:
+            assert g["particle_steps"] > got[r - 1]["particle_steps"]
+            assert g["launches"] > got[r - 1]["launches"]
+            assert g["seconds"] >= got[r - 1]["seconds"]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("batched", [-1, 0, 1])
+def test_gpu_sequence_first_stage_and_modes(batched):
+    pkg = _gpu()
+    prob = problem(0.05, 901, fp64=0, L=5)
+    seq = pkg.mlmc_ap_estimate_sequence(prob, 2e-2, 4, pkg.options(batched=batched))
+    ref = pkg.mlmc_ap_estimate_sequence(prob, 2e-2, 4, pkg.options(batched=0))
+    assert [key(a) for a in seq] == [key(b) for b in ref]
+    one = pkg.mlmc_ap_estimate(prob, 2e-2, pkg.options(batched=batched))
+    assert key(seq[0]) == key(one)
+    exact = CF.level_second_moment(prob, 5)
+    for r, s in enumerate(seq):
+        tol = 2e-2 / math.sqrt(2.0 ** r)
+        assert s["converged"] and s["var_estimator"] <= 0.5 * tol * tol
+        assert abs(s["estimate"] - exact) <= Z_MAX * math.sqrt(s["var_estimator"])
+
+
+@pytest.mark.gpu
+def test_gpu_kd_sequence_on_selected_levels():
+    """The level set is chosen once, after the warm-up, and kept by every
+    stage; it equals that of a plain estimate with the same selection."""
+    pkg = _gpu()
+    prob = problem(0.1, 902, L=6, scheme=pkg.SCHEME_KD)
+    opt = pkg.options(level_select=pkg.LEVELS_HEURISTIC)
+    seq = pkg.mlmc_ap_estimate_sequence(prob, 4e-2, 3, opt)
+    one = pkg.mlmc_ap_estimate(prob, 4e-2, opt)
+    assert key(seq[0]) == key(one)
+    exact = CF.kinetic_limit(0.1, 1.0, 1.0)
+    for r, s in enumerate(seq):
+        tol = 4e-2 / math.sqrt(2.0 ** r)
+        print("KD stage %d set %s N %s estimate %.5f exact %.5f" % (
+            r, s["level_set"], [s["N"][l] for l in s["level_set"]], s["estimate"], exact),
+            flush=True)
+        assert s["level_mask"] == seq[0]["level_mask"]
+        assert s["converged"] and s["var_estimator"] <= 0.5 * tol * tol
+        assert abs(s["estimate"] - exact) <= Z_MAX * math.sqrt(s["var_estimator"])
+    assert np.all(np.diff([s["particle_steps"] for s in seq]) > 0)
