@@ -153,3 +153,21 @@ def test_gpu_kd_sequence_on_selected_levels():
         assert s["converged"] and s["var_estimator"] <= 0.5 * tol * tol
         assert abs(s["estimate"] - exact) <= Z_MAX * math.sqrt(s["var_estimator"])
     assert np.all(np.diff([s["particle_steps"] for s in seq]) > 0)
+
+
+@pytest.mark.gpu
+def test_gpu_sequence_with_capped_iterations_matches_oracle():
+    """With one top-up per stage a stage can end above its tolerance; it is
+    then reported as not converged and the next stage goes on from its
+    samples.  Same sample numbers as the oracle at every stage."""
+    pkg = _gpu()
+    prob = problem(0.3, 903, L=4)
+    got = pkg.mlmc_ap_estimate_sequence(prob, 0.1, 3, pkg.options(max_iter=1))
+    ref = OM.estimate_sequence(prob, 0.1, 3, 4, n_warmup=1000, max_iter=1)
+    for r, (g, o) in enumerate(zip(got, ref)):
+        print("capped stage %d N %s converged %d/%d" % (r, g["N"], g["converged"], o["converged"]),
+              flush=True)
+        assert list(g["N"]) == o["N"]
+        assert bool(g["converged"]) == bool(o["converged"])
+        assert abs(g["estimate"] - o["estimate"]) <= 1e-10 * (abs(o["estimate"]) + 1.0)
+        assert g["iterations"] == r + 1
