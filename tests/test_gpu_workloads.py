@@ -145,3 +145,28 @@ def test_precision_study_estimates():
             assert sum(h[:3 * nb:3]) + h[3 * nb] + h[3 * nb + 1] == r["N"][l]
     say("cfg4: fp32 %.7f fp64 %.7f exact %.7f sd %.2e" % (r32["estimate"], r64["estimate"], exact,
                                                            math.sqrt(r32["var_estimator"])))
+
+
+def test_bench_workload_full_size_against_oracle():
+    """The estimate the benchmark times (eps = 0.01, L = 8, RMSE 1e-3; direct
+    persistent launches with the particle kernel timed by HIP events; block
+    256, one trajectory per lane, 8 waves per SIMD), at its full sample
+    numbers: every level's fine and coarse collision totals over its N_l
+    samples equal the oracle's exactly (integer decisions), and the level
+    means and the estimate agree within the FP32 per-trajectory bar."""
+    prob = W.cfg2()
+    r = pkg.mlmc_ap_estimate(prob, 1e-3, pkg.options(batched=2, block=256, ppt=1,
+                                                     waves_per_simd=8))
+    say("bench workload: N %s estimate %.7f" % (r["N"], r["estimate"]))
+    assert r["converged"]
+    est, levels = OM.estimate_fixed(prob, r["N"])
+    for l, (g, o) in enumerate(zip(r["levels"], levels)):
+        say("  level %d n %d coll %d/%d mean dq %.9e oracle %.9e" % (
+            l, g["n"], g["coll_f"], g["coll_c"], g["mean_dq"], o["mean_dq"]))
+        assert g["n"] == o["n"]
+        assert g["coll_f"] == o["coll_f"] and g["coll_c"] == o["coll_c"]
+        assert abs(g["mean_dq"] - o["mean_dq"]) <= 2e-5 * o["mean_qf"]
+        # FP32 rounding of the positions (~1e-7 relative) against level
+        # differences dQ of standard deviation down to ~1e-3
+        assert g["m2_dq"] == pytest.approx(o["m2_dq"], rel=1e-2)
+    assert abs(r["estimate"] - est) <= 2e-5 * abs(est)
