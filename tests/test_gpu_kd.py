@@ -190,3 +190,25 @@ def test_kd_batch_equals_single_requests():
 def test_kd_rejects_mixed_batches():
     with pytest.raises(pkg.MlmcApError):
         pkg.mlmc_ap_estimate_batch([kd(0.1, L=2), dict(kd(0.1, L=2), scheme=0)], [1e-2, 1e-2])
+
+
+def test_kd_bench_workload_full_size_against_oracle():
+    """The KD estimate the benchmark times (eps = 0.01, L = 8, RMSE 1e-3, FP64
+    state; direct persistent launches timed by HIP events, block 256, 8 waves
+    per SIMD), at its full sample numbers: every level's fine and coarse KD
+    step totals equal the oracle's exactly, and the level means and the
+    estimate agree to FP64 rounding."""
+    prob = W.cfg_kd()
+    r = pkg.mlmc_ap_estimate(prob, 1e-3, pkg.options(batched=2, block=256, ppt=1,
+                                                     waves_per_simd=8))
+    say("KD bench workload: N %s estimate %.9f" % (r["N"], r["estimate"]))
+    assert r["converged"]
+    est, levels = OM.estimate_fixed(prob, r["N"])
+    for l, (g, o) in enumerate(zip(r["levels"], levels)):
+        say("  level %d n %d steps %d/%d mean dq %.12e oracle %.12e" % (
+            l, g["n"], g["coll_f"], g["coll_c"], g["mean_dq"], o["mean_dq"]))
+        assert g["n"] == o["n"]
+        assert g["coll_f"] == o["coll_f"] and g["coll_c"] == o["coll_c"]
+        assert abs(g["mean_dq"] - o["mean_dq"]) <= 1e-10 * o["mean_qf"]
+        assert g["m2_dq"] == pytest.approx(o["m2_dq"], rel=1e-6)
+    assert abs(r["estimate"] - est) <= 1e-10 * abs(est)
