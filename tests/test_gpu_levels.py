@@ -234,3 +234,34 @@ def test_estimate_on_cost_optimal_levels(name, prob, tol):
     assert r["level_set"] in sets
     assert r["converged"]
     assert abs(r["estimate"] - exact) <= 4.5 * sd
+
+
+def test_selected_levels_bench_estimate_full_size_against_oracle():
+    """The level-selection estimate the benchmark reports (eps = 0.01, L = 8,
+    RMSE 1e-3, heuristic set, direct persistent launches): at its full sample
+    numbers every pair of the set, adjacent or not, has the oracle's fine and
+    coarse collision totals exactly, and its mean within the FP32 bar."""
+    prob = W.cfg2()
+    r = pkg.mlmc_ap_estimate(prob, 1e-3, pkg.options(batched=0, block=256, ppt=1,
+                                                     waves_per_simd=8,
+                                                     level_select=pkg.LEVELS_HEURISTIC))
+    lv = r["level_set"]
+    say("selected %s N %s estimate %.7f" % (lv, [r["N"][l] for l in lv], r["estimate"]))
+    assert r["converged"] and lv[0] == 0 and lv[-1] == prob["L"]
+    est = 0.0
+    prev = None
+    for l in lv:
+        n = r["N"][l]
+        ref = O.simulate(prob, l, 0, n, coarse_level=prev) if prev is not None \
+            else O.simulate(prob, 0, 0, n)
+        o = OM.stats_of(ref["xf"], ref["xc"], 0 if prev is None else l)
+        g = r["levels"][l]
+        say("  level %d (coarse %s) n %d coll %d/%d mean dq %.9e oracle %.9e" % (
+            l, prev, n, g["coll_f"], g["coll_c"], g["mean_dq"], o["mean_dq"]))
+        assert g["n"] == n
+        assert g["coll_f"] == int(ref["cf"].astype(np.uint64).sum())
+        assert g["coll_c"] == int(ref["cc"].astype(np.uint64).sum())
+        assert abs(g["mean_dq"] - o["mean_dq"]) <= 2e-5 * o["mean_qf"]
+        est += o["mean_dq"]
+        prev = l
+    assert abs(r["estimate"] - est) <= 2e-5 * abs(est)
