@@ -192,3 +192,25 @@ def test_autotune_keeps_results(tmp_path):
     assert again == t
     after = pkg.mlmc_ap_estimate(prob, 1e-2)
     assert key(before) == key(after)
+
+
+def test_serving_workload_full_trace():
+    """The benchmark's serving workload (400 Poisson requests at 200/s, 4 GiB
+    budget): every request converges, meets the statistical constraint at its
+    own tolerance and lies within 4.5 standard errors of its exact E[Q_L]
+    (eps, T and the tolerance differ per request)."""
+    arr, probs, tols = W.cfg5_trace(400)
+    srv = pkg.mlmc_ap_server_create(hbm_budget_bytes=4 << 30)
+    try:
+        lat, res = pkg.mlmc_ap_server_run_trace(srv, arr, probs, tols)
+    finally:
+        pkg.mlmc_ap_server_destroy(srv)
+    worst = 0.0
+    for p, t, r in zip(probs, tols, res):
+        assert r["converged"] and r["var_estimator"] <= 0.5 * t * t * (1 + 1e-12)
+        z = abs(r["estimate"] - CF.level_second_moment(p, p["L"])) / math.sqrt(r["var_estimator"])
+        worst = max(worst, z)
+        assert z <= 4.5, (p, t, r["estimate"])
+    lat = sorted(lat)
+    print("400 requests: worst |z| %.2f, p50 %.3f ms, p99 %.3f ms" % (
+        worst, lat[200] * 1e3, lat[396] * 1e3), flush=True)
