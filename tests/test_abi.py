@@ -166,12 +166,26 @@ def test_entry_points_report_errors_without_a_device(lib):
     assert e.value.name == "EDEVICE"
 
 
-def test_sequence_rejects_bad_stage_counts(lib):
+def test_sequence_rejects_bad_arguments(lib):
+    """Argument errors are reported before any device work (so also on a
+    machine without a GPU)."""
+    import ctypes
     p = pkg.problem(eps=0.1, T=1.0, dt0=0.5, L=2)
     for R in (-1, 41):
         with pytest.raises(pkg.MlmcApError) as e:
             pkg.mlmc_ap_estimate_sequence(p, 1e-1, R)
         assert e.value.name == "EINVAL"
+    for tol in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(pkg.MlmcApError) as e:
+            pkg.mlmc_ap_estimate_sequence(p, tol, 2)
+        assert e.value.name == "EINVAL"
+    with pytest.raises(pkg.MlmcApError) as e:
+        pkg.mlmc_ap_estimate_sequence(pkg.problem(eps=-1.0, T=1.0, dt0=0.5, L=2), 1e-1, 2)
+    assert e.value.name == "EINVAL"
+    # NULL result array and NULL problem
+    assert lib.mlmc_ap_estimate_sequence(ctypes.byref(p), 0.1, 2, None, None, None) == -1
+    res = (pkg.Result * 3)()
+    assert lib.mlmc_ap_estimate_sequence(None, 0.1, 2, None, res, None) == -1
 
 
 def test_optimal_samples_rejects_bad_input(lib):
