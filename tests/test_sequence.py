@@ -171,3 +171,25 @@ def test_gpu_sequence_with_capped_iterations_matches_oracle():
         assert bool(g["converged"]) == bool(o["converged"])
         assert abs(g["estimate"] - o["estimate"]) <= 1e-10 * (abs(o["estimate"]) + 1.0)
         assert g["iterations"] == r + 1
+
+
+@pytest.mark.gpu
+def test_gpu_sequence_on_the_cost_optimal_set():
+    """With the cost-optimal selection the pilot pairs run in the warm-up
+    only; every stage keeps the chosen set and stage 0 equals the plain
+    estimate with the same options."""
+    pkg = _gpu()
+    prob = problem(0.3, 904, fp64=0, L=6)
+    opt = pkg.options(level_select=pkg.LEVELS_OPTIMAL)
+    seq = pkg.mlmc_ap_estimate_sequence(prob, 3e-2, 3, opt)
+    one = pkg.mlmc_ap_estimate(prob, 3e-2, opt)
+    assert key(seq[0]) == key(one)
+    exact = CF.level_second_moment(prob, 6)
+    for r, s in enumerate(seq):
+        tol = 3e-2 / math.sqrt(2.0 ** r)
+        print("optimal-set stage %d set %s N %s" % (r, s["level_set"],
+                                                    [s["N"][l] for l in s["level_set"]]),
+              flush=True)
+        assert s["level_mask"] == one["level_mask"]
+        assert s["converged"] and s["var_estimator"] <= 0.5 * tol * tol
+        assert abs(s["estimate"] - exact) <= Z_MAX * math.sqrt(s["var_estimator"])
