@@ -95,6 +95,18 @@ __device__ __forceinline__ double kd_g(double y, double em) {
   return y < kKdSeriesY ? kd_series<3>(C.g, y) : -(em * (2.0 + em) + 2.0 * y * (1.0 + em));
 }
 
+// e^{-y} - 1 for y >= 0.  Above y = 45, e^{-y} < 3e-20 lies far below half
+// the spacing of doubles next to -1 (2^-54), so every faithfully rounded
+// expm1 returns exactly -1 there.  A wavefront whose lanes all have y > 45
+// skips the library call; the per-lane select keeps each lane's value the
+// same whichever way its wavefront goes.
+constexpr double kKdExpm1Cut = 45.0;
+
+__device__ __forceinline__ double kd_em(double y) {
+  if (__all(y > kKdExpm1Cut)) return -1.0;
+  return y > kKdExpm1Cut ? -1.0 : expm1(-y);
+}
+
 struct KdParams {
   double dtf, dtc, R, sigma, mu, T;
   double inv_r;   // 1/R
@@ -169,7 +181,7 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
       const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
       const double theta = t_next - cfine;
       const double y = k.R * theta;
-      const double em = expm1(-y);
+      const double em = kd_em(y);
       const double v_next = k.mu + k.sigma * nu_next;
       double a, dd;
       kd_coeffs(k, theta, y, em, v_next, a, dd);
@@ -188,6 +200,9 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
   } else {
     double xc = x0, vc = vf, tc = 0.0, ccoarse = cfine;
     double nu_f = ns;  // velocity number of the fine path's pending flight
+    // index of the fine grid point that ends the pending flight's step
+    // (computed once per flight: the loop test and the next step share it)
+    double nf = floor(cfine / k.dtf) + 1.0;
     while ((ccoarse < k.T || cfine < k.T) && cf < k.guard) {
       // end of the coarse grid step holding the coarse collision, as an
       // index of the fine grid
@@ -198,10 +213,10 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
       do {
         double nu_next, chi, E_next;
         kd_draws(k, smp, b++, nu_next, chi, E_next);
-        const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
+        const double t_next = nf * k.dtf;
         const double theta = t_next - cfine;
         const double y = k.R * theta;
-        const double em = expm1(-y);
+        const double em = kd_em(y);
         const double v_next = k.mu + k.sigma * nu_next;
         double a, dd;
         kd_coeffs(k, theta, y, em, v_next, a, dd);
@@ -210,7 +225,7 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
         // beta over theta' = theta - zeta, i.e. R theta' = kd_h(y)
         const double zeta = -em * k.inv_r;
         const double yp = kd_h(y, em);
-        const double beta = sqrt(k.c2 * kd_h(yp, yp < kKdSeriesY ? 0.0 : expm1(-yp)));
+        const double beta = sqrt(k.c2 * kd_h(yp, yp < kKdSeriesY ? 0.0 : kd_em(yp)));
         if (!first) {
           const double alpha = (tauf + zeta_prev) * k.sigma;
           num += alpha * nu_f;
@@ -223,10 +238,11 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
         tf = t_next;
         tauf = E_next * k.inv_r;
         cfine = tf + tauf;
+        nf = floor(cfine / k.dtf) + 1.0;
         vf = v_next;
         nu_f = nu_next;
         ++cf;
-      } while (!(floor(cfine / k.dtf) + 1.0 > end_c_fine) && cf < k.guard);
+      } while (!(nf > end_c_fine) && cf < k.guard);
       if (ccoarse < k.T) {
         const double chi_c = den > 0.0 ? num / sqrt(den) : 0.0;
         const double t_next = end_c * k.dtc;
@@ -234,7 +250,7 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
         const double y = k.R * theta;
         const double v_next = k.mu + k.sigma * nu_f;
         double a, dd;
-        kd_coeffs(k, theta, y, expm1(-y), v_next, a, dd);
+        kd_coeffs(k, theta, y, kd_em(y), v_next, a, dd);
         xc = xc + vc * (ccoarse - tc) + (a + dd * chi_c);
         tc = t_next;
         ccoarse = cfine;
