@@ -170,3 +170,35 @@ def test_bench_workload_full_size_against_oracle():
         # differences dQ of standard deviation down to ~1e-3
         assert g["m2_dq"] == pytest.approx(o["m2_dq"], rel=1e-2)
     assert abs(r["estimate"] - est) <= 2e-5 * abs(est)
+
+
+def test_plain_mc_full_size():
+    """Plain Monte Carlo at level 8 to RMSE 1e-3 (the benchmark's comparison
+    run, single trajectories): its persistent launches against one per-level
+    run over the same samples [0, N) -- collision totals exactly equal, mean
+    and variance to FP64 summation order -- and sampled runs of 256
+    trajectories at random offsets against the oracle, one by one."""
+    prob = W.cfg2()
+    L = prob["L"]
+    r = pkg.mlmc_ap_plain_mc(prob, 1e-3)
+    N = r["N"][L]
+    g = r["levels"][L]
+    say("plain MC: N %d estimate %.7f" % (N, r["estimate"]))
+    assert r["converged"] and N > 10 ** 7
+    st = pkg.mlmc_ap_simulate_level(prob, L, 0, N, single=True)
+    assert st["n"] == N and st["coll_f"] == g["coll_f"] and st["coll_c"] == 0
+    assert abs(st["mean_dq"] - g["mean_dq"]) <= 1e-12 * g["mean_dq"]
+    assert st["m2_dq"] == pytest.approx(g["m2_dq"], rel=1e-10)
+    rng = np.random.default_rng(12)
+    for begin in rng.integers(0, N - 256, size=4):
+        P = pkg.as_problem(prob)
+        traj = torch.empty(512, dtype=torch.float32, device="cuda")
+        coll = torch.empty(512, dtype=torch.int32, device="cuda")
+        pkg.mlmc_ap_simulate_level(P, L, int(begin), 256, single=True, traj=traj, coll=coll)
+        torch.cuda.synchronize()
+        x = traj.cpu().double().numpy()[:256]
+        c = coll.cpu().numpy().astype(np.int64)[:256]
+        ref = O.simulate(prob, L, int(begin), 256, single=True)
+        assert np.array_equal(c, ref["cf"].astype(np.int64))
+        scale = np.maximum(np.abs(ref["xf"]), math.sqrt(np.mean(ref["xf"] ** 2)))
+        assert np.max(np.abs(x - ref["xf"]) / scale) <= 1e-5
