@@ -202,3 +202,22 @@ def test_plain_mc_full_size():
         assert np.array_equal(c, ref["cf"].astype(np.int64))
         scale = np.maximum(np.abs(ref["xf"]), math.sqrt(np.mean(ref["xf"] ** 2)))
         assert np.max(np.abs(x - ref["xf"]) / scale) <= 1e-5
+
+
+def test_eps_sweep_all_requests_as_benchmarked():
+    """The benchmark's eps sweep: all 15 requests (5 eps x 3 tolerances) in
+    one batched launch per iteration; every estimate meets its own
+    statistical constraint and lies within 4.5 standard errors of its exact
+    E[Q_8]; each equals the same request run alone (bitwise)."""
+    probs, tols = W.cfg3()
+    batch = pkg.mlmc_ap_estimate_batch(probs, tols)
+    worst = 0.0
+    for p, t, r in zip(probs, tols, batch):
+        assert r["converged"] and r["var_estimator"] <= 0.5 * t * t * (1 + 1e-12)
+        z = abs(r["estimate"] - CF.level_second_moment(p, p["L"])) / math.sqrt(r["var_estimator"])
+        worst = max(worst, z)
+        assert z <= 4.5, (p["eps"], t, r["estimate"])
+    say("eps sweep, 15 requests: worst |z| %.2f" % worst)
+    for i in (0, 7, 14):
+        alone = pkg.mlmc_ap_estimate(probs[i], tols[i])
+        assert alone["estimate"] == batch[i]["estimate"] and alone["N"] == batch[i]["N"]
