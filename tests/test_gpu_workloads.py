@@ -221,3 +221,16 @@ def test_eps_sweep_all_requests_as_benchmarked():
     for i in (0, 7, 14):
         alone = pkg.mlmc_ap_estimate(probs[i], tols[i])
         assert alone["estimate"] == batch[i]["estimate"] and alone["N"] == batch[i]["N"]
+
+
+def test_bench_estimate_launch_forms_bitwise_equal():
+    """The benchmarked estimate in each launch form it reports (direct, timed,
+    hipGraph replay, one launch per level) at full size: bitwise the same
+    estimate, sample numbers and per-level statistics."""
+    prob = W.cfg2()
+    tk = dict(block=256, ppt=1, waves_per_simd=8)
+    runs = [pkg.mlmc_ap_estimate(prob, 1e-3, pkg.options(batched=b, **tk)) for b in (0, 2, 1, -1)]
+    ref = runs[0]
+    for r in runs[1:]:
+        assert r["estimate"] == ref["estimate"] and r["N"] == ref["N"]
+        assert r["levels"] == ref["levels"]
