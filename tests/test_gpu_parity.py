@@ -303,3 +303,33 @@ def test_plain_mc_estimate():
     assert res["N"][:L] == [0] * L and res["N"][L] > 0
     exact = CF.level_second_moment(prob, L)
     assert abs(res["estimate"] - exact) <= 4.0 * math.sqrt(res["var_estimator"])
+
+
+def test_concurrent_calls_on_distinct_streams():
+    """Host threads calling the library at once, each on its own stream
+    (ctypes releases the interpreter lock during a call): every result equals
+    the same call made alone, bitwise."""
+    import threading
+    probs = [W.cfg2(eps=e, stream_id=70 + i) for i, e in enumerate((0.01, 0.05, 0.2, 1.0))]
+    alone = [pkg.mlmc_ap_estimate(p, 5e-3) for p in probs]
+    streams = [torch.cuda.Stream() for _ in probs]
+    out = [None] * len(probs)
+    errors = []
+
+    def work(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                out[i] = pkg.mlmc_ap_estimate(probs[i], 5e-3,
+                                              stream=streams[i].cuda_stream)
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(probs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for a, b in zip(alone, out):
+        assert _key(a) == _key(b)
