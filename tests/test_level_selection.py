@@ -94,3 +94,21 @@ def test_selectors_reject_bad_input(lib):
     with pytest.raises(pkg.MlmcApError):
         pkg.mlmc_ap_select_levels_optimal([1.0, 1.0], [1.0, 0.0], [[0, 0], [1, 0]],
                                           [[1, 1], [1, 1]])
+
+
+def test_heuristic_sets_are_nested_in_L(lib):
+    """Section 5.2: the heuristic is level-adaptive; raising the finest level
+    L keeps every level chosen below the old L (the set for L, without the
+    level L that is always added, is contained in the set for L + 1)."""
+    rng = np.random.default_rng(9)
+    for _ in range(200):
+        Lmax = int(rng.integers(2, 14))
+        V = list(rng.uniform(0.5, 2.0, Lmax + 1))
+        Vd = [0.0] + list(np.exp(rng.normal(0, 1.5, Lmax)) * np.geomspace(2, 1e-3, Lmax))
+        prev = None
+        for L in range(0, Lmax + 1):
+            cur = pkg.mlmc_ap_select_levels_heuristic(V[:L + 1], Vd[:L + 1])
+            assert cur == OL.heuristic(V[:L + 1], Vd[:L + 1])
+            if prev is not None:
+                assert set(prev) - {L - 1} <= set(cur), (L, prev, cur)
+            prev = cur
