@@ -81,6 +81,11 @@ def lib():
             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
             ctypes.c_uint32, ctypes.c_uint64, dp, ctypes.c_uint64, dp]
         L.oracle_kd_coarse_numbers.restype = ctypes.c_uint64
+        L.oracle_kd_phases.argtypes = [
+            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+            ctypes.c_uint32, ctypes.c_uint64, dp, ctypes.c_uint64, dp, ctypes.c_uint64, u64p, dp]
+        L.oracle_kd_phases.restype = ctypes.c_uint64
         _lib = L
     return _lib
 
@@ -228,3 +233,29 @@ def kd_coarse_numbers(prob, level, sample, cap=None, coarse_level=None):
         int(prob.get("seed", 42)), int(prob.get("stream_id", 0)), int(sample),
         _ptr(rows, ctypes.c_double), cap, _ptr(fin, ctypes.c_double))
     return rows[:used], fin
+
+
+KD_PHASE_COLUMNS = ("window", "first", "t", "tau", "theta", "zeta", "theta_p", "tau_p", "alpha",
+                    "beta", "nu", "chi", "a", "d", "nu_next", "xf")
+
+
+def kd_phases(prob, level, sample, coarse_level=None):
+    """Fine KD phases of one pair, one row per fine KD step (columns
+    ``KD_PHASE_COLUMNS``: the coarse step it is aggregated into, whether it
+    opens that window, flight start time and length, theta, zeta, theta',
+    tau', the weights alpha and beta, its numbers nu, chi, its a and d, the
+    next velocity number and x_f after it), the coarse rows of
+    ``kd_coarse_numbers`` and the final (x_f, x_c)."""
+    cap = int(round(prob["T"] / prob["dt0"])) * int(prob["M"]) ** level + 2
+    phases = np.zeros((cap, 16))
+    rows = np.zeros((cap, 4))
+    fin = np.zeros(2)
+    nc = np.zeros(1, dtype=np.uint64)
+    used = lib().oracle_kd_phases(
+        float(prob["eps"]), float(prob["T"]), float(prob["dt0"]), int(prob["M"]), int(level),
+        int(level - 1 if coarse_level is None else coarse_level), int(prob["x0_kind"]),
+        float(prob.get("x0_a", 0.0)), float(prob.get("x0_b", 0.0)),
+        int(prob.get("seed", 42)), int(prob.get("stream_id", 0)), int(sample),
+        _ptr(phases, ctypes.c_double), cap, _ptr(rows, ctypes.c_double), cap,
+        _ptr(nc, ctypes.c_uint64), _ptr(fin, ctypes.c_double))
+    return phases[:used], rows[:int(nc[0])], fin

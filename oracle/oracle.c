@@ -538,10 +538,18 @@ static double kd_step_of(double c, double dt)
 }
 
 /* Optional record of the coarse numbers of a pair, 4 doubles per coarse
- * step: (chi~, nu~, E~, number of fine KD steps aggregated). */
+ * step: (chi~, nu~, E~, number of fine KD steps aggregated), and of the fine
+ * phases behind them, 16 doubles per fine KD step m of a pair:
+ *   0 coarse step k the phase is aggregated into, 1 first phase of the
+ *   window (m = kappa_k: no alpha term), 2 grid time t_m the flight starts
+ *   from, 3 flight tau_m, 4 theta_m, 5 zeta_m, 6 theta'_m, 7 tau'_m (0 when
+ *   first), 8 alpha_m (0 when first), 9 beta_m, 10 nu_m (velocity number of
+ *   flight m), 11 chi_m, 12 a_m, 13 d_m, 14 nu_{m+1}, 15 x_f after phase m. */
 typedef struct {
     double *rows;
     uint64_t cap, used;
+    double *phases;
+    uint64_t phase_cap, phase_used;
 } kd_trace_t;
 
 static void simulate_kd_one(const problem_t *P, uint64_t sample,
@@ -630,13 +638,22 @@ static void simulate_kd_one(const problem_t *P, uint64_t sample,
             double zeta = -expm1(-y) / R;                 /* expected time of nu_{m+1} */
             double theta_p = kd_h(y) / R;                 /* theta'_m = theta_m - zeta_m */
             double beta = sqrt(2.0 * sigma * sigma / (R * R) * kd_h(R * theta_p));
+            double alpha = 0.0;
             if (!first) {
-                double alpha = (tauf + zeta_prev) * sigma;   /* sigma tau'_m */
+                alpha = (tauf + zeta_prev) * sigma;          /* sigma tau'_m */
                 num += alpha * nu_f;
                 den += alpha * alpha;
             }
             num += beta * chi;
             den += beta * beta;
+            if (tr && tr->phases && tr->phase_used < tr->phase_cap) {
+                double *r = tr->phases + 16 * tr->phase_used++;
+                r[0] = (double)cc; r[1] = (double)first; r[2] = tf; r[3] = tauf;
+                r[4] = theta; r[5] = zeta; r[6] = theta_p;
+                r[7] = first ? 0.0 : tauf + zeta_prev; r[8] = alpha; r[9] = beta;
+                r[10] = nu_f; r[11] = chi; r[12] = ad[0]; r[13] = ad[1];
+                r[14] = nu_next; r[15] = xf;
+            }
             zeta_prev = zeta;
             first = 0;
             used++;
@@ -704,11 +721,31 @@ uint64_t oracle_kd_coarse_numbers(double eps, double T, double dt0, int M, int l
     problem_t P = make_problem(eps, T, dt0, M, level, 0, x0_kind, x0_a, x0_b,
                                EQ_MAXWELLIAN, 0, seed, stream);
     if (coarse_level >= 0 && coarse_level < level) P.coarse_level = coarse_level;
-    kd_trace_t tr = {rows, cap, 0};
+    kd_trace_t tr = {rows, cap, 0, NULL, 0, 0};
     double xf, xc; uint32_t cf, cc;
     simulate_kd_one(&P, sample, &xf, &xc, &cf, &cc, &tr);
     out_final[0] = xf; out_final[1] = xc;
     return tr.used;
+}
+
+/* Fine phases of one pair (rows of 16 doubles, see kd_trace_t) and its
+ * coarse numbers (rows of 4); *n_coarse_out receives the coarse rows
+ * written; returns the phase rows written.  out_final = (x_f, x_c). */
+uint64_t oracle_kd_phases(double eps, double T, double dt0, int M, int level,
+                          int coarse_level, int x0_kind, double x0_a, double x0_b,
+                          uint64_t seed, uint32_t stream, uint64_t sample,
+                          double *phases, uint64_t phase_cap, double *rows, uint64_t cap,
+                          uint64_t *n_coarse_out, double out_final[2])
+{
+    problem_t P = make_problem(eps, T, dt0, M, level, 0, x0_kind, x0_a, x0_b,
+                               EQ_MAXWELLIAN, 0, seed, stream);
+    if (coarse_level >= 0 && coarse_level < level) P.coarse_level = coarse_level;
+    kd_trace_t tr = {rows, cap, 0, phases, phase_cap, 0};
+    double xf, xc; uint32_t cf, cc;
+    simulate_kd_one(&P, sample, &xf, &xc, &cf, &cc, &tr);
+    out_final[0] = xf; out_final[1] = xc;
+    *n_coarse_out = tr.used;
+    return tr.phase_used;
 }
 
 /* As oracle_simulate / oracle_simulate_kd for a pair whose coarse path is at

@@ -253,6 +253,60 @@ def pin_coupling_laws():
             assert abs(np.corrcoef(kick, hit)[0, 1]) < 4.5 / math.sqrt(kick.size)
 
 
+def pin_kick_block_identity():
+    """The coarse kick is the fine block's displacement that no velocity the
+    coarse path keeps accounts for, normalised by its standard deviation
+    (eq. chi-update with the fixed-step weights).  Deterministic identity on
+    every coarse block of a trace, from the trace's positions, velocities and
+    collision flags alone (no bookkeeping variable of the oracle):
+      D = x_f(block end) - x_f(previous block end) = sum_m (h_f v_m + s_f xi_m),
+    with v_m the velocity the fine move m is made with.
+      kick sum:   kick * s_f sqrt(M) = D - h_f sum_m v_m;
+      aggregated: the velocity carried into the block acts u_0 moves, the
+        draw nu_j of an in-block collision at step k_j acts n_j moves (up to
+        the next in-block collision or the block end); the coarse path keeps
+        the carried velocity and, if it collides, the last draw, so
+        kick * sqrt(M s_f^2 + h_f^2 sum_{j in A} n_j^2)
+            = D - h_f u_0 v_pre - [coarse hit] h_f n_last nu_last,
+        A = the draws the coarse path does not keep."""
+    cases = [(1, 2, 0.05, 3), (1, 3, 0.3, 2), (1, 4, 0.1, 2), (1, 2, 1.0, 3),
+             (0, 2, 0.05, 3), (0, 3, 0.3, 2)]
+    checked = 0
+    for k, (coupling, M, eps, level) in enumerate(cases):
+        prob = maxwell_problem(eps, T=1.5 if M == 3 else 1.0, dt0=0.25 if M != 3 else 0.5,
+                               M=M, coupling=coupling, stream=700 + k)
+        c = O.level_consts(eps, prob["T"], prob["dt0"], M, level)
+        h, sd = c["h"], c["s"]
+        for smp in range(40):
+            rows, _ = O.trace(prob, level, smp)
+            for b in range(1, rows.shape[0] // M):
+                prev = rows[b * M - 1]
+                blk = rows[b * M:(b + 1) * M]
+                D = blk[-1, 10] - prev[10]
+                vpre_m = np.concatenate(([prev[11]], blk[:-1, 11]))   # velocity of each move
+                kick, chit = blk[-1, 12], blk[-1, 13] > 0
+                scale = 1e-11 * (1.0 + abs(blk[-1, 10]) + abs(prev[10]))
+                if coupling == 0:
+                    lhs = kick * sd * math.sqrt(M)
+                    rhs = D - h * np.sum(vpre_m)
+                else:
+                    hits = np.nonzero(blk[:, 9] > 0)[0]
+                    u0 = (hits[0] + 1) if hits.size else M
+                    ends = np.append(hits[1:], M - 1)
+                    n = (ends - hits).astype(np.float64)       # moves made with draw j
+                    nu = blk[hits, 11]                          # draw j = velocity after its hit
+                    assert np.array_equal(nu, blk[hits, 8])     # the Maxwellian draw g
+                    keep_last = chit and hits.size > 0
+                    A = slice(0, hits.size - 1) if keep_last else slice(0, hits.size)
+                    rhs = D - h * u0 * prev[11]
+                    if keep_last:
+                        rhs -= h * n[-1] * nu[-1]
+                    lhs = kick * math.sqrt(M * sd * sd + h * h * np.sum(n[A] ** 2))
+                assert abs(lhs - rhs) <= scale, (coupling, M, eps, smp, b, lhs, rhs)
+                checked += 1
+    assert checked > 2000
+
+
 def pin_coarse_threshold():
     """P(coarse collision) = 1 - (1 - thr_c2/2^32)^M (smallest of M uniform
     words below thr_c2) equals the coarse level's probability thr_c / 2^32
@@ -449,7 +503,88 @@ def pin_kd_nonadjacent_pairs():
         assert abs(_z(a ** 2, CF.kinetic_limit(eps, prob["T"], 1.0))) < Z_MAX
 
 
-KD_PINS = [pin_kd_second_moment_exact, pin_kd_diffusive_phase_bruteforce,
+def _velocity_jump_last_duration(theta, R, n, rng):
+    """Time during which the last velocity of a velocity-jump motion over
+    [0, theta] (collisions at rate R) acts, for n independent paths."""
+    t = np.zeros(n)
+    last = np.zeros(n)
+    live = np.ones(n, dtype=bool)
+    while live.any():
+        idx = np.nonzero(live)[0]
+        tau = rng.exponential(1.0 / R, size=idx.size)
+        end = t[idx] + tau >= theta
+        live[idx[end]] = False
+        go = idx[~end]
+        t[go] += tau[~end]
+        last[go] = t[go]
+    return theta - last
+
+
+def pin_kd_aggregation_weights():
+    """The weights of eq. chi-update (Section 3.2), phase by phase:
+      - zeta_m is the expected time the next velocity acts in diffusive phase
+        m: eq. advection (mu = 0) is a_m = sigma nu_{m+1} zeta_m, checked
+        against the phase's own a_m, and zeta against a brute-force
+        velocity-jump simulation over theta_m;
+      - theta'_m = theta_m - zeta_m and tau'_m = tau_m + zeta_{m-1}, so
+        alpha_m nu_m = sigma tau_m nu_m + a_{m-1}: the whole displacement
+        that nu_m causes (its flight and the previous phase's advection);
+      - beta_m^2 is the variance of the unconditioned diffusive displacement
+        over theta'_m: brute-force velocity-jump simulation;
+      - the coarse number is the normalised weighted sum over its window, the
+        window's first phase (the coarse path's own flight) without an alpha
+        term, and the next window opens with the flight whose velocity
+        number the coarse path takes (eq. nu-update)."""
+    rng = np.random.default_rng(11)
+    picks = []
+    for k, (eps, level, M) in enumerate(((0.3, 3, 2), (0.1, 2, 2), (0.5, 2, 4), (0.3, 2, 3),
+                                         (0.3, 1, 2))):
+        prob = kd_problem(eps, M=M, T=1.5 if M == 3 else 1.0, stream=720 + k)
+        R, sigma = 1.0 / eps ** 2, 1.0 / eps
+        dtf = prob["dt0"] / M ** level
+        for smp in range(60):
+            ph, co, _ = O.kd_phases(prob, level, smp)
+            assert ph.shape[0] >= co.shape[0] >= 1
+            for m in range(ph.shape[0]):
+                r = ph[m]
+                sc = 1e-12 * (1.0 + abs(r[12]) + sigma * abs(r[14]) * dtf)
+                assert abs(sigma * r[14] * r[5] - r[12]) <= sc, (eps, smp, m)
+                assert abs(r[6] - (r[4] - r[5])) <= 1e-15 * (1.0 + r[4])
+                c = r[2] + r[3]
+                assert abs(r[4] - ((math.floor(c / dtf) + 1.0) * dtf - c)) <= 1e-12 * dtf
+                if r[1] == 0:
+                    assert ph[m - 1, 0] == r[0]
+                    assert abs(r[7] - (r[3] + ph[m - 1, 5])) <= 1e-14 * (1.0 + r[7])
+                    lhs = r[8] * r[10]
+                    rhs = sigma * r[3] * r[10] + ph[m - 1, 12]
+                    assert abs(lhs - rhs) <= 1e-12 * (1.0 + abs(lhs)), (eps, smp, m, lhs, rhs)
+                else:
+                    assert r[7] == 0.0 and r[8] == 0.0
+                    assert m == 0 or ph[m - 1, 0] == r[0] - 1
+            for w in range(co.shape[0]):
+                sel = ph[ph[:, 0] == w]
+                assert sel[0, 1] == 1 and np.all(sel[1:, 1] == 0) and sel.shape[0] == co[w, 3]
+                num = np.sum(sel[:, 9] * sel[:, 11]) + np.sum(sel[1:, 8] * sel[1:, 10])
+                den = np.sum(sel[:, 9] ** 2) + np.sum(sel[1:, 8] ** 2)
+                assert abs(co[w, 0] - num / math.sqrt(den)) <= 1e-12 * (1.0 + abs(co[w, 0]))
+                nxt = ph[ph[:, 0] == w + 1]
+                if nxt.shape[0]:
+                    assert co[w, 1] == nxt[0, 10]
+            picks.extend((R, sigma, r[4], r[5], r[6], r[9]) for r in ph)
+    picks = np.array(picks)
+    # brute force at phases spread over y = R theta (both sides of the series switch)
+    y = picks[:, 0] * picks[:, 2]
+    for lo, hi in ((0.005, 0.05), (0.1, 0.8), (1.0, 4.0), (5.0, 20.0)):
+        cand = np.nonzero((y > lo) & (y < hi))[0]
+        assert cand.size > 0, (lo, hi)
+        R, sigma, theta, zeta, theta_p, beta = picks[cand[cand.size // 2]]
+        last = _velocity_jump_last_duration(theta, R, 200000, rng)
+        assert abs(_z(last, zeta)) < Z_MAX, (lo, hi, "zeta")
+        dx, _ = _velocity_jump(theta_p, R, 0.0, sigma, 200000, rng)
+        assert abs(_z(dx * dx, beta * beta)) < Z_MAX, (lo, hi, "beta")
+
+
+KD_PINS = [pin_kd_aggregation_weights, pin_kd_second_moment_exact, pin_kd_diffusive_phase_bruteforce,
            pin_kd_coarse_number_laws, pin_kd_coarse_matches_level_below, pin_kd_invariants,
            pin_kd_nonadjacent_pairs]
 
@@ -469,7 +604,8 @@ def pin_nonadjacent_pairs():
 
 ALL_PINS = [pin_philox_kat, pin_word_layout, pin_uniform, pin_normals, pin_second_moment_cfg1,
             pin_second_moment_levels, pin_cosine_initial, pin_heat_limit, pin_kinetic_limit,
-            pin_two_point_bruteforce, pin_telescoping, pin_coupling_laws, pin_coarse_threshold,
+            pin_two_point_bruteforce, pin_telescoping, pin_coupling_laws, pin_kick_block_identity,
+            pin_coarse_threshold,
             pin_symmetry, pin_optimal_samples, pin_mlmc_unbiased, pin_nonadjacent_pairs]
 
 

@@ -44,6 +44,12 @@ MUTANTS = [
     ("velocity_not_resampled", "vf = v_new;", "vf = vf;"),
     ("coarse_threshold_linearised", "-expm1(log1p(-pc) / (double)M)", "(pc / (double)M)"),
     ("block_min_not_reset", "            min_word = 0xFFFFFFFFu;\n", "\n"),
+    ("aggregate_draw_counts_its_collision_step",
+     "have_draw = 1; last_nu = v_new; last_uses = 0.0;",
+     "have_draw = 1; last_nu = v_new; last_uses = 1.0;"),
+    ("aggregate_unweighted_velocity", "vel_num += last_uses * last_nu;", "vel_num += last_nu;"),
+    ("aggregate_last_draw_never_in_kick", "if (have_draw && !chit) {", "if (0) {"),
+    ("aggregate_last_draw_always_in_kick", "if (have_draw && !chit) {", "if (have_draw) {"),
     ("nonadjacent_block_is_M",
      "const int Mb = coarse ? (int)llround(pow((double)P->M, (double)(l - P->coarse_level))) : 1;",
      "const int Mb = coarse ? P->M : 1;"),
@@ -73,6 +79,10 @@ KD_MUTANTS = [
     ("kd_nonadjacent_block_is_M",
      "const double Mb = coarse ? (double)llround(pow((double)P->M, (double)(l - P->coarse_level))) : 1.0;",
      "const double Mb = coarse ? (double)P->M : 1.0;"),
+    ("kd_beta_over_theta", "kd_h(R * theta_p));", "kd_h(R * theta));"),
+    ("kd_alpha_without_zeta_shift", "alpha = (tauf + zeta_prev) * sigma;", "alpha = tauf * sigma;"),
+    ("kd_alpha_pairs_next_velocity", "num += alpha * nu_f;", "num += alpha * nu_next;"),
+    ("kd_zeta_full_phase", "double zeta = -expm1(-y) / R;", "double zeta = theta;"),
     ("kd_exponential_from_wrong_word", "*E_next = -log(oracle_uniform(w[2]));",
      "*E_next = -log(oracle_uniform(w[0]));"),
 ]
