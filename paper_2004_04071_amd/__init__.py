@@ -182,14 +182,35 @@ def _stream(stream):
     return ctypes.c_void_p(int(stream))
 
 
-def _dev_ptr(t):
+def _dev_ptr(t, min_elems, dtypes, what):
+    """Device address of an optional output tensor after checking, before any
+    launch, everything the kernels will assume of it: a contiguous GPU tensor
+    of one of ``dtypes`` (names of torch dtypes) with at least ``min_elems``
+    elements.  The kernels write that many elements without bounds checks."""
     if t is None:
         return None
-    if hasattr(t, "data_ptr"):
-        if not t.is_cuda or not t.is_contiguous():
-            raise ValueError("device buffers must be contiguous GPU tensors")
-        return ctypes.c_void_p(t.data_ptr())
-    return ctypes.c_void_p(int(t))
+    if not hasattr(t, "data_ptr") or not hasattr(t, "dtype"):
+        raise TypeError("%s must be a torch GPU tensor" % what)
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous GPU tensor" % what)
+    name = str(t.dtype).replace("torch.", "")
+    if name not in dtypes:
+        raise ValueError("%s must have dtype %s, not %s" % (what, " or ".join(dtypes), name))
+    if t.numel() < min_elems:
+        raise ValueError("%s holds %d elements; %d are written" % (what, t.numel(), min_elems))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _traj_dtype(P):
+    """Element type of the trajectory dump: double for FP64 state and the KD
+    scheme (which runs in FP64), float otherwise."""
+    return "float64" if (P.fp64_state or P.scheme == SCHEME_KD) else "float32"
+
+
+def _dump_ptrs(P, n_samples, traj, coll):
+    n2 = 2 * int(n_samples)
+    return (_dev_ptr(traj, n2, (_traj_dtype(P),), "traj"),
+            _dev_ptr(coll, n2, ("int32", "uint32"), "coll"))
 
 
 def problem(eps, T, dt0, M=2, L=0, x0_kind=X0_NORMAL, x0_a=0.0, x0_b=1.0, eq_kind=EQ_MAXWELLIAN,
@@ -316,9 +337,10 @@ def mlmc_ap_simulate_level(p, level, sample_begin, n_samples, single=False, traj
     hbuf = None
     if hist:
         hbuf = (ctypes.c_uint64 * (3 * P.nbins + 4))()
+    tp, cp = _dump_ptrs(P, n_samples, traj, coll)
     _check(lib().mlmc_ap_simulate_level(ctypes.byref(P), int(level), int(bool(single)),
                                         int(sample_begin), int(n_samples), ctypes.byref(out),
-                                        _dev_ptr(traj), _dev_ptr(coll), hbuf, _stream(stream)),
+                                        tp, cp, hbuf, _stream(stream)),
            "mlmc_ap_simulate_level")
     if hist:
         return stats_dict(out), [int(x) for x in hbuf]
@@ -333,9 +355,10 @@ def mlmc_ap_simulate_pair(p, level, coarse_level, sample_begin, n_samples, traj=
     hbuf = None
     if hist:
         hbuf = (ctypes.c_uint64 * (3 * P.nbins + 4))()
+    tp, cp = _dump_ptrs(P, n_samples, traj, coll)
     _check(lib().mlmc_ap_simulate_pair(ctypes.byref(P), int(level), int(coarse_level),
                                        int(sample_begin), int(n_samples), ctypes.byref(out),
-                                       _dev_ptr(traj), _dev_ptr(coll), hbuf, _stream(stream)),
+                                       tp, cp, hbuf, _stream(stream)),
            "mlmc_ap_simulate_pair")
     if hist:
         return stats_dict(out), [int(x) for x in hbuf]
@@ -497,12 +520,16 @@ def mlmc_ap_philox_words(seed, stream_id, tag, sample_begin, n_samples, n_steps,
     """Fills the device tensor ``out`` (n_samples * n_steps * 4 int32) with
     Philox4x32-10 words."""
     _check(lib().mlmc_ap_philox_words(int(seed), int(stream_id), int(tag), int(sample_begin),
-                                      int(n_samples), int(n_steps), _dev_ptr(out), _stream(stream)),
+                                      int(n_samples), int(n_steps),
+                                      _dev_ptr(out, 4 * int(n_samples) * int(n_steps),
+                                               ("int32", "uint32"), "out"), _stream(stream)),
            "mlmc_ap_philox_words")
 
 
 def mlmc_ap_rng_normals(seed, stream_id, tag, sample_begin, n_samples, n_steps, fp64, out,
                         stream=None):
     _check(lib().mlmc_ap_rng_normals(int(seed), int(stream_id), int(tag), int(sample_begin),
-                                     int(n_samples), int(n_steps), int(fp64), _dev_ptr(out),
+                                     int(n_samples), int(n_steps), int(fp64),
+                                     _dev_ptr(out, 4 * int(n_samples) * int(n_steps),
+                                              ("float64",) if fp64 else ("float32",), "out"),
                                      _stream(stream)), "mlmc_ap_rng_normals")

@@ -195,3 +195,59 @@ def test_optimal_samples_rejects_bad_input(lib):
         pkg.mlmc_ap_optimal_samples([1.0], [1.0], 0.0)
     assert pkg.mlmc_ap_optimal_samples([0.0, 1.0], [1.0, 1.0], 1.0) == [0, 2]
     assert math.ceil(2.0 / 1e-4 * 18) == pkg.mlmc_ap_optimal_samples([18.0], [2.0], 1e-2)[0]
+
+
+class _FakeDeviceTensor:
+    """Stands in for a GPU tensor (the checks run before any device call)."""
+
+    def __init__(self, n, dtype, contiguous=True, cuda=True):
+        import torch
+        self.dtype = getattr(torch, dtype)
+        self._n = n
+        self.is_cuda = cuda
+        self._contiguous = contiguous
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return self._contiguous
+
+    def data_ptr(self):
+        return 0x1000
+
+
+@pytest.mark.parametrize("kw,scheme,fp64,err", [
+    (dict(traj=("float64", 200)), 0, 0, "dtype float32"),      # FP32 state writes floats
+    (dict(traj=("float32", 200)), 0, 1, "dtype float64"),      # FP64 state writes doubles
+    (dict(traj=("float32", 200)), 1, 1, "dtype float64"),      # KD writes doubles
+    (dict(traj=("float32", 199)), 0, 0, "200 are written"),    # 2 n_samples values
+    (dict(coll=("int32", 150)), 0, 0, "200 are written"),
+    (dict(coll=("float32", 200)), 0, 0, "dtype int32"),
+    (dict(coll=("int64", 200)), 0, 0, "dtype int32"),
+])
+def test_dump_buffers_checked_before_launch(lib, kw, scheme, fp64, err):
+    """The kernels write 2 n_samples positions (float or double) and counts
+    (32-bit) with no bounds checks, so the binding refuses a buffer of the
+    wrong type or size before anything reaches the device."""
+    P = pkg.problem(eps=0.3, T=1.0, dt0=0.5, L=3, fp64_state=fp64, scheme=scheme)
+    args = {k: _FakeDeviceTensor(n, dt) for k, (dt, n) in kw.items()}
+    for fn in (lambda: pkg.mlmc_ap_simulate_level(P, 2, 0, 100, **args),
+               lambda: pkg.mlmc_ap_simulate_pair(P, 2, 0, 0, 100, **args)):
+        with pytest.raises(ValueError, match=err):
+            fn()
+
+
+def test_dump_buffers_must_be_contiguous_gpu_tensors(lib):
+    P = pkg.problem(eps=0.3, T=1.0, dt0=0.5, L=3)
+    with pytest.raises(ValueError, match="contiguous GPU"):
+        pkg.mlmc_ap_simulate_level(P, 2, 0, 100, traj=_FakeDeviceTensor(200, "float32", cuda=False))
+    with pytest.raises(ValueError, match="contiguous GPU"):
+        pkg.mlmc_ap_simulate_level(P, 2, 0, 100,
+                                   coll=_FakeDeviceTensor(200, "int32", contiguous=False))
+    with pytest.raises(TypeError):
+        pkg.mlmc_ap_simulate_level(P, 2, 0, 100, traj=0x1000)
+    with pytest.raises(ValueError, match="800 are written"):
+        pkg.mlmc_ap_philox_words(42, 0, 0, 0, 10, 20, _FakeDeviceTensor(799, "int32"))
+    with pytest.raises(ValueError, match="dtype float64"):
+        pkg.mlmc_ap_rng_normals(42, 0, 0, 0, 10, 20, 1, _FakeDeviceTensor(800, "float32"))
