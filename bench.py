@@ -28,41 +28,45 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic VALU issue cost of the method, in full-rate lane-slots (one
-# slot = one lane of one full-rate VALU instruction): full-rate ops 1 slot,
-# 32x32->64-bit integer multiplies 2, transcendentals 4 (weights from the
-# measured gfx950 issue rates), per unit of the method as listed below.
-SLOTS_PHILOX_BLOCK = 50.0   # 16 lane-varying 64-bit products (2) + 18 three-input xors (1)
-SLOTS_NORMAL_PAIR = 23.0    # two uniforms (4) + log, sqrt, sin, cos (16) + 3 multiplies
-SLOTS_FINE_MOVE = 5.0       # move (2 FMA) + collision compare, select, count
-SLOTS_COARSE_FINE = 9.0     # per fine step of a pair: block minimum, kick sum, aggregation
-SLOTS_COARSE_STEP = 17.0    # per coarse step: kick normalisation, move, decision, velocity
-SLOTS_SAMPLE_FINE = 15.0    # per level-0 sample: x0, FP64 QoI and shifted-sum update
-SLOTS_SAMPLE_PAIR = 31.0    # per pair: the same for dQ, Q_f, Q_c and their co-moment
-PEAK_SLOTS = 256 * 128 * 2.4e9     # CUs x FP32 lanes/CU/cycle x clock (157.3 TFLOP/s FMA)
+# Roofline of the particle kernels: VALU instruction issue.  MI355X issues one
+# wave64 VALU instruction per SIMD every four cycles (16 lanes per cycle), so
+# the peak is 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-instructions/s:
+# the non-packed FP32 FMA rate (78.6 TFLOP/s) and the FP64 FMA rate alike.
+# (The kernels are built without packed FP32, whose 157.3 TFLOP/s does not apply.)
+PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9
+
+# Per-unit work: VALU lane-instructions per sample of each level of the
+# benchmarked workloads, as issued by the built gfx950 persistent kernels
+# (unit = one sample of level l, i.e. one fine/coarse pair for l >= 1).
+# Measured with rocprofv3 SQ_INSTS_VALU on launches of one size each
+# (bench.py --valu-probe); kept with the kernel source hash they were taken on
+# in profiles/valu_instructions_per_sample.json.  The long levels agree with
+# the static count of the hot loop in the gfx950 assembly (221 instructions
+# per four fine steps of an aggregated M = 2 pair, i.e. 55 per fine step;
+# level 8 measures 53.4 per fine step including the per-sample work).
+VALU_RECORD = os.path.join(ROOT, "profiles", "valu_instructions_per_sample.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_slots(prob, N):
-    """Algorithmic lane-slots of an estimate with N[l] samples per level: a
-    trajectory of n fine steps reads 2 + 3n words of its Philox word stream
-    (ceil((2 + 3n)/4) blocks) and forms n + 1 Box-Muller pairs."""
+def valu_per_sample(scheme):
+    """(per-level VALU lane-instructions per sample, record is current)."""
+    with open(VALU_RECORD) as f:
+        rec = json.load(f)
+    return rec[scheme], rec.get("kernel_source_hash") == kernel_source_hash()
+
+
+def algorithmic_lane_instructions(table, N):
+    """VALU lane-instructions of an estimate with N[l] samples at level l."""
+    return sum(n * table[l] for l, n in enumerate(N))
+
+
+def fine_steps(prob, N):
+    """Fine-path particle steps of an estimate (coarse steps left out)."""
     n0 = int(round(prob["T"] / prob["dt0"]))
-    M = prob["M"]
-    tot = 0.0
-    for l, n in enumerate(N):
-        nf = n0 * M ** l
-        blocks = (2 + 3 * nf + 3) // 4
-        per = blocks * SLOTS_PHILOX_BLOCK + (nf + 1) * SLOTS_NORMAL_PAIR + nf * SLOTS_FINE_MOVE
-        if l >= 1:
-            per += nf * SLOTS_COARSE_FINE + (nf // M) * SLOTS_COARSE_STEP + SLOTS_SAMPLE_PAIR
-        else:
-            per += SLOTS_SAMPLE_FINE
-        tot += n * per
-    return tot
+    return sum(n * n0 * prob["M"] ** l for l, n in enumerate(N))
 
 
 KERNEL_SOURCES = ("kernels.hip", "kernels.hpp", "kd.hpp", "device.hpp", "types.hpp", "stats.hpp")
@@ -114,6 +118,18 @@ def recorded_traffic(tuning):
     return rec.get("bytes_per_launch")
 
 
+def cpu_model():
+    """Model name of the host CPU (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(prob, N, seconds):
     """FP64 oracle on the host cores, on the MLMC sample numbers N scaled
     down so the run takes about `seconds`."""
@@ -134,16 +150,81 @@ def cpu_baseline(prob, N, seconds):
             break
         frac *= 4
     frac = min(1.0, frac * seconds / max(dt, 1e-3))
+    # passes over the (scaled) sample ranges until `seconds` have elapsed: at
+    # frac = 1 one pass is the whole estimate's samples
     t0 = time.perf_counter()
     steps = 0
-    for l, n in enumerate(N):
-        k = max(1, int(n * frac))
-        oracle.simulate(prob, l, 0, k, threads=threads)
-        steps += k * OM.level_cost(prob, l)
+    passes = 0
+    while passes == 0 or time.perf_counter() - t0 < seconds:
+        for l, n in enumerate(N):
+            k = max(1, int(n * frac))
+            oracle.simulate(prob, l, 0, k, threads=threads)
+            steps += k * OM.level_cost(prob, l)
+        passes += 1
     dt = time.perf_counter() - t0
     return dict(value=steps / dt, unit="particle-steps/s", cores=threads, kind="oracle",
-                sample="MLMC-AP eps=0.01 L=8 sample numbers scaled by %.3g "
-                       "(%d particle-steps, %.1f s)" % (frac, steps, dt))
+                cpu_model=cpu_model(), host_logical_cpus=os.cpu_count(),
+                sample="MLMC-AP eps=0.01 L=8: %d pass(es) over the estimate's sample numbers "
+                       "scaled by %.3g (%d particle-steps, %.1f s)" % (passes, frac, steps, dt))
+
+
+def valu_probe():
+    """The launches behind profiles/valu_instructions_per_sample.json (run it
+    under rocprofv3 --pmc SQ_INSTS_VALU): per workload and finest level L,
+    one persistent launch over levels 0..L with VALU_PROBE_SAMPLES samples at
+    every level and the tuning the benchmark times; the time-parallel path is
+    off so that every sample runs the per-lane loop."""
+    import torch
+    import paper_2004_04071_amd as pkg
+    import workloads as W
+    torch.cuda.set_device(0)
+    pkg.mlmc_ap_init()
+    for name, base in (("ap", W.cfg2()), ("kd", W.cfg_kd())):
+        n = VALU_PROBE_SAMPLES[name]
+        for L in range(base["L"] + 1):
+            r = pkg.mlmc_ap_estimate(dict(base, L=L), 100.0, pkg.options(
+                batched=2, n_warmup=n, max_iter=1, tp_max_samples=-1, block=256, ppt=1,
+                waves_per_simd=8))
+            assert r["launches"] == 1 and r["N"] == [n] * (L + 1)
+            print(json.dumps(dict(workload=name, L=L, samples_per_level=n)), flush=True)
+
+
+VALU_PROBE_SAMPLES = {"ap": 1 << 24, "kd": 1 << 20}
+VALU_PROBE_COMMAND = ("rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES --output-format csv -d <dir> "
+                      "-o pmc -- python3 bench.py --valu-probe")
+
+
+def write_valu_record(csv_path):
+    """Per-level VALU lane-instructions per sample from the counters of the
+    --valu-probe launches (persistent kernels only, in dispatch order): the
+    launch over levels 0..L minus the launch over levels 0..L-1, times 64
+    lanes, over the samples per level."""
+    import csv
+    by_dispatch = {}
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if "persistent_kernel" in r["Kernel_Name"] and r["Counter_Name"] == "SQ_INSTS_VALU":
+                by_dispatch[int(r["Dispatch_Id"])] = (r["Kernel_Name"], float(r["Counter_Value"]))
+    launches = [by_dispatch[k] for k in sorted(by_dispatch)]
+    rec = {"kernel_source_hash": kernel_source_hash(), "command": VALU_PROBE_COMMAND,
+           "unit": "VALU lane-instructions per sample of level l (SQ_INSTS_VALU x 64)",
+           "samples_per_level": VALU_PROBE_SAMPLES}
+    k = 0
+    for name, kernel in (("ap", "persistent_kernel<float, 1, false>"),
+                         ("kd", "persistent_kernel<double, 1, true>")):
+        prev, per = 0.0, []
+        for L in range(9):
+            kname, v = launches[k]
+            k += 1
+            assert kernel in kname, (kname, kernel)
+            per.append(round((v - prev) * 64.0 / VALU_PROBE_SAMPLES[name], 2))
+            prev = v
+        rec[name] = per
+        rec[name + "_kernel"] = kernel
+    with open(VALU_RECORD, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec))
 
 
 def main():
@@ -151,7 +232,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--serving-requests", type=int, default=2100,
+                    help="Poisson requests of the serving trace (the first "
+                         "--serving-warmup of them are left out of p50/p99)")
+    ap.add_argument("--serving-warmup", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=("ap", "kd"), default="ap",
@@ -164,7 +248,22 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the known-size "
                          "kernel that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only run, for each finest level L = 0..8 of the benchmarked "
+                         "splitting and KD workloads, one warm-up-only estimate over levels "
+                         "0..L with the same sample number everywhere (one persistent launch "
+                         "each): differences of SQ_INSTS_VALU between consecutive launches "
+                         "give the VALU instructions per sample of level L")
+    ap.add_argument("--valu-record", metavar="CSV",
+                    help="write profiles/valu_instructions_per_sample.json from the "
+                         "rocprofv3 counter CSV of a --valu-probe run (no GPU needed)")
     args = ap.parse_args()
+    if args.valu_record:
+        write_valu_record(args.valu_record)
+        return
+    if args.valu_probe:
+        valu_probe()
+        return
     if args.copy_probe:
         import torch
         n = args.copy_probe * 1024 * 1024 // 4
@@ -213,8 +312,10 @@ def main():
     elapsed = time.perf_counter() - t0
     if kd_mode:   # KD steps actually taken (fine + coarse)
         steps_total = sum(int(l["coll_f"]) + int(l["coll_c"]) for r in results for l in r["levels"])
+        fine_total = sum(int(l["coll_f"]) for r in results for l in r["levels"])
     else:
         steps_total = sum(r["particle_steps"] for r in results)
+        fine_total = sum(fine_steps(prob, r["N"]) for r in results)
     value = steps_total / elapsed
     ms_per = elapsed / args.steps * 1e3
     last = results[-1]
@@ -224,22 +325,22 @@ def main():
 
     # Dominant kernel: the persistent particle kernel (which also runs a
     # warm-up launch's few long trajectories time-parallel), launched directly
-    # so that HIP events on the launch stream time it.
+    # so that HIP events on the launch stream time it.  Work = the per-sample
+    # table times the samples of every level (the time-parallel schedule of a
+    # warm-up's long trajectories is counted as the same per-sample work).
     direct = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=2, **tk))
     kern_s = direct["kernel_seconds"]
     launches = direct["launches"]
-    if kd_mode:
-        # no algorithmic operation count for the FP64 library transcendentals
-        # of a KD step: its kernel is characterised by counters instead
-        roofline = None
-    else:
-        slots = algorithmic_slots(prob, direct["N"])
-        achieved = slots / kern_s
-        roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12,
-                        unit="TOP/s (full-rate VALU lane-slots)", frac=achieved / PEAK_SLOTS,
-                        traffic=recorded_traffic(tuning),
-                        kernel="persistent_kernel<float,%d,false>" % tuning["ppt"],
-                        avg_launch_ms=kern_s / launches * 1e3, launches=launches)
+    table, current = valu_per_sample("kd" if kd_mode else "ap")
+    work = algorithmic_lane_instructions(table, direct["N"])
+    achieved = work / kern_s
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_LANE_INSTR / 1e12,
+                    unit="T VALU lane-instructions/s", frac=achieved / PEAK_LANE_INSTR,
+                    traffic=recorded_traffic(tuning) if not kd_mode else None,
+                    kernel=("persistent_kernel<double,1,true>" if kd_mode else
+                            "persistent_kernel<float,%d,false>" % tuning["ppt"]),
+                    avg_launch_ms=kern_s / launches * 1e3, launches=launches,
+                    lane_instructions_per_estimate=work, per_unit_record_current=current)
     out = {
         "metric": "particle-steps/s; MLMC time-to-RMSE 1e-3 vs plain MC; p50/p99 request latency",
         "value": value,
@@ -261,6 +362,7 @@ def main():
                    "particle_steps_per_estimate": last["particle_steps"],
                    "N": last["N"], "tuning": tuning},
         "time_to_rmse_ms": ms_per,
+        "fine_steps_per_s": fine_total / elapsed,
         "estimate": last["estimate"],
         "estimate_exact": exact,
         "roofline": roofline,
@@ -353,12 +455,20 @@ def main():
             sstats = pkg.mlmc_ap_server_get_stats(srv)
         finally:
             pkg.mlmc_ap_server_destroy(srv)
-        lat_sorted = sorted(lat)
-        span = max(arr[-1], 1e-9)
-        out["serving"] = dict(requests=n, rate_per_s=200.0,
-                              p50_ms=lat_sorted[n // 2] * 1e3,
-                              p99_ms=lat_sorted[min(n - 1, int(0.99 * n))] * 1e3,
-                              particle_steps_per_s=sstats["particle_steps"] / (span + lat[-1]),
+        w = min(args.serving_warmup, n - 1)
+        lat_sorted = sorted(lat[w:])
+        m = len(lat_sorted)
+        # makespan: first arrival to the last completion (not the completion
+        # of the last-submitted request, which an earlier long one can outlast)
+        makespan = max(a + l for a, l in zip(arr, lat)) - arr[0]
+        out["serving"] = dict(requests=n, warmup_requests=w, measured_requests=m,
+                              rate_per_s=200.0,
+                              p50_ms=lat_sorted[m // 2] * 1e3,
+                              p99_ms=lat_sorted[min(m - 1, int(math.ceil(0.99 * m)) - 1)] * 1e3,
+                              max_ms=lat_sorted[-1] * 1e3,
+                              particle_steps=sstats["particle_steps"],
+                              makespan_s=makespan,
+                              particle_steps_per_s=sstats["particle_steps"] / makespan,
                               ticks=sstats["ticks"])
         log("serving", out["serving"])
 
@@ -374,6 +484,9 @@ def main():
         kd_ms = (time.perf_counter() - t0) / reps * 1e3
         kr = kres[-1]
         kd_steps = sum(int(l["coll_f"]) + int(l["coll_c"]) for l in kr["levels"])
+        ktable, kcur = valu_per_sample("kd")
+        kwork = algorithmic_lane_instructions(ktable, kr["N"])
+        kach = kwork / kr["kernel_seconds"]
         ksopt = pkg.options(batched=2, level_select=pkg.LEVELS_HEURISTIC, **tk)
         pkg.mlmc_ap_estimate(KP, tol, ksopt, stream=hs)
         torch.cuda.synchronize()
@@ -386,6 +499,11 @@ def main():
             workload="MLMC-KD eps=0.01 T=1 dt0=0.5 M=2 L=0..8 RMSE=1e-3 x0~N(0,1), "
                      "homogeneous background, FP64 state",
             time_to_rmse_ms=kd_ms, kernel_ms=kr["kernel_seconds"] * 1e3,
+            roofline=dict(bound="alu", achieved=kach / 1e12, peak=PEAK_LANE_INSTR / 1e12,
+                          unit="T VALU lane-instructions/s", frac=kach / PEAK_LANE_INSTR,
+                          kernel="persistent_kernel<double,1,true>",
+                          lane_instructions_per_estimate=kwork,
+                          per_unit_record_current=kcur),
             kd_steps=kd_steps, kd_steps_per_s=kd_steps / (kd_ms * 1e-3),
             N=kr["N"], estimate=kr["estimate"],
             estimate_exact=kd_exact_second_moment(kprob),

@@ -1,8 +1,9 @@
 // Continuous-batching server of MLMC requests and the launch-shape autotuner.
 //
 // Serving: every tick runs one top-up iteration (or warm-up) of every
-// admitted request in ONE persistent launch replayed from the server's
-// captured hipGraph.  Requests arriving while others are in flight are queued
+// admitted request: one persistent launch, issued directly, per particle
+// kernel in use (FP32 splitting, FP64 splitting, KD), so at most three
+// launches per tick.  Requests arriving while others are in flight are queued
 // and admitted at the next tick whose device-memory budget (per-request
 // resident statistics plus the tick's tile partials) has room.  A request's
 // sequence of sample ranges depends only on its own statistics and the

@@ -234,3 +234,49 @@ def test_bench_estimate_launch_forms_bitwise_equal():
     for r in runs[1:]:
         assert r["estimate"] == ref["estimate"] and r["N"] == ref["N"]
         assert r["levels"] == ref["levels"]
+
+
+def test_cfg1_full_size_fp64():
+    """The plain single-level scheme at its stated size (velocities +-1,
+    eps = 0.5, T = 0.5, dt = 0.01, N = 1e5, FP64 state): every trajectory
+    against the oracle (collision counts exact, positions within 1e-12 on
+    the R12 scale), and E[x^2] within 4 standard errors of the scheme's exact
+    second moment 0.5683899408."""
+    prob = W.cfg1()
+    n = W.CFG1_N
+    st, xf, xc, cf, cc = dump(prob, 0, 0, n)
+    ref = O.simulate(prob, 0, 0, n)
+    assert np.array_equal(cf, ref["cf"].astype(np.int64))
+    assert np.all(cc == 0) and np.all(xc == 0.0)
+    scale = np.maximum(np.abs(ref["xf"]), math.sqrt(np.mean(ref["xf"] ** 2)))
+    err = float(np.max(np.abs(xf - ref["xf"]) / scale))
+    q = ref["xf"] ** 2
+    sd = float(np.std(q)) / math.sqrt(n)
+    say("cfg1: N %d, E[x^2] gpu %.10f oracle %.10f exact 0.5683899408 sd %.2e, max traj err %.1e"
+        % (n, st["mean_dq"], q.mean(), sd, err))
+    assert err <= 1e-12
+    assert st["n"] == n and st["coll_f"] == int(ref["cf"].astype(np.uint64).sum())
+    assert abs(st["mean_dq"] - q.mean()) <= 1e-12
+    assert abs(st["mean_dq"] - 0.5683899408) <= 4.0 * sd
+
+
+def test_fp32_estimate_loop_against_oracle_loop():
+    """The FP32-state estimator's own sample-number loop against the oracle's
+    independent loop (``oracle.mlmc.estimate``, FP64) on the same problem.
+    Their level variances differ by the FP32 rounding of the positions (about
+    1e-6 relative), so eqs. Nopt1/Noptj give sample numbers that agree to
+    about that relative size, not exactly: every N_l within 1e-4 relative
+    (+2), the same number of top-up iterations, and estimates within 2e-5 of
+    E[Q_L] of each other."""
+    prob = W.cfg2(eps=0.05, stream_id=33)
+    L, tol = prob["L"], 5e-3
+    res = pkg.mlmc_ap_estimate(prob, tol, pkg.options(max_iter=8))
+    ref = OM.estimate(prob, tol, L, n_warmup=1000, max_iter=8)
+    exact = CF.level_second_moment(prob, L)
+    say("fp32 loop: gpu N %s it %d est %.8f; oracle N %s est %.8f; exact %.8f"
+        % (res["N"], res["iterations"], res["estimate"], ref["N"], ref["estimate"], exact))
+    for a, b in zip(res["N"], ref["N"]):
+        assert abs(a - b) <= 1e-4 * b + 2, (res["N"], ref["N"])
+    assert res["converged"]
+    assert abs(res["estimate"] - ref["estimate"]) <= 2e-5 * abs(exact)
+    assert abs(res["estimate"] - exact) <= 4.0 * math.sqrt(res["var_estimator"])
