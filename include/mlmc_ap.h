@@ -315,6 +315,28 @@ mlmc_ap_status mlmc_ap_simulate_pair(const mlmc_ap_problem* p, int32_t level, in
                                      mlmc_ap_level_stats* out_host, void* traj_dev,
                                      uint32_t* coll_dev, uint64_t* hist_host, void* stream);
 
+/* Allocation-free form of mlmc_ap_simulate_level, for callers that cannot
+ * allocate device memory: code being captured into a HIP graph, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, meaning, layout and
+ * results (bitwise) as mlmc_ap_simulate_level.  It calls no hipMalloc,
+ * hipHostMalloc or hipFree and creates no stream or event: its descriptor,
+ * tile and group records, reduction counter, statistics slot and histogram
+ * counters live in a device array of the library (MLMC_AP_NOALLOC_SCRATCH_BYTES,
+ * about 5 MiB, one copy on every GPU the library runs on, held until the
+ * process ends); the caller still passes the outputs (out_host, and the
+ * optional traj_dev, coll_dev, hist_host).  EINVAL if n_samples exceeds
+ * MLMC_AP_NOALLOC_MAX_SAMPLES.  Every call on a GPU uses that GPU's one array,
+ * which keeps the last call's contents: the library runs these calls one at a
+ * time (each returns after `stream` has finished its work), and kernels that
+ * other code enqueues on that array at the same time would race with it. */
+#define MLMC_AP_NOALLOC_MAX_SAMPLES 4194304ull   /* 2^22 samples per call */
+#define MLMC_AP_NOALLOC_SCRATCH_BYTES 5289216ull
+mlmc_ap_status mlmc_ap_simulate_level_noalloc(const mlmc_ap_problem* p, int32_t level,
+                                              int32_t single, uint64_t sample_begin,
+                                              uint64_t n_samples, mlmc_ap_level_stats* out_host,
+                                              void* traj_dev, uint32_t* coll_dev,
+                                              uint64_t* hist_host, void* stream);
+
 /* MLMC estimate of E[Q_L] to RMSE tolerance rmse_tol (Section 4.1): warm-up
  * samples on every level 0..L, then eqs. Nopt1/Noptj with sample variances
  * and the deterministic cost C_0 = n_0, C_l = n_l + n_{l-1} (particle steps

@@ -110,6 +110,9 @@ _SIGNATURES = {
                                ctypes.c_uint64, _P(LevelStats), _vp, _vp, _P(ctypes.c_uint64), _vp],
     "mlmc_ap_simulate_pair": [_P(Problem), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                               ctypes.c_uint64, _P(LevelStats), _vp, _vp, _P(ctypes.c_uint64), _vp],
+    "mlmc_ap_simulate_level_noalloc": [_P(Problem), ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_uint64, ctypes.c_uint64, _P(LevelStats), _vp, _vp,
+                                       _P(ctypes.c_uint64), _vp],
     "mlmc_ap_select_levels_heuristic": [_P(ctypes.c_double), _P(ctypes.c_double), ctypes.c_int32,
                                         _P(ctypes.c_uint64)],
     "mlmc_ap_select_levels_optimal": [_P(ctypes.c_double), _P(ctypes.c_double),
@@ -342,6 +345,28 @@ def mlmc_ap_simulate_level(p, level, sample_begin, n_samples, single=False, traj
                                         int(sample_begin), int(n_samples), ctypes.byref(out),
                                         tp, cp, hbuf, _stream(stream)),
            "mlmc_ap_simulate_level")
+    if hist:
+        return stats_dict(out), [int(x) for x in hbuf]
+    return stats_dict(out)
+
+
+NOALLOC_MAX_SAMPLES = 1 << 22
+
+
+def mlmc_ap_simulate_level_noalloc(p, level, sample_begin, n_samples, single=False, traj=None,
+                                   coll=None, hist=False, stream=None):
+    """As mlmc_ap_simulate_level, through the allocation-free entry point (the
+    library allocates nothing; at most NOALLOC_MAX_SAMPLES samples per call)."""
+    P = as_problem(p)
+    out = LevelStats()
+    hbuf = None
+    if hist:
+        hbuf = (ctypes.c_uint64 * (3 * P.nbins + 4))()
+    tp, cp = _dump_ptrs(P, n_samples, traj, coll)
+    _check(lib().mlmc_ap_simulate_level_noalloc(ctypes.byref(P), int(level), int(bool(single)),
+                                                int(sample_begin), int(n_samples),
+                                                ctypes.byref(out), tp, cp, hbuf, _stream(stream)),
+           "mlmc_ap_simulate_level_noalloc")
     if hist:
         return stats_dict(out), [int(x) for x in hbuf]
     return stats_dict(out)

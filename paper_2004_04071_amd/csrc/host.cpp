@@ -1008,7 +1008,10 @@ extern "C" {
 
 mlmc_ap_status mlmc_ap_init(void) {
   Workspace* ws = workspace();
-  return ws ? MLMC_AP_OK : MLMC_AP_EDEVICE;
+  if (!ws) return MLMC_AP_EDEVICE;
+  void* scratch = nullptr;  // the allocation-free entry point's array on this device
+  MLMC_HIP(scratch_address(&scratch));
+  return MLMC_AP_OK;
 }
 
 mlmc_ap_status mlmc_ap_release(void) {
@@ -1175,6 +1178,90 @@ mlmc_ap_status mlmc_ap_simulate_level(const mlmc_ap_problem* p, int32_t level, i
                                       uint32_t* coll_dev, uint64_t* hist_host, void* stream) {
   return simulate_common(p, level, single, -1, sample_begin, n_samples, out_host, traj_dev,
                          coll_dev, hist_host, stream);
+}
+
+// The allocation-free form of mlmc_ap_simulate_level: the same per-level
+// kernels, with every buffer they need (descriptor, tile and group records,
+// reduction counter, statistics slot, histogram counters) in the device
+// scratch array of kernels.hip instead of the library workspace.  No hipMalloc,
+// hipHostMalloc, stream or event is created: the descriptor travels as kernel
+// arguments and the results come back by asynchronous copies on `stream`.
+// The time-parallel path is not used (it would need per-sample staging);
+// results are bitwise those of mlmc_ap_simulate_level either way.
+static std::mutex g_scratch_call_mu;
+static_assert(kScratchMaxSamples == MLMC_AP_NOALLOC_MAX_SAMPLES, "header limit");
+static_assert(kScratchBytes == MLMC_AP_NOALLOC_SCRATCH_BYTES, "header size");
+static_assert(kScratchHistCounters == 3 * MLMC_AP_MAX_BINS + 4, "histogram counters");
+
+mlmc_ap_status mlmc_ap_simulate_level_noalloc(const mlmc_ap_problem* p, int32_t level,
+                                              int32_t single, uint64_t sample_begin,
+                                              uint64_t n_samples, mlmc_ap_level_stats* out_host,
+                                              void* traj_dev, uint32_t* coll_dev,
+                                              uint64_t* hist_host, void* stream) {
+  MLMC_TRY(validate_problem(p));
+  if (!out_host) return set_error(MLMC_AP_EINVAL, "out_host is NULL");
+  if (level < 0 || level > p->L) return set_error(MLMC_AP_EINVAL, "level must be in [0, L]");
+  if (single != 0 && single != 1) return set_error(MLMC_AP_EINVAL, "single must be 0 or 1");
+  if (sample_begin > 4294967296ull || n_samples > 4294967296ull - sample_begin)
+    return set_error(MLMC_AP_EINVAL, "sample_begin + n_samples must not exceed 2^32");
+  if (n_samples > kScratchMaxSamples)
+    return set_error(MLMC_AP_EINVAL, "n_samples exceeds MLMC_AP_NOALLOC_MAX_SAMPLES (2^22) of "
+                                     "the allocation-free entry point");
+  const bool hist = p->qoi == MLMC_AP_QOI_X2_HIST;
+  if (hist && !hist_host)
+    return set_error(MLMC_AP_EINVAL, "hist_host is required with QOI_X2_HIST");
+  const size_t hist_n = hist ? 3 * (size_t)p->nbins + 4 : 0;
+  std::memset(out_host, 0, sizeof(*out_host));
+  if (n_samples == 0) {
+    if (hist) std::memset(hist_host, 0, sizeof(uint64_t) * hist_n);
+    return MLMC_AP_OK;
+  }
+  void* base = nullptr;
+  MLMC_HIP(scratch_address(&base));
+  unsigned char* b = static_cast<unsigned char*>(base);
+  WorkHeader* hdr = reinterpret_cast<WorkHeader*>(b);
+  LevelDesc* item = reinterpret_cast<LevelDesc*>(b + 256);
+  unsigned int* item_done = reinterpret_cast<unsigned int*>(b + 512);
+  Stats* resident = reinterpret_cast<Stats*>(b + 768);
+  unsigned long long* hist_dev = reinterpret_cast<unsigned long long*>(b + kScratchHistOffset);
+  Stats* groups = reinterpret_cast<Stats*>(b + kScratchGroupsOffset);
+  Stats* partials = reinterpret_cast<Stats*>(b + kScratchTilesOffset);
+
+  ItemSpec it;
+  it.prob = p;
+  it.level = level;
+  it.single = single != 0;
+  it.coarse_level = -1;
+  it.sample_begin = sample_begin;
+  it.n_samples = n_samples;
+  it.result_slot = 0;
+  it.hist = hist ? hist_dev : nullptr;
+  it.traj = traj_dev;
+  it.coll = coll_dev;
+  it.accumulate = false;
+  const LevelDesc d = make_desc(it, false);  // tile_base = group_base = 0
+  if (d.n_tiles > kScratchMaxTiles || d.n_groups > kScratchMaxGroups)
+    return set_error(MLMC_AP_EINVAL, "work item does not fit the scratch array");
+  WorkHeader h;
+  h.n_items = 1;
+  h.total_chunks = d.n_chunks;
+  h.total_groups = d.n_groups;
+  h.total_tp = 0;
+  hipStream_t s = (hipStream_t)stream;
+  Stats host_stats;
+  // every call on a device shares its scratch array: one call at a time
+  std::lock_guard<std::mutex> lk(g_scratch_call_mu);
+  MLMC_HIP(launch_stage_args(h, d, hdr, item, item_done, hist_dev, (uint32_t)hist_n, s));
+  MLMC_HIP(launch_level(p->fp64_state != 0, 1, d.kind, item, 0, d.n_tiles, 256, partials, s));
+  MLMC_HIP(launch_reduce(item, hdr, partials, groups, item_done, resident, nullptr,
+                         (int)std::min<uint32_t>(d.n_groups, 1024u), s));
+  MLMC_HIP(hipMemcpyAsync(&host_stats, resident, sizeof(Stats), hipMemcpyDeviceToHost, s));
+  if (hist)
+    MLMC_HIP(hipMemcpyAsync(hist_host, hist_dev, sizeof(uint64_t) * hist_n,
+                            hipMemcpyDeviceToHost, s));
+  MLMC_HIP(hipStreamSynchronize(s));
+  *out_host = stats_to_api(host_stats);
+  return MLMC_AP_OK;
 }
 
 mlmc_ap_status mlmc_ap_simulate_pair(const mlmc_ap_problem* p, int32_t level, int32_t coarse_level,

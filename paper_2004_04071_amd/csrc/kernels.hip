@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "device.hpp"
 #include "kd.hpp"
 #include "kernels.hpp"
@@ -1038,6 +1040,22 @@ __global__ void stage_kernel(const WorkHeader* __restrict__ hdr_src,
   }
 }
 
+// First kernel of an allocation-free launch: the work header and the single
+// descriptor arrive as kernel arguments (no host-side table, no copy), and the
+// reduction's item counter and the histogram counters are cleared.
+__global__ void stage_args_kernel(WorkHeader h, LevelDesc d, WorkHeader* __restrict__ hdr_dst,
+                                  LevelDesc* __restrict__ item_dst,
+                                  unsigned int* __restrict__ item_done,
+                                  unsigned long long* __restrict__ hist, uint32_t hist_n) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    *hdr_dst = h;
+    *item_dst = d;
+    item_done[0] = 0u;
+  }
+  for (uint32_t i = t; i < hist_n; i += gridDim.x * blockDim.x) hist[i] = 0ull;
+}
+
 __global__ void fill_u32_kernel(unsigned int* p, uint64_t n, unsigned int v) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
@@ -1250,6 +1268,45 @@ hipError_t launch_normals(bool fp64, uint32_t key0, uint32_t key1, uint32_t strm
     hipLaunchKernelGGL(normals_kernel<float>, g, dim3(256), 0, s, key0, key1, strm, tag,
                        sample_begin, n_samples, n_steps, (float*)out);
   return hipGetLastError();
+}
+
+hipError_t launch_stage_args(const WorkHeader& h, const LevelDesc& d, WorkHeader* hdr_dst,
+                             LevelDesc* item_dst, unsigned int* item_done,
+                             unsigned long long* hist, uint32_t hist_n, hipStream_t s) {
+  hipLaunchKernelGGL(stage_args_kernel, dim3(hist_n > 256 ? 4 : 1), dim3(256), 0, s, h, d,
+                     hdr_dst, item_dst, item_done, hist, hist_n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch memory of the allocation-free entry point: a file-scope device
+// array, one copy on every GPU the library runs on, held until the process
+// ends.  Host code never passes `scratch` itself to a kernel (in host code the
+// name stands for a host-side shadow, not a device address): the device
+// address is looked up once per device, with that device current, and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchMaxDevices];
+}  // namespace
+
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace mlmc

@@ -47,6 +47,35 @@ hipError_t launch_tp(bool fp64, const LevelDesc* items_dev, const WorkHeader* hd
 hipError_t launch_stage(const WorkHeader* hdr_src, const LevelDesc* items_src, uint32_t cap,
                         WorkHeader* hdr_dst, LevelDesc* items_dst, unsigned int* counter,
                         unsigned int* item_done, hipStream_t s);
+// Allocation-free launch: header and one descriptor as kernel arguments into
+// device memory; clears item_done[0] and hist_n histogram counters.
+hipError_t launch_stage_args(const WorkHeader& h, const LevelDesc& d, WorkHeader* hdr_dst,
+                             LevelDesc* item_dst, unsigned int* item_done,
+                             unsigned long long* hist, uint32_t hist_n, hipStream_t s);
+
+// Scratch of the allocation-free entry point (a file-scope device array in
+// kernels.hip): kScratchMaxSamples samples per call at most, laid out as
+//   [0, 256)              WorkHeader
+//   [256, 512)            LevelDesc
+//   [512, 768)            item counter of the reduction
+//   [768, 1024)           resident Stats slot
+//   [1024, ...)           histogram counters, 3 MLMC_AP_MAX_BINS + 4 (uint64)
+//   kScratchGroupsOffset  Stats per reduction group
+//   kScratchTilesOffset   Stats per tile (a tile holds at least 64 samples)
+constexpr uint64_t kScratchMaxSamples = 1ull << 22;
+constexpr uint64_t kScratchMaxTiles = kScratchMaxSamples / 64;
+constexpr uint64_t kScratchMaxGroups = kScratchMaxTiles / 256;
+constexpr uint64_t kScratchHistCounters = 3 * 1024 + 4;
+constexpr uint64_t kScratchHistOffset = 1024;
+constexpr uint64_t kScratchGroupsOffset =
+    (kScratchHistOffset + kScratchHistCounters * 8 + 255) / 256 * 256;
+constexpr uint64_t kScratchTilesOffset =
+    (kScratchGroupsOffset + kScratchMaxGroups * sizeof(Stats) + 255) / 256 * 256;
+constexpr uint64_t kScratchBytes = kScratchTilesOffset + kScratchMaxTiles * sizeof(Stats);
+// Device address of the current device's scratch (looked up on the first call
+// on each device, then cached).
+hipError_t scratch_address(void** out);
+
 hipError_t launch_fill_u32(unsigned int* p, uint64_t n, unsigned int v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_words(uint32_t key0, uint32_t key1, uint32_t strm, uint32_t tag,

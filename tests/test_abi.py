@@ -251,3 +251,14 @@ def test_dump_buffers_must_be_contiguous_gpu_tensors(lib):
         pkg.mlmc_ap_philox_words(42, 0, 0, 0, 10, 20, _FakeDeviceTensor(799, "int32"))
     with pytest.raises(ValueError, match="dtype float64"):
         pkg.mlmc_ap_rng_normals(42, 0, 0, 0, 10, 20, 1, _FakeDeviceTensor(800, "float32"))
+
+
+def test_noalloc_entry_point_size_limit(lib):
+    """The allocation-free entry point refuses more samples than its scratch
+    array holds, before touching any device."""
+    P = pkg.problem(eps=0.3, T=1.0, dt0=0.5, L=3)
+    out = pkg.LevelStats()
+    st = lib.mlmc_ap_simulate_level_noalloc(pkg.ctypes.byref(P), 1, 0, 0,
+                                            pkg.NOALLOC_MAX_SAMPLES + 1,
+                                            pkg.ctypes.byref(out), None, None, None, None)
+    assert st == -1 and "NOALLOC_MAX_SAMPLES" in pkg.mlmc_ap_last_error()
