@@ -27,6 +27,8 @@ _LIB_PATH = os.environ.get("ORACLE_LIB_PATH", os.path.join(_HERE, "liboracle.so"
 _lib = None
 
 X0_DELTA, X0_NORMAL, X0_COSINE = 0, 1, 2
+BG_DIFFUSIVE, BG_B1, BG_B2 = 0, 1, 2
+QOI_X2, QOI_X2_HIST, QOI_X = 0, 1, 2
 EQ_TWO_POINT, EQ_MAXWELLIAN = 0, 1
 COUPLING_KICK_SUM, COUPLING_AGGREGATE = 0, 1
 SCHEME_SPLITTING, SCHEME_KD = 0, 1
@@ -86,6 +88,23 @@ def lib():
             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
             ctypes.c_uint32, ctypes.c_uint64, dp, ctypes.c_uint64, dp, ctypes.c_uint64, u64p, dp]
         L.oracle_kd_phases.restype = ctypes.c_uint64
+        L.oracle_simulate_kd_bg.argtypes = [
+            ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+            ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+            ctypes.c_uint64, u64p, ctypes.c_uint64, dp, dp, u32p, u32p, ctypes.c_int]
+        L.oracle_simulate_kd_bg.restype = ctypes.c_int
+        L.oracle_kd_bg_phases.argtypes = [
+            ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+            ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, dp,
+            ctypes.c_uint64, dp, ctypes.c_uint64, u64p, dp]
+        L.oracle_kd_bg_phases.restype = ctypes.c_uint64
+        for name in ("oracle_bg_rate", "oracle_bg_rate_integral", "oracle_bg_flight"):
+            getattr(L, name).restype = ctypes.c_double
+        L.oracle_bg_rate.argtypes = [ctypes.c_int] + [ctypes.c_double] * 3
+        L.oracle_bg_rate_integral.argtypes = [ctypes.c_int] + [ctypes.c_double] * 5
+        L.oracle_bg_flight.argtypes = [ctypes.c_int] + [ctypes.c_double] * 5
         _lib = L
     return _lib
 
@@ -153,6 +172,9 @@ def simulate(prob, level, sample_begin=0, n=None, samples=None, single=False, th
     kd = int(prob.get("scheme", SCHEME_SPLITTING)) == SCHEME_KD
     if kd and int(prob["eq_kind"]) != EQ_MAXWELLIAN:
         raise ValueError("the KD scheme needs the Maxwellian equilibrium")
+    if kd and int(prob.get("background", BG_DIFFUSIVE)) != BG_DIFFUSIVE:
+        return simulate_kd_bg(prob, level, sample_begin, n, samples, single, threads,
+                              coarse_level)
     if samples is not None:
         idx = np.ascontiguousarray(samples, dtype=np.uint64)
         count = idx.size
@@ -259,3 +281,70 @@ def kd_phases(prob, level, sample, coarse_level=None):
         _ptr(phases, ctypes.c_double), cap, _ptr(rows, ctypes.c_double), cap,
         _ptr(nc, ctypes.c_uint64), _ptr(fin, ctypes.c_double))
     return phases[:used], rows[:int(nc[0])], fin
+
+
+def simulate_kd_bg(prob, level, sample_begin=0, n=None, samples=None, single=False, threads=None,
+                   coarse_level=None, general=False, pair_tag=False):
+    """KD paths or pairs in a background of Section 5 (prob["background"] =
+    BG_B1 or BG_B2, parameters prob["bg_a"], prob["bg_b"]; Maxwellian with mu
+    = 0, sigma = 1; eps is not used).  general=True takes the background path
+    also at a = 0 (which otherwise runs the homogeneous path with R = b);
+    pair_tag=True runs single paths under the counter tag of the level's
+    pairs (the random numbers of the pairs' fine paths)."""
+    if samples is not None:
+        idx = np.ascontiguousarray(samples, dtype=np.uint64)
+        count = idx.size
+        idx_p = _ptr(idx, ctypes.c_uint64)
+    else:
+        count = int(n)
+        idx_p = None
+    xf = np.zeros(count)
+    xc = np.zeros(count)
+    cf = np.zeros(count, dtype=np.uint32)
+    cc = np.zeros(count, dtype=np.uint32)
+    if count:
+        st = lib().oracle_simulate_kd_bg(
+            float(prob["T"]), float(prob["dt0"]), int(prob["M"]), int(level),
+            -1 if coarse_level is None else int(coarse_level),
+            2 if (single and pair_tag) else int(bool(single)),
+            int(prob["x0_kind"]), float(prob.get("x0_a", 0.0)), float(prob.get("x0_b", 0.0)),
+            int(prob["background"]), float(prob["bg_a"]), float(prob["bg_b"]), int(bool(general)),
+            int(prob.get("seed", 42)), int(prob.get("stream_id", 0)), int(sample_begin), idx_p,
+            count, _ptr(xf, ctypes.c_double), _ptr(xc, ctypes.c_double),
+            _ptr(cf, ctypes.c_uint32), _ptr(cc, ctypes.c_uint32), int(threads or default_threads()))
+        if st != 0:
+            raise ValueError("bad background or coarse level")
+    return dict(xf=xf, xc=xc, cf=cf, cc=cc)
+
+
+def kd_bg_phases(prob, level, sample, coarse_level=None):
+    """As kd_phases for a pair in a background (phase column 15 = the phase's
+    collision rate R_m)."""
+    cap = 2 * int(round(prob["T"] / prob["dt0"])) * int(prob["M"]) ** level + 4
+    phases = np.zeros((cap, 16))
+    rows = np.zeros((cap, 4))
+    fin = np.zeros(2)
+    nc = np.zeros(1, dtype=np.uint64)
+    used = lib().oracle_kd_bg_phases(
+        float(prob["T"]), float(prob["dt0"]), int(prob["M"]), int(level),
+        int(level - 1 if coarse_level is None else coarse_level), int(prob["x0_kind"]),
+        float(prob.get("x0_a", 0.0)), float(prob.get("x0_b", 0.0)), int(prob["background"]),
+        float(prob["bg_a"]), float(prob["bg_b"]), int(prob.get("seed", 42)),
+        int(prob.get("stream_id", 0)), int(sample), _ptr(phases, ctypes.c_double), cap,
+        _ptr(rows, ctypes.c_double), cap, _ptr(nc, ctypes.c_uint64), _ptr(fin, ctypes.c_double))
+    return phases[:used], rows[:int(nc[0])], fin
+
+
+def bg_rate(kind, a, b, x):
+    return lib().oracle_bg_rate(int(kind), float(a), float(b), float(x))
+
+
+def bg_rate_integral(kind, a, b, x, v, t):
+    """int_0^t R(x + v s) ds of a background."""
+    return lib().oracle_bg_rate_integral(int(kind), float(a), float(b), float(x), float(v),
+                                         float(t))
+
+
+def bg_flight(kind, a, b, x, v, E):
+    """Flight time of eq. intinv in a background."""
+    return lib().oracle_bg_flight(int(kind), float(a), float(b), float(x), float(v), float(E))

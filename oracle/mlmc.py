@@ -29,11 +29,18 @@ def level_cost(prob, level):
     return n if level == 0 else n + level_steps(prob, level - 1)
 
 
-def stats_of(xf, xc, level):
-    """Two-pass statistics of dQ = x_f^2 - x_c^2 (dQ = x_f^2 at level 0), of
-    Q_f, Q_c and of their co-moment."""
-    qf = xf * xf
-    qc = xc * xc if level > 0 else np.zeros_like(xf)
+QOI_X = 2   # Q = x(T), the position itself (the paper's Section 5); else Q = x(T)^2
+
+
+def stats_of(xf, xc, level, qoi=0):
+    """Two-pass statistics of dQ = Q_f - Q_c (dQ = Q_f at level 0), of Q_f,
+    Q_c and of their co-moment; Q = x^2, or Q = x with qoi = QOI_X."""
+    if qoi == QOI_X:
+        qf = np.array(xf, dtype=np.float64)
+        qc = np.array(xc, dtype=np.float64) if level > 0 else np.zeros_like(qf)
+    else:
+        qf = xf * xf
+        qc = xc * xc if level > 0 else np.zeros_like(xf)
     dq = qf - qc
     n = dq.size
     out = dict(n=n)
@@ -67,7 +74,7 @@ def estimate_fixed(prob, N, threads=None):
     levels = []
     for l, n in enumerate(N):
         r = simulate(prob, l, 0, int(n), threads=threads)
-        st = stats_of(r["xf"], r["xc"], l)
+        st = stats_of(r["xf"], r["xc"], l, prob.get("qoi", 0))
         st["coll_f"] = int(r["cf"].astype(np.uint64).sum())
         st["coll_c"] = int(r["cc"].astype(np.uint64).sum())
         levels.append(st)
@@ -93,16 +100,16 @@ def estimate(prob, tol, L, n_warmup=1000, max_iter=8, threads=None):
     for l in range(L + 1):
         run(l, n_warmup)
     for _ in range(max_iter):
-        st = [stats_of(xs[l][0], xs[l][1], l) for l in range(L + 1)]
+        st = [stats_of(xs[l][0], xs[l][1], l, prob.get("qoi", 0)) for l in range(L + 1)]
         V = [sample_variance(s) for s in st]
         N = optimal_samples(V, C, tol)
         for l in range(L + 1):
             run(l, max(N[l], done[l]))
-        st = [stats_of(xs[l][0], xs[l][1], l) for l in range(L + 1)]
+        st = [stats_of(xs[l][0], xs[l][1], l, prob.get("qoi", 0)) for l in range(L + 1)]
         V = [sample_variance(s) for s in st]
         if sum(v / d for v, d in zip(V, done)) <= 0.5 * tol * tol:
             break
-    st = [stats_of(xs[l][0], xs[l][1], l) for l in range(L + 1)]
+    st = [stats_of(xs[l][0], xs[l][1], l, prob.get("qoi", 0)) for l in range(L + 1)]
     return dict(estimate=sum(s["mean_dq"] for s in st), N=list(done), levels=st,
                 var_estimator=sum(sample_variance(s) / d for s, d in zip(st, done)))
 
@@ -127,7 +134,7 @@ def estimate_sequence(prob, tol0, R, L, n_warmup=1000, max_iter=10, threads=None
         done[l] = upto
 
     def state(tol):
-        st = [stats_of(xs[l][0], xs[l][1], l) for l in range(L + 1)]
+        st = [stats_of(xs[l][0], xs[l][1], l, prob.get("qoi", 0)) for l in range(L + 1)]
         var = sum(sample_variance(s) / d for s, d in zip(st, done))
         return dict(estimate=sum(s["mean_dq"] for s in st), N=list(done), levels=st,
                     var_estimator=var, converged=var <= 0.5 * tol * tol, tol=tol)

@@ -217,6 +217,10 @@ typedef struct {
     int eq_kind, coupling;
     uint32_t key[2];
     uint32_t stream;
+    /* KD scheme in a homogeneous background: collision rate and Maxwellian
+     * standard deviation (the diffusive scaling: 1/eps^2 and 1/eps) */
+    double R, sigma;
+    int pair_tag;        /* single paths under the pair's counter tag (tests) */
 } problem_t;
 
 /* Optional per-step record for tiny golden traces. */
@@ -347,6 +351,9 @@ static problem_t make_problem(double eps, double T, double dt0, int M, int level
     P.key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
     P.key[1] = (uint32_t)(seed >> 32);
     P.stream = stream;
+    P.R = eps > 0.0 ? 1.0 / (eps * eps) : 0.0;
+    P.sigma = eps > 0.0 ? 1.0 / eps : 0.0;
+    P.pair_tag = 0;
     return P;
 }
 
@@ -560,9 +567,9 @@ static void simulate_kd_one(const problem_t *P, uint64_t sample,
     const int coarse = (!P->single && l >= 1);
     const uint32_t tag = (uint32_t)l + (P->single ? 64u : 0u);
     const uint32_t smp = (uint32_t)sample;
-    const double R = 1.0 / (P->eps * P->eps);     /* collision rate */
+    const double R = P->R;                        /* collision rate */
     const double mu = 0.0;                        /* Maxwellian mean */
-    const double sigma = 1.0 / P->eps;            /* Maxwellian standard deviation */
+    const double sigma = P->sigma;                /* Maxwellian standard deviation */
     const double T = P->T;
     const double dtf = P->dt0 / pow((double)P->M, (double)l);
     const double dtc = coarse ? P->dt0 / pow((double)P->M, (double)P->coarse_level) : 0.0;
@@ -769,4 +776,330 @@ int oracle_simulate_pair(int kd, double eps, double T, double dt0, int M, int le
         else simulate_one(&P, s, &xf[i], &xc[i], &cf[i], &cc[i], NULL);
     }
     return 0;
+}
+
+
+/* ================================================================== */
+/* Kinetic-diffusion scheme in the backgrounds of Section 5            */
+/* ================================================================== */
+/*
+ * The test case of the paper's Section 5: post-collision Maxwellian with
+ * mu = 0 and sigma = 1, and a collision rate that is piecewise linear with a
+ * kink at x = 1,
+ *   B1 (symmetric):  R(x) = b (a |x - 1| + 1),
+ *   B2 (asymmetric): R(x) = b for x <= 1, b (a (x - 1) + 1) for x > 1,
+ * (a = 0: the homogeneous case R = b).
+ *
+ * Flight (eq. intinv): the flight time tau of a particle at x with velocity
+ * v and exponential number E solves  int_0^tau R(x + v s) ds = E.  The
+ * integral is exact by the trapezoid rule on each linear piece of R along the
+ * flight; the root is found by bisection (R >= b, so tau <= E/b).
+ *
+ * Diffusive phase: eqs. advection and diffusion with the collision rate taken
+ * where the phase starts, at the collision point.  READING: the corrected
+ * coefficients a^hetero, d^hetero that the paper uses are not given in it
+ * (they differ by evaluating the Maxwellian at a midpoint, which changes
+ * nothing here since mu and sigma are constant, and by an extra advection
+ * term for a strongly varying R); the local-rate form is exact for a = 0 and
+ * tends to the kinetic process as dt -> 0.
+ *
+ * Correlated pair (Algorithm "Correlated KD algorithm", literally): the fine
+ * path steps until its pending collision lies in a fine step that ends after
+ * the coarse step holding the coarse collision (at least one fine step per
+ * coarse step); the coarse step then takes nu~ of the pending fine flight
+ * kappa (eq. nu-update), chi~ from eq. chi-update with the weights of
+ * Section 3.2 (rate of each phase = its local rate), and for its next flight
+ * E~ = E_kappa - int_0^{t_c - t_kappa} R(x_kappa + v_kappa s) ds (eq.
+ * epsilon-update, the part of the fine flight before the coarse time), from
+ * which it solves eq. intinv from its own position.  Fine KD steps taken
+ * from a state whose pending collision is at or after T are used for the
+ * aggregation only: the fine path ends at the first such state and flies
+ * kinetically to T ("remove fine steps beyond T").
+ *
+ * Random numbers: as for the homogeneous KD scheme (block 0 initial
+ * condition, block k+1 KD step k).
+ *
+ * PARITY: pinned by the CPU tests (flight times against a brute-force
+ * thinning simulation of the inhomogeneous Poisson process of collisions;
+ * a = 0 against the homogeneous KD path; E[x(T)] = 1 in the symmetric
+ * background; the coarse path against the level below; the kinetic limit
+ * against a brute-force velocity-jump simulation in the background).
+ */
+enum { BG_DIFFUSIVE = 0, BG_B1 = 1, BG_B2 = 2 };
+
+typedef struct {
+    int kind;
+    double a, b;
+} bg_t;
+
+/* R(x) of a background */
+static double bg_rate(const bg_t *g, double x)
+{
+    double u = x - 1.0;
+    if (g->kind == BG_B1) return g->b * (g->a * fabs(u) + 1.0);
+    if (u <= 0.0) return g->b;
+    return g->b * (g->a * u + 1.0);
+}
+
+/* int_0^t R(x + v s) ds for t >= 0 (trapezoid rule on each linear piece of R
+ * along the straight flight, exact); for t < 0 the integral over [t, 0],
+ * negated. */
+static double bg_rate_integral(const bg_t *g, double x, double v, double t)
+{
+    if (t < 0.0) return -bg_rate_integral(g, x + v * t, v, -t);
+    if (t == 0.0) return 0.0;
+    double xe = x + v * t;
+    if ((x - 1.0) * (xe - 1.0) < 0.0) {            /* crosses the kink */
+        double tk = (1.0 - x) / v;
+        return 0.5 * tk * (bg_rate(g, x) + bg_rate(g, 1.0)) +
+               0.5 * (t - tk) * (bg_rate(g, 1.0) + bg_rate(g, xe));
+    }
+    return 0.5 * t * (bg_rate(g, x) + bg_rate(g, xe));
+}
+
+/* Flight time of eq. intinv by bisection. */
+static double bg_flight(const bg_t *g, double x, double v, double E)
+{
+    double lo = 0.0, hi = E / g->b;
+    if (!(E > 0.0)) return 0.0;
+    for (int it = 0; it < 400; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (bg_rate_integral(g, x, v, mid) < E) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+double oracle_bg_rate(int kind, double a, double b, double x)
+{
+    bg_t g = {kind, a, b};
+    return bg_rate(&g, x);
+}
+
+double oracle_bg_rate_integral(int kind, double a, double b, double x, double v, double t)
+{
+    bg_t g = {kind, a, b};
+    return bg_rate_integral(&g, x, v, t);
+}
+
+double oracle_bg_flight(int kind, double a, double b, double x, double v, double E)
+{
+    bg_t g = {kind, a, b};
+    return bg_flight(&g, x, v, E);
+}
+
+/* One path or one correlated pair in a background; the coarse numbers (and
+ * fine phases) are recorded as for the homogeneous pair. */
+static void simulate_kd_bg_one(const problem_t *P, const bg_t *g, uint64_t sample,
+                               double *xf_out, double *xc_out,
+                               uint32_t *cf_out, uint32_t *cc_out, kd_trace_t *tr)
+{
+    const int l = P->level;
+    const int coarse = (!P->single && l >= 1);
+    const uint32_t tag = (uint32_t)l + ((P->single && !P->pair_tag) ? 64u : 0u);
+    const uint32_t smp = (uint32_t)sample;
+    const double mu = 0.0, sigma = 1.0;
+    const double T = P->T;
+    const double dtf = P->dt0 / pow((double)P->M, (double)l);
+    const double dtc = coarse ? P->dt0 / pow((double)P->M, (double)P->coarse_level) : 0.0;
+    const double Mb = coarse ? (double)llround(pow((double)P->M, (double)(l - P->coarse_level))) : 1.0;
+    /* a fine KD step advances at least one fine grid step; beyond T the
+     * fine path takes at most one step per coarse step */
+    const uint64_t guard = 2u * (uint64_t)llround(T / dtf) + 4u;
+
+    uint32_t w[4];
+    kd_block(P, smp, tag, 0, w);
+    double nc, ns;
+    box_muller(w[0], w[1], &nc, &ns);
+    double x0;
+    if (P->x0_kind == X0_DELTA) x0 = P->x0_a;
+    else if (P->x0_kind == X0_NORMAL) x0 = P->x0_a + nc * P->x0_b;
+    else x0 = oracle_cosine_icdf(oracle_uniform(w[3]));
+    double nu = ns;
+    double E = -log(oracle_uniform(w[2]));
+
+    /* fine path: position, velocity, grid time, flight, its exponential
+     * number and pending collision */
+    double xf = x0, vf = mu + sigma * nu, tf = 0.0;
+    double Ef = E, tauf = bg_flight(g, xf, vf, Ef);
+    double cfine = tf + tauf;
+    uint32_t cf = 0, cc = 0, b = 1;
+    uint64_t steps = 0;
+
+    if (!coarse) {
+        while (cfine < T && steps < guard) {
+            double nu_next, chi, E_next;
+            kd_block(P, smp, tag, b++, w);
+            kd_draws(w, &nu_next, &chi, &E_next);
+            double t_next = (kd_step_of(cfine, dtf) + 1.0) * dtf;
+            double theta = t_next - cfine;                  /* eq. diffusive-time */
+            double v_next = mu + sigma * nu_next;
+            double Rloc = bg_rate(g, xf + vf * tauf);       /* rate at the collision */
+            double ad[2];
+            oracle_kd_coeffs(theta, Rloc, mu, sigma, v_next, ad);
+            xf = xf + vf * tauf + (ad[0] + ad[1] * chi);    /* eq. position-update */
+            tf = t_next;
+            vf = v_next;
+            Ef = E_next;
+            tauf = bg_flight(g, xf, vf, Ef);
+            cfine = tf + tauf;
+            cf++;
+            steps++;
+        }
+        if (tf < T) xf = xf + vf * (T - tf);
+        *xf_out = xf; *xc_out = 0.0; *cf_out = cf; *cc_out = 0;
+        return;
+    }
+
+    double xc = x0, vc = vf, tc = 0.0, tauc = tauf, ccoarse = tc + tauc;
+    double nu_f = nu;
+    int fine_done = 0;                 /* the fine path has ended */
+    double xf_end = 0.0;
+    uint64_t phases = 0;
+    while ((ccoarse < T || cfine < T) && steps < guard) {
+        const double end_c = kd_step_of(ccoarse, dtc) + 1.0;
+        const double end_c_fine = end_c * Mb;
+        double num = 0.0, den = 0.0, zeta_prev = 0.0;
+        int first = 1;
+        uint32_t used = 0;
+        do {
+            if (cfine >= T && !fine_done) {
+                /* the first fine state whose pending collision is at or
+                 * after T: the fine path flies from here to T */
+                xf_end = tf < T ? xf + vf * (T - tf) : xf;
+                fine_done = 1;
+            }
+            double nu_next, chi, E_next;
+            kd_block(P, smp, tag, b++, w);
+            kd_draws(w, &nu_next, &chi, &E_next);
+            double t_next = (kd_step_of(cfine, dtf) + 1.0) * dtf;
+            double theta = t_next - cfine;
+            double v_next = mu + sigma * nu_next;
+            double Rm = bg_rate(g, xf + vf * tauf);
+            double ad[2];
+            oracle_kd_coeffs(theta, Rm, mu, sigma, v_next, ad);
+            xf = xf + vf * tauf + (ad[0] + ad[1] * chi);
+
+            /* aggregation weights of phase m with its rate R_m (Section 3.2) */
+            double y = Rm * theta;
+            double zeta = -expm1(-y) / Rm;
+            double theta_p = kd_h(y) / Rm;
+            double beta = sqrt(2.0 * sigma * sigma / (Rm * Rm) * kd_h(Rm * theta_p));
+            double alpha = 0.0;
+            if (!first) {
+                alpha = (tauf + zeta_prev) * sigma;
+                num += alpha * nu_f;
+                den += alpha * alpha;
+            }
+            num += beta * chi;
+            den += beta * beta;
+            if (tr && tr->phases && tr->phase_used < tr->phase_cap) {
+                double *r = tr->phases + 16 * tr->phase_used++;
+                r[0] = (double)cc; r[1] = (double)first; r[2] = tf; r[3] = tauf;
+                r[4] = theta; r[5] = zeta; r[6] = theta_p;
+                r[7] = first ? 0.0 : tauf + zeta_prev; r[8] = alpha; r[9] = beta;
+                r[10] = nu_f; r[11] = chi; r[12] = ad[0]; r[13] = ad[1];
+                r[14] = nu_next; r[15] = Rm;
+            }
+            zeta_prev = zeta;
+            first = 0;
+            used++;
+            phases++;
+
+            if (!fine_done) cf++;
+            tf = t_next;
+            vf = v_next;
+            nu_f = nu_next;
+            Ef = E_next;
+            tauf = bg_flight(g, xf, vf, Ef);
+            cfine = tf + tauf;
+            steps++;
+        } while (!(kd_step_of(cfine, dtf) + 1.0 > end_c_fine) && steps < guard);
+
+        if (ccoarse < T) {
+            double nu_c = nu_f;                               /* eq. nu-update */
+            double chi_c = den > 0.0 ? num / sqrt(den) : 0.0; /* eq. chi-update */
+            double t_next = end_c * dtc;
+            double theta = t_next - ccoarse;
+            double v_next = mu + sigma * nu_c;
+            double Rc = bg_rate(g, xc + vc * tauc);
+            double ad[2];
+            oracle_kd_coeffs(theta, Rc, mu, sigma, v_next, ad);
+            xc = xc + vc * tauc + (ad[0] + ad[1] * chi_c);
+            tc = t_next;
+            vc = v_next;
+            /* eq. epsilon-update: the part of the pending fine flight before
+             * the coarse time is used up */
+            double E_c = Ef - bg_rate_integral(g, xf, vf, tc - tf);
+            if (E_c < 0.0) E_c = 0.0;
+            tauc = bg_flight(g, xc, vc, E_c);
+            ccoarse = tc + tauc;
+            cc++;
+            if (tr && tr->rows && tr->used < tr->cap) {
+                double *r = tr->rows + 4 * tr->used++;
+                r[0] = chi_c; r[1] = nu_c; r[2] = E_c; r[3] = (double)used;
+            }
+        }
+    }
+    (void)phases;
+    if (!fine_done) xf_end = tf < T ? xf + vf * (T - tf) : xf;
+    if (tc < T) xc = xc + vc * (T - tc);
+    *xf_out = xf_end; *xc_out = xc; *cf_out = cf; *cc_out = cc;
+}
+
+/* Paths or pairs (coarse_level < 0: level - 1) in a background; kind
+ * BG_B1/BG_B2 with parameters a, b.  general = 0 routes a = 0 to the
+ * homogeneous KD path with R = b, sigma = 1; general = 1 always takes the
+ * background path (to compare the two). */
+int oracle_simulate_kd_bg(double T, double dt0, int M, int level, int coarse_level, int single,
+                          int x0_kind, double x0_a, double x0_b, int bg_kind, double bg_a,
+                          double bg_b, int general, uint64_t seed, uint32_t stream,
+                          uint64_t sample_begin, const uint64_t *idx, uint64_t n,
+                          double *xf, double *xc, uint32_t *cf, uint32_t *cc, int nthreads)
+{
+    if (bg_kind != BG_B1 && bg_kind != BG_B2) return -1;
+    if (!(bg_b > 0.0) || !(bg_a >= 0.0)) return -1;
+    /* single = 2: single paths under the counter tag of the level's pairs */
+    problem_t P = make_problem(1.0, T, dt0, M, level, single != 0, x0_kind, x0_a, x0_b,
+                               EQ_MAXWELLIAN, 0, seed, stream);
+    P.pair_tag = single == 2;
+    if (!single && level >= 1) {
+        if (coarse_level < 0) coarse_level = level - 1;
+        if (coarse_level >= level) return -1;
+        P.coarse_level = coarse_level;
+    }
+    P.R = bg_b;
+    P.sigma = 1.0;
+    bg_t g = {bg_kind, bg_a, bg_b};
+    const int homogeneous = bg_a == 0.0 && !general;
+    (void)nthreads;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+        uint64_t s = idx ? idx[i] : sample_begin + (uint64_t)i;
+        if (homogeneous) simulate_kd_one(&P, s, &xf[i], &xc[i], &cf[i], &cc[i], NULL);
+        else simulate_kd_bg_one(&P, &g, s, &xf[i], &xc[i], &cf[i], &cc[i], NULL);
+    }
+    return 0;
+}
+
+/* Coarse numbers and fine phases of one pair in a background (as
+ * oracle_kd_phases; phase column 15 holds the phase's rate R_m). */
+uint64_t oracle_kd_bg_phases(double T, double dt0, int M, int level, int coarse_level,
+                             int x0_kind, double x0_a, double x0_b, int bg_kind, double bg_a,
+                             double bg_b, uint64_t seed, uint32_t stream, uint64_t sample,
+                             double *phases, uint64_t phase_cap, double *rows, uint64_t cap,
+                             uint64_t *n_coarse_out, double out_final[2])
+{
+    problem_t P = make_problem(1.0, T, dt0, M, level, 0, x0_kind, x0_a, x0_b,
+                               EQ_MAXWELLIAN, 0, seed, stream);
+    if (coarse_level >= 0 && coarse_level < level) P.coarse_level = coarse_level;
+    P.R = bg_b;
+    P.sigma = 1.0;
+    bg_t g = {bg_kind, bg_a, bg_b};
+    kd_trace_t tr = {rows, cap, 0, phases, phase_cap, 0};
+    double xf, xc; uint32_t cf, cc;
+    simulate_kd_bg_one(&P, &g, sample, &xf, &xc, &cf, &cc, &tr);
+    out_final[0] = xf; out_final[1] = xc;
+    *n_coarse_out = tr.used;
+    return tr.phase_used;
 }

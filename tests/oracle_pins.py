@@ -612,7 +612,7 @@ ALL_PINS = [pin_philox_kat, pin_word_layout, pin_uniform, pin_normals, pin_secon
 def run_all(stop_at_first=False, pins=None):
     """Runs every pin (or those given), returns the names of the failing ones."""
     failed = []
-    for f in (ALL_PINS + KD_PINS if pins is None else pins):
+    for f in (ALL_PINS + KD_PINS + BG_PINS if pins is None else pins):
         try:
             f()
         except Exception as e:       # a mutant may also crash or produce NaN
@@ -622,8 +622,228 @@ def run_all(stop_at_first=False, pins=None):
     return failed
 
 
+# --------------------------------------------------------------------------
+# KD scheme in the backgrounds of Section 5 (piecewise-linear collision rate)
+# --------------------------------------------------------------------------
+def bg_problem(kind, a, b, T=1.0, dt0=1.0, M=2, seed=42, stream=0, x0_kind=0):
+    """x(0) = 1, Maxwellian mu = 0, sigma = 1, dt_l = dt0 / M^l (Section 5)."""
+    return dict(eps=1.0, T=T, dt0=dt0, M=M, x0_kind=x0_kind, x0_a=1.0, x0_b=0.0, eq_kind=1,
+                coupling=1, seed=seed, stream_id=stream, scheme=O.SCHEME_KD,
+                background=kind, bg_a=a, bg_b=b)
+
+
+def paper_rate(kind, a, b, x):
+    """The collision rates R_1 and R_2 as Section 5 defines them."""
+    x = np.asarray(x, dtype=np.float64)
+    if kind == O.BG_B1:
+        return np.where(x <= 1.0, -b * (a * (x - 1.0) - 1.0), b * (a * (x - 1.0) + 1.0))
+    return np.where(x <= 1.0, b, b * (a * (x - 1.0) + 1.0))
+
+
+def _thinning_flights(kind, a, b, x, v, n, rng, horizon):
+    """First event times of the Poisson process of rate R(x + v t), by
+    thinning with the bound of R over the flight's reach in [0, horizon]."""
+    ends = x + v * np.array([0.0, horizon])
+    rmax = float(np.max(paper_rate(kind, a, b, np.append(ends, 1.0))))
+    t = np.zeros(n)
+    out = np.full(n, np.inf)
+    live = np.ones(n, dtype=bool)
+    while live.any():
+        idx = np.nonzero(live)[0]
+        t[idx] += rng.exponential(1.0 / rmax, size=idx.size)
+        over = t[idx] > horizon
+        live[idx[over]] = False
+        idx = idx[~over]
+        acc = rng.uniform(size=idx.size) * rmax < paper_rate(kind, a, b, x + v * t[idx])
+        out[idx[acc]] = t[idx[acc]]
+        live[idx[acc]] = False
+    return out
+
+
+def pin_bg_flight_law():
+    """eq. intinv: flight times from exponential numbers have the law of the
+    first collision of the inhomogeneous Poisson process of rate R(x + v t),
+    checked against a brute-force thinning simulation (flights that cross the
+    kink at x = 1 in both directions, toward and away from higher rates)."""
+    rng = np.random.default_rng(21)
+    cases = [(O.BG_B1, 10.0, 1.0, 0.5, 1.3), (O.BG_B1, 10.0, 1.0, 1.4, -2.0),
+             (O.BG_B2, 20.0, 2.0, 0.8, 0.9), (O.BG_B2, 5.0, 1.0, 1.5, -1.1),
+             (O.BG_B1, 0.0, 3.0, 1.0, 0.7), (O.BG_B1, 50.0, 0.5, 1.0, 0.05)]
+    for kind, a, b, x, v in cases:
+        n = 20000
+        E = rng.exponential(size=n)
+        tau = np.array([O.bg_flight(kind, a, b, x, v, e) for e in E])
+        for e, t in zip(E[:200], tau[:200]):     # the root solves eq. intinv
+            assert abs(O.bg_rate_integral(kind, a, b, x, v, t) - e) <= 1e-12 * (1.0 + e)
+        ref = _thinning_flights(kind, a, b, x, v, n, rng, 40.0 / b)
+        assert np.all(np.isfinite(ref))
+        assert stats.ks_2samp(tau, ref).pvalue > P_MIN, (kind, a, b, x, v)
+        crossed = np.mean((x - 1.0) * (x + v * tau - 1.0) < 0.0)
+        assert crossed > 0.05 or a == 0.0 or v == 0.05, (kind, a, b, x, v, crossed)
+
+
+def pin_bg_rate_integral_exact():
+    """The rate integral along a flight against adaptive quadrature of the
+    paper's R (both sides of the kink, backward integration for t < 0)."""
+    from scipy import integrate
+    rng = np.random.default_rng(22)
+    for _ in range(60):
+        kind = int(rng.choice([O.BG_B1, O.BG_B2]))
+        a, b = float(rng.uniform(0, 30)), float(rng.uniform(0.5, 5))
+        x, v, t = float(rng.uniform(-1, 3)), float(rng.normal() * 2), float(rng.uniform(-1, 1))
+        f = lambda s: float(paper_rate(kind, a, b, x + v * s))
+        lo, hi = (0.0, t) if t >= 0 else (t, 0.0)
+        pts = [(1.0 - x) / v] if v != 0 and lo < (1.0 - x) / v < hi else None
+        q = integrate.quad(f, lo, hi, points=pts, epsabs=1e-13, epsrel=1e-13)[0]
+        q = q if t >= 0 else -q
+        assert abs(O.bg_rate_integral(kind, a, b, x, v, t) - q) <= 1e-10 * (1.0 + abs(q))
+
+
+def pin_bg_homogeneous_limit():
+    """a = 0 is the homogeneous background R = b: the background path agrees
+    with the homogeneous KD path (exact flight E/b, coarse collision = fine
+    collision) to rounding, with equal KD step counts, for paths and pairs."""
+    for k, (b, level, single) in enumerate(((1.0, 3, False), (100.0, 4, False), (10.0, 2, True),
+                                            (1000.0, 6, False))):
+        prob = bg_problem(O.BG_B1, 0.0, b, stream=500 + k)
+        h = O.simulate(prob, level, 0, 3000, single=single)
+        g = O.simulate_kd_bg(prob, level, 0, 3000, single=single, general=True)
+        assert np.array_equal(h["cf"], g["cf"]) and np.array_equal(h["cc"], g["cc"]), (b, level)
+        scale = max(1.0, float(np.max(np.abs(h["xf"]))))
+        assert np.max(np.abs(h["xf"] - g["xf"])) <= 1e-12 * scale, (b, level)
+        assert np.max(np.abs(h["xc"] - g["xc"])) <= 1e-12 * scale, (b, level)
+
+
+def pin_bg_symmetric_mean():
+    """In the symmetric background B1 (x0 = 1, mu = 0) the law of x(T) - 1 is
+    symmetric, so E[x(T)] = 1 and E[(x(T) - 1)^3] = 0, for single paths and
+    both paths of a pair, in the kinetic and the diffusive regime."""
+    for k, (a, b, level) in enumerate(((10.0, 1.0, 3), (10.0, 100.0, 2), (2.0, 1000.0, 6),
+                                       (100.0, 10.0, 4))):
+        prob = bg_problem(O.BG_B1, a, b, stream=520 + k)
+        r = O.simulate(prob, level, 0, 40000)
+        for x in (r["xf"], r["xc"]):
+            assert abs(_z(x, 1.0)) < Z_MAX, (a, b, level)
+            assert abs(_z((x - 1.0) ** 3, 0.0)) < Z_MAX, (a, b, level)
+
+
+def pin_bg_pair_paths_have_level_laws():
+    """In a background, the fine path of a level-l pair has the law of the
+    single path of level l (the pair loop's extra fine steps beyond T are
+    removed), in B1 and B2; with a = 0 the coarse path also has the law of
+    the single path of level l - 1 (telescoping).  With a > 0 the coarse law
+    is only close to it: the flight time then depends on the velocity, so the
+    weight alpha_m = sigma tau'_m of eq. chi-update is no longer independent
+    of nu_m and chi~ is not exactly N(0,1) (measured in the consistency
+    harness)."""
+    for k, (kind, a, b, level) in enumerate(((O.BG_B1, 10.0, 100.0, 3), (O.BG_B2, 10.0, 10.0, 2),
+                                             (O.BG_B2, 50.0, 1000.0, 5), (O.BG_B1, 5.0, 1.0, 1),
+                                             (O.BG_B1, 0.0, 100.0, 3), (O.BG_B2, 0.0, 3.0, 2))):
+        prob = bg_problem(kind, a, b, stream=540 + k)
+        pair = O.simulate_kd_bg(prob, level, 0, 40000, general=True)
+        checks = [(level, pair["xf"])] + ([(level - 1, pair["xc"])] if a == 0.0 else [])
+        for lev, x in checks:
+            ind = O.simulate(dict(prob, stream_id=560 + k), lev, 0, 40000, single=True)
+            assert stats.ks_2samp(x, ind["xf"]).pvalue > P_MIN, (kind, a, b, level, lev)
+            d = np.mean(x ** 2) - np.mean(ind["xf"] ** 2)
+            se = math.sqrt((np.var(x ** 2) + np.var(ind["xf"] ** 2)) / x.size)
+            assert abs(d / se) < Z_MAX, (kind, a, b, level, lev)
+
+
+def _kinetic_background_paths(kind, a, b, T, n, rng):
+    """Brute-force velocity-jump process in a background: x(0) = 1, velocities
+    N(0, 1) redrawn at the collisions of the Poisson process of rate R(x)."""
+    x = np.ones(n)
+    v = rng.standard_normal(n)
+    t = np.zeros(n)
+    live = np.ones(n, dtype=bool)
+    while live.any():
+        idx = np.nonzero(live)[0]
+        # bound of R over the rest of each flight (|x| moves by at most |v| T)
+        reach = np.abs(v[idx]) * (T - t[idx])
+        rmax = paper_rate(kind, a, b, np.array([1.0]))[0] + b * a * (np.abs(x[idx] - 1.0) + reach)
+        dt = rng.exponential(1.0 / rmax)
+        end = t[idx] + dt >= T
+        stop = idx[end]
+        x[stop] += v[stop] * (T - t[stop])
+        live[stop] = False
+        go = idx[~end]
+        dtg = dt[~end]
+        x[go] += v[go] * dtg
+        t[go] += dtg
+        acc = rng.uniform(size=go.size) * rmax[~end] < paper_rate(kind, a, b, x[go])
+        hit = go[acc]
+        v[hit] = rng.standard_normal(hit.size)
+    return x
+
+
+def pin_bg_kinetic_limit():
+    """dt << 1/R: every KD step is a kinetic flight plus a short diffusive
+    remainder, so the scheme tends to the kinetic process; x(T) against a
+    brute-force velocity-jump simulation in the same background (KS test and
+    the second moment)."""
+    rng = np.random.default_rng(23)
+    for k, (kind, a, b) in enumerate(((O.BG_B1, 10.0, 1.0), (O.BG_B2, 20.0, 2.0))):
+        prob = bg_problem(kind, a, b, stream=580 + k)
+        kd = O.simulate(prob, 10, 0, 30000, single=True)["xf"]
+        ref = _kinetic_background_paths(kind, a, b, 1.0, 30000, rng)
+        assert stats.ks_2samp(kd, ref).pvalue > P_MIN, (kind, a, b)
+        d = np.mean(kd ** 2) - np.mean(ref ** 2)
+        se = math.sqrt((np.var(kd ** 2) + np.var(ref ** 2)) / kd.size)
+        assert abs(d / se) < Z_MAX, (kind, a, b)
+
+
+def pin_bg_coarse_number_laws():
+    """Section 5.1's check in the paper's background B1 (a = 10, b = 100 and
+    1000): the aggregated coarse numbers have the laws of the coarse path's
+    own numbers -- chi~, nu~ ~ N(0,1), E~ ~ Exp(1) (eq. epsilon-update with
+    the rate integral along the fine flight) -- by Anderson-Darling, and the
+    phase weights satisfy the identities of the homogeneous case with the
+    phase's own rate R_m (a_m = sigma nu_{m+1} zeta_m, and alpha_m nu_m =
+    sigma tau_m nu_m + a_{m-1})."""
+    for k, (a, b, level) in enumerate(((10.0, 100.0, 5), (10.0, 1000.0, 5), (10.0, 100.0, 9))):
+        prob = bg_problem(O.BG_B1, a, b, stream=600 + k)
+        rows, checked = [], 0
+        for smp in range(2000 if level < 9 else 300):
+            ph, co, _ = O.kd_bg_phases(prob, level, smp)
+            rows.append(co)
+            for m in range(ph.shape[0]):
+                r = ph[m]
+                assert abs(r[14] * r[5] - r[12]) <= 1e-12 * (1.0 + abs(r[12]))
+                if r[1] == 0:
+                    lhs, rhs = r[8] * r[10], r[3] * r[10] + ph[m - 1, 12]
+                    assert abs(lhs - rhs) <= 1e-12 * (1.0 + abs(lhs))
+                    checked += 1
+        rows = np.concatenate(rows)
+        assert rows.shape[0] > 1000 and checked > 0
+        assert anderson_darling(rows[:, 0], stats.norm.cdf) < AD_MAX, (a, b, level, "chi")
+        assert anderson_darling(rows[:, 1], stats.norm.cdf) < AD_MAX, (a, b, level, "nu")
+        assert anderson_darling(rows[:, 2], stats.expon.cdf) < AD_MAX, (a, b, level, "E")
+
+
+def pin_bg_pair_fine_path_is_its_own_path():
+    """A pair's fine path consumes exactly the random numbers of a single KD
+    path under the same counter tag, and the pair loop's fine steps beyond T
+    only feed the coarse aggregation (the fine path ends at the first state
+    whose pending collision is at or after T): positions equal to rounding,
+    KD step counts equal, including the samples where the coarse path still
+    collides before T after the fine path has ended."""
+    for k, (kind, a, b, level) in enumerate(((O.BG_B1, 10.0, 100.0, 3), (O.BG_B2, 50.0, 10.0, 2),
+                                             (O.BG_B1, 100.0, 1.0, 4), (O.BG_B2, 10.0, 1000.0, 6))):
+        prob = bg_problem(kind, a, b, stream=620 + k)
+        pair = O.simulate(prob, level, 0, 20000)
+        own = O.simulate_kd_bg(prob, level, 0, 20000, single=True, pair_tag=True)
+        assert np.array_equal(pair["cf"], own["cf"]), (kind, a, b, level)
+        assert np.max(np.abs(pair["xf"] - own["xf"])) <= 1e-13 * (1.0 + np.max(np.abs(own["xf"])))
+
+
+BG_PINS = [pin_bg_pair_fine_path_is_its_own_path, pin_bg_flight_law, pin_bg_rate_integral_exact, pin_bg_homogeneous_limit,
+           pin_bg_symmetric_mean, pin_bg_pair_paths_have_level_laws, pin_bg_kinetic_limit,
+           pin_bg_coarse_number_laws]
+
+
 if __name__ == "__main__":
     import json
     import sys
-    print(json.dumps(run_all(stop_at_first="--first" in sys.argv,
-                             pins=KD_PINS if "--kd" in sys.argv else None)))
+    sel = KD_PINS if "--kd" in sys.argv else (BG_PINS if "--bg" in sys.argv else None)
+    print(json.dumps(run_all(stop_at_first="--first" in sys.argv, pins=sel)))

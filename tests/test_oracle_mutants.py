@@ -88,6 +88,25 @@ KD_MUTANTS = [
 ]
 
 
+# Mistakes in the KD scheme in the backgrounds of Section 5; these run the
+# background pins only.
+BG_MUTANTS = [
+    ("bg_kink_ignored", "if ((x - 1.0) * (xe - 1.0) < 0.0) {            /* crosses the kink */",
+     "if (0) {"),
+    ("bg_b1_rate_not_symmetric", "if (g->kind == BG_B1) return g->b * (g->a * fabs(u) + 1.0);",
+     "if (g->kind == BG_B1) return g->b * (g->a * fmax(u, 0.0) + 1.0);"),
+    ("bg_flight_frozen_rate", "double lo = 0.0, hi = E / g->b;\n    if (!(E > 0.0)) return 0.0;",
+     "double lo = 0.0, hi = E / g->b;\n    if (!(E > 0.0) || 1) return E / bg_rate(g, x);"),
+    ("bg_epsilon_not_reduced", "double E_c = Ef - bg_rate_integral(g, xf, vf, tc - tf);",
+     "double E_c = Ef;"),
+    ("bg_epsilon_reduced_along_coarse", "double E_c = Ef - bg_rate_integral(g, xf, vf, tc - tf);",
+     "double E_c = Ef - bg_rate_integral(g, xc, vf, tc - tf) * 0.5;"),
+    ("bg_fine_steps_beyond_T_kept", "if (cfine >= T && !fine_done) {", "if (0) {"),
+    ("bg_trapezoid_half_missing", "return 0.5 * t * (bg_rate(g, x) + bg_rate(g, xe));",
+     "return t * bg_rate(g, x);"),
+]
+
+
 @pytest.fixture(scope="module")
 def source():
     with open(os.path.join(ROOT, "oracle", "oracle.c")) as f:
@@ -119,3 +138,8 @@ def test_mutant_is_caught(source, tmp_path, name, old, new):
 @pytest.mark.parametrize("name,old,new", KD_MUTANTS, ids=[m[0] for m in KD_MUTANTS])
 def test_kd_mutant_is_caught(source, tmp_path, name, old, new):
     _run_mutant(source, tmp_path, name, old, new, ["--kd"])
+
+
+@pytest.mark.parametrize("name,old,new", BG_MUTANTS, ids=[m[0] for m in BG_MUTANTS])
+def test_bg_mutant_is_caught(source, tmp_path, name, old, new):
+    _run_mutant(source, tmp_path, name, old, new, ["--bg"])

@@ -5,6 +5,6 @@ import pytest
 import oracle_pins as P
 
 
-@pytest.mark.parametrize("pin", P.ALL_PINS + P.KD_PINS, ids=lambda f: f.__name__)
+@pytest.mark.parametrize("pin", P.ALL_PINS + P.KD_PINS + P.BG_PINS, ids=lambda f: f.__name__)
 def test_pin(oracle_lib, pin):
     pin()
