@@ -82,7 +82,22 @@ enum { MLMC_AP_COUPLING_KICK_SUM = 0,  /* normalised sum of the M fine kick norm
 
 /* Quantity of interest. */
 enum { MLMC_AP_QOI_X2 = 0,        /* Q = x(T)^2 */
-       MLMC_AP_QOI_X2_HIST = 1 }; /* x(T)^2 plus a position histogram */
+       MLMC_AP_QOI_X2_HIST = 1,   /* x(T)^2 plus a position histogram */
+       MLMC_AP_QOI_X = 2 };       /* Q = x(T), the expected position of Section 5 */
+
+/* Background of the KD scheme.  DIFFUSIVE: the diffusive scaling, collision
+ * rate R = 1/eps^2 and Maxwellian N(0, 1/eps^2).  B1, B2: the test case of
+ * Section 5, Maxwellian N(0, 1) (mu = 0, sigma = 1; eps is not used) and a
+ * collision rate that is piecewise linear with a kink at x = 1:
+ *   B1 (symmetric):  R(x) = b (a |x - 1| + 1),
+ *   B2 (asymmetric): R(x) = b for x <= 1, b (a (x - 1) + 1) for x > 1,
+ * parameters bg_a = a >= 0 and bg_b = b > 0 (a = 0: homogeneous, R = b).
+ * Flight times solve eq. intinv exactly for the piecewise-linear rate; the
+ * diffusive phase uses eqs. advection and diffusion with the collision rate
+ * at the collision point (the paper's corrected a^hetero, d^hetero are not
+ * stated in it); pairs follow Algorithm "Correlated KD algorithm" with the
+ * general eq. epsilon-update (the rate integral along the fine flight). */
+enum { MLMC_AP_BG_DIFFUSIVE = 0, MLMC_AP_BG_B1 = 1, MLMC_AP_BG_B2 = 2 };
 
 /* Particle scheme (Section 2).  SPLITTING: the asymptotic-preserving
  * splitting scheme at fixed dt (transport-diffusion step with the
@@ -123,6 +138,8 @@ typedef struct mlmc_ap_problem {
     uint64_t seed;       /* Philox key */
     uint32_t stream_id;  /* fourth counter word (request / stream id) */
     uint32_t scheme;     /* MLMC_AP_SCHEME_* (0 = splitting) */
+    uint32_t background; /* MLMC_AP_BG_* (KD scheme only; 0 = diffusive scaling) */
+    double bg_a, bg_b;   /* B1/B2 parameters a >= 0, b > 0 */
 } mlmc_ap_problem;
 
 /* Per-level statistics, mergeable (Chan et al. pairwise update) in FP64.

@@ -21,7 +21,8 @@ MAX_LEVELS = 31
 X0_DELTA, X0_NORMAL, X0_COSINE = 0, 1, 2
 EQ_TWO_POINT, EQ_MAXWELLIAN = 0, 1
 COUPLING_KICK_SUM, COUPLING_AGGREGATE = 0, 1
-QOI_X2, QOI_X2_HIST = 0, 1
+QOI_X2, QOI_X2_HIST, QOI_X = 0, 1, 2
+BG_DIFFUSIVE, BG_B1, BG_B2 = 0, 1, 2
 SCHEME_SPLITTING, SCHEME_KD = 0, 1
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EBUSY",
@@ -42,7 +43,9 @@ class Problem(ctypes.Structure):
                 ("coupling", ctypes.c_int32), ("qoi", ctypes.c_int32), ("nbins", ctypes.c_int32),
                 ("fp64_state", ctypes.c_int32), ("hist_lo", ctypes.c_double),
                 ("hist_hi", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("stream_id", ctypes.c_uint32), ("scheme", ctypes.c_uint32)]
+                ("stream_id", ctypes.c_uint32), ("scheme", ctypes.c_uint32),
+                ("background", ctypes.c_uint32), ("bg_a", ctypes.c_double),
+                ("bg_b", ctypes.c_double)]
 
 
 class LevelStats(ctypes.Structure):
@@ -218,17 +221,20 @@ def _dump_ptrs(P, n_samples, traj, coll):
 
 def problem(eps, T, dt0, M=2, L=0, x0_kind=X0_NORMAL, x0_a=0.0, x0_b=1.0, eq_kind=EQ_MAXWELLIAN,
             coupling=None, qoi=QOI_X2, nbins=64, hist_lo=-4.0, hist_hi=5.0, fp64_state=0,
-            seed=42, stream_id=0, scheme=SCHEME_SPLITTING):
+            seed=42, stream_id=0, scheme=SCHEME_SPLITTING, background=BG_DIFFUSIVE, bg_a=0.0,
+            bg_b=0.0):
     """Builds an ``mlmc_ap_problem``; the coupling defaults to the aggregated
     kick for the Maxwellian equilibrium and the kick sum otherwise.
     ``scheme``: SCHEME_SPLITTING (default) or SCHEME_KD (kinetic-diffusion;
-    Maxwellian, eps > 0, fp64_state = 1)."""
+    Maxwellian, fp64_state = 1, and eps > 0 or a background).  ``background``
+    (KD only): BG_DIFFUSIVE (rate 1/eps^2) or BG_B1 / BG_B2 of Section 5 with
+    parameters ``bg_a`` >= 0, ``bg_b`` > 0."""
     if coupling is None:
         coupling = COUPLING_AGGREGATE if eq_kind == EQ_MAXWELLIAN else COUPLING_KICK_SUM
     return Problem(eps=eps, T=T, dt0=dt0, M=M, L=L, x0_kind=x0_kind, eq_kind=eq_kind, x0_a=x0_a,
                    x0_b=x0_b, coupling=coupling, qoi=qoi, nbins=nbins, fp64_state=fp64_state,
                    hist_lo=hist_lo, hist_hi=hist_hi, seed=seed, stream_id=stream_id,
-                   scheme=scheme)
+                   scheme=scheme, background=background, bg_a=bg_a, bg_b=bg_b)
 
 
 def as_problem(p):

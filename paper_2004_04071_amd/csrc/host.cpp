@@ -64,9 +64,10 @@ uint64_t coarse_threshold(uint64_t thr_f, uint64_t thr_c, int M) {
 // Expected KD steps of one path of a level: a KD step runs from a grid point
 // to the end of the grid step holding the next collision, which advances
 // 1/(1 - e^{-R dt}) steps on average, so n (1 - e^{-R dt}) steps per path.
+// In a background of Section 5 the rate is at least b, and b is taken.
 static double kd_path_cost(const mlmc_ap_problem& p, int level) {
   const LevelConst c = level_const(p, level);
-  const double R = 1.0 / (p.eps * p.eps);
+  const double R = p.background == MLMC_AP_BG_DIFFUSIVE ? 1.0 / (p.eps * p.eps) : p.bg_b;
   return (double)c.n_steps * -std::expm1(-R * c.dt);
 }
 
@@ -117,7 +118,7 @@ mlmc_ap_status validate_problem(const mlmc_ap_problem* p) {
     return set_error(MLMC_AP_EINVAL,
                      "the aggregated coupling needs the Maxwellian equilibrium (a weighted sum "
                      "of +-1 velocities is not Gaussian)");
-  if (p->qoi != MLMC_AP_QOI_X2 && p->qoi != MLMC_AP_QOI_X2_HIST)
+  if (p->qoi != MLMC_AP_QOI_X2 && p->qoi != MLMC_AP_QOI_X2_HIST && p->qoi != MLMC_AP_QOI_X)
     return set_error(MLMC_AP_EINVAL, "unknown qoi");
   if (p->qoi == MLMC_AP_QOI_X2_HIST) {
     if (p->nbins < 1 || p->nbins > MLMC_AP_MAX_BINS)
@@ -129,8 +130,19 @@ mlmc_ap_status validate_problem(const mlmc_ap_problem* p) {
     return set_error(MLMC_AP_EINVAL, "fp64_state must be 0 or 1");
   if (p->scheme != MLMC_AP_SCHEME_SPLITTING && p->scheme != MLMC_AP_SCHEME_KD)
     return set_error(MLMC_AP_EINVAL, "unknown scheme");
+  if (p->background != MLMC_AP_BG_DIFFUSIVE && p->background != MLMC_AP_BG_B1 &&
+      p->background != MLMC_AP_BG_B2)
+    return set_error(MLMC_AP_EINVAL, "unknown background");
+  if (p->background != MLMC_AP_BG_DIFFUSIVE) {
+    if (p->scheme != MLMC_AP_SCHEME_KD)
+      return set_error(MLMC_AP_EINVAL, "the backgrounds B1, B2 are for the KD scheme");
+    if (!(p->bg_b > 0.0) || !std::isfinite(p->bg_b) || !(p->bg_a >= 0.0) ||
+        !std::isfinite(p->bg_a))
+      return set_error(MLMC_AP_EINVAL, "a background needs bg_a >= 0 and bg_b > 0, finite");
+  }
   if (p->scheme == MLMC_AP_SCHEME_KD) {
-    if (!(p->eps > 0.0)) return set_error(MLMC_AP_EINVAL, "the KD scheme needs eps > 0");
+    if (p->background == MLMC_AP_BG_DIFFUSIVE && !(p->eps > 0.0))
+      return set_error(MLMC_AP_EINVAL, "the KD scheme needs eps > 0");
     if (p->eq_kind != MLMC_AP_EQ_MAXWELLIAN)
       return set_error(MLMC_AP_EINVAL, "the KD scheme needs the Maxwellian equilibrium");
     if (p->fp64_state != 1)
@@ -220,7 +232,8 @@ LevelDesc make_desc(const ItemSpec& s, bool tp) {
   d.flags = (coarse ? kFlagCoarse : 0u) | (maxwell ? kFlagMaxwell : 0u) |
             (agg ? kFlagAggregate : 0u) | (s.hist ? kFlagHist : 0u) |
             (s.accumulate ? kFlagAccumulate : 0u) |
-            ((s.hist || s.traj || s.coll) ? kFlagSampleOutputs : 0u);
+            ((s.hist || s.traj || s.coll) ? kFlagSampleOutputs : 0u) |
+            (p.qoi == MLMC_AP_QOI_X ? kFlagQoiX : 0u);
   if (d.thr_f == 0 || d.thr_c2 == 0) d.flags |= kFlagWide;
   d.kind = coarse ? (maxwell ? (agg ? kKindPairMaxwellAggregate : kKindPairMaxwellSum)
                              : kKindPairTwoPointSum)
@@ -230,11 +243,20 @@ LevelDesc make_desc(const ItemSpec& s, bool tp) {
     // the KD kinds read their constants from the coefficient slots
     d.h_f = F.dt;
     d.h_c = coarse ? C.dt : 0.0;
-    d.s_f = 1.0 / (p.eps * p.eps);  // collision rate R
-    d.s_c = 1.0 / p.eps;            // Maxwellian standard deviation sigma
     d.agg_ms2 = p.T;
     d.h_f2 = 0.0;                   // Maxwellian mean mu
     d.rsqrt_m = 0.0;
+    if (p.background == MLMC_AP_BG_DIFFUSIVE) {
+      d.s_f = 1.0 / (p.eps * p.eps);  // collision rate R
+      d.s_c = 1.0 / p.eps;            // Maxwellian standard deviation sigma
+    } else {
+      // Section 5: sigma = 1 and R(x) from (a, b); a = 0 runs the
+      // homogeneous path with R = b
+      d.s_f = p.bg_b;
+      d.s_c = 1.0;
+      d.rsqrt_m = p.bg_a;             // slope parameter a of the background
+      if (p.bg_a > 0.0) d.flags |= p.background == MLMC_AP_BG_B1 ? kFlagBgB1 : kFlagBgB2;
+    }
     d.thr_f = d.thr_c2 = 0;
     d.thr_f_m1 = d.thr_c2_m1 = 0u;
     d.flags &= ~(kFlagWide | kFlagAggregate);

@@ -267,4 +267,211 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
   }
 }
 
+// ---------------------------------------------------------------------------
+// The KD scheme in the backgrounds of Section 5 (flags kFlagBgB1 / kFlagBgB2;
+// a > 0 -- a = 0 is the homogeneous path above with R = b): Maxwellian with
+// mu = 0 and sigma = 1, collision rate piecewise linear with a kink at x = 1,
+//   B1: R(x) = b (a |x - 1| + 1),   B2: R(x) = b (a max(x - 1, 0) + 1).
+// ---------------------------------------------------------------------------
+struct KdBackground {
+  double a, b;
+  bool b1;
+};
+
+__device__ __forceinline__ double bg_rate(const KdBackground& g, double x) {
+  const double u = x - 1.0;
+  return g.b * (g.a * (g.b1 ? fabs(u) : fmax(u, 0.0)) + 1.0);
+}
+
+// Flight time of eq. intinv from x with velocity v and exponential number E.
+// Along the flight the rate is linear in time on each side of the kink, so
+// the root of r0 s + k s^2/2 = E is s = 2E / (r0 + sqrt(r0^2 + 2 k E)) (the
+// square root is the rate at the collision); a flight heading for the kink
+// first spends I1 = s_k (r0 + b)/2 of E on the way there.
+__device__ __forceinline__ double bg_flight(const KdBackground& g, double x, double v, double E) {
+  const double u = x - 1.0;
+  const double r0 = bg_rate(g, x);
+  const double ab = g.a * g.b;
+  const bool toward = (u < 0.0 && v > 0.0) || (u > 0.0 && v < 0.0);
+  // d/ds R(x + v s) on the piece the flight starts on
+  double k1;
+  if (g.b1) k1 = (u > 0.0 || (u == 0.0 && v > 0.0)) ? ab * v : -ab * v;
+  else k1 = (u > 0.0 || (u == 0.0 && v > 0.0)) ? ab * v : 0.0;
+  if (toward) {
+    const double sk = -u / v;
+    const double i1 = 0.5 * sk * (r0 + g.b);
+    if (E > i1) {
+      const double e2 = E - i1;
+      const double k2 = g.b1 ? ab * fabs(v) : (v > 0.0 ? ab * v : 0.0);
+      return sk + 2.0 * e2 / (g.b + sqrt(g.b * g.b + 2.0 * k2 * e2));
+    }
+  }
+  return 2.0 * E / (r0 + sqrt(r0 * r0 + 2.0 * k1 * E));
+}
+
+// int_0^t R(x + v s) ds (t < 0: minus the integral over [t, 0]); exact by
+// the trapezoid rule on each linear piece.
+__device__ __forceinline__ double bg_rate_integral(const KdBackground& g, double x, double v,
+                                                   double t) {
+  double sign = 1.0;
+  if (t < 0.0) {
+    x = x + v * t;
+    t = -t;
+    sign = -1.0;
+  }
+  const double xe = x + v * t;
+  const double u0 = x - 1.0, u1 = xe - 1.0;
+  double r;
+  if (u0 * u1 < 0.0) {
+    const double sk = -u0 / v;
+    r = 0.5 * sk * (bg_rate(g, x) + g.b) + 0.5 * (t - sk) * (g.b + bg_rate(g, xe));
+  } else {
+    r = 0.5 * t * (bg_rate(g, x) + bg_rate(g, xe));
+  }
+  return sign * r;
+}
+
+// eqs. advection and diffusion with the local rate R of the phase (its
+// 1/R and 2 sigma^2/R^2 are returned for the aggregation weights).
+__device__ __forceinline__ void bg_coeffs(double R, double mu, double sigma, double theta,
+                                          double y, double em, double v_next, double& a,
+                                          double& dd, double& inv_r, double& c2) {
+  inv_r = 1.0 / R;
+  const double inv_r2 = inv_r * inv_r;
+  c2 = 2.0 * sigma * sigma * inv_r2;
+  const double dv = v_next - mu;
+  a = mu * theta + dv * (-em) * inv_r;
+  const double d2 = c2 * kd_f(y, em) + dv * dv * inv_r2 * kd_g(y, em);
+  dd = sqrt(d2 > 0.0 ? d2 : 0.0);
+}
+
+// One path or one correlated pair in a background (Algorithm "KD algorithm",
+// Algorithm "Correlated KD algorithm" with the general eq. epsilon-update).
+// A pair's fine path keeps stepping past T while the coarse path still has a
+// collision before T (those steps only feed the aggregation); the fine path
+// itself ends at the first state whose pending collision is at or after T.
+template <bool COARSE>
+__device__ __forceinline__ void kd_sample_bg(const LevelDesc& d, uint32_t smp, double& xf_out,
+                                             double& xc_out, uint32_t& cf_out,
+                                             uint32_t& cc_out) {
+  const KdParams k = kd_params(d);
+  const KdBackground g{d.rsqrt_m, d.s_f, (d.flags & kFlagBgB1) != 0};
+  const uint32_t guard = 2u * d.n_steps + 4u;
+  const Words w0 = philox4x32_10(0u, smp, k.tag, k.strm, k.key0, k.key1);
+  double nc, ns;
+  box_muller(w0.w0, w0.w1, nc, ns);
+  double x0;
+  if (d.x0_kind == 0) x0 = d.x0_a;
+  else if (d.x0_kind == 1) x0 = d.x0_a + d.x0_b * nc;
+  else x0 = cosine_icdf(uniform_f64(w0.w3));
+  const double E0 = -log(uniform_f64(w0.w2));
+
+  double xf = x0, vf = k.mu + k.sigma * ns, tf = 0.0, Ef = E0;
+  double tauf = bg_flight(g, xf, vf, Ef);
+  double cfine = tf + tauf;
+  uint32_t cf = 0, cc = 0, b = 1, steps = 0;
+
+  if constexpr (!COARSE) {
+    while (cfine < k.T && steps < guard) {
+      double nu_next, chi, E_next;
+      kd_draws(k, smp, b++, nu_next, chi, E_next);
+      const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
+      const double theta = t_next - cfine;
+      const double rl = bg_rate(g, xf + vf * tauf);   // rate at the collision
+      const double y = rl * theta;
+      const double v_next = k.mu + k.sigma * nu_next;
+      double a, dd, inv_r, c2;
+      bg_coeffs(rl, k.mu, k.sigma, theta, y, kd_em(y), v_next, a, dd, inv_r, c2);
+      xf = xf + vf * tauf + (a + dd * chi);
+      tf = t_next;
+      vf = v_next;
+      Ef = E_next;
+      tauf = bg_flight(g, xf, vf, Ef);
+      cfine = tf + tauf;
+      ++cf;
+      ++steps;
+    }
+    if (tf < k.T) xf = xf + vf * (k.T - tf);
+    xf_out = xf;
+    xc_out = 0.0;
+    cf_out = cf;
+    cc_out = 0u;
+  } else {
+    double xc = x0, vc = vf, tc = 0.0, tauc = tauf, ccoarse = tc + tauc;
+    double nu_f = ns;
+    bool fine_done = false;
+    double xf_end = 0.0;
+    while ((ccoarse < k.T || cfine < k.T) && steps < guard) {
+      const double end_c = floor(ccoarse / k.dtc) + 1.0;
+      const double end_c_fine = end_c * (double)k.M;
+      double num = 0.0, den = 0.0, zeta_prev = 0.0;
+      bool first = true;
+      do {
+        if (cfine >= k.T && !fine_done) {
+          xf_end = tf < k.T ? xf + vf * (k.T - tf) : xf;
+          fine_done = true;
+        }
+        double nu_next, chi, E_next;
+        kd_draws(k, smp, b++, nu_next, chi, E_next);
+        const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
+        const double theta = t_next - cfine;
+        const double rm = bg_rate(g, xf + vf * tauf);
+        const double y = rm * theta;
+        const double em = kd_em(y);
+        const double v_next = k.mu + k.sigma * nu_next;
+        double a, dd, inv_r, c2;
+        bg_coeffs(rm, k.mu, k.sigma, theta, y, em, v_next, a, dd, inv_r, c2);
+        xf = xf + vf * tauf + (a + dd * chi);
+        // aggregation weights of this phase with its own rate
+        const double zeta = -em * inv_r;
+        const double yp = kd_h(y, em);
+        const double beta = sqrt(c2 * kd_h(yp, yp < kKdSeriesY ? 0.0 : kd_em(yp)));
+        if (!first) {
+          const double alpha = (tauf + zeta_prev) * k.sigma;
+          num += alpha * nu_f;
+          den += alpha * alpha;
+        }
+        num += beta * chi;
+        den += beta * beta;
+        zeta_prev = zeta;
+        first = false;
+        if (!fine_done) ++cf;
+        tf = t_next;
+        vf = v_next;
+        nu_f = nu_next;
+        Ef = E_next;
+        tauf = bg_flight(g, xf, vf, Ef);
+        cfine = tf + tauf;
+        ++steps;
+      } while (!(floor(cfine / k.dtf) + 1.0 > end_c_fine) && steps < guard);
+      if (ccoarse < k.T) {
+        const double chi_c = den > 0.0 ? num / sqrt(den) : 0.0;
+        const double t_next = end_c * k.dtc;
+        const double theta = t_next - ccoarse;
+        const double rc = bg_rate(g, xc + vc * tauc);
+        const double y = rc * theta;
+        const double v_next = k.mu + k.sigma * nu_f;
+        double a, dd, inv_r, c2;
+        bg_coeffs(rc, k.mu, k.sigma, theta, y, kd_em(y), v_next, a, dd, inv_r, c2);
+        xc = xc + vc * tauc + (a + dd * chi_c);
+        tc = t_next;
+        vc = v_next;
+        // eq. epsilon-update: the pending fine flight's exponential number
+        // less the rate integral along it up to the coarse time
+        double ec = Ef - bg_rate_integral(g, xf, vf, tc - tf);
+        ec = ec < 0.0 ? 0.0 : ec;
+        tauc = bg_flight(g, xc, vc, ec);
+        ccoarse = tc + tauc;
+        ++cc;
+      }
+    }
+    if (!fine_done) xf_end = tf < k.T ? xf + vf * (k.T - tf) : xf;
+    if (tc < k.T) xc = xc + vc * (k.T - tc);
+    xf_out = xf_end;
+    xc_out = xc;
+    cf_out = cf;
+    cc_out = cc;
+  }
+}
+
 }  // namespace mlmc

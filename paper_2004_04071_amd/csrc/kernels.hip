@@ -454,8 +454,9 @@ __device__ __forceinline__ void run_tile_impl(const LevelDesc& d, uint32_t tile,
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const Real xf = st.pos_f(p), xc = st.pos_c(p);
-      const double qf = (double)xf * (double)xf;
-      const double qc = kCoarse ? (double)xc * (double)xc : 0.0;
+      const bool qoi_x = (d.flags & kFlagQoiX) != 0;
+      const double qf = qoi_x ? (double)xf : (double)xf * (double)xf;
+      const double qc = kCoarse ? (qoi_x ? (double)xc : (double)xc * (double)xc) : 0.0;
       const double dq = qf - qc;
       if (r == 0 && p == 0) acc.shift<kCoarse>(dq, qf, qc);  // lane 0, sample 0 always exists
       if (valid[p]) {
@@ -483,9 +484,14 @@ __device__ __forceinline__ void run_kd_tile(const LevelDesc& d, uint32_t tile,
     const bool valid = local < d.n_samples;
     double xf = 0.0, xc = 0.0;
     uint32_t cf = 0, cc = 0;
-    if (valid) kd_sample<kCoarse>(d, (uint32_t)(d.sample_begin + local), xf, xc, cf, cc);
-    const double qf = xf * xf;
-    const double qc = kCoarse ? xc * xc : 0.0;
+    if (valid) {
+      const uint32_t smp = (uint32_t)(d.sample_begin + local);
+      if (d.flags & (kFlagBgB1 | kFlagBgB2)) kd_sample_bg<kCoarse>(d, smp, xf, xc, cf, cc);
+      else kd_sample<kCoarse>(d, smp, xf, xc, cf, cc);
+    }
+    const bool qoi_x = (d.flags & kFlagQoiX) != 0;
+    const double qf = qoi_x ? xf : xf * xf;
+    const double qc = kCoarse ? (qoi_x ? xc : xc * xc) : 0.0;
     const double dq = qf - qc;
     if (j == 0) acc.shift<kCoarse>(dq, qf, qc);  // lane 0, sample 0 always exists
     if (valid) {
@@ -663,8 +669,9 @@ __device__ __forceinline__ Stats tp_tile_record(const LevelDesc& d, uint32_t til
   const bool valid = local < d.n_samples;
   TpSample r{0.0, 0.0, 0u, 0u};
   if (valid) r = d.tp_out[local];
-  const double qf = r.xf * r.xf;
-  const double qc = kCoarse ? r.xc * r.xc : 0.0;
+  const bool qoi_x = (d.flags & kFlagQoiX) != 0;
+  const double qf = qoi_x ? r.xf : r.xf * r.xf;
+  const double qc = kCoarse ? (qoi_x ? r.xc : r.xc * r.xc) : 0.0;
   const double dq = qf - qc;
   TileSums acc;
   acc.shift<kCoarse>(dq, qf, qc);

@@ -48,6 +48,9 @@ enum : uint32_t {
   kFlagAccumulate = 1u << 6,  // merge into the resident statistics (else overwrite)
   kFlagTimeParallel = 1u << 7,  // one trajectory per wavefront, steps across lanes
   kFlagSampleOutputs = 1u << 8, // a dump or a histogram is requested
+  kFlagQoiX = 1u << 9,          // Q = x(T) (else x(T)^2)
+  kFlagBgB1 = 1u << 10,         // KD in background B1 (a > 0): R(x) = b (a |x - 1| + 1)
+  kFlagBgB2 = 1u << 11,         // KD in background B2 (a > 0): R = b left of 1, linear right
 };
 
 // Final state of one sample of a time-parallel item.
@@ -68,9 +71,10 @@ enum : int {
 };
 
 // The KD kinds use the coefficient slots of LevelDesc as
-//   h_f = fine step dt_l, h_c = coarse step dt_{l-1}, s_f = collision rate R,
-//   s_c = Maxwellian standard deviation sigma, agg_ms2 = end time T,
-//   h_f2 = Maxwellian mean mu.
+//   h_f = fine step dt_l, h_c = coarse step dt_{l-1}, s_f = collision rate R
+//   (in a background: its parameter b), s_c = Maxwellian standard deviation
+//   sigma, agg_ms2 = end time T, h_f2 = Maxwellian mean mu, rsqrt_m = the
+//   background's slope parameter a.
 __host__ __device__ inline bool is_kd_kind(int kind) { return kind >= kKindKdFine; }
 
 struct alignas(16) LevelDesc {

@@ -115,7 +115,8 @@ def test_merge_stats_equals_two_pass(lib):
 @pytest.mark.parametrize("field,value", [
     ("eps", -1.0), ("eps", float("nan")), ("T", 0.0), ("dt0", -0.5), ("M", 1), ("M", 65),
     ("L", -1), ("L", 31), ("dt0", 0.3), ("x0_kind", 3), ("eq_kind", 2), ("x0_b", -1.0),
-    ("coupling", 2), ("qoi", 2), ("fp64_state", 2), ("scheme", 2)])
+    ("coupling", 2), ("qoi", 3), ("fp64_state", 2), ("scheme", 2), ("background", 3),
+    ("background", 1)])
 def test_validation_rejects(lib, field, value):
     p = pkg.problem(eps=0.1, T=1.0, dt0=0.5, L=3)
     setattr(p, field, value)
@@ -144,6 +145,18 @@ def test_validation_special_cases(lib):
     assert pkg.mlmc_ap_validate(pkg.problem(**dict(kd, fp64_state=0))) == -1
     assert pkg.mlmc_ap_validate(pkg.problem(**dict(kd, eq_kind=pkg.EQ_TWO_POINT,
                                                    coupling=pkg.COUPLING_KICK_SUM))) == -1
+    # the backgrounds of Section 5: KD only, a >= 0, b > 0, eps not used
+    bg = dict(kd, eps=0.0, background=pkg.BG_B1, bg_a=10.0, bg_b=100.0)
+    assert pkg.mlmc_ap_validate(pkg.problem(**bg)) == 0
+    assert pkg.mlmc_ap_validate(pkg.problem(**dict(bg, background=pkg.BG_B2, bg_a=0.0))) == 0
+    assert pkg.mlmc_ap_validate(pkg.problem(**dict(bg, bg_b=0.0))) == -1
+    assert pkg.mlmc_ap_validate(pkg.problem(**dict(bg, bg_a=-1.0))) == -1
+    assert pkg.mlmc_ap_validate(pkg.problem(**dict(bg, bg_b=float("inf")))) == -1
+    assert pkg.mlmc_ap_validate(pkg.problem(**dict(bg, scheme=pkg.SCHEME_SPLITTING,
+                                                   fp64_state=0))) == -1
+    # the position QoI of Section 5, for either scheme
+    assert pkg.mlmc_ap_validate(pkg.problem(**dict(bg, qoi=pkg.QOI_X))) == 0
+    assert pkg.mlmc_ap_validate(pkg.problem(eps=0.1, T=1.0, dt0=0.5, qoi=pkg.QOI_X)) == 0
 
 
 def test_entry_points_report_errors_without_a_device(lib):

@@ -17,6 +17,10 @@ asymptotic-preserving Monte Carlo study in plain numbers:
 * ``cfg_kd`` the cfg2 estimate with the kinetic-diffusion scheme (homogeneous
             background: collision rate 1/eps^2, Maxwellian velocities of
             standard deviation 1/eps), FP64 state.
+* ``cfg_bg`` the test case of Section 5: KD scheme, x(0) = 1, T = 1, dt_l =
+            2^-l, Maxwellian N(0, 1), collision rate of background B1
+            (b (a |x-1| + 1)) or B2 (b left of 1, b (a (x-1) + 1) right of it),
+            QoI the position x(T).
 * ``cfg5``  serving stream: Poisson arrivals at 200/s, eps log-uniform in
             [1e-4, 1], T uniform in [0.1, 1] (dt0 = T/2, L = 8), RMSE
             log-uniform in [1e-3, 1e-2], Maxwellian, x0 ~ N(0,1).
@@ -24,6 +28,8 @@ asymptotic-preserving Monte Carlo study in plain numbers:
 import numpy as np
 
 X0_DELTA, X0_NORMAL, X0_COSINE = 0, 1, 2
+BG_DIFFUSIVE, BG_B1, BG_B2 = 0, 1, 2
+QOI_X2, QOI_X2_HIST, QOI_X = 0, 1, 2
 EQ_TWO_POINT, EQ_MAXWELLIAN = 0, 1
 COUPLING_KICK_SUM, COUPLING_AGGREGATE = 0, 1
 SCHEME_SPLITTING, SCHEME_KD = 0, 1
@@ -54,6 +60,16 @@ def cfg_kd(eps=0.01, stream_id=6):
     """The cfg2 estimate with the kinetic-diffusion scheme instead of the
     splitting scheme (homogeneous background, FP64 state)."""
     return dict(cfg2(eps=eps, stream_id=stream_id), fp64_state=1, scheme=SCHEME_KD)
+
+
+def cfg_bg(background=BG_B1, a=10.0, b=1000.0, M=2, L=8, stream_id=7):
+    """The test case of Section 5 with the KD scheme: x(0) = 1, T = 1, time
+    steps dt_l = 2^-l (dt0 = 1, M = 2), Maxwellian N(0, 1), collision rate of
+    background B1 or B2 with parameters a, b; QoI the position x(T)."""
+    return dict(eps=0.0, T=1.0, dt0=1.0, M=M, L=L, x0_kind=X0_DELTA, x0_a=1.0, x0_b=0.0,
+                eq_kind=EQ_MAXWELLIAN, coupling=COUPLING_AGGREGATE, fp64_state=1, seed=42,
+                stream_id=stream_id, scheme=SCHEME_KD, background=background, bg_a=a, bg_b=b,
+                qoi=QOI_X)
 
 
 def cfg3():
