@@ -467,6 +467,24 @@ mlmc_ap_status mlmc_ap_server_run_trace(mlmc_ap_server* srv, int32_t n, const do
                                         const mlmc_ap_problem* p, const double* rmse_tol,
                                         mlmc_ap_result* results_out, double* latency_s_out);
 
+/* Consistency harness of Section 5.1: the aggregated coarse numbers of KD
+ * pairs (scheme KD), for checking that they follow the laws the coarse path
+ * needs (eq. null_hypothesis: nu~ ~ N(0,1), E~ ~ Exp(1), chi~ ~ N(0,1)).  The
+ * fine step is dt0 / M^level and the coarse step dt0 / M^coarse_level; T/dt0
+ * need not be an integer here, so the coarse step may exceed T (as in the
+ * paper's table).  For pair i = sample - sample_begin:
+ *   rows_dev[((i * max_rows) + k) * 4 + j], k < min(counts, max_rows): coarse KD
+ *     step k's chi~ (eq. chi-update), nu~ (eq. nu-update), E~ (eq.
+ *     epsilon-update) and the number of fine KD steps aggregated into it;
+ *   counts_dev[i]: the pair's coarse KD steps (rows beyond max_rows are not
+ *     written).
+ * Both buffers are caller-owned device memory (n_samples * max_rows * 4
+ * doubles, n_samples uint32).  The call synchronises `stream`. */
+mlmc_ap_status mlmc_ap_kd_coarse_numbers(const mlmc_ap_problem* p, int32_t level,
+                                         int32_t coarse_level, uint64_t sample_begin,
+                                         uint64_t n_samples, uint32_t max_rows, double* rows_dev,
+                                         uint32_t* counts_dev, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Validation entry points (bit-exact checks of the random number path).  */
 /* ---------------------------------------------------------------------- */

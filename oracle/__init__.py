@@ -17,6 +17,7 @@ Contents
 ``build.py``           compiles ``oracle.c`` with gcc into ``liboracle.so``
 """
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -245,8 +246,8 @@ def kd_coarse_numbers(prob, level, sample, cap=None, coarse_level=None):
     """Coarse numbers of one KD pair (coarse path at coarse_level, default
     level - 1), one row per coarse KD step: (chi~, nu~, E~, fine KD steps
     aggregated), and the final (x_f, x_c)."""
-    if cap is None:
-        cap = int(round(prob["T"] / prob["dt0"])) * int(prob["M"]) ** level + 2
+    if cap is None:   # coarse steps of a pair, up to the end of the last one (past T)
+        cap = 2 * int(math.ceil(prob["T"] / prob["dt0"] - 1e-9)) * int(prob["M"]) ** level + 8
     rows = np.zeros((cap, 4))
     fin = np.zeros(2)
     used = lib().oracle_kd_coarse_numbers(
@@ -268,7 +269,7 @@ def kd_phases(prob, level, sample, coarse_level=None):
     tau', the weights alpha and beta, its numbers nu, chi, its a and d, the
     next velocity number and x_f after it), the coarse rows of
     ``kd_coarse_numbers`` and the final (x_f, x_c)."""
-    cap = int(round(prob["T"] / prob["dt0"])) * int(prob["M"]) ** level + 2
+    cap = 2 * int(math.ceil(prob["T"] / prob["dt0"] - 1e-9)) * int(prob["M"]) ** level + 8
     phases = np.zeros((cap, 16))
     rows = np.zeros((cap, 4))
     fin = np.zeros(2)
@@ -320,7 +321,7 @@ def simulate_kd_bg(prob, level, sample_begin=0, n=None, samples=None, single=Fal
 def kd_bg_phases(prob, level, sample, coarse_level=None):
     """As kd_phases for a pair in a background (phase column 15 = the phase's
     collision rate R_m)."""
-    cap = 2 * int(round(prob["T"] / prob["dt0"])) * int(prob["M"]) ** level + 4
+    cap = 2 * int(math.ceil(prob["T"] / prob["dt0"] - 1e-9)) * int(prob["M"]) ** level + 8
     phases = np.zeros((cap, 16))
     rows = np.zeros((cap, 4))
     fin = np.zeros(2)

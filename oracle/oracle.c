@@ -903,9 +903,11 @@ static void simulate_kd_bg_one(const problem_t *P, const bg_t *g, uint64_t sampl
     const double dtf = P->dt0 / pow((double)P->M, (double)l);
     const double dtc = coarse ? P->dt0 / pow((double)P->M, (double)P->coarse_level) : 0.0;
     const double Mb = coarse ? (double)llround(pow((double)P->M, (double)(l - P->coarse_level))) : 1.0;
-    /* a fine KD step advances at least one fine grid step; beyond T the
-     * fine path takes at most one step per coarse step */
-    const uint64_t guard = 2u * (uint64_t)llround(T / dtf) + 4u;
+    /* a fine KD step advances at least one fine grid step; beyond T a pair's
+     * fine path steps at most to the end of the last coarse step (a coarse
+     * step may reach past T), one step per coarse step and one more */
+    const double grid_end = coarse ? ceil(T / dtc - 1e-9) * dtc : T;
+    const uint64_t guard = 2u * (uint64_t)llround(grid_end / dtf) + 4u;
 
     uint32_t w[4];
     kd_block(P, smp, tag, 0, w);

@@ -113,6 +113,8 @@ _SIGNATURES = {
                                ctypes.c_uint64, _P(LevelStats), _vp, _vp, _P(ctypes.c_uint64), _vp],
     "mlmc_ap_simulate_pair": [_P(Problem), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                               ctypes.c_uint64, _P(LevelStats), _vp, _vp, _P(ctypes.c_uint64), _vp],
+    "mlmc_ap_kd_coarse_numbers": [_P(Problem), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                  ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp],
     "mlmc_ap_simulate_level_noalloc": [_P(Problem), ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_uint64, ctypes.c_uint64, _P(LevelStats), _vp, _vp,
                                        _P(ctypes.c_uint64), _vp],
@@ -545,6 +547,20 @@ def mlmc_ap_server_run_trace(srv, arrival_s, problems, rmse_tols):
     _check(lib().mlmc_ap_server_run_trace(srv, n, arr, Ps, tols, res, lat),
            "mlmc_ap_server_run_trace")
     return [float(x) for x in lat], [result_dict(r) for r in res]
+
+
+def mlmc_ap_kd_coarse_numbers(p, level, coarse_level, sample_begin, n_samples, max_rows, rows,
+                              counts, stream=None):
+    """Coarse numbers of KD pairs into the device tensors ``rows`` (float64,
+    n_samples * max_rows * 4: chi~, nu~, E~, fine steps aggregated per coarse
+    KD step) and ``counts`` (int32/uint32, n_samples: coarse KD steps per
+    pair)."""
+    n, m = int(n_samples), int(max_rows)
+    _check(lib().mlmc_ap_kd_coarse_numbers(
+        ctypes.byref(as_problem(p)), int(level), int(coarse_level), int(sample_begin), n, m,
+        _dev_ptr(rows, n * m * 4, ("float64",), "rows"),
+        _dev_ptr(counts, n, ("int32", "uint32"), "counts"), _stream(stream)),
+        "mlmc_ap_kd_coarse_numbers")
 
 
 def mlmc_ap_philox_words(seed, stream_id, tag, sample_begin, n_samples, n_steps, out, stream=None):

@@ -1297,6 +1297,55 @@ mlmc_ap_status mlmc_ap_simulate_pair(const mlmc_ap_problem* p, int32_t level, in
                          coll_dev, hist_host, stream);
 }
 
+mlmc_ap_status mlmc_ap_kd_coarse_numbers(const mlmc_ap_problem* p, int32_t level,
+                                         int32_t coarse_level, uint64_t sample_begin,
+                                         uint64_t n_samples, uint32_t max_rows, double* rows_dev,
+                                         uint32_t* counts_dev, void* stream) {
+  if (!p) return set_error(MLMC_AP_EINVAL, "problem is NULL");
+  // the coarse step may exceed T here (the paper's table runs coarse steps up
+  // to 64 fine steps from T/2), so T/dt0 need not be an integer: the rest of
+  // the problem is checked with dt0 = T
+  mlmc_ap_problem q = *p;
+  q.dt0 = q.T;
+  q.L = std::max(q.L, level);
+  MLMC_TRY(validate_problem(&q));
+  if (!(p->dt0 > 0.0) || !std::isfinite(p->dt0))
+    return set_error(MLMC_AP_EINVAL, "dt0 must be > 0");
+  if (p->scheme != MLMC_AP_SCHEME_KD)
+    return set_error(MLMC_AP_EINVAL, "coarse numbers are those of the KD scheme");
+  if (level < 1 || level >= MLMC_AP_MAX_LEVELS || coarse_level < 0 || coarse_level >= level)
+    return set_error(MLMC_AP_EINVAL, "a pair needs 0 <= coarse_level < level <= 30");
+  if (sample_begin > 4294967296ull || n_samples > 4294967296ull - sample_begin)
+    return set_error(MLMC_AP_EINVAL, "sample_begin + n_samples must not exceed 2^32");
+  if (max_rows < 1) return set_error(MLMC_AP_EINVAL, "max_rows must be >= 1");
+  if (n_samples == 0) return MLMC_AP_OK;
+  if (!rows_dev || !counts_dev) return set_error(MLMC_AP_EINVAL, "rows_dev / counts_dev is NULL");
+  // fine steps up to the end of the last coarse step (which may lie past T):
+  // what bounds the pair loops
+  const double dtc = p->dt0 / std::pow((double)p->M, (double)coarse_level);
+  const double K = std::pow((double)p->M, (double)(level - coarse_level));
+  const double steps = std::ceil(p->T / dtc - 1e-9) * K;
+  if (steps >= 1073741824.0) return set_error(MLMC_AP_EINVAL, "too many fine steps");
+  ItemSpec it;
+  it.prob = p;
+  it.level = level;
+  it.single = false;
+  it.coarse_level = coarse_level;
+  it.sample_begin = sample_begin;
+  it.n_samples = n_samples;
+  it.result_slot = 0;
+  it.hist = nullptr;
+  it.traj = nullptr;
+  it.coll = nullptr;
+  it.accumulate = false;
+  LevelDesc d = make_desc(it, false);
+  d.n_steps = (uint32_t)std::max(1.0, steps);  // bounds the KD step loops (2 n + 4)
+  hipStream_t s = (hipStream_t)stream;
+  MLMC_HIP(launch_kd_numbers(d, n_samples, max_rows, rows_dev, counts_dev, s));
+  MLMC_HIP(hipStreamSynchronize(s));
+  return MLMC_AP_OK;
+}
+
 // stages > 0: one request run through the tolerance sequence
 // tols[0] 2^(-r/2), r = 0..stages-1; out receives one result per stage.
 static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* tols, int32_t n_req,

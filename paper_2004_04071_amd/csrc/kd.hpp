@@ -154,11 +154,37 @@ __device__ __forceinline__ void kd_draws(const KdParams& k, uint32_t smp, uint32
   E_next = -log(uniform_f64(w.w2));
 }
 
+// Optional record of a pair's coarse numbers, for the consistency harness of
+// Section 5.1: row k = (chi~, nu~, E~, fine KD steps aggregated) of coarse KD
+// step k.  The simulation kernels use KdNoRecord, which compiles away.
+struct KdNoRecord {
+  static constexpr bool kOn = false;
+  __device__ __forceinline__ void put(double, double, double, uint32_t) {}
+};
+
+struct KdRecord {
+  static constexpr bool kOn = true;
+  double* rows;
+  uint32_t cap;
+  uint32_t n;
+  __device__ __forceinline__ void put(double chi, double nu, double e, uint32_t used) {
+    if (n < cap) {
+      double* r = rows + 4ull * n;
+      r[0] = chi;
+      r[1] = nu;
+      r[2] = e;
+      r[3] = (double)used;
+    }
+    ++n;
+  }
+};
+
 // One path (COARSE = false) or a correlated pair of sample smp: final
 // positions and KD step counts (collisions before T).
-template <bool COARSE>
-__device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, double& xf_out,
-                                          double& xc_out, uint32_t& cf_out, uint32_t& cc_out) {
+template <bool COARSE, typename Rec>
+__device__ __forceinline__ void kd_sample_rec(const LevelDesc& d, uint32_t smp, double& xf_out,
+                                              double& xc_out, uint32_t& cf_out, uint32_t& cc_out,
+                                              Rec& rec) {
   const KdParams k = kd_params(d);
   // initial condition, shared by both paths
   const Words w0 = philox4x32_10(0u, smp, k.tag, k.strm, k.key0, k.key1);
@@ -210,7 +236,9 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
       const double end_c_fine = end_c * (double)k.M;
       double num = 0.0, den = 0.0, zeta_prev = 0.0;
       bool first = true;
+      uint32_t used = 0;
       do {
+        if constexpr (Rec::kOn) ++used;
         double nu_next, chi, E_next;
         kd_draws(k, smp, b++, nu_next, chi, E_next);
         const double t_next = nf * k.dtf;
@@ -256,6 +284,8 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
         ccoarse = cfine;
         vc = v_next;
         ++cc;
+        // E~ of eq. epsilon-update: what is left of the fine flight's number
+        if constexpr (Rec::kOn) rec.put(chi_c, nu_f, k.R * (cfine - tc), used);
       }
     }
     if (tf < k.T) xf = xf + vf * (k.T - tf);
@@ -265,6 +295,13 @@ __device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, doub
     cf_out = cf;
     cc_out = cc;
   }
+}
+
+template <bool COARSE>
+__device__ __forceinline__ void kd_sample(const LevelDesc& d, uint32_t smp, double& xf_out,
+                                          double& xc_out, uint32_t& cf_out, uint32_t& cc_out) {
+  KdNoRecord none;
+  kd_sample_rec<COARSE>(d, smp, xf_out, xc_out, cf_out, cc_out, none);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,10 +387,10 @@ __device__ __forceinline__ void bg_coeffs(double R, double mu, double sigma, dou
 // A pair's fine path keeps stepping past T while the coarse path still has a
 // collision before T (those steps only feed the aggregation); the fine path
 // itself ends at the first state whose pending collision is at or after T.
-template <bool COARSE>
-__device__ __forceinline__ void kd_sample_bg(const LevelDesc& d, uint32_t smp, double& xf_out,
-                                             double& xc_out, uint32_t& cf_out,
-                                             uint32_t& cc_out) {
+template <bool COARSE, typename Rec>
+__device__ __forceinline__ void kd_sample_bg_rec(const LevelDesc& d, uint32_t smp,
+                                                 double& xf_out, double& xc_out,
+                                                 uint32_t& cf_out, uint32_t& cc_out, Rec& rec) {
   const KdParams k = kd_params(d);
   const KdBackground g{d.rsqrt_m, d.s_f, (d.flags & kFlagBgB1) != 0};
   const uint32_t guard = 2u * d.n_steps + 4u;
@@ -406,7 +443,9 @@ __device__ __forceinline__ void kd_sample_bg(const LevelDesc& d, uint32_t smp, d
       const double end_c_fine = end_c * (double)k.M;
       double num = 0.0, den = 0.0, zeta_prev = 0.0;
       bool first = true;
+      uint32_t used = 0;
       do {
+        if constexpr (Rec::kOn) ++used;
         if (cfine >= k.T && !fine_done) {
           xf_end = tf < k.T ? xf + vf * (k.T - tf) : xf;
           fine_done = true;
@@ -463,6 +502,7 @@ __device__ __forceinline__ void kd_sample_bg(const LevelDesc& d, uint32_t smp, d
         tauc = bg_flight(g, xc, vc, ec);
         ccoarse = tc + tauc;
         ++cc;
+        if constexpr (Rec::kOn) rec.put(chi_c, nu_f, ec, used);
       }
     }
     if (!fine_done) xf_end = tf < k.T ? xf + vf * (k.T - tf) : xf;
@@ -472,6 +512,14 @@ __device__ __forceinline__ void kd_sample_bg(const LevelDesc& d, uint32_t smp, d
     cf_out = cf;
     cc_out = cc;
   }
+}
+
+template <bool COARSE>
+__device__ __forceinline__ void kd_sample_bg(const LevelDesc& d, uint32_t smp, double& xf_out,
+                                             double& xc_out, uint32_t& cf_out,
+                                             uint32_t& cc_out) {
+  KdNoRecord none;
+  kd_sample_bg_rec<COARSE>(d, smp, xf_out, xc_out, cf_out, cc_out, none);
 }
 
 }  // namespace mlmc

@@ -1277,6 +1277,31 @@ hipError_t launch_normals(bool fp64, uint32_t key0, uint32_t key1, uint32_t strm
   return hipGetLastError();
 }
 
+// Consistency harness of Section 5.1: one KD pair per thread, its coarse
+// numbers recorded (at most `cap` rows per pair; counts[i] = all of its coarse
+// KD steps).
+__global__ void __launch_bounds__(256) kd_numbers_kernel(LevelDesc d, uint64_t n, uint32_t cap,
+                                                         double* __restrict__ rows,
+                                                         uint32_t* __restrict__ counts) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  KdRecord rec{rows + i * (uint64_t)cap * 4ull, cap, 0u};
+  double xf, xc;
+  uint32_t cf, cc;
+  const uint32_t smp = (uint32_t)(d.sample_begin + i);
+  if (d.flags & (kFlagBgB1 | kFlagBgB2)) kd_sample_bg_rec<true>(d, smp, xf, xc, cf, cc, rec);
+  else kd_sample_rec<true>(d, smp, xf, xc, cf, cc, rec);
+  counts[i] = rec.n;
+}
+
+hipError_t launch_kd_numbers(const LevelDesc& d, uint64_t n, uint32_t cap, double* rows,
+                             uint32_t* counts, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(kd_numbers_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, n,
+                     cap, rows, counts);
+  return hipGetLastError();
+}
+
 hipError_t launch_stage_args(const WorkHeader& h, const LevelDesc& d, WorkHeader* hdr_dst,
                              LevelDesc* item_dst, unsigned int* item_done,
                              unsigned long long* hist, uint32_t hist_n, hipStream_t s) {

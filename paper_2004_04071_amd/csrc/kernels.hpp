@@ -76,6 +76,11 @@ constexpr uint64_t kScratchBytes = kScratchTilesOffset + kScratchMaxTiles * size
 // on each device, then cached).
 hipError_t scratch_address(void** out);
 
+// Consistency harness: coarse numbers of the KD pairs of one item (the
+// descriptor as a kernel argument), `cap` rows of 4 doubles per pair.
+hipError_t launch_kd_numbers(const LevelDesc& d, uint64_t n, uint32_t cap, double* rows,
+                             uint32_t* counts, hipStream_t s);
+
 hipError_t launch_fill_u32(unsigned int* p, uint64_t n, unsigned int v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_words(uint32_t key0, uint32_t key1, uint32_t strm, uint32_t tag,

@@ -47,6 +47,28 @@ def anderson_darling(x, cdf):
     return float(-n - np.sum((2 * i - 1) * (np.log(F) + np.log1p(-F[::-1]))) / n)
 
 
+AD_CRIT_1PCT = 3.857   # A^2 above which a fully specified law is rejected at the 1 % level
+
+
+def ad_pvalue(a2):
+    """p-value of an Anderson-Darling distance A^2 for a fully specified law:
+    1 - ADinf(A^2), with ADinf the asymptotic distribution function in the
+    approximation of G. Marsaglia and J. Marsaglia, "Evaluating the
+    Anderson-Darling distribution", J. Stat. Softw. 9(2), 2004."""
+    z = float(a2)
+    if z <= 0.0:
+        return 1.0
+    if z < 2.0:
+        cdf = math.exp(-1.2337141 / z) / math.sqrt(z) * (
+            2.00012 + (0.247105 - (0.0649821 - (0.0347962 - (0.011672 - 0.00168691 * z) * z)
+                                   * z) * z) * z)
+    else:
+        cdf = math.exp(-math.exp(1.0776 - (2.30695 - (0.43424 - (0.082433 - (0.008056 -
+                                                                       0.0003146 * z) * z)
+                                                      * z) * z) * z))
+    return max(0.0, 1.0 - cdf)
+
+
 def _z(sample, exact):
     return (float(np.mean(sample)) - exact) / (float(np.std(sample)) / math.sqrt(sample.size))
 

@@ -1,8 +1,12 @@
-"""Consistency of the coarse KD random numbers (the paper's Section 5.1
-check, in a homogeneous background): for fine steps dt = T/2^l and coarse
-steps K dt, the aggregated coarse numbers nu~, E~ and chi~ of 1000 pairs
-follow N(0,1), Exp(1) and N(0,1) (eq. null_hypothesis), by the
-Anderson-Darling distance of eq. anderson (CPU, oracle only)."""
+"""Consistency of the coarse KD random numbers (the paper's Section 5.1, on
+the CPU oracle): for fine steps dt = T/2^l and coarse steps K dt, the first
+1000 aggregated coarse numbers nu~, E~ and chi~ follow N(0,1), Exp(1) and
+N(0,1) (eq. null_hypothesis) by the Anderson-Darling test of eq. anderson at
+the paper's 1 % level.  Over many cells some rejections happen by chance even
+for exact laws, so the bar is on their number: at most 4 of the 90 tests of
+each background (binomial(90, 0.01) exceeds 4 with probability 0.002), and no
+A^2 beyond the 1e-4 level.  The GPU harness (tests/test_gpu_consistency.py)
+runs the paper's full table on the device's own numbers."""
 import math
 
 import numpy as np
@@ -10,22 +14,52 @@ import pytest
 from scipy import stats
 
 import oracle as O
-from oracle_pins import AD_MAX, anderson_darling
+from oracle_pins import AD_CRIT_1PCT, ad_pvalue, anderson_darling
 
-CASES = [(l, K) for l in (2, 5, 8, 11, 14) for K in (2, 4, 8, 16, 32, 64) if 2 ** l >= K]
+LEVELS = (2, 5, 8, 11, 14)
+KS = (2, 4, 8, 16, 32, 64)
 
 
-@pytest.mark.parametrize("level,K", CASES, ids=["l%d_K%d" % c for c in CASES])
-def test_coarse_numbers_follow_their_laws(oracle_lib, level, K):
-    # dt0 = T and M = 2: level l has dt = T/2^l; the coarse level l - log2 K
-    prob = dict(eps=0.1, T=1.0, dt0=1.0, M=2, x0_kind=0, x0_a=0.0, x0_b=0.0, eq_kind=1,
-                coupling=1, seed=7, stream_id=1000 + 31 * level + K, scheme=O.SCHEME_KD)
-    lc = level - int(round(math.log2(K)))
-    rows = np.concatenate([O.kd_coarse_numbers(prob, level, s, coarse_level=lc)[0]
-                           for s in range(1000)])
-    a_nu = anderson_darling(rows[:, 1], stats.norm.cdf)
-    a_e = anderson_darling(rows[:, 2], stats.expon.cdf)
-    a_chi = anderson_darling(rows[:, 0], stats.norm.cdf)
-    print("l=%d K=%d: %d coarse steps, A^2 nu %.2f E %.2f chi %.2f"
-          % (level, K, rows.shape[0], a_nu, a_e, a_chi))
-    assert max(a_nu, a_e, a_chi) < AD_MAX
+def cell_problem(level, K, background):
+    """Fine step 2^-l, coarse step K 2^-l, as (dt0, M, level 1, coarse level 0)."""
+    p = dict(eps=0.1, T=1.0, dt0=K * 2.0 ** -level, M=K, x0_kind=0, x0_a=1.0, x0_b=0.0,
+             eq_kind=1, coupling=1, seed=7, stream_id=1000 + 31 * level + K, scheme=O.SCHEME_KD)
+    if background:
+        p.update(background=O.BG_B1, bg_a=10.0, bg_b=1000.0)
+    return p
+
+
+def first_numbers(prob, n=1000):
+    rows, s = [], 0
+    while sum(r.shape[0] for r in rows) < n:
+        if prob.get("background", 0):
+            rows.append(O.kd_bg_phases(prob, 1, s, coarse_level=0)[1])
+        else:
+            rows.append(O.kd_coarse_numbers(prob, 1, s, coarse_level=0)[0])
+        s += 1
+    return np.concatenate(rows)[:n]
+
+
+def test_ad_pvalue_reproduces_published_critical_values():
+    """Case 0 (fully specified law) critical values of the AD statistic."""
+    for a2, p in ((1.933, 0.10), (2.492, 0.05), (3.070, 0.025), (3.857, 0.01)):
+        assert abs(ad_pvalue(a2) - p) < 0.05 * p
+
+
+@pytest.mark.parametrize("background", [False, True], ids=["homogeneous_eps0.1", "B1_a10_b1000"])
+def test_coarse_numbers_follow_their_laws(oracle_lib, background):
+    rejected, worst = [], 1.0
+    for level in LEVELS:
+        for K in KS:
+            rows = first_numbers(cell_problem(level, K, background))
+            a2 = (anderson_darling(rows[:, 1], stats.norm.cdf),
+                  anderson_darling(rows[:, 2], stats.expon.cdf),
+                  anderson_darling(rows[:, 0], stats.norm.cdf))
+            print("l=%2d K=%2d: A^2 nu %.3f E %.3f chi %.3f" % ((level, K) + a2))
+            for name, a in zip(("nu", "E", "chi"), a2):
+                worst = min(worst, ad_pvalue(a))
+                if a >= AD_CRIT_1PCT:
+                    rejected.append((level, K, name, a))
+    print("rejected at 1 %%: %s; smallest p %.3g" % (rejected, worst))
+    assert len(rejected) <= 4
+    assert worst > 1e-4
