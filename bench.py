@@ -194,6 +194,53 @@ VALU_PROBE_COMMAND = ("rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES --output-format cs
                       "-o pmc -- python3 bench.py --valu-probe")
 
 
+def _counter_per_dispatch(csv_path, counter):
+    """(kernel name, value) of `counter` per dispatch, in dispatch order."""
+    import csv
+    rows = {}
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                rows[int(r["Dispatch_Id"])] = (r["Kernel_Name"], float(r["Counter_Value"]))
+    return [rows[k] for k in sorted(rows)]
+
+
+def write_traffic_record(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
+    """HBM bytes per launch of the particle kernel: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) scaled by what they read for a plain copy of known
+    size (--copy-probe 256: each copy reads and writes 256 MiB)."""
+    copy_bytes = 256.0 * 1024 * 1024
+    def factor(path, counter):
+        # the three copies (the probe's fill of the source is not a copy)
+        vals = [v for name, v in _counter_per_dispatch(path, counter) if "copy" in name.lower()]
+        assert len(vals) == 3, vals
+        return copy_bytes / (1024.0 * (sum(vals) / len(vals)))
+    ff = factor(copy_fetch_csv, "FETCH_SIZE")
+    fw = factor(copy_write_csv, "WRITE_SIZE")
+    def mean_kib(path, counter):
+        vals = [v for name, v in _counter_per_dispatch(path, counter)
+                if "persistent_kernel<float" in name]
+        return sum(vals) / len(vals), len(vals)
+    fk, n = mean_kib(fetch_csv, "FETCH_SIZE")
+    wk, _ = mean_kib(write_csv, "WRITE_SIZE")
+    rec = {"kernel": "persistent_kernel<float, 1, false>",
+           "workload": "MLMC-AP eps=0.01 L=8 RMSE 1e-3 (bench timed region)",
+           "kernel_source_hash": kernel_source_hash(),
+           "tuning": {"block": 256, "ppt": 1, "waves_per_simd": 8},
+           "dispatches": n, "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
+           "fetch_factor": ff, "write_factor": fw,
+           "bytes_per_launch": fk * 1024.0 * ff + wk * 1024.0 * fw,
+           "commands": ["rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --no-extras "
+                        "--no-cpu-baseline --steps 5 --warmup 1 --tuning 256,1,8",
+                        "rocprofv3 --pmc WRITE_SIZE -- (the same)",
+                        "rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --copy-probe 256",
+                        "rocprofv3 --pmc WRITE_SIZE -- python3 bench.py --copy-probe 256"]}
+    with open(TRAFFIC_RECORD, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec))
+
+
 def write_valu_record(csv_path):
     """Per-level VALU lane-instructions per sample from the counters of the
     --valu-probe launches (persistent kernels only, in dispatch order): the
@@ -257,7 +304,15 @@ def main():
     ap.add_argument("--valu-record", metavar="CSV",
                     help="write profiles/valu_instructions_per_sample.json from the "
                          "rocprofv3 counter CSV of a --valu-probe run (no GPU needed)")
+    ap.add_argument("--traffic-record", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH",
+                                                          "COPY_WRITE"),
+                    help="write profiles/persistent_kernel_hbm_traffic.json from the rocprofv3 "
+                         "FETCH_SIZE and WRITE_SIZE CSVs of the benchmark (--no-extras) and of "
+                         "--copy-probe 256 (no GPU needed)")
     args = ap.parse_args()
+    if args.traffic_record:
+        write_traffic_record(*args.traffic_record)
+        return
     if args.valu_record:
         write_valu_record(args.valu_record)
         return
@@ -512,6 +567,42 @@ def main():
                                  N=[ks["N"][l] for l in ks["level_set"]],
                                  estimate=ks["estimate"], sd=math.sqrt(ks["var_estimator"])))
         log("kd", out["kd"])
+
+        # the test case of Section 5: KD in background B1 with a = 10, b = 1000
+        # (x(0) = 1, dt_l = 2^-l, QoI E[x(T)], exact value 1 by symmetry), the
+        # case of the paper's cost-complexity study; multilevel estimates (all
+        # levels, heuristic and cost-optimal level sets) against single-level
+        # KDMC at the finest level, at the same RMSE
+        bprob = W.cfg_bg(W.BG_B1, 10.0, 1000.0, L=14)
+        BP = pkg.as_problem(bprob)
+        btol = 1e-4
+        bres = {}
+        for name, fn, bopt in (
+                ("mlmc_all_levels", pkg.mlmc_ap_estimate, pkg.options(batched=2, **tk)),
+                ("mlmc_heuristic_levels", pkg.mlmc_ap_estimate,
+                 pkg.options(batched=2, level_select=pkg.LEVELS_HEURISTIC, **tk)),
+                ("mlmc_optimal_levels", pkg.mlmc_ap_estimate,
+                 pkg.options(batched=2, level_select=pkg.LEVELS_OPTIMAL, **tk)),
+                ("single_level_kdmc", pkg.mlmc_ap_plain_mc, pkg.options(batched=2, **tk))):
+            fn(BP, btol, bopt, stream=hs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn(BP, btol, bopt, stream=hs)
+            torch.cuda.synchronize()
+            bres[name] = dict(time_ms=(time.perf_counter() - t0) * 1e3, estimate=r["estimate"],
+                              sd=math.sqrt(r["var_estimator"]), levels=r["level_set"],
+                              N=[r["N"][l] for l in r["level_set"]],
+                              kd_steps=sum(int(l["coll_f"]) + int(l["coll_c"])
+                                           for l in r["levels"]))
+        out["background_b1"] = dict(
+            workload="KD, background B1 a=10 b=1000, x(0)=1, T=1, dt_l=2^-l, L=14, "
+                     "QoI E[x(T)] (exact 1), RMSE 1e-4",
+            exact=1.0, **bres,
+            speedup_heuristic_vs_single_level=(bres["single_level_kdmc"]["time_ms"]
+                                               / bres["mlmc_heuristic_levels"]["time_ms"]),
+            speedup_all_levels_vs_single_level=(bres["single_level_kdmc"]["time_ms"]
+                                                / bres["mlmc_all_levels"]["time_ms"]))
+        log("background_b1", out["background_b1"])
     if not args.no_cpu_baseline and not kd_mode:
         out["cpu_baseline"] = cpu_baseline(prob, last["N"], args.cpu_seconds)
     print(json.dumps(out), flush=True)
