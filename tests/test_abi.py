@@ -275,3 +275,39 @@ def test_noalloc_entry_point_size_limit(lib):
                                             pkg.NOALLOC_MAX_SAMPLES + 1,
                                             pkg.ctypes.byref(out), None, None, None, None)
     assert st == -1 and "NOALLOC_MAX_SAMPLES" in pkg.mlmc_ap_last_error()
+
+
+def test_every_kernel_stub_has_a_gfx950_kernel(lib, tmp_path):
+    """Every kernel the host side of the library can launch (its
+    __device_stub__ functions) exists in the library's gfx950 code object.
+    A stub without a kernel makes the HIP runtime abort at the launch with
+    'Cannot find Symbol' -- the failure a host-only instantiation of a kernel
+    template causes.  Reads the library built here (no GPU needed)."""
+    import shutil
+    import subprocess
+    tools = "/opt/rocm/llvm/bin"
+    need = [os.path.join(tools, t) for t in ("llvm-objcopy", "clang-offload-bundler", "llvm-readelf")]
+    if not all(os.path.exists(t) for t in need) or not shutil.which("nm"):
+        pytest.skip("ROCm LLVM tools not found")
+    so = pkg.LIB_PATH
+    fat, co = str(tmp_path / "fatbin.bin"), str(tmp_path / "gfx950.co")
+    subprocess.check_call([need[0], "--dump-section", ".hip_fatbin=" + fat, so,
+                           str(tmp_path / "copy.so")])
+    listed = subprocess.check_output([need[1], "--list", "--type=o", "--input=" + fat], text=True)
+    target = [t for t in listed.split() if t.endswith("gfx950")]
+    assert target, listed
+    subprocess.check_call([need[1], "--unbundle", "--type=o", "--input=" + fat,
+                           "--targets=" + target[0], "--output=" + co])
+    syms = subprocess.check_output([need[2], "--symbols", co], text=True)
+    kernels = {w[:-3] for line in syms.splitlines() for w in line.split() if w.endswith(".kd")}
+    host = subprocess.check_output(["nm", so], text=True)
+    stubs = set()
+    for line in host.splitlines():
+        name = line.split()[-1]
+        m = re.search(r"(\d+)__device_stub__", name)
+        if m:   # the stub's name is the kernel's with "__device_stub__" inserted
+            n = int(m.group(1))
+            stubs.add(name[:m.start()] + str(n - 15) + name[m.end():])
+    assert len(stubs) >= 40 and len(kernels) >= 40
+    missing = sorted(stubs - kernels)
+    assert not missing, missing
