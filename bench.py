@@ -583,6 +583,11 @@ def main():
                  pkg.options(batched=2, level_select=pkg.LEVELS_HEURISTIC, **tk)),
                 ("mlmc_optimal_levels", pkg.mlmc_ap_estimate,
                  pkg.options(batched=2, level_select=pkg.LEVELS_OPTIMAL, **tk)),
+                # Section 5.3's protocol: 100 warm-up samples on levels 0..tau
+                # only, the O(dt^3) profile beyond, the heuristic set
+                ("mlmc_section53_protocol", pkg.mlmc_ap_estimate,
+                 pkg.options(batched=2, level_select=pkg.LEVELS_HEURISTIC_TAU, n_warmup=100,
+                             **tk)),
                 ("single_level_kdmc", pkg.mlmc_ap_plain_mc, pkg.options(batched=2, **tk))):
             fn(BP, btol, bopt, stream=hs)
             torch.cuda.synchronize()
@@ -593,7 +598,8 @@ def main():
                               sd=math.sqrt(r["var_estimator"]), levels=r["level_set"],
                               N=[r["N"][l] for l in r["level_set"]],
                               kd_steps=sum(int(l["coll_f"]) + int(l["coll_c"])
-                                           for l in r["levels"]))
+                                           for l in r["levels"]),
+                              tau=r["tau"], cost_model_steps=r["particle_steps"])
         out["background_b1"] = dict(
             workload="KD, background B1 a=10 b=1000, x(0)=1, T=1, dt_l=2^-l, L=14, "
                      "QoI E[x(T)] (exact 1), RMSE 1e-4",
@@ -601,7 +607,9 @@ def main():
             speedup_heuristic_vs_single_level=(bres["single_level_kdmc"]["time_ms"]
                                                / bres["mlmc_heuristic_levels"]["time_ms"]),
             speedup_all_levels_vs_single_level=(bres["single_level_kdmc"]["time_ms"]
-                                                / bres["mlmc_all_levels"]["time_ms"]))
+                                                / bres["mlmc_all_levels"]["time_ms"]),
+            speedup_protocol_vs_single_level=(bres["single_level_kdmc"]["time_ms"]
+                                              / bres["mlmc_section53_protocol"]["time_ms"]))
         log("background_b1", out["background_b1"])
     if not args.no_cpu_baseline and not kd_mode:
         out["cpu_baseline"] = cpu_baseline(prob, last["N"], args.cpu_seconds)

@@ -213,11 +213,34 @@ typedef struct mlmc_ap_options {
                                running pilot pairs (L, i), i <= L-2: the variances of
                                the pairs (i, i-1) and (L, i) are measured, the others
                                taken from eq. V_approx with the correlations
-                               rho_{L,i}; costs n_i (+ n_j) */
-    int32_t reserved;       /* must be 0 */
+                               rho_{L,i}; costs n_i (+ n_j);
+                               MLMC_AP_LEVELS_HEURISTIC_TAU (KD scheme only): the
+                               off-line part of Section 5.3, a warm-up of the
+                               adjacent pairs of levels 0..tau only (tau of
+                               mlmc_ap_warmup_depth, dt_tau about the mean free
+                               time), the profile beyond tau from
+                               mlmc_ap_extrapolate_variances, then the heuristic
+                               set; warm-up pairs that stay in the set keep their
+                               samples, the other items of the set get a warm-up of
+                               their own.  Costs: expected KD steps
+                               n_l (1 - exp(-R dt_l)) per path (R = bg_b, or 1/eps^2
+                               in the diffusive scaling). */
+    int32_t L_max;          /* 0: the finest level is p->L.  p->L < L_max <= 30:
+                               level-adaptive finest level (eq. bias_constraint;
+                               the nested level sets of Section 5.2): each time the
+                               statistical constraint holds, if bias_estimate of
+                               the result exceeds tol/sqrt(2) and L < L_max, L
+                               grows by one, the set is chosen again for the new L
+                               (LEVELS_ALL: the adjacent pair (L+1, L) is added;
+                               LEVELS_HEURISTIC_TAU: the heuristic on the same
+                               warm-up profile) and the estimate goes on with every
+                               sample of the items that stay.  Only with
+                               LEVELS_ALL or LEVELS_HEURISTIC_TAU, not with plain
+                               Monte Carlo or per-level histograms. */
 } mlmc_ap_options;
 
-enum { MLMC_AP_LEVELS_ALL = 0, MLMC_AP_LEVELS_HEURISTIC = 1, MLMC_AP_LEVELS_OPTIMAL = 2 };
+enum { MLMC_AP_LEVELS_ALL = 0, MLMC_AP_LEVELS_HEURISTIC = 1, MLMC_AP_LEVELS_OPTIMAL = 2,
+       MLMC_AP_LEVELS_HEURISTIC_TAU = 3 };
 
 typedef struct mlmc_ap_result {
     double estimate;         /* eq. mlmc-compact: sum_l mean(dQ_l) */
@@ -237,6 +260,15 @@ typedef struct mlmc_ap_result {
     uint64_t level_mask;     /* bit l set for every level of the hierarchy used; N[l]
                                 and lv[l] of a level l_j of the set hold the samples of
                                 Q_{l_j} - Q_{l_{j-1}} (of Q_{l_1} for the first) */
+    double bias_estimate;    /* |E[Q_L - Q]| estimated from the finest term:
+                                |mean(Q_L - Q_c)| / (M^(L-c) - 1), c the level below L
+                                in the set (first-order weak convergence in dt); NaN
+                                if the set is {L} alone */
+    double bias_se;          /* standard error of bias_estimate:
+                                sqrt(V_{L,c} / N_L) / (M^(L-c) - 1) (NaN as above) */
+    int32_t tau;             /* highest level of the warm-up before the selection (p->L
+                                but for LEVELS_HEURISTIC_TAU) */
+    int32_t levels_added;    /* finest levels added by options.L_max (L = p->L + this) */
 } mlmc_ap_result;
 
 /* Library and device set-up.  mlmc_ap_init is optional (every entry point
@@ -274,12 +306,14 @@ mlmc_ap_status mlmc_ap_optimal_samples(const double* V_host, const double* C_hos
 /* Level selection (host only).  Heuristic of Section 5.2 (Algorithm
  * "Heuristic level selection approach"): from V_l = Var[Q_l] (l = 0..L) and
  * Vdiff_l = Var[Q_l - Q_{l-1}] (l = 1..L; Vdiff_host[0] is ignored), start
- * with the first l whose Vdiff_l < V_l and l - 1, then add every later level
+ * with the first l whose Vdiff_l <= V_l and l - 1, then add every later level
  * whose Vdiff_l is below half the last one added.  Readings: the scan starts
  * after that first pair (the printed loop from l = 0 would read Vdiff_0);
  * if no level qualifies the set is {L} (plain Monte Carlo at L); L is always
- * added, since the estimator targets E[Q_L].  *mask_out: bit l set for each
- * selected level. */
+ * added (Section 4.1 restricts the sets to l_J = L, which makes the estimator
+ * unbiased for E[Q_L]).  So the sets for L and L + 1 share every level below
+ * L (the nesting of Section 5.2, up to the finest level).  *mask_out: bit l
+ * set for each selected level. */
 mlmc_ap_status mlmc_ap_select_levels_heuristic(const double* V_host, const double* Vdiff_host,
                                                int32_t L, uint64_t* mask_out);
 
@@ -293,6 +327,23 @@ mlmc_ap_status mlmc_ap_select_levels_heuristic(const double* V_host, const doubl
 mlmc_ap_status mlmc_ap_select_levels_optimal(const double* V_host, const double* C_host,
                                              const double* Vpair_host, const double* Cpair_host,
                                              int32_t L, uint64_t* mask_out, double* cost_out);
+
+/* Warm-up depth of Section 5.3 (host only): the level tau whose step
+ * dt_tau = dt0 M^-tau is nearest, in log scale, to the mean free time 1/R
+ * (R = bg_b in a background of Section 5, 1/eps^2 in the diffusive scaling),
+ * clamped to [1, L] (0 if L = 0).  Levels 0..tau are those whose steps are
+ * at least about 1/R, where the measured difference variances are needed. */
+mlmc_ap_status mlmc_ap_warmup_depth(const mlmc_ap_problem* p, int32_t* tau_out);
+
+/* Variance profile of Section 5.3 (host only): from measured V_l and
+ * V_{l,l-1} of levels 0..tau (V_host, Vdiff_host: tau+1 values, Vdiff_host[0]
+ * ignored), the profile of levels 0..L (V_out_host, Vdiff_out_host: L+1
+ * values): the measured values up to tau, beyond it the asymptotic rate
+ * V_{l,l-1} = O(dt_l^3), i.e. V_{l,l-1} = V_{tau,tau-1} / M^(3 (l - tau)), and
+ * V_l = V_tau.  0 <= tau <= L <= 30, 2 <= M <= 64, values >= 0. */
+mlmc_ap_status mlmc_ap_extrapolate_variances(const double* V_host, const double* Vdiff_host,
+                                             int32_t tau, int32_t M, int32_t L,
+                                             double* V_out_host, double* Vdiff_out_host);
 
 /* Pairwise merge of two statistics records (host only; the same update the
  * device reductions apply): out = a (+) b.  out may alias a or b. */
@@ -429,7 +480,9 @@ typedef struct mlmc_ap_server_config {
     uint64_t max_samples_per_tick; /* per request and level per tick (0 = 2^24) */
     int32_t max_active;            /* admitted requests at once (0 = 256) */
     int32_t reserved;
-    mlmc_ap_options options;       /* n_warmup, max_iter, tuning (batched is implied) */
+    mlmc_ap_options options;       /* n_warmup, max_iter, tuning (batched is implied;
+                                      level_select and L_max must be 0: the server
+                                      runs every level 0..L) */
 } mlmc_ap_server_config;
 
 typedef struct mlmc_ap_server_stats {

@@ -10,6 +10,9 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
   is {L}.
 * ``optimal``: eq. level_selection by plain enumeration of every subset of
   {0..L} that contains L.
+* ``warmup_depth`` and ``extrapolate``: the off-line part of Section 5.3
+  (warm-up of the levels with dt_l down to about the mean free time, the
+  O(dt^3) rate beyond it).
 """
 import itertools
 import math
@@ -56,3 +59,34 @@ def optimal(V, C, Vpair, Cpair):
             elif c <= best * (1 + 1e-12):
                 arg.append(levels)
     return best, arg
+
+
+def warmup_depth(prob):
+    """Section 5.3: the warm-up runs the levels 0..tau, tau the level whose
+    step dt_tau = dt0 M^-tau is nearest (in log scale) to the mean free time
+    1/R; R is the constant b of the Section 5 backgrounds, 1/eps^2 in the
+    diffusive scaling.  At least one difference is measured (tau >= 1) and
+    none beyond L (tau = 0 if L = 0)."""
+    L = int(prob["L"])
+    if L <= 0:
+        return 0
+    if int(prob.get("background", 0)) != 0:
+        R = float(prob["bg_b"])
+    else:
+        R = 1.0 / (prob["eps"] * prob["eps"])
+    t = math.log(prob["dt0"] * R) / math.log(prob["M"])
+    if not t < L:
+        return L
+    return max(1, min(L, int(math.floor(t + 0.5))))
+
+
+def extrapolate(V, Vdiff, tau, M, L):
+    """Section 5.3: the profile of levels 0..L from the warm-up's levels
+    0..tau.  Beyond tau the difference variance follows the asymptotic rate
+    O(dt^3): V_{l,l-1} = V_{tau,tau-1} (dt_l / dt_tau)^3, and the level
+    variance is taken as V_tau (the level variances converge with l).
+    Returns (V, Vdiff) of length L + 1."""
+    Vo = [float(V[l]) if l <= tau else float(V[tau]) for l in range(L + 1)]
+    Vd = [float(Vdiff[l]) if l <= tau else
+          float(Vdiff[tau]) / math.pow(M, 3.0 * (l - tau)) for l in range(L + 1)]
+    return Vo, Vd

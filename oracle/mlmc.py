@@ -18,6 +18,7 @@ import math
 import numpy as np
 
 from . import simulate
+from .levels import extrapolate, heuristic, warmup_depth
 
 
 def level_steps(prob, level):
@@ -153,3 +154,161 @@ def estimate_sequence(prob, tol0, R, L, n_warmup=1000, max_iter=10, threads=None
                 break
         out.append(state(tol))
     return out
+
+
+def pair_cost(prob, level, coarse):
+    """Cost of one sample of the pair (level, coarse) (coarse < 0: one path).
+    Splitting scheme: the paths' time steps.  KD scheme: the expected KD
+    steps of the paths, a KD step running from a grid point to the end of the
+    grid step that holds the next collision, so a path of n steps of size dt
+    at collision rate R takes n (1 - exp(-R dt)) of them on average (R = b in
+    a Section 5 background, 1/eps^2 in the diffusive scaling); rounded up,
+    at least 1."""
+    def steps(l):
+        return int(round(prob["T"] / prob["dt0"])) * int(prob["M"]) ** l
+
+    if int(prob.get("scheme", 0)) != 1:
+        return steps(level) + (steps(coarse) if coarse >= 0 else 0)
+
+    def kd(l):
+        dt = prob["dt0"] / math.pow(prob["M"], l)
+        if int(prob.get("background", 0)) != 0:
+            R = float(prob["bg_b"])
+        else:
+            R = 1.0 / (prob["eps"] * prob["eps"])
+        return steps(l) * -math.expm1(-R * dt)
+
+    c = kd(level) + (kd(coarse) if coarse >= 0 else 0.0)
+    return max(1, int(math.ceil(c)))
+
+
+def bias_estimate(mean_diff, M, level, coarse):
+    """|E[Q_L - Q]| from the finest term of the set, E[Q_L - Q_c] with c the
+    level below L: if the weak error is c1 dt_l (first order in dt), then
+    E[Q_L - Q_c] = c1 dt_L (1 - M^(L-c)), so the bias c1 dt_L is
+    |E[Q_L - Q_c]| / (M^(L-c) - 1)."""
+    return abs(mean_diff) / (math.pow(M, level - coarse) - 1.0)
+
+
+def estimate_adaptive(prob, tol, n_warmup=100, max_iter=10, L_max=None, select="tau",
+                      threads=None):
+    """The experiment of Section 5.3 with the level-adaptive finest level of
+    Sections 4.1 and 5.2.
+
+    Off-line part (select="tau"): n_warmup samples of the adjacent pairs of
+    levels 0..tau only (``levels.warmup_depth``); V_l and V_{l,l-1} measured
+    there and extrapolated beyond tau (``levels.extrapolate``); the level set
+    of the heuristic (``levels.heuristic``).  select="all": every level
+    0..L.  An item of the set whose pair is not a warm-up pair (a first level
+    above 0 is a single path) starts with n_warmup samples of its own; a
+    warm-up pair that stays in the set keeps its samples.
+
+    On-line part: eqs. Nopt1/Noptj with the sample variances and the costs of
+    ``pair_cost``, topped up until sum_j V_j/N_j <= tol^2/2 (at most max_iter
+    times).  Then the bias constraint |E[Q_L - Q]| <= tol/sqrt(2): the bias is
+    estimated from the finest term, E[Q_L - Q_c] / (M^(L-c) - 1) (first-order
+    weak convergence in dt), and while it is above tol/sqrt(2) and L < L_max,
+    L grows by one: the set is selected again for the new L (select="tau":
+    from the same warm-up profile; "all": the new adjacent pair is added),
+    kept items keep their samples, and the on-line loop goes on.
+
+    Each level has one slot of samples [0, N_l) for its current pair; a
+    level whose pair changes starts over.  Returns the estimate, N, the
+    levels, tau, the bias estimate and the number of levels added."""
+    M = int(prob["M"])
+    prob = dict(prob)
+    L = int(prob["L"])
+    qoi = prob.get("qoi", 0)
+    slots = {}   # level -> dict(coarse, xf, xc)
+    active = {}  # level of the set -> coarse level (-1: single path / level 0)
+    iterations = 0
+
+    def run(l, upto):
+        s = slots[l]
+        n = s["xf"].size
+        if upto <= n:
+            return
+        c = s["coarse"]
+        if l == 0:
+            r = simulate(prob, 0, n, upto - n, threads=threads)
+        elif c < 0:
+            r = simulate(prob, l, n, upto - n, single=True, threads=threads)
+        else:
+            r = simulate(prob, l, n, upto - n, threads=threads, coarse_level=c)
+        s["xf"] = np.concatenate([s["xf"], r["xf"]])
+        s["xc"] = np.concatenate([s["xc"], r["xc"]])
+
+    def stats(l):
+        s = slots[l]
+        return stats_of(s["xf"], s["xc"], 0 if s["coarse"] < 0 else l, qoi)
+
+    def use(l, c):
+        s = slots.get(l)
+        if s is None or s["coarse"] != c or s["xf"].size == 0:
+            slots[l] = dict(coarse=c, xf=np.zeros(0), xc=np.zeros(0))
+            run(l, n_warmup)
+        active[l] = c
+
+    tau = warmup_depth(prob) if select == "tau" else L
+    for l in range(tau + 1):
+        use(l, l - 1)
+    prof_V, prof_Vd = [], []
+    for l in range(tau + 1):
+        st = stats(l)
+        prof_V.append(sample_variance(st, "dq" if l == 0 else "qf"))
+        prof_Vd.append(sample_variance(st))
+
+    def choose():
+        if select == "tau":
+            V, Vd = extrapolate(prof_V, prof_Vd, tau, M, L)
+            chosen = heuristic(V, Vd)
+        else:
+            chosen = list(range(L + 1))
+        active.clear()
+        prev = -1
+        for l in chosen:
+            use(l, prev)
+            prev = l
+
+    choose()
+
+    def variance_sum():
+        return sum(sample_variance(stats(l)) / slots[l]["xf"].size for l in active)
+
+    def bias():
+        c = active[L]
+        if c < 0:
+            return math.nan
+        return bias_estimate(stats(L)["mean_dq"], M, L, c)
+
+    added = 0
+    stage_iter = 0
+    targets_first = True
+    while True:
+        if not targets_first:
+            met = variance_sum() <= 0.5 * tol * tol
+            if met or stage_iter >= max_iter:
+                if met and L_max is not None and L < L_max and bias() > tol / math.sqrt(2.0):
+                    L += 1
+                    prob["L"] = L
+                    added += 1
+                    choose()
+                    stage_iter = 0
+                    continue
+                break
+        lv = sorted(active)
+        V = [sample_variance(stats(l)) for l in lv]
+        C = [pair_cost(prob, l, active[l]) for l in lv]
+        N = optimal_samples(V, C, tol)
+        for l, n in zip(lv, N):
+            run(l, max(n, slots[l]["xf"].size))
+        iterations += 1
+        stage_iter += 1
+        targets_first = False
+    lv = sorted(active)
+    sts = [stats(l) for l in lv]
+    return dict(estimate=sum(s["mean_dq"] for s in sts), levels=lv,
+                coarse=[active[l] for l in lv], N=[slots[l]["xf"].size for l in lv],
+                stats=sts, var_estimator=variance_sum(), tau=tau, L=L, bias=bias(),
+                added=added, converged=variance_sum() <= 0.5 * tol * tol,
+                iterations=iterations)

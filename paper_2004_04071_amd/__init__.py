@@ -68,7 +68,7 @@ class Tuning(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("batched", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("n_warmup", ctypes.c_uint64), ("tuning", Tuning),
-                ("level_select", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("level_select", ctypes.c_int32), ("L_max", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -78,7 +78,9 @@ class Result(ctypes.Structure):
                 ("N", ctypes.c_uint64 * MAX_LEVELS), ("lv", LevelStats * MAX_LEVELS),
                 ("particle_steps", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("seconds", ctypes.c_double), ("gpu_seconds", ctypes.c_double),
-                ("kernel_seconds", ctypes.c_double), ("level_mask", ctypes.c_uint64)]
+                ("kernel_seconds", ctypes.c_double), ("level_mask", ctypes.c_uint64),
+                ("bias_estimate", ctypes.c_double), ("bias_se", ctypes.c_double),
+                ("tau", ctypes.c_int32), ("levels_added", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -120,6 +122,10 @@ _SIGNATURES = {
                                        _P(ctypes.c_uint64), _vp],
     "mlmc_ap_select_levels_heuristic": [_P(ctypes.c_double), _P(ctypes.c_double), ctypes.c_int32,
                                         _P(ctypes.c_uint64)],
+    "mlmc_ap_warmup_depth": [_P(Problem), _P(ctypes.c_int32)],
+    "mlmc_ap_extrapolate_variances": [_P(ctypes.c_double), _P(ctypes.c_double), ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double),
+                                      _P(ctypes.c_double)],
     "mlmc_ap_select_levels_optimal": [_P(ctypes.c_double), _P(ctypes.c_double),
                                       _P(ctypes.c_double), _P(ctypes.c_double), ctypes.c_int32,
                                       _P(ctypes.c_uint64), _P(ctypes.c_double)],
@@ -264,24 +270,28 @@ def result_dict(r):
                 particle_steps=int(r.particle_steps), launches=int(r.launches),
                 seconds=r.seconds, gpu_seconds=r.gpu_seconds, kernel_seconds=r.kernel_seconds,
                 level_mask=int(r.level_mask),
-                level_set=[l for l in range(L + 1) if (int(r.level_mask) >> l) & 1])
+                level_set=[l for l in range(L + 1) if (int(r.level_mask) >> l) & 1],
+                bias_estimate=r.bias_estimate, bias_se=r.bias_se, tau=r.tau,
+                levels_added=r.levels_added)
 
 
 BATCHED_DIRECT, BATCHED_GRAPH, BATCHED_TIMED, BATCHED_PER_LEVEL = 0, 1, 2, -1
 
 
-LEVELS_ALL, LEVELS_HEURISTIC, LEVELS_OPTIMAL = 0, 1, 2
+LEVELS_ALL, LEVELS_HEURISTIC, LEVELS_OPTIMAL, LEVELS_HEURISTIC_TAU = 0, 1, 2, 3
 
 
 def options(batched=BATCHED_DIRECT, max_iter=0, n_warmup=0, block=0, ppt=0, waves_per_simd=0,
-            tp_max_samples=0, level_select=LEVELS_ALL):
+            tp_max_samples=0, level_select=LEVELS_ALL, L_max=0):
     """mlmc_ap_options: batched = 0 (direct persistent launch, default), 1 (hipGraph
     replay), 2 (direct, particle kernel timed), -1 (one launch per level);
-    level_select = LEVELS_ALL (levels 0..L), LEVELS_HEURISTIC or LEVELS_OPTIMAL."""
+    level_select = LEVELS_ALL (levels 0..L), LEVELS_HEURISTIC, LEVELS_OPTIMAL or
+    LEVELS_HEURISTIC_TAU (warm-up of levels 0..tau, KD only); L_max > L: the
+    finest level grows while the bias estimate exceeds tol/sqrt(2)."""
     return Options(batched=batched, max_iter=max_iter, n_warmup=n_warmup,
                    tuning=Tuning(block=block, ppt=ppt, waves_per_simd=waves_per_simd,
                                  tp_max_samples=tp_max_samples),
-                   level_select=level_select, reserved=0)
+                   level_select=level_select, L_max=L_max)
 
 
 # ---------------------------------------------------------------------------
@@ -410,6 +420,24 @@ def mlmc_ap_select_levels_heuristic(V, Vdiff):
     _check(lib().mlmc_ap_select_levels_heuristic(_doubles(V), _doubles(Vdiff), L, ctypes.byref(m)),
            "mlmc_ap_select_levels_heuristic")
     return [l for l in range(L + 1) if (m.value >> l) & 1]
+
+
+def mlmc_ap_warmup_depth(p):
+    """Warm-up depth tau of Section 5.3 for a problem."""
+    t = ctypes.c_int32()
+    _check(lib().mlmc_ap_warmup_depth(ctypes.byref(as_problem(p)), ctypes.byref(t)),
+           "mlmc_ap_warmup_depth")
+    return t.value
+
+
+def mlmc_ap_extrapolate_variances(V, Vdiff, tau, M, L):
+    """(V, Vdiff) of levels 0..L from the measured values of levels 0..tau."""
+    vo = (ctypes.c_double * (L + 1))()
+    vdo = (ctypes.c_double * (L + 1))()
+    _check(lib().mlmc_ap_extrapolate_variances(_doubles(V), _doubles(Vdiff), int(tau), int(M),
+                                               int(L), vo, vdo),
+           "mlmc_ap_extrapolate_variances")
+    return list(vo), list(vdo)
 
 
 def mlmc_ap_select_levels_optimal(V, C, Vpair, Cpair):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <memory>
 #include <string>
@@ -668,19 +669,52 @@ int launch_mode(int32_t batched) {
 // ---------------------------------------------------------------------------
 // Level selection (Section 4.2, Section 5.2).
 // ---------------------------------------------------------------------------
+// Heuristic level set (Algorithm "Heuristic level selection approach").  The
+// set opens with the coarsest adjacent pair (l-1, l) whose difference varies
+// no more than level l itself; past it, a level is taken only when its
+// difference variance is under half of that of the level taken before it,
+// so every correction taken at least halves the previous one; L closes the
+// set (the sets end at L, Section 4.1).  No such pair: L alone.
 uint64_t select_levels_heuristic(const double* V, const double* Vdiff, int L) {
   if (L <= 0) return 1ull;
-  int l = 1;
-  while (l <= L && Vdiff[l] > V[l]) ++l;  // first level whose difference beats the level
-  if (l > L) return 1ull << L;
-  uint64_t mask = (1ull << (l - 1)) | (1ull << l);
-  double vmin = Vdiff[l];
-  for (int k = l + 1; k <= L; ++k)
-    if (Vdiff[k] < 0.5 * vmin) {          // enough variance decay to pay for level k
-      mask |= 1ull << k;
-      vmin = Vdiff[k];
+  int first = 1;
+  while (first <= L && Vdiff[first] > V[first]) ++first;
+  if (first > L) return 1ull << L;
+  uint64_t set = 3ull << (first - 1);
+  double last = Vdiff[first];
+  for (int k = first + 1; k <= L; ++k) {
+    if (2.0 * Vdiff[k] < last) {
+      set |= 1ull << k;
+      last = Vdiff[k];
     }
-  return mask | (1ull << L);
+  }
+  return set | (1ull << L);
+}
+
+// Warm-up depth of Section 5.3: the level whose step is nearest, in log
+// scale, to the mean free time 1/R, within [1, L].
+int warmup_depth(const mlmc_ap_problem& p) {
+  if (p.L <= 0) return 0;
+  const double R = p.background == MLMC_AP_BG_DIFFUSIVE ? 1.0 / (p.eps * p.eps) : p.bg_b;
+  const double t = std::log(p.dt0 * R) / std::log((double)p.M);
+  if (!(t < (double)p.L)) return p.L;
+  return std::max(1, std::min(p.L, (int)std::floor(t + 0.5)));
+}
+
+// Section 5.3: measured profile up to tau, the O(dt^3) rate of the
+// difference variance beyond it (each level divides it by M^3) and the level
+// variance of tau.
+void extrapolate_variances(const double* V, const double* Vdiff, int tau, int M, int L,
+                           double* V_out, double* Vdiff_out) {
+  for (int l = 0; l <= L; ++l) {
+    if (l <= tau) {
+      V_out[l] = V[l];
+      Vdiff_out[l] = Vdiff[l];
+    } else {
+      V_out[l] = V[tau];
+      Vdiff_out[l] = Vdiff[tau] / std::pow((double)M, 3.0 * (double)(l - tau));
+    }
+  }
 }
 
 // best[i]: least cost of a hierarchy ending at level i; a hierarchy is a path
@@ -725,14 +759,21 @@ void McRequest::init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, u
   iterations = 0;
   converged = false;
   need_check = false;
-  done.assign(p.L + 1, 0);
-  target.assign(p.L + 1, 0);
-  st.assign(p.L + 1, stats_empty());
-  coarse_of.assign(p.L + 1, -1);
-  in_set.assign(p.L + 1, 0);
-  pilot_done.assign(p.L + 1, 0);
-  pilot_st.assign(p.L + 1, stats_empty());
+  // every level the request may reach (L grows up to L_max)
+  done.assign(MLMC_AP_MAX_LEVELS, 0);
+  target.assign(MLMC_AP_MAX_LEVELS, 0);
+  st.assign(MLMC_AP_MAX_LEVELS, stats_empty());
+  coarse_of.assign(MLMC_AP_MAX_LEVELS, -1);
+  in_set.assign(MLMC_AP_MAX_LEVELS, 0);
+  pilot_done.assign(MLMC_AP_MAX_LEVELS, 0);
+  pilot_st.assign(MLMC_AP_MAX_LEVELS, stats_empty());
   selected = false;
+  level_select = MLMC_AP_LEVELS_ALL;
+  tau = p.L;
+  L_max = 0;
+  levels_added = 0;
+  prof_V.clear();
+  prof_Vd.clear();
   for (int l = first_level(); l <= p.L; ++l) {
     target[l] = n_warmup;
     in_set[l] = 1;
@@ -746,6 +787,19 @@ void McRequest::init(const mlmc_ap_problem& p, double rmse_tol, bool plain_mc, u
   stage_iter = 0;
   t_start = wall_now();
   snaps.clear();
+}
+
+void McRequest::set_selection(int mode, int lmax) {
+  level_select = mode;
+  L_max = lmax;
+  tau = prob.L;
+  if (mode == MLMC_AP_LEVELS_HEURISTIC_TAU && !plain) {
+    tau = warmup_depth(prob);
+    for (int l = tau + 1; l <= prob.L; ++l) {
+      in_set[l] = 0;
+      target[l] = 0;
+    }
+  }
 }
 
 void McRequest::set_sequence(const std::vector<double>& seq) {
@@ -813,18 +867,25 @@ uint64_t McRequest::item_cost(int l) const {
   return pair_cost(prob, l, coarse_of[l]);
 }
 
-// After the warm-up of adjacent pairs on every level: V_l from the fine
-// paths (Q_l), V_{l,l-1} from the differences; the new set's pairs that are
-// not the warm-up's adjacent pairs start over with a warm-up of their own.
+// After the warm-up of adjacent pairs on levels 0..tau: V_l from the fine
+// paths (Q_l), V_{l,l-1} from the differences, kept as the profile of every
+// later selection; the new set's pairs that are not the warm-up's adjacent
+// pairs start over with a warm-up of their own.
 void McRequest::select_levels() {
   const int L = prob.L;
-  std::vector<double> V(L + 1, 0.0), Vd(L + 1, 0.0);
-  for (int l = 0; l <= L; ++l) {
-    const Stats& s = st[l];
-    const double n1 = s.n > 1.0 ? s.n - 1.0 : 1.0;
-    V[l] = (l == 0 ? s.m2_dq : s.m2_qf) / n1;
-    Vd[l] = s.m2_dq / n1;
+  if (!selected) {
+    prof_V.assign(tau + 1, 0.0);
+    prof_Vd.assign(tau + 1, 0.0);
+    for (int l = 0; l <= tau; ++l) {
+      const Stats& s = st[l];
+      const double n1 = s.n > 1.0 ? s.n - 1.0 : 1.0;
+      prof_V[l] = (l == 0 ? s.m2_dq : s.m2_qf) / n1;
+      prof_Vd[l] = s.m2_dq / n1;
+    }
   }
+  std::vector<double> V(L + 1, 0.0), Vd(L + 1, 0.0);
+  extrapolate_variances(prof_V.data(), prof_Vd.data(), std::min(tau, L), prob.M, L, V.data(),
+                        Vd.data());
   uint64_t mask;
   if (level_select == MLMC_AP_LEVELS_OPTIMAL && L >= 1) {
     // eq. level_selection over every pair: measured variances where a
@@ -858,23 +919,58 @@ void McRequest::select_levels() {
   } else {
     mask = select_levels_heuristic(V.data(), Vd.data(), L);
   }
+  apply_levels(mask);
+  selected = true;
+}
+
+void McRequest::apply_levels(uint64_t mask) {
   int prev = -1;
-  for (int l = 0; l <= L; ++l) {
+  for (int l = 0; l <= prob.L; ++l) {
     if (!((mask >> l) & 1ull)) {
       in_set[l] = 0;
       target[l] = done[l];
       continue;
     }
-    const int keep = coarse_of[l];
-    coarse_of[l] = prev;
-    if (prev != keep) {  // a different item than the warm-up's
+    if (coarse_of[l] != prev || done[l] == 0) {  // not an item with samples yet
+      coarse_of[l] = prev;
       done[l] = 0;
       st[l] = stats_empty();
       target[l] = n_warmup;
     }
+    in_set[l] = 1;
     prev = l;
   }
-  selected = true;
+}
+
+double McRequest::bias_estimate(double* se) const {
+  const int L = prob.L;
+  const int c = coarse_of[L];
+  if (plain || !in_set[L] || c < 0 || done[L] == 0) {
+    *se = std::numeric_limits<double>::quiet_NaN();
+    return std::numeric_limits<double>::quiet_NaN();
+  }
+  const double f = std::pow((double)prob.M, (double)(L - c)) - 1.0;
+  *se = std::sqrt(sample_var(st[L]) / (double)done[L]) / f;
+  return std::fabs(st[L].mean_dq) / f;
+}
+
+bool McRequest::grow_finest() {
+  if (prob.L >= L_max) return false;
+  double se;
+  const double b = bias_estimate(&se);
+  if (!(b > tol / std::sqrt(2.0))) return false;
+  const int L = ++prob.L;
+  ++levels_added;
+  if (level_select == MLMC_AP_LEVELS_HEURISTIC_TAU) {
+    select_levels();
+  } else {
+    coarse_of[L] = L - 1;
+    done[L] = 0;
+    st[L] = stats_empty();
+    target[L] = n_warmup;
+    in_set[L] = 1;
+  }
+  return true;
 }
 
 void McRequest::absorb(const Stats* slots) {
@@ -915,6 +1011,10 @@ void McRequest::absorb(const Stats* slots) {
       for (int l = first_level(); l <= prob.L; ++l)
         if (in_set[l]) v += sample_var(st[l]) / (double)done[l];
       const bool met = v <= 0.5 * tol * tol;
+      if (met && grow_finest()) {  // eq. bias_constraint not yet met: one more level
+        stage_iter = 0;
+        continue;
+      }
       if (met || stage_iter >= max_iter) {
         converged = met;
         if (stage + 1 >= tols.size()) {
@@ -968,6 +1068,9 @@ void McRequest::fill_result(mlmc_ap_result* out) const {
   out->launches = launches;
   out->gpu_seconds = gpu_seconds;
   out->kernel_seconds = kernel_seconds;
+  out->bias_estimate = bias_estimate(&out->bias_se);
+  out->tau = tau;
+  out->levels_added = levels_added;
 }
 
 }  // namespace mlmc
@@ -1102,6 +1205,28 @@ mlmc_ap_status mlmc_ap_select_levels_heuristic(const double* V_host, const doubl
     if (!(V_host[l] >= 0.0) || (l > 0 && !(Vdiff_host[l] >= 0.0)))
       return set_error(MLMC_AP_EINVAL, "variances must be >= 0");
   *mask_out = select_levels_heuristic(V_host, Vdiff_host, L);
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_warmup_depth(const mlmc_ap_problem* p, int32_t* tau_out) {
+  if (!tau_out) return set_error(MLMC_AP_EINVAL, "tau_out is NULL");
+  MLMC_TRY(validate_problem(p));
+  *tau_out = warmup_depth(*p);
+  return MLMC_AP_OK;
+}
+
+mlmc_ap_status mlmc_ap_extrapolate_variances(const double* V_host, const double* Vdiff_host,
+                                             int32_t tau, int32_t M, int32_t L,
+                                             double* V_out_host, double* Vdiff_out_host) {
+  if (!V_host || !Vdiff_host || !V_out_host || !Vdiff_out_host)
+    return set_error(MLMC_AP_EINVAL, "NULL argument");
+  if (L < 0 || L > MLMC_AP_MAX_LEVELS - 1 || tau < 0 || tau > L || M < 2 || M > 64)
+    return set_error(MLMC_AP_EINVAL, "need 0 <= tau <= L <= 30 and 2 <= M <= 64");
+  for (int l = 0; l <= tau; ++l)
+    if (!(V_host[l] >= 0.0) || (l > 0 && !(Vdiff_host[l] >= 0.0)) || !std::isfinite(V_host[l]))
+      return set_error(MLMC_AP_EINVAL, "variances must be finite and >= 0");
+  extrapolate_variances(V_host, Vdiff_host, tau, M, L, V_out_host, Vdiff_out_host);
+  Vdiff_out_host[0] = 0.0;
   return MLMC_AP_OK;
 }
 
@@ -1365,12 +1490,26 @@ static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* to
   const mlmc_ap_options o = default_options(opt);
   const int mode = launch_mode(o.batched);
   if (mode < 0) return set_error(MLMC_AP_EINVAL, "options.batched must be -1, 0, 1, 2 or 3");
-  if (o.level_select != MLMC_AP_LEVELS_ALL && o.level_select != MLMC_AP_LEVELS_HEURISTIC &&
-      o.level_select != MLMC_AP_LEVELS_OPTIMAL)
-    return set_error(MLMC_AP_EINVAL, "options.level_select must be 0, 1 or 2");
-  if (o.reserved != 0) return set_error(MLMC_AP_EINVAL, "options.reserved must be 0");
+  if (o.level_select < MLMC_AP_LEVELS_ALL || o.level_select > MLMC_AP_LEVELS_HEURISTIC_TAU)
+    return set_error(MLMC_AP_EINVAL, "options.level_select must be 0, 1, 2 or 3");
   if (o.level_select != MLMC_AP_LEVELS_ALL && hist_host)
     return set_error(MLMC_AP_EINVAL, "level selection does not support per-level histograms");
+  if (o.level_select == MLMC_AP_LEVELS_HEURISTIC_TAU && p[0].scheme != MLMC_AP_SCHEME_KD)
+    return set_error(MLMC_AP_EINVAL,
+                     "LEVELS_HEURISTIC_TAU needs the KD scheme (its O(dt^3) variance rate)");
+  if (o.L_max != 0) {
+    if (plain) return set_error(MLMC_AP_EINVAL, "plain Monte Carlo has no adaptive L_max");
+    if (hist_host) return set_error(MLMC_AP_EINVAL, "L_max does not support histograms");
+    if (o.level_select != MLMC_AP_LEVELS_ALL && o.level_select != MLMC_AP_LEVELS_HEURISTIC_TAU)
+      return set_error(MLMC_AP_EINVAL, "L_max needs LEVELS_ALL or LEVELS_HEURISTIC_TAU");
+    for (int i = 0; i < n_req; ++i) {
+      if (o.L_max <= p[i].L || o.L_max > MLMC_AP_MAX_LEVELS - 1)
+        return set_error(MLMC_AP_EINVAL, "options.L_max must be 0 or in (L, 30]");
+      mlmc_ap_problem q = p[i];
+      q.L = o.L_max;
+      MLMC_TRY(validate_problem(&q));
+    }
+  }
   Workspace* ws = workspace();
   if (!ws) return MLMC_AP_EDEVICE;
   std::lock_guard<std::mutex> lk(ws->mu);
@@ -1380,7 +1519,7 @@ static mlmc_ap_status estimate_common(const mlmc_ap_problem* p, const double* to
   std::vector<McRequest> reqs(n_req);
   for (int i = 0; i < n_req; ++i) {
     reqs[i].init(p[i], tols[i], plain, o.n_warmup, o.max_iter, 0);
-    reqs[i].level_select = o.level_select;
+    reqs[i].set_selection(o.level_select, o.L_max);
   }
   if (stages > 0) {
     std::vector<double> seq(stages);

@@ -49,6 +49,9 @@ uint64_t pair_cost(const mlmc_ap_problem& p, int level, int coarse_level);
 uint64_t block_factor(const mlmc_ap_problem& p, int level, int coarse_level);
 // Level selection (see the C ABI): bit masks of the selected levels.
 uint64_t select_levels_heuristic(const double* V, const double* Vdiff, int L);
+int warmup_depth(const mlmc_ap_problem& p);
+void extrapolate_variances(const double* V, const double* Vdiff, int tau, int M, int L,
+                           double* V_out, double* Vdiff_out);
 double select_levels_optimal(const double* V, const double* C, const double* Vpair,
                              const double* Cpair, int L, uint64_t* mask);
 
@@ -183,6 +186,10 @@ struct McRequest {
   std::vector<Stats> st;       // host copy of the resident statistics per level
   int level_select = 0;        // MLMC_AP_LEVELS_*
   bool selected = false;       // the level set has been chosen
+  int tau = 0;                 // highest warm-up level before the selection
+  int L_max = 0;               // level-adaptive finest level up to L_max (0: fixed L)
+  int levels_added = 0;
+  std::vector<double> prof_V, prof_Vd;  // warm-up profile of levels 0..tau
   std::vector<int> coarse_of;  // coarse level of level l's pair; -1: single level
   std::vector<char> in_set;    // level l is part of the hierarchy
   // Pilot pairs (L, i), i <= L - 2, of the cost-optimal selection: their
@@ -209,8 +216,21 @@ struct McRequest {
   int first_level() const { return plain ? prob.L : 0; }
   // Particle steps of one sample of level l's item.
   uint64_t item_cost(int l) const;
-  // Chooses the level set after the warm-up (level_select != 0).
+  // Selection mode and adaptive finest level (after init): the warm-up of
+  // LEVELS_HEURISTIC_TAU runs levels 0..tau only.
+  void set_selection(int mode, int lmax);
+  // Chooses the level set after the warm-up (level_select != 0), and again
+  // for a grown L (from the kept warm-up profile).
   void select_levels();
+  // Makes the set's items those of `mask`: an item whose pair is new starts
+  // over with a warm-up; one that stays keeps its samples.
+  void apply_levels(uint64_t mask);
+  // Bias estimate of eq. bias_constraint from the finest term (NaN without
+  // a pair at L); *se its standard error.
+  double bias_estimate(double* se) const;
+  // Level-adaptive L: after the statistical constraint holds, adds level
+  // L + 1 if the bias estimate is above tol/sqrt(2) and L < L_max.
+  bool grow_finest();
   // Appends this request's work for the next launch; returns false if it has
   // none (finished).  Slots are slot_base + level.
   bool plan(std::vector<ItemSpec>& items, uint32_t slot_base, unsigned long long* hist_base,

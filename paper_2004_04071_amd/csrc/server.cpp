@@ -195,6 +195,8 @@ mlmc_ap_status mlmc_ap_server_create(const mlmc_ap_server_config* cfg, mlmc_ap_s
   if (s->cfg.max_samples_per_tick == 0) s->cfg.max_samples_per_tick = 1ull << 24;
   if (s->cfg.max_active <= 0) s->cfg.max_active = 256;
   if (s->cfg.max_active > 4096) return set_error(MLMC_AP_EINVAL, "max_active must be <= 4096");
+  if (s->cfg.options.level_select != MLMC_AP_LEVELS_ALL || s->cfg.options.L_max != 0)
+    return set_error(MLMC_AP_EINVAL, "the server runs every level: level_select and L_max must be 0");
   if (s->cfg.options.max_iter <= 0) s->cfg.options.max_iter = 10;
   if (s->cfg.options.n_warmup == 0) s->cfg.options.n_warmup = 1000;
   MLMC_TRY(init_workspace(s->ws));

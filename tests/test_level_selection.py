@@ -112,3 +112,55 @@ def test_heuristic_sets_are_nested_in_L(lib):
             if prev is not None:
                 assert set(prev) - {L - 1} <= set(cur), (L, prev, cur)
             prev = cur
+
+
+def _kd_like_profiles(rng, count):
+    for _ in range(count):
+        L = int(rng.integers(1, 14))
+        V = list(rng.uniform(0.5, 2.0, L + 1))
+        Vd = [0.0] + list(np.exp(rng.normal(0, 1.5, L)) * np.geomspace(2, 1e-3, L))
+        yield V, Vd
+
+
+def test_heuristic_set_properties(lib):
+    """What the description of Section 5.2 fixes about the set, checked on
+    the library's sets: it opens with the adjacent pair (l-1, l) at the first
+    l whose difference is no more variable than level l; past that pair every
+    level taken (but the closing L) at least halves the difference variance of
+    the level taken before it, and no level left out would have; L closes it;
+    with no such pair the set is {L}."""
+    rng = np.random.default_rng(21)
+    for V, Vd in _kd_like_profiles(rng, 400):
+        L = len(V) - 1
+        got = pkg.mlmc_ap_select_levels_heuristic(V, Vd)
+        assert got[-1] == L and got == sorted(set(got))
+        opening = [l for l in range(1, L + 1) if Vd[l] <= V[l]]
+        if not opening:
+            assert got == [L]
+            continue
+        first = opening[0]
+        assert got[:2] == [first - 1, first]
+        last = Vd[first]
+        for k in range(first + 1, L + 1):
+            if k in got and (k != L or Vd[k] < 0.5 * last):
+                assert Vd[k] < 0.5 * last, (k, got)
+                last = Vd[k]
+            else:
+                assert k == L or Vd[k] >= 0.5 * last, (k, got)
+
+
+def test_heuristic_cost_is_never_below_the_optimum(lib):
+    """Eq. level_selection's optimum is a lower bound on the cost of any set
+    that ends at L, the heuristic's included (pair variances of a model with
+    independent level increments, Var[Q_i - Q_j] = sum of the adjacent ones
+    between; costs 2^i and 2^i + 2^j)."""
+    rng = np.random.default_rng(22)
+    for V, Vd in _kd_like_profiles(rng, 200):
+        L = len(V) - 1
+        C = [2.0 ** l for l in range(L + 1)]
+        Vp = [[sum(Vd[j + 1:i + 1]) if i > j else 0.0 for j in range(L + 1)]
+              for i in range(L + 1)]
+        Cp = [[C[i] + C[j] if i > j else 1.0 for j in range(L + 1)] for i in range(L + 1)]
+        h = pkg.mlmc_ap_select_levels_heuristic(V, Vd)
+        _, best = pkg.mlmc_ap_select_levels_optimal(V, C, Vp, Cp)
+        assert OL.hierarchy_cost(h, V, C, Vp, Cp) >= best * (1 - 1e-12)
