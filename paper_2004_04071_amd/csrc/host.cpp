@@ -154,14 +154,18 @@ mlmc_ap_status validate_problem(const mlmc_ap_problem* p) {
 
 bool time_parallel_candidate(const ItemSpec& s, int32_t tp_max_samples) {
   const mlmc_ap_problem& p = *s.prob;
-  if (p.scheme == MLMC_AP_SCHEME_KD) return false;  // KD steps depend on the previous ones
+  const bool kd = p.scheme == MLMC_AP_SCHEME_KD;
+  // in a heterogeneous background a KD flight depends on the position
+  if (kd && p.background != MLMC_AP_BG_DIFFUSIVE && p.bg_a > 0.0) return false;
   const int64_t limit = tp_max_samples == 0 ? kTpDefaultMaxSamples : tp_max_samples;
   if (limit <= 0 || s.n_samples == 0 || s.n_samples > (uint64_t)limit) return false;
   const bool coarse = !s.single && s.level >= 1;
   const uint64_t mb = coarse ? block_factor(p, s.level, s.coarse_level >= 0 ? s.coarse_level
                                                                               : s.level - 1)
                              : 1;
-  if (coarse && mb != 2 && mb != 4) return false;  // coarse blocks inside a 64-step chunk
+  // splitting scheme: coarse blocks inside a 64-step chunk (the KD form
+  // carries its coarse steps across windows)
+  if (!kd && coarse && mb != 2 && mb != 4) return false;
   return level_const(p, s.level).n_steps >= (int64_t)kLongLevelSteps;
 }
 
@@ -584,7 +588,7 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
   if (mode == kModePerLevel) {
     MLMC_TRY(stage(ws, stream));
     MLMC_HIP(hipEventRecord(ws.ev[1], stream));
-    if (has_tp) MLMC_HIP(launch_tp(fp64, ws.items_dev, ws.hdr_dev, tp_grid(ws), stream));
+    if (has_tp) MLMC_HIP(launch_tp(fp64, ws.items_dev, ws.hdr_dev, tp_grid(ws), stream, kd));
     for (size_t i = 0; i < d.size(); ++i)
       if (!(d[i].flags & kFlagTimeParallel))
         MLMC_HIP(launch_level(fp64, tuning.ppt, d[i].kind, ws.items_dev, (uint32_t)i,

@@ -679,6 +679,188 @@ __device__ __forceinline__ Stats tp_tile_record(const LevelDesc& d, uint32_t til
   return acc.record<kCoarse>();
 }
 
+// ---------------------------------------------------------------------------
+// Time-parallel KD path or pair in a homogeneous background, for items of few
+// long paths (the warm-up of the fine levels).  A wavefront simulates one
+// sample, in windows of up to 64 fine KD steps.  With a constant collision
+// rate the only serial dependence between KD steps is the chain of collision
+// times (c_{k+1} = end of the grid step holding c_k, plus the next flight
+// E_{k+1}/R) and, for a pair, the coarse steps that chain delimits; a step's
+// position increment, its coefficients of eqs. advection and diffusion and
+// its aggregation weights depend only on its diffusive length theta and on
+// random numbers.  Per window: (A) lane j draws the numbers of step j; (B)
+// the chain is walked on wave-uniform values, lane j keeping theta of step j
+// (and, where step j ends a coarse step, that coarse step's theta and flight
+// increment); (C) every lane evaluates its step; (D) the increments and the
+// aggregation sums are added in step order on wave-uniform values.  Every
+// quantity is computed with the operations of the per-lane loop
+// (kd_sample_rec) on the same inputs, and the sums are taken in its order, so
+// both forms give bitwise identical paths.
+// ---------------------------------------------------------------------------
+template <bool COARSE>
+__device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
+  const KdParams k = kd_params(d);
+  const uint32_t lane = threadIdx.x & (kLanes - 1);
+  const uint32_t smp = (uint32_t)(d.sample_begin + local);
+  const Words w0 = philox4x32_10(0u, smp, k.tag, k.strm, k.key0, k.key1);
+  double nc, ns;
+  box_muller(w0.w0, w0.w1, nc, ns);
+  double x0;
+  if (d.x0_kind == 0) x0 = d.x0_a;
+  else if (d.x0_kind == 1) x0 = d.x0_a + d.x0_b * nc;
+  else x0 = cosine_icdf(uniform_f64(w0.w3));
+  const double E0 = -log(uniform_f64(w0.w2));
+
+  double xf = x0, vf = k.mu + k.sigma * ns, tf = 0.0, tauf = E0 * k.inv_r;
+  double cfine = tf + tauf;
+  uint32_t cf = 0, cc = 0, b = 1;
+  double xc = x0, vc = vf, tc = 0.0, ccoarse = cfine;
+  double nu_f = ns;                          // velocity number of the pending flight
+  double nf = floor(cfine / k.dtf) + 1.0;    // pair: grid end of the pending flight's step
+  double end_c = 0.0, end_c_fine = 0.0, num = 0.0, den = 0.0, zeta_prev = 0.0;
+  bool in_inner = false, done = false;
+
+#pragma unroll 1
+  while (!done) {
+    // (A) the numbers of the window's steps: lane j takes Philox block b + j
+    double nu_next, chi, E_next;
+    kd_draws(k, smp, b + lane, nu_next, chi, E_next);
+    // inputs of the window's first step that come from the step before it
+    const double tauf0 = tauf, vf0 = vf, nu_f0 = nu_f, zeta0 = zeta_prev;
+
+    // (B) the collision-time chain and the coarse steps
+    double theta = 0.0, theta_c = 0.0, pc = 0.0;
+    uint64_t first_m = 0, exit_m = 0, upd_m = 0;
+    uint32_t cnt = 0;
+#pragma unroll 1
+    for (uint32_t j = 0; j < (uint32_t)kLanes; ++j) {
+      double th;
+      if constexpr (!COARSE) {
+        if (!(cfine < k.T && cf < k.guard)) {
+          done = true;
+          break;
+        }
+        const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
+        th = t_next - cfine;
+        tf = t_next;
+        tauf = lane_value(E_next, j) * k.inv_r;
+        cfine = tf + tauf;
+      } else {
+        if (!in_inner) {  // head of the per-lane loop's outer iteration
+          if (!((ccoarse < k.T || cfine < k.T) && cf < k.guard)) {
+            done = true;
+            break;
+          }
+          end_c = floor(ccoarse / k.dtc) + 1.0;
+          end_c_fine = end_c * (double)k.M;
+          first_m |= 1ull << j;
+          in_inner = true;
+        }
+        const double t_next = nf * k.dtf;
+        th = t_next - cfine;
+        tf = t_next;
+        tauf = lane_value(E_next, j) * k.inv_r;
+        cfine = tf + tauf;
+        nf = floor(cfine / k.dtf) + 1.0;
+      }
+      theta = lane == j ? th : theta;
+      ++cf;
+      ++cnt;
+      if constexpr (COARSE) {
+        if (!(!(nf > end_c_fine) && cf < k.guard)) {  // the inner loop ends after step j
+          in_inner = false;
+          exit_m |= 1ull << j;
+          if (ccoarse < k.T) {
+            const double t_next_c = end_c * k.dtc;
+            const double thc = t_next_c - ccoarse;
+            const double p_c = vc * (ccoarse - tc);
+            theta_c = lane == j ? thc : theta_c;
+            pc = lane == j ? p_c : pc;
+            tc = t_next_c;
+            ccoarse = cfine;
+            vc = k.mu + k.sigma * lane_value(nu_next, j);
+            ++cc;
+            upd_m |= 1ull << j;
+          }
+        }
+      }
+    }
+    if (cnt == 0) break;
+
+    // (C) each lane's step: flight and diffusive increments, weights
+    const uint32_t up = lane == 0 ? 0u : lane - 1u;
+    const double E_up = __shfl(E_next, (int)up, kLanes);
+    const double nu_up = __shfl(nu_next, (int)up, kLanes);
+    const double tauf_j = lane == 0 ? tauf0 : E_up * k.inv_r;
+    const double vf_j = lane == 0 ? vf0 : k.mu + k.sigma * nu_up;
+    const double y = k.R * theta;
+    const double em = kd_em(y);
+    const double v_next = k.mu + k.sigma * nu_next;
+    double a, dd;
+    kd_coeffs(k, theta, y, em, v_next, a, dd);
+    const double p = vf_j * tauf_j;
+    const double q = a + dd * chi;
+    double A1 = 0.0, A2 = 0.0, B1 = 0.0, B2 = 0.0, ac = 0.0, ddc = 0.0;
+    if constexpr (COARSE) {
+      const double nu_f_j = lane == 0 ? nu_f0 : nu_up;
+      const double zeta = -em * k.inv_r;
+      const double yp = kd_h(y, em);
+      const double beta = sqrt(k.c2 * kd_h(yp, yp < kKdSeriesY ? 0.0 : kd_em(yp)));
+      const double zeta_up = __shfl(zeta, (int)up, kLanes);
+      const double alpha = (tauf_j + (lane == 0 ? zeta0 : zeta_up)) * k.sigma;
+      A1 = alpha * nu_f_j;
+      A2 = alpha * alpha;
+      B1 = beta * chi;
+      B2 = beta * beta;
+      zeta_prev = lane_value(zeta, cnt - 1u);
+      // coarse coefficients, kept by the lanes whose step ends a coarse step
+      const double yc = k.R * theta_c;
+      kd_coeffs(k, theta_c, yc, kd_em(yc), v_next, ac, ddc);
+    }
+
+    // (D) the sums in step order
+#pragma unroll 1
+    for (uint32_t j = 0; j < cnt; ++j) {
+      xf = xf + lane_value(p, j) + lane_value(q, j);
+      if constexpr (COARSE) {
+        if (!((first_m >> j) & 1ull)) {
+          num += lane_value(A1, j);
+          den += lane_value(A2, j);
+        }
+        num += lane_value(B1, j);
+        den += lane_value(B2, j);
+        if ((exit_m >> j) & 1ull) {
+          if ((upd_m >> j) & 1ull) {
+            const double chi_c = den > 0.0 ? num / sqrt(den) : 0.0;
+            xc = xc + lane_value(pc, j) + (lane_value(ac, j) + lane_value(ddc, j) * chi_c);
+          }
+          num = 0.0;
+          den = 0.0;
+        }
+      }
+    }
+    const double nu_last = lane_value(nu_next, cnt - 1u);
+    nu_f = nu_last;
+    vf = k.mu + k.sigma * nu_last;
+    b += cnt;
+  }
+  if (tf < k.T) xf = xf + vf * (k.T - tf);
+  if constexpr (COARSE) {
+    if (tc < k.T) xc = xc + vc * (k.T - tc);
+  }
+  const double xco = COARSE ? xc : 0.0;
+  const uint32_t cco = COARSE ? cc : 0u;
+  if (lane == 0) {
+    TpSample r;
+    r.xf = xf;
+    r.xc = xco;
+    r.cf = cf;
+    r.cc = cco;
+    d.tp_out[local] = r;
+    if (d.flags & kFlagSampleOutputs) sample_outputs<double, COARSE>(d, local, xf, xco, cf, cco);
+  }
+}
+
 // One tile of an item (per-lane loop).
 template <typename Real, int P, int KIND>
 __device__ __forceinline__ void run_unit(const LevelDesc& d, uint32_t unit,
@@ -788,6 +970,27 @@ __device__ __forceinline__ void run_tp_index(const LevelDesc* __restrict__ items
   }
 }
 
+// Trajectory g of the time-parallel space of a KD work table.
+__device__ __forceinline__ void run_kd_tp_index(const LevelDesc* __restrict__ items,
+                                                uint32_t n_items, uint32_t g,
+                                                const uint32_t* tp_bases) {
+  uint32_t lo = 0;
+  if (tp_bases) {
+    lo = last_base_le(tp_bases, n_items, g);
+  } else {
+    uint32_t hi = n_items;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (items[mid].tp_base <= g) lo = mid; else hi = mid;
+    }
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const LevelDesc d = items[lo];
+  const uint32_t local = g - d.tp_base;
+  if (d.kind == kKindKdPair) run_kd_tp<true>(d, local);
+  else run_kd_tp<false>(d, local);
+}
+
 // The time-parallel items alone (the per-level launch form).
 template <typename Real>
 __global__ void __launch_bounds__(256) tp_kernel(const LevelDesc* __restrict__ items,
@@ -797,6 +1000,16 @@ __global__ void __launch_bounds__(256) tp_kernel(const LevelDesc* __restrict__ i
   const uint32_t waves = gridDim.x * (blockDim.x / kLanes);
   const uint32_t first = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kLanes);
   for (uint32_t g = first; g < total; g += waves) run_tp_index<Real>(items, n_items, g, nullptr);
+}
+
+// The time-parallel items of a KD table alone (the per-level launch form).
+__global__ void __launch_bounds__(256) kd_tp_kernel(const LevelDesc* __restrict__ items,
+                                                     const WorkHeader* __restrict__ hdr) {
+  const uint32_t n_items = hdr->n_items;
+  const uint32_t total = hdr->total_tp;
+  const uint32_t waves = gridDim.x * (blockDim.x / kLanes);
+  const uint32_t first = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kLanes);
+  for (uint32_t g = first; g < total; g += waves) run_kd_tp_index(items, n_items, g, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -837,12 +1050,14 @@ __global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __rest
                                               threadIdx.x / kLanes);  // static index
   // Time-parallel trajectories first, dealt from the last wavefront down (the
   // chunk streams hand out their first chunks to the first wavefronts).
-  const uint32_t total_tp = KD ? 0u : hdr->total_tp;
+  const uint32_t total_tp = hdr->total_tp;
   if (total_tp) {
     const uint32_t waves = gridDim.x * wpb;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + threadIdx.x / kLanes);
-    for (uint32_t t = waves - 1u - wave; t < total_tp; t += waves)
-      run_tp_index<Real>(items, n_items, t, lds ? tp_bases : nullptr);
+    for (uint32_t t = waves - 1u - wave; t < total_tp; t += waves) {
+      if constexpr (KD) run_kd_tp_index(items, n_items, t, lds ? tp_bases : nullptr);
+      else run_tp_index<Real>(items, n_items, t, lds ? tp_bases : nullptr);
+    }
   }
   if (!one_round) {
     unsigned int first = 0;
@@ -1218,8 +1433,10 @@ hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev, 
 }
 
 hipError_t launch_tp(bool fp64, const LevelDesc* items_dev, const WorkHeader* hdr_dev, int grid,
-                     hipStream_t s) {
-  if (fp64)
+                     hipStream_t s, bool kd) {
+  if (kd)
+    hipLaunchKernelGGL(kd_tp_kernel, dim3(grid), dim3(256), 0, s, items_dev, hdr_dev);
+  else if (fp64)
     hipLaunchKernelGGL(tp_kernel<double>, dim3(grid), dim3(256), 0, s, items_dev, hdr_dev);
   else
     hipLaunchKernelGGL(tp_kernel<float>, dim3(grid), dim3(256), 0, s, items_dev, hdr_dev);

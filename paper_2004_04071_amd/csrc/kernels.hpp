@@ -39,9 +39,10 @@ hipError_t launch_persistent(bool fp64, int ppt, const LevelDesc* items_dev,
 hipError_t launch_reduce(const LevelDesc* items_dev, const WorkHeader* hdr_dev, Stats* partials,
                          Stats* groups, unsigned int* item_done, Stats* resident, Stats* mirror,
                          int grid, hipStream_t s);
-// Time-parallel items of the table (one wavefront per trajectory, grid-stride).
+// Time-parallel items of the table (one wavefront per trajectory, grid-stride);
+// kd: the kinetic-diffusion form.
 hipError_t launch_tp(bool fp64, const LevelDesc* items_dev, const WorkHeader* hdr_dev, int grid,
-                     hipStream_t s);
+                     hipStream_t s, bool kd);
 // Work table and header from host-mapped pinned memory to the device; clears
 // the persistent kernel's chunk counters and the reduction's item counters.
 hipError_t launch_stage(const WorkHeader* hdr_src, const LevelDesc* items_src, uint32_t cap,

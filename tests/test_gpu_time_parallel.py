@@ -110,3 +110,75 @@ def test_estimates_equal_with_and_without_time_parallel(batched):
     on = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=batched))
     off = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=batched, tp_max_samples=-1))
     assert key(on) == key(off)
+
+
+# Kinetic-diffusion items (homogeneous background): the time-parallel form
+# walks the collision-time chain on wave-uniform values and sums the step
+# increments in the per-lane loop's order.
+KD_CASES = [
+    ("kd_pair_l6", W.cfg_kd(eps=0.01, stream_id=91), 6, 0, 100, False),
+    ("kd_pair_l8_ragged", W.cfg_kd(eps=0.01, stream_id=92), 8, 5, 70, False),
+    ("kd_single_l6", W.cfg_kd(eps=0.01, stream_id=93), 6, 3, 100, True),
+    ("kd_fine_l0_long", dict(W.cfg_kd(eps=0.01, stream_id=94), dt0=1.0 / 128), 0, 0, 65, False),
+    ("kd_pair_l7_sparse", W.cfg_kd(eps=0.3, stream_id=95), 7, 0, 130, False),
+    ("kd_pair_l6_flights_past_T", W.cfg_kd(eps=2.0, stream_id=96), 6, 9, 64, False),
+    ("kd_pair_l10_many_windows", dict(W.cfg_kd(eps=0.01, stream_id=97), L=10), 10, 0, 20, False),
+    ("kd_pair_m3_l4", dict(W.cfg_kd(eps=0.05, stream_id=98), M=3, L=5), 4, 0, 90, False),
+    ("kd_pair_m4_l4", dict(W.cfg_kd(eps=0.05, stream_id=99), M=4, L=5), 4, 1, 90, False),
+    ("kd_cosine_x0_l6", dict(W.cfg_kd(eps=0.05, stream_id=100), x0_kind=2), 6, 0, 80, False),
+    ("kd_bg_a0_l10", W.cfg_bg(a=0.0, b=1000.0, L=12, stream_id=101), 10, 0, 64, False),
+]
+
+
+@pytest.mark.parametrize("name,prob,level,begin,n,single", KD_CASES, ids=[c[0] for c in KD_CASES])
+def test_kd_time_parallel_equals_per_lane(name, prob, level, begin, n, single):
+    say("case", name)
+    a = run(prob, level, begin, n, single, tp=True)
+    b = run(prob, level, begin, n, single, tp=False)
+    assert a[0] == b[0], "statistics differ"
+    assert torch.equal(a[1], b[1]), "positions differ"
+    assert torch.equal(a[2], b[2]), "KD step counts differ"
+    assert a[0]["n"] == n and not torch.isnan(a[1]).any()
+
+
+def test_kd_time_parallel_nonadjacent_pair_equals_per_lane():
+    """Levels 7 and 4 (block factor 8): coarse steps of up to 8 fine steps,
+    carried across the 64-step windows."""
+    prob = W.cfg_kd(eps=0.05, stream_id=102)
+    res = []
+    for tp in (DEFAULT_TP, -1):
+        pkg.mlmc_ap_set_tuning(tp_max_samples=tp)
+        traj = torch.zeros(2 * 100, dtype=torch.float64, device="cuda")
+        coll = torch.zeros(2 * 100, dtype=torch.int32, device="cuda")
+        st = pkg.mlmc_ap_simulate_pair(prob, 7, 4, 0, 100, traj=traj, coll=coll)
+        torch.cuda.synchronize()
+        res.append((st, traj.cpu(), coll.cpu()))
+    pkg.mlmc_ap_set_tuning(tp_max_samples=DEFAULT_TP)
+    assert res[0][0] == res[1][0]
+    assert torch.equal(res[0][1], res[1][1]) and torch.equal(res[0][2], res[1][2])
+
+
+def test_kd_time_parallel_case_matches_oracle():
+    """A time-parallel KD run against the oracle directly (positions within
+    1e-12 of the R12 scale, KD step counts exactly)."""
+    prob = W.cfg_kd(eps=0.01, stream_id=103)
+    st, traj, coll, _ = run(prob, 8, 11, 30, False, tp=True)
+    ref = O.simulate(prob, 8, 11, 30)
+    x = traj.numpy()
+    c = coll.numpy().astype(np.int64)
+    assert np.array_equal(c[:30], ref["cf"].astype(np.int64))
+    assert np.array_equal(c[30:], ref["cc"].astype(np.int64))
+    for got, want in ((x[:30], ref["xf"]), (x[30:], ref["xc"])):
+        scale = np.maximum(np.abs(want), np.sqrt(np.mean(want ** 2)))
+        assert np.max(np.abs(got - want) / scale) <= 1e-12
+
+
+@pytest.mark.parametrize("batched", [-1, 0, 1])
+def test_kd_estimates_equal_with_and_without_time_parallel(batched):
+    """The KD estimate's warm-up runs its long levels time-parallel; the
+    estimate is bitwise the same with the path switched off."""
+    pkg.mlmc_ap_set_tuning(tp_max_samples=DEFAULT_TP)
+    prob = W.cfg_kd(eps=0.01, stream_id=104)
+    on = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=batched))
+    off = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=batched, tp_max_samples=-1))
+    assert key(on) == key(off)
