@@ -155,8 +155,6 @@ mlmc_ap_status validate_problem(const mlmc_ap_problem* p) {
 bool time_parallel_candidate(const ItemSpec& s, int32_t tp_max_samples) {
   const mlmc_ap_problem& p = *s.prob;
   const bool kd = p.scheme == MLMC_AP_SCHEME_KD;
-  // in a heterogeneous background a KD flight depends on the position
-  if (kd && p.background != MLMC_AP_BG_DIFFUSIVE && p.bg_a > 0.0) return false;
   const int64_t limit = tp_max_samples == 0 ? kTpDefaultMaxSamples : tp_max_samples;
   if (limit <= 0 || s.n_samples == 0 || s.n_samples > (uint64_t)limit) return false;
   const bool coarse = !s.single && s.level >= 1;
@@ -169,12 +167,81 @@ bool time_parallel_candidate(const ItemSpec& s, int32_t tp_max_samples) {
   return level_const(p, s.level).n_steps >= (int64_t)kLongLevelSteps;
 }
 
+static bool in_background(const mlmc_ap_problem& p) {
+  return p.scheme == MLMC_AP_SCHEME_KD && p.background != MLMC_AP_BG_DIFFUSIVE && p.bg_a > 0.0;
+}
+
+// Time-parallel choice for the KD items of a launch that run in a background
+// of Section 5.  There a time-parallel wavefront walks every KD step's state
+// itself, so the form trades a shorter chain for far more issue slots.
+// Latencies in GPU cycles per KD step as kd_path_cost counts them, measured
+// on MI355X (B1, a = 10, b = 1000, level 14 paths and pairs with coarse level
+// 13 or 3, 1000 samples, one wavefront per SIMD): per lane, a path alone
+// 6800 per step, a pair 10200 per fine step (its aggregation weights) and
+// 3900 per coarse step; time-parallel 3400, 4700 and 3600.  A time-parallel
+// wavefront keeps its SIMD busy for less than half of that time (0.4 is
+// taken), so several of them on one SIMD queue behind each other.  The
+// launch takes about the longest of: the longest per-lane item, the longest
+// time-parallel item, and the time-parallel issue spread over the SIMDs.
+// Items are taken longest first while that estimate falls.
+constexpr double kBgLaneFine = 6800.0, kBgLanePairFine = 10200.0, kBgLaneCoarse = 3900.0;
+constexpr double kBgTpFine = 3400.0, kBgTpPairFine = 4700.0, kBgTpCoarse = 3600.0;
+constexpr double kBgTpBusy = 0.4;
+
+static void choose_background_tp(const std::vector<ItemSpec>& specs, int32_t tp_max_samples,
+                                 int n_simd, std::vector<bool>& tp) {
+  struct Cand {
+    double lane, tp;  // latency estimates, cycles
+    size_t i;
+    bool ok;          // qualifies for the time-parallel form
+  };
+  std::vector<Cand> c;
+  for (size_t i = 0; i < specs.size(); ++i) {
+    const ItemSpec& s = specs[i];
+    if (!in_background(*s.prob)) continue;
+    const double f = kd_path_cost(*s.prob, s.level);
+    const bool pair = !s.single && s.level >= 1;
+    const double cc = pair ? kd_path_cost(*s.prob, s.coarse_level >= 0 ? s.coarse_level
+                                                                       : s.level - 1)
+                           : 0.0;
+    const double lane = pair ? kBgLanePairFine * f + kBgLaneCoarse * cc : kBgLaneFine * f;
+    const double tpl = pair ? kBgTpPairFine * f + kBgTpCoarse * cc : kBgTpFine * f;
+    c.push_back({lane, tpl, i, time_parallel_candidate(s, tp_max_samples)});
+  }
+  if (c.empty()) return;
+  std::stable_sort(c.begin(), c.end(), [](const Cand& a, const Cand& b) { return a.lane > b.lane; });
+  // the per-lane latency no choice removes: items that do not qualify
+  double floor_lat = 0.0;
+  for (const Cand& x : c)
+    if (!x.ok) floor_lat = std::max(floor_lat, x.lane);
+  std::vector<size_t> order;
+  for (size_t j = 0; j < c.size(); ++j)
+    if (c[j].ok) order.push_back(j);
+  double best = 0.0, tp_lat = 0.0, issue = 0.0;
+  size_t best_k = 0;
+  for (size_t k = 0; k <= order.size(); ++k) {
+    if (k > 0) {
+      const Cand& x = c[order[k - 1]];
+      tp_lat = std::max(tp_lat, x.tp);
+      issue += (double)specs[x.i].n_samples * kBgTpBusy * x.tp / (double)std::max(1, n_simd);
+    }
+    const double lane = k < order.size() ? c[order[k]].lane : 0.0;
+    const double t = std::max(std::max(floor_lat, lane), std::max(tp_lat, issue));
+    if (k == 0 || t < best) {
+      best = t;
+      best_k = k;
+    }
+  }
+  for (size_t k = 0; k < best_k; ++k) tp[c[order[k]].i] = true;
+}
+
 std::vector<bool> choose_time_parallel(const std::vector<ItemSpec>& specs,
-                                       int32_t tp_max_samples) {
+                                       int32_t tp_max_samples, int n_simd) {
   std::vector<bool> tp(specs.size(), false);
+  choose_background_tp(specs, tp_max_samples, n_simd, tp);
   std::vector<std::pair<int64_t, size_t>> cand;  // (fine steps, index)
   for (size_t i = 0; i < specs.size(); ++i)
-    if (time_parallel_candidate(specs[i], tp_max_samples))
+    if (!in_background(*specs[i].prob) && time_parallel_candidate(specs[i], tp_max_samples))
       cand.push_back({level_const(*specs[i].prob, specs[i].level).n_steps, i});
   if (cand.empty()) return tp;
   std::stable_sort(cand.begin(), cand.end(),
@@ -540,7 +607,7 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
   for (const auto& sp : specs)
     if (sp.n_samples == 0) return set_error(MLMC_AP_EINVAL, "work item without samples");
   std::vector<LevelDesc> d(specs.size());
-  const std::vector<bool> tp = choose_time_parallel(specs, tuning.tp_max_samples);
+  const std::vector<bool> tp = choose_time_parallel(specs, tuning.tp_max_samples, 4 * ws.n_cu);
   for (size_t i = 0; i < specs.size(); ++i) d[i] = make_desc(specs[i], tp[i]);
   const bool fp64 = specs[0].prob->fp64_state != 0;
   for (const auto& s : specs)

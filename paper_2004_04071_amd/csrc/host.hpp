@@ -73,13 +73,14 @@ struct ItemSpec {
 // the C ABI): an item qualifies with at most tp_max_samples samples
 // (0 = kTpDefaultMaxSamples) of >= 64 fine steps; of the qualifying items of a
 // launch the longest are taken while their trajectory steps stay within
-// kTpStepsPerLongestStep times the longest item's step count.  Results do not
-// depend on the choice.
+// kTpStepsPerLongestStep times the longest item's step count.  KD items in a
+// background of Section 5 are chosen by a latency estimate of their own
+// (n_simd: SIMDs of the device).  Results do not depend on the choice.
 constexpr int64_t kTpDefaultMaxSamples = 4096;
 constexpr int64_t kTpStepsPerLongestStep = 4096;
 bool time_parallel_candidate(const ItemSpec& s, int32_t tp_max_samples);
 std::vector<bool> choose_time_parallel(const std::vector<ItemSpec>& specs,
-                                       int32_t tp_max_samples);
+                                       int32_t tp_max_samples, int n_simd);
 LevelDesc make_desc(const ItemSpec& s, bool tp);
 
 // Device workspace of one device: work table, tile partials, group results,

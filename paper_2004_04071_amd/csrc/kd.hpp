@@ -114,7 +114,21 @@ struct KdParams {
   double c2;      // 2 sigma^2 / R^2
   uint32_t M, tag, strm, key0, key1;
   uint32_t guard;  // bound on fine KD steps (a step advances at least one grid step)
+  double inv_dtf, inv_dtc;  // 1/dtf, 1/dtc
+  bool pow2_f, pow2_c;      // dtf (dtc) is a power of two
 };
+
+__device__ __forceinline__ bool kd_is_pow2(double x) {
+  int e;
+  return x > 0.0 && frexp(x, &e) == 0.5;
+}
+
+// floor(c / dt) on a grid of step dt.  Where dt is a power of two, c (1/dt)
+// is exact and equal to the quotient, and the FP64 division is skipped.
+__device__ __forceinline__ double kd_grid_floor(double c, double dt, double inv_dt, bool pow2) {
+  if (pow2) return floor(c * inv_dt);
+  return floor(c / dt);
+}
 
 __device__ __forceinline__ KdParams kd_params(const LevelDesc& d) {
   KdParams k;
@@ -133,6 +147,10 @@ __device__ __forceinline__ KdParams kd_params(const LevelDesc& d) {
   k.inv_r = 1.0 / k.R;
   k.inv_r2 = k.inv_r * k.inv_r;
   k.c2 = 2.0 * k.sigma * k.sigma * k.inv_r2;
+  k.pow2_f = kd_is_pow2(k.dtf);
+  k.pow2_c = kd_is_pow2(k.dtc);
+  k.inv_dtf = k.pow2_f ? 1.0 / k.dtf : 0.0;
+  k.inv_dtc = k.pow2_c ? 1.0 / k.dtc : 0.0;
   return k;
 }
 
@@ -204,7 +222,7 @@ __device__ __forceinline__ void kd_sample_rec(const LevelDesc& d, uint32_t smp, 
     while (cfine < k.T && cf < k.guard) {
       double nu_next, chi, E_next;
       kd_draws(k, smp, b++, nu_next, chi, E_next);
-      const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
+      const double t_next = (kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0) * k.dtf;
       const double theta = t_next - cfine;
       const double y = k.R * theta;
       const double em = kd_em(y);
@@ -228,11 +246,11 @@ __device__ __forceinline__ void kd_sample_rec(const LevelDesc& d, uint32_t smp, 
     double nu_f = ns;  // velocity number of the fine path's pending flight
     // index of the fine grid point that ends the pending flight's step
     // (computed once per flight: the loop test and the next step share it)
-    double nf = floor(cfine / k.dtf) + 1.0;
+    double nf = kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0;
     while ((ccoarse < k.T || cfine < k.T) && cf < k.guard) {
       // end of the coarse grid step holding the coarse collision, as an
       // index of the fine grid
-      const double end_c = floor(ccoarse / k.dtc) + 1.0;
+      const double end_c = kd_grid_floor(ccoarse, k.dtc, k.inv_dtc, k.pow2_c) + 1.0;
       const double end_c_fine = end_c * (double)k.M;
       double num = 0.0, den = 0.0, zeta_prev = 0.0;
       bool first = true;
@@ -266,7 +284,7 @@ __device__ __forceinline__ void kd_sample_rec(const LevelDesc& d, uint32_t smp, 
         tf = t_next;
         tauf = E_next * k.inv_r;
         cfine = tf + tauf;
-        nf = floor(cfine / k.dtf) + 1.0;
+        nf = kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0;
         vf = v_next;
         nu_f = nu_next;
         ++cf;
@@ -368,14 +386,21 @@ __device__ __forceinline__ double bg_rate_integral(const KdBackground& g, double
   return sign * r;
 }
 
+// 1/R and 2 sigma^2/R^2 of a local rate R.
+__device__ __forceinline__ void bg_rate_consts(double R, double sigma, double& inv_r,
+                                               double& inv_r2, double& c2) {
+  inv_r = 1.0 / R;
+  inv_r2 = inv_r * inv_r;
+  c2 = 2.0 * sigma * sigma * inv_r2;
+}
+
 // eqs. advection and diffusion with the local rate R of the phase (its
 // 1/R and 2 sigma^2/R^2 are returned for the aggregation weights).
 __device__ __forceinline__ void bg_coeffs(double R, double mu, double sigma, double theta,
                                           double y, double em, double v_next, double& a,
                                           double& dd, double& inv_r, double& c2) {
-  inv_r = 1.0 / R;
-  const double inv_r2 = inv_r * inv_r;
-  c2 = 2.0 * sigma * sigma * inv_r2;
+  double inv_r2;
+  bg_rate_consts(R, sigma, inv_r, inv_r2, c2);
   const double dv = v_next - mu;
   a = mu * theta + dv * (-em) * inv_r;
   const double d2 = c2 * kd_f(y, em) + dv * dv * inv_r2 * kd_g(y, em);
@@ -412,7 +437,7 @@ __device__ __forceinline__ void kd_sample_bg_rec(const LevelDesc& d, uint32_t sm
     while (cfine < k.T && steps < guard) {
       double nu_next, chi, E_next;
       kd_draws(k, smp, b++, nu_next, chi, E_next);
-      const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
+      const double t_next = (kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0) * k.dtf;
       const double theta = t_next - cfine;
       const double rl = bg_rate(g, xf + vf * tauf);   // rate at the collision
       const double y = rl * theta;
@@ -438,71 +463,88 @@ __device__ __forceinline__ void kd_sample_bg_rec(const LevelDesc& d, uint32_t sm
     double nu_f = ns;
     bool fine_done = false;
     double xf_end = 0.0;
-    while ((ccoarse < k.T || cfine < k.T) && steps < guard) {
-      const double end_c = floor(ccoarse / k.dtc) + 1.0;
-      const double end_c_fine = end_c * (double)k.M;
-      double num = 0.0, den = 0.0, zeta_prev = 0.0;
-      bool first = true;
-      uint32_t used = 0;
-      do {
-        if constexpr (Rec::kOn) ++used;
-        if (cfine >= k.T && !fine_done) {
-          xf_end = tf < k.T ? xf + vf * (k.T - tf) : xf;
-          fine_done = true;
+    // The algorithm's two nested loops (coarse KD steps; the fine steps of
+    // each) as one loop of fine steps, a coarse KD step closing each block:
+    // the arithmetic and its order are unchanged, but lanes whose blocks
+    // differ in length keep stepping together instead of waiting for the
+    // longest block of the wavefront.
+    double end_c = 0.0, end_c_fine = 0.0, num = 0.0, den = 0.0, zeta_prev = 0.0;
+    bool first = true, in_block = false;
+    uint32_t used = 0;
+    for (;;) {
+      if (!in_block) {  // a coarse KD step begins
+        if (!((ccoarse < k.T || cfine < k.T) && steps < guard)) break;
+        end_c = kd_grid_floor(ccoarse, k.dtc, k.inv_dtc, k.pow2_c) + 1.0;
+        end_c_fine = end_c * (double)k.M;
+        num = 0.0;
+        den = 0.0;
+        zeta_prev = 0.0;
+        first = true;
+        used = 0;
+        in_block = true;
+      }
+      if constexpr (Rec::kOn) ++used;
+      if (cfine >= k.T && !fine_done) {
+        xf_end = tf < k.T ? xf + vf * (k.T - tf) : xf;
+        fine_done = true;
+      }
+      double nu_next, chi, E_next;
+      kd_draws(k, smp, b++, nu_next, chi, E_next);
+      const double t_next = (kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0) * k.dtf;
+      const double theta = t_next - cfine;
+      const double rm = bg_rate(g, xf + vf * tauf);
+      const double y = rm * theta;
+      const double em = kd_em(y);
+      const double v_next = k.mu + k.sigma * nu_next;
+      double a, dd, inv_r, c2;
+      bg_coeffs(rm, k.mu, k.sigma, theta, y, em, v_next, a, dd, inv_r, c2);
+      xf = xf + vf * tauf + (a + dd * chi);
+      // aggregation weights of this phase with its own rate
+      const double zeta = -em * inv_r;
+      const double yp = kd_h(y, em);
+      const double beta = sqrt(c2 * kd_h(yp, yp < kKdSeriesY ? 0.0 : kd_em(yp)));
+      if (!first) {
+        const double alpha = (tauf + zeta_prev) * k.sigma;
+        num += alpha * nu_f;
+        den += alpha * alpha;
+      }
+      num += beta * chi;
+      den += beta * beta;
+      zeta_prev = zeta;
+      first = false;
+      if (!fine_done) ++cf;
+      tf = t_next;
+      vf = v_next;
+      nu_f = nu_next;
+      Ef = E_next;
+      tauf = bg_flight(g, xf, vf, Ef);
+      cfine = tf + tauf;
+      ++steps;
+      // the block ends with the first fine step whose pending collision lies
+      // past the coarse grid step
+      if (kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0 > end_c_fine || steps >= guard) {
+        in_block = false;
+        if (ccoarse < k.T) {
+          const double chi_c = den > 0.0 ? num / sqrt(den) : 0.0;
+          const double t_nc = end_c * k.dtc;
+          const double theta_c = t_nc - ccoarse;
+          const double rc = bg_rate(g, xc + vc * tauc);
+          const double yc = rc * theta_c;
+          const double v_nc = k.mu + k.sigma * nu_f;
+          double ac, ddc, inv_rc, c2c;
+          bg_coeffs(rc, k.mu, k.sigma, theta_c, yc, kd_em(yc), v_nc, ac, ddc, inv_rc, c2c);
+          xc = xc + vc * tauc + (ac + ddc * chi_c);
+          tc = t_nc;
+          vc = v_nc;
+          // eq. epsilon-update: the pending fine flight's exponential number
+          // less the rate integral along it up to the coarse time
+          double ec = Ef - bg_rate_integral(g, xf, vf, tc - tf);
+          ec = ec < 0.0 ? 0.0 : ec;
+          tauc = bg_flight(g, xc, vc, ec);
+          ccoarse = tc + tauc;
+          ++cc;
+          if constexpr (Rec::kOn) rec.put(chi_c, nu_f, ec, used);
         }
-        double nu_next, chi, E_next;
-        kd_draws(k, smp, b++, nu_next, chi, E_next);
-        const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
-        const double theta = t_next - cfine;
-        const double rm = bg_rate(g, xf + vf * tauf);
-        const double y = rm * theta;
-        const double em = kd_em(y);
-        const double v_next = k.mu + k.sigma * nu_next;
-        double a, dd, inv_r, c2;
-        bg_coeffs(rm, k.mu, k.sigma, theta, y, em, v_next, a, dd, inv_r, c2);
-        xf = xf + vf * tauf + (a + dd * chi);
-        // aggregation weights of this phase with its own rate
-        const double zeta = -em * inv_r;
-        const double yp = kd_h(y, em);
-        const double beta = sqrt(c2 * kd_h(yp, yp < kKdSeriesY ? 0.0 : kd_em(yp)));
-        if (!first) {
-          const double alpha = (tauf + zeta_prev) * k.sigma;
-          num += alpha * nu_f;
-          den += alpha * alpha;
-        }
-        num += beta * chi;
-        den += beta * beta;
-        zeta_prev = zeta;
-        first = false;
-        if (!fine_done) ++cf;
-        tf = t_next;
-        vf = v_next;
-        nu_f = nu_next;
-        Ef = E_next;
-        tauf = bg_flight(g, xf, vf, Ef);
-        cfine = tf + tauf;
-        ++steps;
-      } while (!(floor(cfine / k.dtf) + 1.0 > end_c_fine) && steps < guard);
-      if (ccoarse < k.T) {
-        const double chi_c = den > 0.0 ? num / sqrt(den) : 0.0;
-        const double t_next = end_c * k.dtc;
-        const double theta = t_next - ccoarse;
-        const double rc = bg_rate(g, xc + vc * tauc);
-        const double y = rc * theta;
-        const double v_next = k.mu + k.sigma * nu_f;
-        double a, dd, inv_r, c2;
-        bg_coeffs(rc, k.mu, k.sigma, theta, y, kd_em(y), v_next, a, dd, inv_r, c2);
-        xc = xc + vc * tauc + (a + dd * chi_c);
-        tc = t_next;
-        vc = v_next;
-        // eq. epsilon-update: the pending fine flight's exponential number
-        // less the rate integral along it up to the coarse time
-        double ec = Ef - bg_rate_integral(g, xf, vf, tc - tf);
-        ec = ec < 0.0 ? 0.0 : ec;
-        tauc = bg_flight(g, xc, vc, ec);
-        ccoarse = tc + tauc;
-        ++cc;
-        if constexpr (Rec::kOn) rec.put(chi_c, nu_f, ec, used);
       }
     }
     if (!fine_done) xf_end = tf < k.T ? xf + vf * (k.T - tf) : xf;

@@ -716,7 +716,7 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
   uint32_t cf = 0, cc = 0, b = 1;
   double xc = x0, vc = vf, tc = 0.0, ccoarse = cfine;
   double nu_f = ns;                          // velocity number of the pending flight
-  double nf = floor(cfine / k.dtf) + 1.0;    // pair: grid end of the pending flight's step
+  double nf = kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0;    // pair: grid end of the pending flight's step
   double end_c = 0.0, end_c_fine = 0.0, num = 0.0, den = 0.0, zeta_prev = 0.0;
   bool in_inner = false, done = false;
 
@@ -740,7 +740,7 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
           done = true;
           break;
         }
-        const double t_next = (floor(cfine / k.dtf) + 1.0) * k.dtf;
+        const double t_next = (kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0) * k.dtf;
         th = t_next - cfine;
         tf = t_next;
         tauf = lane_value(E_next, j) * k.inv_r;
@@ -751,7 +751,7 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
             done = true;
             break;
           }
-          end_c = floor(ccoarse / k.dtc) + 1.0;
+          end_c = kd_grid_floor(ccoarse, k.dtc, k.inv_dtc, k.pow2_c) + 1.0;
           end_c_fine = end_c * (double)k.M;
           first_m |= 1ull << j;
           in_inner = true;
@@ -761,7 +761,7 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
         tf = t_next;
         tauf = lane_value(E_next, j) * k.inv_r;
         cfine = tf + tauf;
-        nf = floor(cfine / k.dtf) + 1.0;
+        nf = kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0;
       }
       theta = lane == j ? th : theta;
       ++cf;
@@ -858,6 +858,225 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
     r.cc = cco;
     d.tp_out[local] = r;
     if (d.flags & kFlagSampleOutputs) sample_outputs<double, COARSE>(d, local, xf, xco, cf, cco);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Time-parallel KD path or pair in a background of Section 5 (kFlagBgB1 /
+// kFlagBgB2), for items of few long paths.  A flight's length depends on
+// where it starts and a diffusive phase on the rate at its collision, so the
+// fine path's state (position, velocity, pending collision) is a serial
+// chain; the rest runs across the lanes.  A wavefront simulates one sample
+// in windows of up to 64 fine KD steps:
+//   (A) lane j draws the numbers of the window's step j;
+//   (B) the fine chain is walked on wave-uniform values; lane j keeps step
+//       j's diffusive exponent y = R theta, its local rate and its end state;
+//   (C) pair: every lane evaluates the aggregation weights of its step
+//       (zeta, beta, alpha of eqs. chi-update and weights-beta);
+//   (D) pair: the steps are walked again in order on wave-uniform values:
+//       the fine steps that make up each coarse KD step, the weighted sums,
+//       and the coarse KD steps themselves (eq. chi-update, the coarse
+//       diffusive phase, eq. epsilon-update and the next coarse flight).
+// The fine path does not depend on the coarse one, so (B) may run ahead of
+// the step where (D) ends the pair; steps that (D) does not take are
+// dropped.  Every quantity comes from the operations of the per-lane loop
+// (kd_sample_bg_rec) on the same inputs, and sums are taken in its order, so
+// the two forms give bitwise identical results.
+// ---------------------------------------------------------------------------
+template <bool COARSE>
+__device__ __forceinline__ void run_kd_bg_tp(const LevelDesc& d, uint32_t local) {
+  const KdParams k = kd_params(d);
+  const KdBackground g{d.rsqrt_m, d.s_f, (d.flags & kFlagBgB1) != 0};
+  const uint32_t guard = 2u * d.n_steps + 4u;
+  const uint32_t lane = threadIdx.x & (kLanes - 1);
+  const uint32_t smp = (uint32_t)(d.sample_begin + local);
+  const Words w0 = philox4x32_10(0u, smp, k.tag, k.strm, k.key0, k.key1);
+  double nc, ns;
+  box_muller(w0.w0, w0.w1, nc, ns);
+  double x0;
+  if (d.x0_kind == 0) x0 = d.x0_a;
+  else if (d.x0_kind == 1) x0 = d.x0_a + d.x0_b * nc;
+  else x0 = cosine_icdf(uniform_f64(w0.w3));
+  const double E0 = -log(uniform_f64(w0.w2));
+
+  // fine path (wave-uniform)
+  double xf = x0, vf = k.mu + k.sigma * ns, tf = 0.0, Ef = E0;
+  double tauf = bg_flight(g, xf, vf, Ef);
+  double cfine = tf + tauf;
+  uint32_t cf = 0, b = 1, steps = 0;
+  // coarse path and the state of the pair loop (wave-uniform)
+  double xc = x0, vc = vf, tc = 0.0, tauc = tauf, ccoarse = tc + tauc;
+  double nu_f = ns, zeta_last = 0.0, xf_end = 0.0, end_c_fine = 0.0, end_c = 0.0;
+  double num = 0.0, den = 0.0;
+  uint32_t cc = 0;
+  bool fine_done = false, in_inner = false, first = true, done = false;
+
+#pragma unroll 1
+  while (!done) {
+    if constexpr (COARSE) {
+      if (!in_inner && !((ccoarse < k.T || cfine < k.T) && steps < guard)) break;
+    }
+    // (A)
+    double nu_next, chi, E_next;
+    kd_draws(k, smp, b + lane, nu_next, chi, E_next);
+    const double xf0 = xf, vf0 = vf, tf0 = tf, tauf0 = tauf, cfine0 = cfine, nu_f0 = nu_f;
+
+    // (B)
+    double y_j = 0.0, r_j = 1.0, x_j = 0.0, t_j = 0.0, tau_j = 0.0, c_j = 0.0;
+    uint32_t cnt = 0;
+#pragma unroll 1
+    for (uint32_t j = 0; j < (uint32_t)kLanes; ++j) {
+      if constexpr (!COARSE) {
+        if (!(cfine < k.T && steps < guard)) {
+          done = true;
+          break;
+        }
+      } else {
+        if (steps + cnt >= guard) break;
+      }
+      const double t_next = (kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0) * k.dtf;
+      const double theta = t_next - cfine;
+      const double rm = bg_rate(g, xf + vf * tauf);
+      const double y = rm * theta;
+      const double v_next = k.mu + k.sigma * lane_value(nu_next, j);
+      double a, dd, inv_r, c2;
+      bg_coeffs(rm, k.mu, k.sigma, theta, y, kd_em(y), v_next, a, dd, inv_r, c2);
+      xf = xf + vf * tauf + (a + dd * lane_value(chi, j));
+      tf = t_next;
+      vf = v_next;
+      Ef = lane_value(E_next, j);
+      tauf = bg_flight(g, xf, vf, Ef);
+      cfine = tf + tauf;
+      ++cnt;
+      if constexpr (!COARSE) {
+        ++cf;
+        ++steps;
+      } else {
+        const bool mine = lane == j;
+        y_j = mine ? y : y_j;
+        r_j = mine ? rm : r_j;
+        x_j = mine ? xf : x_j;
+        t_j = mine ? tf : t_j;
+        tau_j = mine ? tauf : tau_j;
+        c_j = mine ? cfine : c_j;
+      }
+    }
+    if constexpr (!COARSE) {
+      b += cnt;
+      continue;
+    }
+    if (cnt == 0) break;
+
+    // (C)
+    const uint32_t up = lane == 0 ? 0u : lane - 1u;
+    const double em_j = kd_em(y_j);
+    double inv_r, inv_r2, c2;
+    bg_rate_consts(r_j, k.sigma, inv_r, inv_r2, c2);
+    const double zeta = -em_j * inv_r;
+    const double yp = kd_h(y_j, em_j);
+    const double beta = sqrt(c2 * kd_h(yp, yp < kKdSeriesY ? 0.0 : kd_em(yp)));
+    const double zeta_up = __shfl(zeta, (int)up, kLanes);
+    const double tau_up = __shfl(tau_j, (int)up, kLanes);
+    const double nu_up = __shfl(nu_next, (int)up, kLanes);
+    const double alpha = ((lane == 0 ? tauf0 : tau_up) + (lane == 0 ? zeta_last : zeta_up)) * k.sigma;
+    const double A1 = alpha * (lane == 0 ? nu_f0 : nu_up);
+    const double A2 = alpha * alpha;
+    const double B1 = beta * chi;
+    const double B2 = beta * beta;
+    const double nfp = kd_grid_floor(c_j, k.dtf, k.inv_dtf, k.pow2_f) + 1.0;
+
+    // (D)
+    uint32_t taken = 0;
+#pragma unroll 1
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const double c_pre = j == 0 ? cfine0 : lane_value(c_j, j - 1u);
+      if (!in_inner) {  // head of the per-lane loop's outer iteration
+        if (!((ccoarse < k.T || c_pre < k.T) && steps < guard)) {
+          done = true;
+          break;
+        }
+        end_c = kd_grid_floor(ccoarse, k.dtc, k.inv_dtc, k.pow2_c) + 1.0;
+        end_c_fine = end_c * (double)k.M;
+        num = 0.0;
+        den = 0.0;
+        first = true;
+        in_inner = true;
+      }
+      if (c_pre >= k.T && !fine_done) {
+        const double x_pre = j == 0 ? xf0 : lane_value(x_j, j - 1u);
+        const double t_pre = j == 0 ? tf0 : lane_value(t_j, j - 1u);
+        const double v_pre = j == 0 ? vf0 : k.mu + k.sigma * lane_value(nu_next, j - 1u);
+        xf_end = t_pre < k.T ? x_pre + v_pre * (k.T - t_pre) : x_pre;
+        fine_done = true;
+      }
+      if (!first) {
+        num += lane_value(A1, j);
+        den += lane_value(A2, j);
+      }
+      num += lane_value(B1, j);
+      den += lane_value(B2, j);
+      first = false;
+      if (!fine_done) ++cf;
+      ++steps;
+      ++taken;
+      if (!(!(lane_value(nfp, j) > end_c_fine) && steps < guard)) {  // the inner loop ends
+        in_inner = false;
+        if (ccoarse < k.T) {
+          const double nu_e = lane_value(nu_next, j);
+          const double xf_e = lane_value(x_j, j), tf_e = lane_value(t_j, j);
+          const double vf_e = k.mu + k.sigma * nu_e;
+          const double chi_c = den > 0.0 ? num / sqrt(den) : 0.0;
+          const double t_next = end_c * k.dtc;
+          const double theta = t_next - ccoarse;
+          const double rc = bg_rate(g, xc + vc * tauc);
+          const double y = rc * theta;
+          double a, dd, ir, cq;
+          bg_coeffs(rc, k.mu, k.sigma, theta, y, kd_em(y), vf_e, a, dd, ir, cq);
+          xc = xc + vc * tauc + (a + dd * chi_c);
+          tc = t_next;
+          vc = vf_e;
+          double ec = lane_value(E_next, j) - bg_rate_integral(g, xf_e, vf_e, tc - tf_e);
+          ec = ec < 0.0 ? 0.0 : ec;
+          tauc = bg_flight(g, xc, vc, ec);
+          ccoarse = tc + tauc;
+          ++cc;
+        }
+      }
+    }
+    if (done) {
+      // the fine state is the end state of the last step taken
+      if (taken > 0) {
+        xf = lane_value(x_j, taken - 1u);
+        tf = lane_value(t_j, taken - 1u);
+        vf = k.mu + k.sigma * lane_value(nu_next, taken - 1u);
+      } else {
+        xf = xf0;
+        tf = tf0;
+        vf = vf0;
+      }
+    } else {
+      nu_f = lane_value(nu_next, cnt - 1u);
+      zeta_last = lane_value(zeta, cnt - 1u);
+    }
+    b += cnt;
+  }
+  if constexpr (!COARSE) {
+    if (tf < k.T) xf = xf + vf * (k.T - tf);
+    xf_end = xf;
+  } else {
+    if (!fine_done) xf_end = tf < k.T ? xf + vf * (k.T - tf) : xf;
+    if (tc < k.T) xc = xc + vc * (k.T - tc);
+  }
+  const double xco = COARSE ? xc : 0.0;
+  const uint32_t cco = COARSE ? cc : 0u;
+  if (lane == 0) {
+    TpSample r;
+    r.xf = xf_end;
+    r.xc = xco;
+    r.cf = cf;
+    r.cc = cco;
+    d.tp_out[local] = r;
+    if (d.flags & kFlagSampleOutputs) sample_outputs<double, COARSE>(d, local, xf_end, xco, cf, cco);
   }
 }
 
@@ -987,8 +1206,14 @@ __device__ __forceinline__ void run_kd_tp_index(const LevelDesc* __restrict__ it
   lo = __builtin_amdgcn_readfirstlane(lo);
   const LevelDesc d = items[lo];
   const uint32_t local = g - d.tp_base;
-  if (d.kind == kKindKdPair) run_kd_tp<true>(d, local);
-  else run_kd_tp<false>(d, local);
+  const bool bg = (d.flags & (kFlagBgB1 | kFlagBgB2)) != 0;
+  if (d.kind == kKindKdPair) {
+    if (bg) run_kd_bg_tp<true>(d, local);
+    else run_kd_tp<true>(d, local);
+  } else {
+    if (bg) run_kd_bg_tp<false>(d, local);
+    else run_kd_tp<false>(d, local);
+  }
 }
 
 // The time-parallel items alone (the per-level launch form).

@@ -61,7 +61,7 @@ uint64_t tick_bytes(const McRequest& mc, int32_t tp_max_samples) {
   uint64_t tp_levels = 0;  // levels that can run time-parallel
   for (int l = 0; l <= mc.prob.L; ++l)
     if (level_const(mc.prob, l).n_steps >= (int64_t)kLongLevelSteps &&
-        (l == 0 || mc.prob.M == 2 || mc.prob.M == 4))
+        (l == 0 || mc.prob.scheme == MLMC_AP_SCHEME_KD || mc.prob.M == 2 || mc.prob.M == 4))
       ++tp_levels;
   return levels * ((tiles + groups) * sizeof(Stats) + sizeof(LevelDesc) + sizeof(unsigned int)) +
          tp_levels * std::min(per_level, tp_limit) * sizeof(TpSample);

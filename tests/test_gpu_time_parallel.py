@@ -182,3 +182,83 @@ def test_kd_estimates_equal_with_and_without_time_parallel(batched):
     on = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=batched))
     off = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=batched, tp_max_samples=-1))
     assert key(on) == key(off)
+
+
+# KD items in the backgrounds of Section 5: the time-parallel form walks the
+# fine path's state chain on wave-uniform values and, for a pair, the coarse
+# KD steps in a second in-order pass over each window.
+BG_CASES = [
+    ("bg_b1_a10_b1000_pair_l10", W.cfg_bg(W.BG_B1, 10.0, 1000.0, L=10, stream_id=111), 10, 3,
+     70, False),
+    ("bg_b1_a10_b100_pair_l8", W.cfg_bg(W.BG_B1, 10.0, 100.0, stream_id=112), 8, 0, 100, False),
+    ("bg_b2_a10_b100_pair_l9", W.cfg_bg(W.BG_B2, 10.0, 100.0, L=9, stream_id=113), 9, 0, 64,
+     False),
+    ("bg_b1_a10_b1000_single_l12", W.cfg_bg(W.BG_B1, 10.0, 1000.0, L=12, stream_id=114), 12, 0,
+     40, True),
+    ("bg_b2_a20_b1_pair_l8_flights_past_T", W.cfg_bg(W.BG_B2, 20.0, 1.0, stream_id=115), 8, 0,
+     130, False),
+    ("bg_b1_a10_b100_M4_pair_l4", W.cfg_bg(W.BG_B1, 10.0, 100.0, M=4, L=4, stream_id=116), 4, 0,
+     80, False),
+    ("bg_b1_a100_b10_pair_l7", W.cfg_bg(W.BG_B1, 100.0, 10.0, stream_id=117), 7, 0, 90, False),
+    ("bg_b2_a10_b100_normal_x0_l7", dict(W.cfg_bg(W.BG_B2, 10.0, 100.0, stream_id=118),
+                                         x0_kind=W.X0_NORMAL, x0_a=1.0, x0_b=0.3), 7, 0, 64,
+     False),
+    ("bg_b1_a10_b1000_pair_l14_long", W.cfg_bg(W.BG_B1, 10.0, 1000.0, L=14, stream_id=119), 14,
+     0, 8, False),
+    ("bg_b1_a10_b1000_last_samples", W.cfg_bg(W.BG_B1, 10.0, 1000.0, L=8, stream_id=120), 8,
+     2 ** 32 - 65, 65, False),
+]
+
+
+@pytest.mark.parametrize("name,prob,level,begin,n,single", BG_CASES, ids=[c[0] for c in BG_CASES])
+def test_kd_background_time_parallel_equals_per_lane(name, prob, level, begin, n, single):
+    say("case", name)
+    a = run(prob, level, begin, n, single, tp=True)
+    b = run(prob, level, begin, n, single, tp=False)
+    assert a[0] == b[0], "statistics differ"
+    assert torch.equal(a[1], b[1]), "positions differ"
+    assert torch.equal(a[2], b[2]), "KD step counts differ"
+    assert a[0]["n"] == n and not torch.isnan(a[1]).any()
+
+
+def test_kd_background_time_parallel_nonadjacent_pair_equals_per_lane():
+    """Levels 11 and 3 in B1 (block factor 256): coarse KD steps that gather
+    hundreds of fine steps across many windows."""
+    prob = W.cfg_bg(W.BG_B1, 10.0, 1000.0, L=11, stream_id=121)
+    res = []
+    for tp in (DEFAULT_TP, -1):
+        pkg.mlmc_ap_set_tuning(tp_max_samples=tp)
+        traj = torch.zeros(2 * 50, dtype=torch.float64, device="cuda")
+        coll = torch.zeros(2 * 50, dtype=torch.int32, device="cuda")
+        st = pkg.mlmc_ap_simulate_pair(prob, 11, 3, 0, 50, traj=traj, coll=coll)
+        torch.cuda.synchronize()
+        res.append((st, traj.cpu(), coll.cpu()))
+    pkg.mlmc_ap_set_tuning(tp_max_samples=DEFAULT_TP)
+    assert res[0][0] == res[1][0]
+    assert torch.equal(res[0][1], res[1][1]) and torch.equal(res[0][2], res[1][2])
+
+
+def test_kd_background_time_parallel_case_matches_oracle():
+    """A time-parallel run in B1 against the oracle directly (positions within
+    1e-12 of the R12 scale, KD step counts exactly)."""
+    prob = W.cfg_bg(W.BG_B1, 10.0, 1000.0, L=9, stream_id=122)
+    st, traj, coll, _ = run(prob, 9, 5, 24, False, tp=True)
+    ref = O.simulate(prob, 9, 5, 24)
+    x = traj.numpy()
+    c = coll.numpy().astype(np.int64)
+    assert np.array_equal(c[:24], ref["cf"].astype(np.int64))
+    assert np.array_equal(c[24:], ref["cc"].astype(np.int64))
+    for got, want in ((x[:24], ref["xf"]), (x[24:], ref["xc"])):
+        scale = np.maximum(np.abs(want), np.sqrt(np.mean(want ** 2)))
+        assert np.max(np.abs(got - want) / scale) <= 1e-12
+
+
+@pytest.mark.parametrize("batched", [-1, 0, 1])
+def test_kd_background_estimates_equal_with_and_without_time_parallel(batched):
+    """An estimate in B1 whose warm-up runs its long levels time-parallel;
+    bitwise the same with the path switched off."""
+    pkg.mlmc_ap_set_tuning(tp_max_samples=DEFAULT_TP)
+    prob = W.cfg_bg(W.BG_B1, 10.0, 1000.0, L=10, stream_id=123)
+    on = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=batched))
+    off = pkg.mlmc_ap_estimate(prob, 1e-2, pkg.options(batched=batched, tp_max_samples=-1))
+    assert key(on) == key(off)
