@@ -610,6 +610,32 @@ def main():
                                                 / bres["mlmc_all_levels"]["time_ms"]),
             speedup_protocol_vs_single_level=(bres["single_level_kdmc"]["time_ms"]
                                               / bres["mlmc_section53_protocol"]["time_ms"]))
+        # the cost complexity of Section 5.3 in the same case: time and KD
+        # steps of the protocol's estimate and of single-level KDMC over a
+        # sequence of tolerances (each tolerance a fresh estimate after an
+        # untimed one, L = 14)
+        sweep = []
+        for btol_r in (1e-3, 5e-4, 2.5e-4, 1.25e-4, 6.25e-5, 3.125e-5, 1.5625e-5):
+            row = dict(rmse_tol=btol_r)
+            for name, fn, bopt in (
+                    ("protocol", pkg.mlmc_ap_estimate,
+                     pkg.options(batched=2, level_select=pkg.LEVELS_HEURISTIC_TAU, n_warmup=100,
+                                 **tk)),
+                    ("single_level", pkg.mlmc_ap_plain_mc, pkg.options(batched=2, **tk))):
+                fn(BP, btol_r, bopt, stream=hs)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = fn(BP, btol_r, bopt, stream=hs)
+                torch.cuda.synchronize()
+                row[name + "_ms"] = (time.perf_counter() - t0) * 1e3
+                row[name + "_kd_steps"] = sum(int(l["coll_f"]) + int(l["coll_c"])
+                                              for l in r["levels"])
+                row[name + "_estimate"] = r["estimate"]
+                row[name + "_sd"] = math.sqrt(r["var_estimator"])
+            row["speedup"] = row["single_level_ms"] / row["protocol_ms"]
+            row["work_ratio"] = row["single_level_kd_steps"] / row["protocol_kd_steps"]
+            sweep.append(row)
+        out["background_b1"]["tolerance_sweep"] = sweep
         log("background_b1", out["background_b1"])
     if not args.no_cpu_baseline and not kd_mode:
         out["cpu_baseline"] = cpu_baseline(prob, last["N"], args.cpu_seconds)
