@@ -361,10 +361,13 @@ def main():
     for _ in range(args.warmup):
         pkg.mlmc_ap_estimate(P, tol, opt, stream=hs)
     torch.cuda.synchronize()
+    raw = [pkg.Result() for _ in range(args.steps)]
     t0 = time.perf_counter()
-    results = [pkg.mlmc_ap_estimate(P, tol, opt, stream=hs) for _ in range(args.steps)]
+    for r in raw:
+        pkg.mlmc_ap_estimate_into(P, tol, opt, r, stream=hs)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    results = [pkg.result_dict(r) for r in raw]
     if kd_mode:   # KD steps actually taken (fine + coarse)
         steps_total = sum(int(l["coll_f"]) + int(l["coll_c"]) for r in results for l in r["levels"])
         fine_total = sum(int(l["coll_f"]) for r in results for l in r["levels"])
@@ -440,6 +443,17 @@ def main():
         for _ in range(reps):
             pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=1, **tk))
         graph_ms = (time.perf_counter() - t0) / reps * 1e3
+        # the same direct launches with every launch planned by the host (no
+        # device-planned first top-up)
+        hopt = pkg.options(batched=3, **tk)
+        hraw = pkg.Result()
+        pkg.mlmc_ap_estimate_into(P, tol, hopt, hraw, stream=hs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pkg.mlmc_ap_estimate_into(P, tol, hopt, hraw, stream=hs)
+        torch.cuda.synchronize()
+        out["host_planned_time_to_rmse_ms"] = (time.perf_counter() - t0) / args.steps * 1e3
         out["graph_replay_time_to_rmse_ms"] = graph_ms
         out["per_level_launch_time_to_rmse_ms"] = per_level_ms
         out["plain_mc_time_to_rmse_ms"] = plain_ms

@@ -190,15 +190,20 @@ typedef struct mlmc_ap_tuning {
 } mlmc_ap_tuning;
 
 typedef struct mlmc_ap_options {
-    int32_t batched;        /* 0 = 3 (default): all levels of an iteration in one
+    int32_t batched;        /* 0 (default): all levels of an iteration in one
                                   persistent launch (stage, persistent, reduce
-                                  kernels) issued directly;
-                               1: the same launch replayed from a captured hipGraph
-                                  (one graph per launch shape, kept by the library);
-                               2: as 3, with HIP events around the particle kernel,
-                                  so kernel_seconds is measured;
+                                  kernels) issued directly; the warm-up launch of
+                                  a lone request with all levels of a fixed L
+                                  takes its first top-up along, planned on the
+                                  device (result.device_planned);
+                               3: as 0, every launch planned by the host;
+                               1: the same launches replayed from captured
+                                  hipGraphs (one graph per launch shape, kept by
+                                  the library), planned by the host;
+                               2: as 0, with HIP events around the particle
+                                  kernels, so kernel_seconds is measured;
                                -1: one plain launch per level.
-                               All four give bitwise identical results. */
+                               All five give bitwise identical results. */
     int32_t max_iter;       /* MLMC top-up iterations after warm-up (0 = 10) */
     uint64_t n_warmup;      /* warm-up samples per level (0 = 1000) */
     mlmc_ap_tuning tuning;
@@ -269,6 +274,11 @@ typedef struct mlmc_ap_result {
     int32_t tau;             /* highest level of the warm-up before the selection (p->L
                                 but for LEVELS_HEURISTIC_TAU) */
     int32_t levels_added;    /* finest levels added by options.L_max (L = p->L + this) */
+    int32_t device_planned;  /* top-ups whose sample numbers and work table the device
+                                computed right after the warm-up (direct launch forms,
+                                one request, all levels; the host checks the numbers),
+                                0 or 1: the results are the same either way */
+    int32_t reserved;
 } mlmc_ap_result;
 
 /* Library and device set-up.  mlmc_ap_init is optional (every entry point

@@ -80,7 +80,8 @@ class Result(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("gpu_seconds", ctypes.c_double),
                 ("kernel_seconds", ctypes.c_double), ("level_mask", ctypes.c_uint64),
                 ("bias_estimate", ctypes.c_double), ("bias_se", ctypes.c_double),
-                ("tau", ctypes.c_int32), ("levels_added", ctypes.c_int32)]
+                ("tau", ctypes.c_int32), ("levels_added", ctypes.c_int32),
+                ("device_planned", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -272,7 +273,7 @@ def result_dict(r):
                 level_mask=int(r.level_mask),
                 level_set=[l for l in range(L + 1) if (int(r.level_mask) >> l) & 1],
                 bias_estimate=r.bias_estimate, bias_se=r.bias_se, tau=r.tau,
-                levels_added=r.levels_added)
+                levels_added=r.levels_added, device_planned=r.device_planned)
 
 
 BATCHED_DIRECT, BATCHED_GRAPH, BATCHED_TIMED, BATCHED_PER_LEVEL = 0, 1, 2, -1
@@ -470,6 +471,16 @@ def mlmc_ap_estimate(p, rmse_tol, opt=None, hist=False, stream=None):
         w = 3 * P.nbins + 4
         d["hist"] = [[int(x) for x in hbuf[l * w:(l + 1) * w]] for l in range(P.L + 1)]
     return d
+
+
+def mlmc_ap_estimate_into(P, rmse_tol, opt, res, stream=None):
+    """mlmc_ap_estimate of a marshalled Problem into a caller-owned Result,
+    without conversion (for loops that convert only what they keep, with
+    result_dict); returns res."""
+    _check(lib().mlmc_ap_estimate(ctypes.byref(P), float(rmse_tol),
+                                  ctypes.byref(opt) if opt is not None else None,
+                                  ctypes.byref(res), None, _stream(stream)), "mlmc_ap_estimate")
+    return res
 
 
 def mlmc_ap_estimate_sequence(p, rmse_tol0, R, opt=None, stream=None):

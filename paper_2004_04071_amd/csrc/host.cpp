@@ -22,11 +22,6 @@ namespace mlmc {
 namespace {
 thread_local std::string g_last_error;
 constexpr double kTwo32 = 4294967296.0;
-// Fine steps per lane a persistent-kernel chunk aims at (load balance versus
-// work-counter traffic); chunks never exceed 64 tiles, and on the long levels
-// a chunk is a single tile so that the slowest chunks end early.
-constexpr uint64_t kChunkLaneSteps = 128;
-constexpr uint64_t kMinChunksPerItem = 64;
 }  // namespace
 
 mlmc_ap_status set_error(mlmc_ap_status s, const std::string& msg) {
@@ -334,22 +329,12 @@ LevelDesc make_desc(const ItemSpec& s, bool tp) {
     d.flags &= ~(kFlagWide | kFlagAggregate);
     d.kind = coarse ? kKindKdPair : kKindKdFine;
   }
-  // wide tiles (several samples per lane) only where they still give the
-  // item at least one wavefront per SIMD; a few samples of short
-  // trajectories are spread over one per lane instead
-  d.spl = samples_per_lane((uint32_t)F.n_steps);
-  while (d.spl > 1 && s.n_samples < kMinWideTiles * (uint64_t)kLanes * d.spl) d.spl /= 4;
-  const uint64_t tile_samples = (uint64_t)kLanes * d.spl;
-  d.n_tiles = (uint32_t)((s.n_samples + tile_samples - 1) / tile_samples);
-  d.n_groups = (d.n_tiles + kGroupTiles - 1) / kGroupTiles;
-  // a chunk is about kChunkLaneSteps lane-steps of work, but an item keeps at
-  // least kMinChunksPerItem chunks so that a small one is not serialised
-  uint64_t ct = kChunkLaneSteps / ((uint64_t)d.spl * (F.n_steps + 1));
-  ct = std::min<uint64_t>(ct, std::max<uint64_t>(1, d.n_tiles / kMinChunksPerItem));
-  if (ct < 1) ct = 1;
-  if (ct > 64) ct = 64;
-  d.chunk_tiles = (uint32_t)ct;
-  d.n_chunks = (d.n_tiles + d.chunk_tiles - 1) / d.chunk_tiles;
+  const ItemLayout lay = item_layout(F.n_steps, s.n_samples);
+  d.spl = lay.spl;
+  d.n_tiles = lay.n_tiles;
+  d.n_groups = lay.n_groups;
+  d.chunk_tiles = lay.chunk_tiles;
+  d.n_chunks = lay.n_chunks;
   if (tp) {  // no persistent-kernel chunks; tp_base and tp_out are set by the caller
     d.flags |= kFlagTimeParallel;
     d.n_chunks = 0;
@@ -477,6 +462,9 @@ void Workspace::release() {
   if (groups) (void)hipFree(groups);
   if (resident) (void)hipFree(resident);
   if (resident_host) (void)hipHostFree(resident_host);
+  if (plan_host) (void)hipHostFree(plan_host);
+  plan_host = nullptr;
+  plan_host_dev = nullptr;
   if (hist_dev) (void)hipFree(hist_dev);
   if (tp_buf) (void)hipFree(tp_buf);
   tp_buf = nullptr;
@@ -601,7 +589,7 @@ static mlmc_ap_status record_device_work(Workspace& ws, bool fp64, bool kd,
 
 mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size_t n_slots,
                          int mode, const mlmc_ap_tuning& tuning, hipStream_t stream,
-                         LaunchTiming* timing) {
+                         LaunchTiming* timing, const PlanArgs* plan) {
   MLMC_TRY(check_tuning(tuning));
   if (specs.empty()) return MLMC_AP_OK;
   for (const auto& sp : specs)
@@ -633,8 +621,12 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
   }
   if (chunks >= 0xFFFFFFF0ull || groups >= 0xFFFFFFF0ull || tp_samples >= 0xFFFFFFF0ull)
     return set_error(MLMC_AP_EINVAL, "work table too large for one launch");
-  MLMC_TRY(ws.ensure(d.size(), tiles, groups, n_slots, 0));
+  if (plan && ((mode != kModeDirect && mode != kModeTimed) || d.size() > MLMC_AP_MAX_LEVELS))
+    return set_error(MLMC_AP_EINVAL, "a device-planned top-up needs a direct launch");
+  MLMC_TRY(ws.ensure(d.size(), plan ? std::max<size_t>(tiles, kPlanTiles) : tiles,
+                     plan ? std::max<size_t>(groups, kPlanGroups) : groups, n_slots, 0));
   MLMC_TRY(ws.ensure_tp(tp_samples));
+  if (plan && !ws.plan_host) MLMC_TRY(grow_pinned(ws.plan_host, ws.plan_host_dev, 0, 1));
   uint64_t tp_off = 0;
   for (auto& x : d) {
     x.tp_base = (uint32_t)tp_off;
@@ -663,7 +655,7 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
     MLMC_HIP(hipEventRecord(ws.ev[2], stream));
     MLMC_TRY(reduce(ws, stream));
     kernel_timed = true;
-  } else if (mode == kModeTimed || mode == kModeDirect) {
+  } else if (mode == kModeTimed || mode == kModeDirect || mode == kModeDirectHost) {
     kernel_timed = mode == kModeTimed;
     MLMC_TRY(stage(ws, stream));
     if (kernel_timed) MLMC_HIP(hipEventRecord(ws.ev[1], stream));
@@ -672,6 +664,21 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
                                stream, kd));
     if (kernel_timed) MLMC_HIP(hipEventRecord(ws.ev[2], stream));
     MLMC_TRY(reduce(ws, stream));
+    if (plan) {
+      // the first top-up, planned on the device from the warm-up's statistics
+      PlanArgs a = *plan;
+      a.n_items = (uint32_t)d.size();
+      a.cap_tiles = (uint32_t)std::min<size_t>(ws.partials_cap, 0xFFFFFFF0u);
+      a.cap_groups = (uint32_t)std::min<size_t>(ws.groups_cap, 0xFFFFFFF0u);
+      MLMC_HIP(launch_plan(a, ws.items_dev, ws.hdr_dev, ws.resident, ws.counter_dev,
+                           ws.item_done, ws.plan_host_dev, stream));
+      if (kernel_timed) MLMC_HIP(hipEventRecord(ws.ev[4], stream));
+      MLMC_HIP(launch_persistent(fp64, tuning.ppt, ws.items_dev, ws.hdr_dev, ws.counter_dev,
+                                 ws.partials, tuning.block, persistent_grid(ws, tuning, fp64, kd),
+                                 stream, kd));
+      if (kernel_timed) MLMC_HIP(hipEventRecord(ws.ev[5], stream));
+      MLMC_TRY(reduce(ws, stream));
+    }
   } else if (mode == kModeGraph) {
     const uint64_t key = ((uint64_t)tuning.block << 48) ^ ((uint64_t)tuning.ppt << 40) ^
                          ((uint64_t)tuning.waves_per_simd << 32) ^ (fp64 ? 1ull : 2ull) ^
@@ -721,6 +728,10 @@ mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& specs, size
     if (kernel_timed) {
       MLMC_HIP(hipEventElapsedTime(&ms, ws.ev[1], ws.ev[2]));
       timing->kernel_s = ms * 1e-3;
+      if (plan) {
+        MLMC_HIP(hipEventElapsedTime(&ms, ws.ev[4], ws.ev[5]));
+        timing->kernel_s += ms * 1e-3;
+      }
     }
   }
   return MLMC_AP_OK;
@@ -732,7 +743,7 @@ int launch_mode(int32_t batched) {
     case 0: return kModeDirect;
     case 1: return kModeGraph;
     case 2: return kModeTimed;
-    case 3: return kModeDirect;
+    case 3: return kModeDirectHost;
     default: return -1;
   }
 }
@@ -931,11 +942,31 @@ bool McRequest::plan(std::vector<ItemSpec>& items, uint32_t slot_base,
   return any;
 }
 
-static double sample_var(const Stats& s) { return s.n > 1.0 ? s.m2_dq / (s.n - 1.0) : 0.0; }
+static double sample_var(const Stats& s) { return level_variance(s); }
 
 uint64_t McRequest::item_cost(int l) const {
   if (plain) return sample_cost(prob, l, true);
   return pair_cost(prob, l, coarse_of[l]);
+}
+
+bool McRequest::device_plannable(PlanArgs& a) const {
+  // the first launch of a one-stage estimate on a fixed level set: after it
+  // the host would compute the targets of eqs. Nopt1/Noptj and launch them
+  if (phase != 0 || iterations != 0 || tols.size() != 1 || L_max != 0 || max_per_tick != 0)
+    return false;
+  if (!plain && level_select != MLMC_AP_LEVELS_ALL) return false;
+  if (pilots_active()) return false;
+  std::memset(&a, 0, sizeof(a));
+  a.tol = tol;
+  a.slot_base = 0;
+  for (int l = first_level(); l <= prob.L; ++l) {
+    if (!in_set[l]) continue;
+    // every level of the set runs its warm-up in this launch
+    if (done[l] != 0 || target[l] != n_warmup) return false;
+    a.level_mask |= 1u << l;
+    a.cost[l] = item_cost(l);
+  }
+  return a.level_mask != 0;
 }
 
 // After the warm-up of adjacent pairs on levels 0..tau: V_l from the fine
@@ -1103,16 +1134,12 @@ void McRequest::absorb(const Stats* slots) {
       }
     }
     // eqs. Nopt1/Noptj with sample variances and the deterministic costs
+    // (the arithmetic of plan.hpp, which the device-planned top-up shares)
     double S = 0.0;
     for (int l = first_level(); l <= prob.L; ++l)
-      if (in_set[l]) S += std::sqrt(sample_var(st[l]) * (double)item_cost(l));
-    for (int l = first_level(); l <= prob.L; ++l) {
-      if (!in_set[l]) continue;
-      const double c = (double)item_cost(l);
-      const double N = std::ceil(2.0 / (tol * tol) * std::sqrt(sample_var(st[l]) / c) * S);
-      const uint64_t Ni = N >= 4294967295.0 ? 4294967295ull : (uint64_t)N;
-      target[l] = std::max<uint64_t>(Ni, done[l]);
-    }
+      if (in_set[l]) S += cost_variance_root(sample_var(st[l]), item_cost(l));
+    for (int l = first_level(); l <= prob.L; ++l)
+      if (in_set[l]) target[l] = level_target(sample_var(st[l]), item_cost(l), S, tol, done[l]);
     ++iterations;
     ++stage_iter;
   }
@@ -1142,6 +1169,7 @@ void McRequest::fill_result(mlmc_ap_result* out) const {
   out->bias_estimate = bias_estimate(&out->bias_se);
   out->tau = tau;
   out->levels_added = levels_added;
+  out->device_planned = device_planned;
 }
 
 }  // namespace mlmc
@@ -1186,8 +1214,36 @@ mlmc_ap_status run_requests(Workspace& ws, std::vector<McRequest>& reqs, int mod
       if (items.size() > before) owners.push_back(r);
     }
     if (items.empty()) return MLMC_AP_OK;
+    // A lone request's warm-up in a direct launch takes its first top-up
+    // along: the device plans it from the warm-up's statistics (plan_kernel).
+    PlanArgs pa;
+    const bool chain = (mode == kModeDirect || mode == kModeTimed) && reqs.size() == 1 &&
+                       !hist_dev && reqs[0].device_plannable(pa);
     LaunchTiming t;
-    MLMC_TRY(run_table(ws, items, n_slots, mode, tuning, stream, &t));
+    MLMC_TRY(run_table(ws, items, n_slots, mode, tuning, stream, &t, chain ? &pa : nullptr));
+    if (chain) {
+      // the host's own planning from the warm-up's statistics must give the
+      // numbers the device launched
+      McRequest& q = reqs[0];
+      const PlanRecord& rec = *ws.plan_host;
+      std::vector<Stats> warm(kStride, stats_empty());
+      for (int l = 0; l <= q.prob.L; ++l)
+        if ((pa.level_mask >> l) & 1u) warm[l] = rec.warmup[l];
+      q.launches += 1;
+      q.gpu_seconds += t.total_s;
+      q.kernel_seconds += t.kernel_s;
+      q.absorb(warm.data());
+      for (int l = 0; l <= q.prob.L; ++l)
+        if (((pa.level_mask >> l) & 1u) && q.target[l] != rec.target[l])
+          return set_error(MLMC_AP_EDEVICE, "device-planned top-up of level " + std::to_string(l) +
+                                                " differs from the host's sample number");
+      if (!rec.declined) {
+        q.launches += 1;
+        q.device_planned += 1;
+        q.absorb(ws.resident_host);
+      }
+      continue;
+    }
     for (size_t r : owners) {
       reqs[r].launches += 1;
       reqs[r].gpu_seconds += t.total_s;

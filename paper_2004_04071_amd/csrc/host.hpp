@@ -11,6 +11,7 @@
 
 #include "kernels.hpp"
 #include "mlmc_ap.h"
+#include "plan.hpp"
 #include "types.hpp"
 
 namespace mlmc {
@@ -91,7 +92,9 @@ struct Workspace {
   std::string name;
   std::mutex mu;
   hipStream_t capture_stream = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // launch start, particle kernel start/end, launch end; particle kernel
+  // start/end of a device-planned top-up
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 
   // *_host: pinned host memory the kernels access directly at *_host_dev
   LevelDesc* items_dev = nullptr;
@@ -115,6 +118,8 @@ struct Workspace {
   unsigned int* item_done = nullptr;  // reduction: finished groups per item (items_cap)
   TpSample* tp_buf = nullptr;  // final states of time-parallel samples
   size_t tp_cap = 0;
+  PlanRecord* plan_host = nullptr;  // device-planned top-up: the plan kernel's record
+  PlanRecord* plan_host_dev = nullptr;
 
   // Captured launches by shape (tuning, precision, time-parallel node); every
   // buffer they name is in the workspace, so any reallocation drops them all.
@@ -155,16 +160,26 @@ enum LaunchMode : int {
   kModeGraph = 1,     // stage, persistent, reduce replayed from a captured graph
   kModeTimed = 2,     // the three kernels issued directly, HIP events around the particle kernel
   kModeDirect = 3,    // the three kernels issued directly
+  kModeDirectHost = 4,  // as kModeDirect, every launch planned by the host
 };
 // Maps mlmc_ap_options.batched to a launch mode (-1 if invalid).
 int launch_mode(int32_t batched);
 
+// Tiles and reduction groups the buffers keep for a device-planned top-up
+// (20 MiB of tile records); a larger top-up is declined and planned by the host.
+constexpr size_t kPlanTiles = 1u << 18;
+constexpr size_t kPlanGroups = kPlanTiles / kGroupTiles + MLMC_AP_MAX_LEVELS;
+
 // Builds the work table of `items` (assigning tile, group and chunk bases),
 // launches it in the given mode and leaves the updated resident statistics
-// slots in ws.resident_host (written by the reduction).
+// slots in ws.resident_host (written by the reduction).  With `plan` (direct
+// and timed modes, items one per level of one request, all levels of
+// plan->level_mask): the table is a warm-up; the device then plans the first
+// top-up from its statistics and launches it behind it (plan_kernel), and
+// ws.plan_host holds the warm-up's statistics and the planned numbers.
 mlmc_ap_status run_table(Workspace& ws, const std::vector<ItemSpec>& items, size_t n_slots,
                          int mode, const mlmc_ap_tuning& tuning, hipStream_t stream,
-                         LaunchTiming* timing);
+                         LaunchTiming* timing, const PlanArgs* plan = nullptr);
 
 Stats stats_from_api(const mlmc_ap_level_stats& a);
 mlmc_ap_level_stats stats_to_api(const Stats& s);
@@ -201,6 +216,7 @@ struct McRequest {
   bool pilots_active() const;
   uint64_t particle_steps = 0;
   uint64_t launches = 0;
+  int device_planned = 0;      // top-ups the device planned after the warm-up
   double gpu_seconds = 0.0, kernel_seconds = 0.0;
   // Tolerance sequence of the epsilon-adaptive on-line phase (Section 5.3):
   // stage r ends when the statistical constraint holds at tols[r] (or after
@@ -238,6 +254,9 @@ struct McRequest {
             size_t hist_stride);
   // Takes the statistics of the launch and advances the state machine.
   void absorb(const Stats* resident_slots);
+  // The next launch is the warm-up of every level of a one-stage estimate,
+  // whose first top-up the device can plan (slots from 0): fills `a`.
+  bool device_plannable(PlanArgs& a) const;
   void fill_result(mlmc_ap_result* out) const;
   // Replaces the tolerance by a sequence (before the first launch).
   void set_sequence(const std::vector<double>& seq);

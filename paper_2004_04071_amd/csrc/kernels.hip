@@ -33,6 +33,7 @@
 #include "device.hpp"
 #include "kd.hpp"
 #include "kernels.hpp"
+#include "plan.hpp"
 
 namespace mlmc {
 
@@ -1487,6 +1488,124 @@ __global__ void stage_kernel(const WorkHeader* __restrict__ hdr_src,
   }
 }
 
+// Device-planned top-up.  Right after a warm-up launch's reduction, one block
+// computes eqs. Nopt1/Noptj from the warm-up's resident statistics and builds
+// the top-up's work table in place of the warm-up's, so that the top-up's
+// particle and reduction kernels follow on the stream without a return to
+// the host.  The arithmetic is the host's (plan.hpp); every descriptor field
+// is the warm-up's except the sample range, the accumulate flag and the tile
+// layout.  The warm-up's statistics and the planned numbers go to `rec`
+// (host-mapped) for the host's check.  A table that would not fit the tile or
+// group buffers is not built: the header then holds no work and rec->declined
+// is set.
+constexpr int kPlanThreads = 256;
+
+__global__ void __launch_bounds__(kPlanThreads) plan_kernel(
+    PlanArgs a, LevelDesc* __restrict__ items, WorkHeader* __restrict__ hdr,
+    const Stats* __restrict__ resident, unsigned int* __restrict__ counter,
+    unsigned int* __restrict__ item_done, PlanRecord* __restrict__ rec) {
+  constexpr int kMax = MLMC_AP_MAX_LEVELS;
+  constexpr int kWords = sizeof(LevelDesc) / sizeof(uint4);
+  static_assert(kMax <= kPlanThreads, "one thread per level");
+  __shared__ LevelDesc src[kMax];
+  __shared__ uint64_t begin[kMax], count[kMax], tile_b[kMax], group_b[kMax], chunk_b[kMax];
+  __shared__ ItemLayout lay[kMax];
+  __shared__ uint32_t src_of[kMax];
+  __shared__ uint32_t n_out;
+  __shared__ double var[kMax], root[kMax], S_sh;
+  __shared__ uint64_t done[kMax], target[kMax];
+  const uint32_t t = threadIdx.x;
+  const uint32_t nw = a.n_items < (uint32_t)kMax ? a.n_items : (uint32_t)kMax;
+  for (uint32_t i = t; i < nw * kWords; i += blockDim.x)
+    reinterpret_cast<uint4*>(src)[i] = reinterpret_cast<const uint4*>(items)[i];
+  // thread l: level l's statistics, variance and term of S
+  const bool lvl = t < (uint32_t)kMax && ((a.level_mask >> t) & 1u);
+  if (t < (uint32_t)kMax) {
+    var[t] = 0.0;
+    root[t] = 0.0;
+    done[t] = 0;
+    target[t] = 0;
+    if (lvl) {
+      const Stats st = resident[a.slot_base + t];
+      rec->warmup[t] = st;
+      var[t] = level_variance(st);
+      root[t] = cost_variance_root(var[t], a.cost[t]);
+      done[t] = (uint64_t)st.n;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    double S = 0.0;  // in level order, as the host sums
+    for (int l = 0; l < kMax; ++l)
+      if ((a.level_mask >> l) & 1u) S += root[l];
+    S_sh = S;
+  }
+  __syncthreads();
+  if (lvl) {
+    target[t] = level_target(var[t], a.cost[t], S_sh, a.tol, done[t]);
+    rec->target[t] = target[t];
+  }
+  __syncthreads();
+  // thread i: the layout of warm-up item i's top-up (if its level needs one)
+  if (t < nw) {
+    const uint32_t l = src[t].result_slot - a.slot_base;
+    count[t] = (l < (uint32_t)kMax && target[l] > done[l]) ? target[l] - done[l] : 0u;
+    begin[t] = l < (uint32_t)kMax ? done[l] : 0u;
+    if (count[t]) lay[t] = item_layout(src[t].n_steps, count[t]);
+  }
+  __syncthreads();
+  if (t == 0) {
+    // the top-up's items keep the warm-up table's order
+    uint64_t tiles = 0, groups = 0, chunks = 0;
+    uint32_t n = 0;
+    for (uint32_t i = 0; i < nw; ++i) {
+      if (!count[i]) continue;
+      src_of[n] = i;
+      tile_b[n] = tiles;
+      group_b[n] = groups;
+      chunk_b[n] = chunks;
+      tiles += lay[i].n_tiles;
+      groups += lay[i].n_groups;
+      chunks += lay[i].n_chunks;
+      ++n;
+    }
+    const bool fits = tiles <= a.cap_tiles && groups <= a.cap_groups && chunks < 0xFFFFFFF0ull;
+    if (!fits) n = 0;
+    n_out = n;
+    WorkHeader h;
+    h.n_items = n;
+    h.total_chunks = n ? (uint32_t)chunks : 0u;
+    h.total_groups = n ? (uint32_t)groups : 0u;
+    h.total_tp = 0u;
+    *hdr = h;
+    rec->declined = fits ? 0u : 1u;
+    rec->n_items = n;
+  }
+  __syncthreads();
+  const uint32_t n = n_out;
+  if (t < n) {
+    const uint32_t i = src_of[t];
+    LevelDesc d = src[i];
+    const ItemLayout o = lay[i];
+    d.sample_begin = begin[i];
+    d.n_samples = count[i];
+    d.flags = (d.flags & ~(uint32_t)kFlagTimeParallel) | kFlagAccumulate;
+    d.spl = o.spl;
+    d.n_tiles = o.n_tiles;
+    d.n_groups = o.n_groups;
+    d.chunk_tiles = o.chunk_tiles;
+    d.n_chunks = o.n_chunks;
+    d.tile_base = tile_b[t];
+    d.group_base = group_b[t];
+    d.chunk_base = chunk_b[t];
+    d.tp_base = 0u;
+    d.tp_out = nullptr;
+    items[t] = d;
+    item_done[t] = 0u;
+  }
+  if (t < kChunkStreams) counter[t * kCounterStride] = 0u;
+}
+
 // First kernel of an allocation-free launch: the work header and the single
 // descriptor arrive as kernel arguments (no host-side table, no copy), and the
 // reduction's item counter and the histogram counters are cleared.
@@ -1741,6 +1860,15 @@ hipError_t launch_kd_numbers(const LevelDesc& d, uint64_t n, uint32_t cap, doubl
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(kd_numbers_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, n,
                      cap, rows, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan(const PlanArgs& a, LevelDesc* items_dev, WorkHeader* hdr_dev,
+                       const Stats* resident, unsigned int* counter, unsigned int* item_done,
+                       PlanRecord* rec, hipStream_t s) {
+  if (a.n_items > (uint32_t)MLMC_AP_MAX_LEVELS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, a, items_dev, hdr_dev,
+                     resident, counter, item_done, rec);
   return hipGetLastError();
 }
 

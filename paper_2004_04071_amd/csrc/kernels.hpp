@@ -48,6 +48,15 @@ hipError_t launch_tp(bool fp64, const LevelDesc* items_dev, const WorkHeader* hd
 hipError_t launch_stage(const WorkHeader* hdr_src, const LevelDesc* items_src, uint32_t cap,
                         WorkHeader* hdr_dst, LevelDesc* items_dst, unsigned int* counter,
                         unsigned int* item_done, hipStream_t s);
+struct PlanArgs;
+struct PlanRecord;
+// Device-planned top-up after a warm-up launch (one block): eqs. Nopt1/Noptj
+// from the resident statistics, the top-up's table in place of the warm-up's
+// (a.n_items <= MLMC_AP_MAX_LEVELS items, one per level), counters cleared;
+// the warm-up's statistics and the planned numbers to `rec` (host-mapped).
+hipError_t launch_plan(const PlanArgs& a, LevelDesc* items_dev, WorkHeader* hdr_dev,
+                       const Stats* resident, unsigned int* counter, unsigned int* item_done,
+                       PlanRecord* rec, hipStream_t s);
 // Allocation-free launch: header and one descriptor as kernel arguments into
 // device memory; clears item_done[0] and hist_n histogram counters.
 hipError_t launch_stage_args(const WorkHeader& h, const LevelDesc& d, WorkHeader* hdr_dst,

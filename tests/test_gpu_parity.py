@@ -333,3 +333,45 @@ def test_concurrent_calls_on_distinct_streams():
     assert not errors, errors
     for a, b in zip(alone, out):
         assert _key(a) == _key(b)
+
+
+# ---------------------------------------------------------------------------
+# Device-planned top-up: after the warm-up of a lone request in a direct
+# launch, the device computes eqs. Nopt1/Noptj and the top-up's table and
+# launches it behind the warm-up; the host checks the numbers (an error if
+# they differ).  Results are those of the host-planned forms, bit for bit.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,prob,tol,plain", [
+    ("cfg2_eps0.05", W.cfg2(eps=0.05, stream_id=41), 5e-3, False),
+    ("cfg2_eps1e-4", W.cfg2(eps=1e-4, stream_id=42), 1e-2, False),
+    ("plain_mc_eps0.3", W.cfg2(eps=0.3, stream_id=43), 2e-2, True),
+    ("kd_eps0.05", W.cfg_kd(eps=0.05, stream_id=44), 1e-2, False),
+    ("bg_b2_L5", dict(W.cfg_bg(W.BG_B2, 10.0, 100.0, stream_id=45), L=5), 5e-3, False),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_device_planned_top_up_equals_host_planned(name, prob, tol, plain):
+    say("case", name)
+    fn = pkg.mlmc_ap_plain_mc if plain else pkg.mlmc_ap_estimate
+    host = fn(prob, tol, pkg.options(batched=-1))
+    for batched in (0, 2):
+        dev = fn(prob, tol, pkg.options(batched=batched))
+        assert dev["device_planned"] == 1, (batched, dev["launches"])
+        assert _key(dev) == _key(host)
+        assert dev["launches"] == host["launches"]
+        assert dev["particle_steps"] == host["particle_steps"]
+    assert host["device_planned"] == 0
+    for batched in (1, 3):  # graph replays; direct launches planned by the host
+        r = fn(prob, tol, pkg.options(batched=batched))
+        assert r["device_planned"] == 0 and _key(r) == _key(host)
+
+
+def test_device_planned_top_up_declined_when_too_large():
+    """A first top-up of more tile records than the buffers hold (about 3.5e6
+    tiles at level 0 here) is not launched by the device: the host plans it,
+    with the same results as the per-level form."""
+    prob = dict(W.cfg2(eps=0.01, stream_id=46), L=2)
+    dev = pkg.mlmc_ap_estimate(prob, 1e-4, pkg.options(batched=0))
+    host = pkg.mlmc_ap_estimate(prob, 1e-4, pkg.options(batched=-1))
+    say("N", dev["N"], "device_planned", dev["device_planned"])
+    assert dev["N"][0] > 2 ** 31
+    assert dev["device_planned"] == 0
+    assert _key(dev) == _key(host)
