@@ -538,7 +538,13 @@ def main():
                               particle_steps=sstats["particle_steps"],
                               makespan_s=makespan,
                               particle_steps_per_s=sstats["particle_steps"] / makespan,
-                              ticks=sstats["ticks"])
+                              ticks=sstats["ticks"],
+                              # the trace offers less work than the GPU can do:
+                              # time inside ticks, and the rate while in them
+                              busy_s=sstats["busy_seconds"],
+                              busy_fraction=sstats["busy_seconds"] / makespan,
+                              particle_steps_per_busy_s=(sstats["particle_steps"]
+                                                         / max(sstats["busy_seconds"], 1e-12)))
         log("serving", out["serving"])
 
         # the paper's kinetic-diffusion scheme on the same estimate (FP64 state)
