@@ -172,8 +172,9 @@ def valu_probe():
     """The launches behind profiles/valu_instructions_per_sample.json (run it
     under rocprofv3 --pmc SQ_INSTS_VALU): per workload and finest level L,
     one persistent launch over levels 0..L with VALU_PROBE_SAMPLES samples at
-    every level and the tuning the benchmark times; the time-parallel path is
-    off so that every sample runs the per-lane loop."""
+    every level and the tuning the benchmark times (host-planned direct form,
+    so that no device-planned top-up follows the launch); the time-parallel
+    path is off so that every sample runs the per-lane loop."""
     import torch
     import paper_2004_04071_amd as pkg
     import workloads as W
@@ -183,7 +184,7 @@ def valu_probe():
         n = VALU_PROBE_SAMPLES[name]
         for L in range(base["L"] + 1):
             r = pkg.mlmc_ap_estimate(dict(base, L=L), 100.0, pkg.options(
-                batched=2, n_warmup=n, max_iter=1, tp_max_samples=-1, block=256, ppt=1,
+                batched=3, n_warmup=n, max_iter=1, tp_max_samples=-1, block=256, ppt=1,
                 waves_per_simd=8))
             assert r["launches"] == 1 and r["N"] == [n] * (L + 1)
             print(json.dumps(dict(workload=name, L=L, samples_per_level=n)), flush=True)
