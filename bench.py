@@ -69,7 +69,8 @@ def fine_steps(prob, N):
     return sum(n * n0 * prob["M"] ** l for l, n in enumerate(N))
 
 
-KERNEL_SOURCES = ("kernels.hip", "kernels.hpp", "kd.hpp", "device.hpp", "types.hpp", "stats.hpp")
+KERNEL_SOURCES = ("kernels.hip", "kernels.hpp", "kd.hpp", "device.hpp", "types.hpp", "stats.hpp",
+                  "unit_math.hpp", "plan.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "persistent_kernel_hbm_traffic.json")
 
 

@@ -5,6 +5,7 @@
 
 #include "stats.hpp"
 #include "types.hpp"
+#include "unit_math.hpp"
 
 namespace mlmc {
 
@@ -76,12 +77,14 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& xi, 
   g = r * __builtin_amdgcn_sinf(u2);
 }
 
+// FP64: the logarithm and sine/cosine of unit_math.hpp (series written for
+// these uniforms, within 2 ulp).
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& xi, double& g) {
   const double u1 = uniform_f64(wa);
   const double u2 = uniform_f64(wb);
-  const double r = sqrt(-2.0 * log(u1));
+  const double r = sqrt(-2.0 * log_unit(u1));
   double s, c;
-  sincospi(2.0 * u2, &s, &c);
+  sincospi_unit(2.0 * u2, s, c);
   xi = r * c;
   g = r * s;
 }

@@ -169,7 +169,7 @@ __device__ __forceinline__ void kd_draws(const KdParams& k, uint32_t smp, uint32
                                          double& nu_next, double& chi, double& E_next) {
   const Words w = philox4x32_10(b, smp, k.tag, k.strm, k.key0, k.key1);
   box_muller(w.w0, w.w1, nu_next, chi);
-  E_next = -log(uniform_f64(w.w2));
+  E_next = -log_unit(uniform_f64(w.w2));
 }
 
 // Optional record of a pair's coarse numbers, for the consistency harness of
@@ -212,7 +212,7 @@ __device__ __forceinline__ void kd_sample_rec(const LevelDesc& d, uint32_t smp, 
   if (d.x0_kind == 0) x0 = d.x0_a;
   else if (d.x0_kind == 1) x0 = d.x0_a + d.x0_b * nc;
   else x0 = cosine_icdf(uniform_f64(w0.w3));
-  const double E0 = -log(uniform_f64(w0.w2));
+  const double E0 = -log_unit(uniform_f64(w0.w2));
 
   double xf = x0, vf = k.mu + k.sigma * ns, tf = 0.0, tauf = E0 * k.inv_r;
   double cfine = tf + tauf;
@@ -426,7 +426,7 @@ __device__ __forceinline__ void kd_sample_bg_rec(const LevelDesc& d, uint32_t sm
   if (d.x0_kind == 0) x0 = d.x0_a;
   else if (d.x0_kind == 1) x0 = d.x0_a + d.x0_b * nc;
   else x0 = cosine_icdf(uniform_f64(w0.w3));
-  const double E0 = -log(uniform_f64(w0.w2));
+  const double E0 = -log_unit(uniform_f64(w0.w2));
 
   double xf = x0, vf = k.mu + k.sigma * ns, tf = 0.0, Ef = E0;
   double tauf = bg_flight(g, xf, vf, Ef);

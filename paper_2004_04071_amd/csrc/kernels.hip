@@ -710,7 +710,7 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
   if (d.x0_kind == 0) x0 = d.x0_a;
   else if (d.x0_kind == 1) x0 = d.x0_a + d.x0_b * nc;
   else x0 = cosine_icdf(uniform_f64(w0.w3));
-  const double E0 = -log(uniform_f64(w0.w2));
+  const double E0 = -log_unit(uniform_f64(w0.w2));
 
   double xf = x0, vf = k.mu + k.sigma * ns, tf = 0.0, tauf = E0 * k.inv_r;
   double cfine = tf + tauf;
@@ -898,7 +898,7 @@ __device__ __forceinline__ void run_kd_bg_tp(const LevelDesc& d, uint32_t local)
   if (d.x0_kind == 0) x0 = d.x0_a;
   else if (d.x0_kind == 1) x0 = d.x0_a + d.x0_b * nc;
   else x0 = cosine_icdf(uniform_f64(w0.w3));
-  const double E0 = -log(uniform_f64(w0.w2));
+  const double E0 = -log_unit(uniform_f64(w0.w2));
 
   // fine path (wave-uniform)
   double xf = x0, vf = k.mu + k.sigma * ns, tf = 0.0, Ef = E0;
