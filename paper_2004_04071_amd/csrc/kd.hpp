@@ -95,16 +95,16 @@ __device__ __forceinline__ double kd_g(double y, double em) {
   return y < kKdSeriesY ? kd_series<3>(C.g, y) : -(em * (2.0 + em) + 2.0 * y * (1.0 + em));
 }
 
-// e^{-y} - 1 for y >= 0.  Above y = 45, e^{-y} < 3e-20 lies far below half
-// the spacing of doubles next to -1 (2^-54), so every faithfully rounded
-// expm1 returns exactly -1 there.  A wavefront whose lanes all have y > 45
+// e^{-y} - 1 for y >= 0 (expm1_neg of unit_math.hpp).  Above y = 45,
+// e^{-y} < 3e-20 lies far below half the spacing of doubles next to -1
+// (2^-54), so every faithfully rounded expm1 returns exactly -1 there.  A wavefront whose lanes all have y > 45
 // skips the library call; the per-lane select keeps each lane's value the
 // same whichever way its wavefront goes.
 constexpr double kKdExpm1Cut = 45.0;
 
 __device__ __forceinline__ double kd_em(double y) {
   if (__all(y > kKdExpm1Cut)) return -1.0;
-  return y > kKdExpm1Cut ? -1.0 : expm1(-y);
+  return y > kKdExpm1Cut ? -1.0 : expm1_neg(y);
 }
 
 struct KdParams {

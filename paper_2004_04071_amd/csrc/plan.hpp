@@ -29,9 +29,10 @@ __host__ __device__ inline ItemLayout item_layout(uint64_t n_steps, uint64_t n_s
   // item at least one wavefront per SIMD; a few samples of short
   // trajectories are spread over one per lane instead
   o.spl = samples_per_lane((uint32_t)n_steps);
-  while (o.spl > 1 && n_samples < kMinWideTiles * (uint64_t)kLanes * o.spl) o.spl /= 4;
-  // tiles of 64 spl samples (spl = 1, 4 or 16: a power of two)
-  const uint32_t tile_shift = 6u + (o.spl == 16u ? 4u : (o.spl == 4u ? 2u : 0u));
+  while (o.spl > 1 && n_samples < kMinWideTiles * (uint64_t)kLanes * o.spl)
+    o.spl = o.spl > 4u ? o.spl / 4u : 1u;
+  // tiles of 64 spl samples (spl a power of two)
+  const uint32_t tile_shift = 6u + (uint32_t)__builtin_ctz(o.spl);
   o.n_tiles = (uint32_t)((n_samples + ((1ull << tile_shift) - 1)) >> tile_shift);
   o.n_groups = (o.n_tiles + kGroupTiles - 1) / kGroupTiles;
   // a chunk is about kChunkLaneSteps lane-steps of work, but an item keeps at

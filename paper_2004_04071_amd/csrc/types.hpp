@@ -16,8 +16,8 @@
 namespace mlmc {
 
 constexpr int kLanes = 64;                       // gfx950 wavefront
-constexpr int kMaxSamplesPerLane = 16;           // shortest levels: 1024-sample tiles
-constexpr uint32_t kShortLevelSteps = 16;        // from here on: 256-sample tiles
+constexpr uint32_t kTinyLevelSteps = 4;          // below: 2048-sample tiles
+constexpr uint32_t kShortLevelSteps = 16;        // below: 1024-sample tiles; from here on 256
 constexpr uint32_t kLongLevelSteps = 64;         // from here on: 64-sample tiles
 
 // Samples per lane of a tile of a level with n_steps fine steps: the tile's
@@ -27,7 +27,8 @@ constexpr uint32_t kLongLevelSteps = 64;         // from here on: 64-sample tile
 // to one sample per lane).
 constexpr uint64_t kMinWideTiles = 1024;
 __host__ __device__ inline uint32_t samples_per_lane(uint32_t n_steps) {
-  return n_steps >= kLongLevelSteps ? 1u : (n_steps >= kShortLevelSteps ? 4u : 16u);
+  return n_steps >= kLongLevelSteps ? 1u
+       : (n_steps >= kShortLevelSteps ? 4u : (n_steps >= kTinyLevelSteps ? 16u : 32u));
 }
 constexpr int kGroupTiles = 256;                 // tiles per first-stage group
 constexpr int kReduceThreads = 256;

@@ -1,5 +1,6 @@
 // FP64 logarithm and sine/cosine of pi x for the uniforms of the random-number
-// stream, written from their series.  The library versions carry argument
+// stream, and e^{-y} - 1 for the diffusive phases of the KD scheme, written
+// from their series.  The library versions carry argument
 // handling the particle loops never need (their inputs are the 24-bit
 // uniforms (2k+1) 2^-24); these take about a third of the instructions and
 // stay within 2 ulp (checked over every possible input on the host, where the
@@ -77,6 +78,36 @@ __host__ __device__ inline void sincospi_unit(double x, double& s, double& c) {
   const double c0 = (q & 1) ? sp : cp;
   s = (q & 2) ? -s0 : s0;
   c = ((q + 1) & 2) ? -c0 : c0;
+}
+
+// e^{-y} - 1 for 0 <= y <= 700.  y = k ln 2 + r with k the nearest integer
+// to y/ln 2, |r| <= ln(2)/2 (r by a two-part ln 2, exact in its first
+// product); expm1(-r) by its Taylor series to the 15th power (the next term
+// is below 2^-60 of it), and e^{-y} - 1 = 2^-k expm1(-r) + (2^-k - 1) in one
+// rounding (2^-k - 1 is exact).
+__host__ __device__ inline double expm1_neg(double y) {
+  constexpr double kInvLn2 = 1.4426950408889634;
+  constexpr double kLn2Hi = 0.6931471805598903;
+  constexpr double kLn2Lo = 5.497923018708371e-14;
+  const double k = rint(y * kInvLn2);
+  const double x = fma(k, kLn2Lo, fma(k, kLn2Hi, -y));  // -(y - k ln 2)
+  double q = 7.647163731819816e-13;                      // 1/15!
+  q = fma(q, x, 1.1470745597729725e-11);
+  q = fma(q, x, 1.6059043836821613e-10);
+  q = fma(q, x, 2.08767569878681e-09);
+  q = fma(q, x, 2.505210838544172e-08);
+  q = fma(q, x, 2.755731922398589e-07);
+  q = fma(q, x, 2.7557319223985893e-06);
+  q = fma(q, x, 2.48015873015873e-05);
+  q = fma(q, x, 0.0001984126984126984);
+  q = fma(q, x, 0.001388888888888889);
+  q = fma(q, x, 0.008333333333333333);
+  q = fma(q, x, 0.041666666666666664);
+  q = fma(q, x, 0.16666666666666666);
+  q = fma(q, x, 0.5);
+  const double p = fma(x * x, q, x);                     // expm1(x)
+  const double scale = ldexp(1.0, -(int)k);
+  return fma(scale, p, scale - 1.0);
 }
 
 }  // namespace mlmc

@@ -1,7 +1,8 @@
 // Host check of log_unit and sincospi_unit (csrc/unit_math.hpp) over every
 // uniform of the random-number stream, u = (2k+1) 2^-24, k < 2^23: log_unit(u)
-// and sincospi_unit(2u) against long-double references.  Prints the largest
-// errors in units of the last place of the double result.
+// and sincospi_unit(2u) against long-double references; and of expm1_neg on a
+// dense sample of [0, 45].  Prints the largest errors in units of the last
+// place of the double result.
 #include <math.h>
 #include <stdio.h>
 #include <stdint.h>
@@ -40,6 +41,28 @@ int main() {
     if (es > max_sin) max_sin = es;
     if (ec > max_cos) max_cos = ec;
   }
-  printf("%.4Lf %.4Lf %.4Lf %.3Le\n", max_log, max_sin, max_cos, max_log_abs);
+  // e^{-y} - 1 on [0, 45] (the KD scheme's exponents R theta): an even grid of
+  // 2^24 points, 1024 points per binade down to 2^-1000, and the ulps around
+  // every switch of the reduction's k
+  long double max_em = 0;
+  auto em_check = [&](double y) {
+    const long double r = expm1l(-(long double)y);
+    const double e = mlmc::expm1_neg(y);
+    const long double err = r == 0 ? (e == 0 ? 0.0L : 1e30L) : fabsl((long double)e - r) / ulp_of((double)r);
+    if (err > max_em) max_em = err;
+  };
+  for (uint32_t i = 0; i <= (1u << 24); ++i) em_check((double)i * (45.0 / 16777216.0));
+  for (int j = 1; j <= 1000; ++j)
+    for (int i = 0; i < 1024; ++i) em_check(ldexp(1.0 + i / 1024.0, -j));
+  for (int k = 0; k < 66; ++k) {
+    double lo = (k + 0.5) * 0.69314718055994530942, hi = lo;
+    for (int t = 0; t < 64; ++t) {
+      lo = nextafter(lo, 0.0);
+      hi = nextafter(hi, 100.0);
+      if (lo >= 0.0 && lo <= 45.0) em_check(lo);
+      if (hi <= 45.0) em_check(hi);
+    }
+  }
+  printf("%.4Lf %.4Lf %.4Lf %.3Le %.4Lf\n", max_log, max_sin, max_cos, max_log_abs, max_em);
   return 0;
 }
