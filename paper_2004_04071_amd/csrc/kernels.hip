@@ -1252,7 +1252,8 @@ __global__ void __launch_bounds__(256) kd_tp_kernel(const LevelDesc* __restrict_
 // items only and no time-parallel items).
 // ---------------------------------------------------------------------------
 template <typename Real, int P, bool KD>
-__global__ void __launch_bounds__(256) persistent_kernel(const LevelDesc* __restrict__ items,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KD ? 3 : 1)))
+persistent_kernel(const LevelDesc* __restrict__ items,
                                                           const WorkHeader* __restrict__ hdr,
                                                           unsigned int* __restrict__ counter,
                                                           Stats* __restrict__ partials) {
