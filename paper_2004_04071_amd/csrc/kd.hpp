@@ -80,19 +80,31 @@ __device__ __forceinline__ double kd_series(const double (&c)[kKdTerms + 1], dou
 //   kd_h = em + y,   kd_f = 2 em + y (2 + em),   kd_g = -(em (2 + em) + 2 y (1 + em)),
 // so one expm1 per diffusive phase serves eqs. advection and diffusion and
 // the aggregation weights.
+// Branch condition c.  U: c has the same value in every lane (the
+// time-parallel paths walk one path per wavefront on wave-uniform values),
+// so the branch is taken on the scalar unit instead of under an exec mask;
+// the arithmetic on either side is the same.
+template <bool U>
+__device__ __forceinline__ bool when(bool c) {
+  if constexpr (U) return __builtin_amdgcn_readfirstlane((int)c) != 0;
+  else return c;
+}
+
 __device__ __forceinline__ double kd_h(double y, double em) {
   constexpr KdCoefs C = kd_make_coefs();
   return y < kKdSeriesY ? kd_series<2>(C.h, y) : em + y;
 }
 
+template <bool U = false>
 __device__ __forceinline__ double kd_f(double y, double em) {
   constexpr KdCoefs C = kd_make_coefs();
-  return y < kKdSeriesY ? kd_series<3>(C.f, y) : 2.0 * em + y * (2.0 + em);
+  return when<U>(y < kKdSeriesY) ? kd_series<3>(C.f, y) : 2.0 * em + y * (2.0 + em);
 }
 
+template <bool U = false>
 __device__ __forceinline__ double kd_g(double y, double em) {
   constexpr KdCoefs C = kd_make_coefs();
-  return y < kKdSeriesY ? kd_series<3>(C.g, y) : -(em * (2.0 + em) + 2.0 * y * (1.0 + em));
+  return when<U>(y < kKdSeriesY) ? kd_series<3>(C.g, y) : -(em * (2.0 + em) + 2.0 * y * (1.0 + em));
 }
 
 // e^{-y} - 1 for y >= 0 (expm1_neg of unit_math.hpp).  Above y = 45,
@@ -102,9 +114,14 @@ __device__ __forceinline__ double kd_g(double y, double em) {
 // same whichever way its wavefront goes.
 constexpr double kKdExpm1Cut = 45.0;
 
+template <bool U = false>
 __device__ __forceinline__ double kd_em(double y) {
-  if (__all(y > kKdExpm1Cut)) return -1.0;
-  return y > kKdExpm1Cut ? -1.0 : expm1_neg(y);
+  if constexpr (U) {
+    return when<U>(y > kKdExpm1Cut) ? -1.0 : expm1_neg(y);
+  } else {
+    if (__all(y > kKdExpm1Cut)) return -1.0;
+    return y > kKdExpm1Cut ? -1.0 : expm1_neg(y);
+  }
 }
 
 struct KdParams {
@@ -343,6 +360,7 @@ __device__ __forceinline__ double bg_rate(const KdBackground& g, double x) {
 // the root of r0 s + k s^2/2 = E is s = 2E / (r0 + sqrt(r0^2 + 2 k E)) (the
 // square root is the rate at the collision); a flight heading for the kink
 // first spends I1 = s_k (r0 + b)/2 of E on the way there.
+template <bool U = false>
 __device__ __forceinline__ double bg_flight(const KdBackground& g, double x, double v, double E) {
   const double u = x - 1.0;
   const double r0 = bg_rate(g, x);
@@ -352,10 +370,10 @@ __device__ __forceinline__ double bg_flight(const KdBackground& g, double x, dou
   double k1;
   if (g.b1) k1 = (u > 0.0 || (u == 0.0 && v > 0.0)) ? ab * v : -ab * v;
   else k1 = (u > 0.0 || (u == 0.0 && v > 0.0)) ? ab * v : 0.0;
-  if (toward) {
+  if (when<U>(toward)) {
     const double sk = -u / v;
     const double i1 = 0.5 * sk * (r0 + g.b);
-    if (E > i1) {
+    if (when<U>(E > i1)) {
       const double e2 = E - i1;
       const double k2 = g.b1 ? ab * fabs(v) : (v > 0.0 ? ab * v : 0.0);
       return sk + 2.0 * e2 / (g.b + sqrt(g.b * g.b + 2.0 * k2 * e2));
@@ -366,10 +384,11 @@ __device__ __forceinline__ double bg_flight(const KdBackground& g, double x, dou
 
 // int_0^t R(x + v s) ds (t < 0: minus the integral over [t, 0]); exact by
 // the trapezoid rule on each linear piece.
+template <bool U = false>
 __device__ __forceinline__ double bg_rate_integral(const KdBackground& g, double x, double v,
                                                    double t) {
   double sign = 1.0;
-  if (t < 0.0) {
+  if (when<U>(t < 0.0)) {
     x = x + v * t;
     t = -t;
     sign = -1.0;
@@ -377,7 +396,7 @@ __device__ __forceinline__ double bg_rate_integral(const KdBackground& g, double
   const double xe = x + v * t;
   const double u0 = x - 1.0, u1 = xe - 1.0;
   double r;
-  if (u0 * u1 < 0.0) {
+  if (when<U>(u0 * u1 < 0.0)) {
     const double sk = -u0 / v;
     r = 0.5 * sk * (bg_rate(g, x) + g.b) + 0.5 * (t - sk) * (g.b + bg_rate(g, xe));
   } else {
@@ -396,6 +415,7 @@ __device__ __forceinline__ void bg_rate_consts(double R, double sigma, double& i
 
 // eqs. advection and diffusion with the local rate R of the phase (its
 // 1/R and 2 sigma^2/R^2 are returned for the aggregation weights).
+template <bool U = false>
 __device__ __forceinline__ void bg_coeffs(double R, double mu, double sigma, double theta,
                                           double y, double em, double v_next, double& a,
                                           double& dd, double& inv_r, double& c2) {
@@ -403,7 +423,7 @@ __device__ __forceinline__ void bg_coeffs(double R, double mu, double sigma, dou
   bg_rate_consts(R, sigma, inv_r, inv_r2, c2);
   const double dv = v_next - mu;
   a = mu * theta + dv * (-em) * inv_r;
-  const double d2 = c2 * kd_f(y, em) + dv * dv * inv_r2 * kd_g(y, em);
+  const double d2 = c2 * kd_f<U>(y, em) + dv * dv * inv_r2 * kd_g<U>(y, em);
   dd = sqrt(d2 > 0.0 ? d2 : 0.0);
 }
 

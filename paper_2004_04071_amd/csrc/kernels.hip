@@ -819,7 +819,10 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
       kd_coeffs(k, theta_c, yc, kd_em(yc), v_next, ac, ddc);
     }
 
-    // (D) the sums in step order
+    // (D) the sums in step order.  Lane j keeps the sums of the coarse step
+    // that step j ends; the coarse moves follow the pass, their divisions and
+    // square roots taken across the lanes instead of on the serial chain.
+    double num_j = 0.0, den_j = 0.0;
 #pragma unroll 1
     for (uint32_t j = 0; j < cnt; ++j) {
       xf = xf + lane_value(p, j) + lane_value(q, j);
@@ -831,13 +834,20 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
         num += lane_value(B1, j);
         den += lane_value(B2, j);
         if ((exit_m >> j) & 1ull) {
-          if ((upd_m >> j) & 1ull) {
-            const double chi_c = den > 0.0 ? num / sqrt(den) : 0.0;
-            xc = xc + lane_value(pc, j) + (lane_value(ac, j) + lane_value(ddc, j) * chi_c);
-          }
+          num_j = lane == j ? num : num_j;
+          den_j = lane == j ? den : den_j;
           num = 0.0;
           den = 0.0;
         }
+      }
+    }
+    if constexpr (COARSE) {
+      const double chi_c = den_j > 0.0 ? num_j / sqrt(den_j) : 0.0;
+      const double inc = ac + ddc * chi_c;
+#pragma unroll 1
+      for (uint64_t m = upd_m; m != 0; m &= m - 1ull) {
+        const uint32_t j = (uint32_t)__builtin_ctzll(m);
+        xc = xc + lane_value(pc, j) + lane_value(inc, j);
       }
     }
     const double nu_last = lane_value(nu_next, cnt - 1u);
@@ -902,7 +912,7 @@ __device__ __forceinline__ void run_kd_bg_tp(const LevelDesc& d, uint32_t local)
 
   // fine path (wave-uniform)
   double xf = x0, vf = k.mu + k.sigma * ns, tf = 0.0, Ef = E0;
-  double tauf = bg_flight(g, xf, vf, Ef);
+  double tauf = bg_flight<true>(g, xf, vf, Ef);
   double cfine = tf + tauf;
   uint32_t cf = 0, b = 1, steps = 0;
   // coarse path and the state of the pair loop (wave-uniform)
@@ -915,7 +925,7 @@ __device__ __forceinline__ void run_kd_bg_tp(const LevelDesc& d, uint32_t local)
 #pragma unroll 1
   while (!done) {
     if constexpr (COARSE) {
-      if (!in_inner && !((ccoarse < k.T || cfine < k.T) && steps < guard)) break;
+      if (when<true>(!in_inner && !((ccoarse < k.T || cfine < k.T) && steps < guard))) break;
     }
     // (A)
     double nu_next, chi, E_next;
@@ -928,7 +938,7 @@ __device__ __forceinline__ void run_kd_bg_tp(const LevelDesc& d, uint32_t local)
 #pragma unroll 1
     for (uint32_t j = 0; j < (uint32_t)kLanes; ++j) {
       if constexpr (!COARSE) {
-        if (!(cfine < k.T && steps < guard)) {
+        if (when<true>(!(cfine < k.T && steps < guard))) {
           done = true;
           break;
         }
@@ -941,12 +951,12 @@ __device__ __forceinline__ void run_kd_bg_tp(const LevelDesc& d, uint32_t local)
       const double y = rm * theta;
       const double v_next = k.mu + k.sigma * lane_value(nu_next, j);
       double a, dd, inv_r, c2;
-      bg_coeffs(rm, k.mu, k.sigma, theta, y, kd_em(y), v_next, a, dd, inv_r, c2);
+      bg_coeffs<true>(rm, k.mu, k.sigma, theta, y, kd_em<true>(y), v_next, a, dd, inv_r, c2);
       xf = xf + vf * tauf + (a + dd * lane_value(chi, j));
       tf = t_next;
       vf = v_next;
       Ef = lane_value(E_next, j);
-      tauf = bg_flight(g, xf, vf, Ef);
+      tauf = bg_flight<true>(g, xf, vf, Ef);
       cfine = tf + tauf;
       ++cnt;
       if constexpr (!COARSE) {
@@ -991,8 +1001,8 @@ __device__ __forceinline__ void run_kd_bg_tp(const LevelDesc& d, uint32_t local)
 #pragma unroll 1
     for (uint32_t j = 0; j < cnt; ++j) {
       const double c_pre = j == 0 ? cfine0 : lane_value(c_j, j - 1u);
-      if (!in_inner) {  // head of the per-lane loop's outer iteration
-        if (!((ccoarse < k.T || c_pre < k.T) && steps < guard)) {
+      if (when<true>(!in_inner)) {  // head of the per-lane loop's outer iteration
+        if (when<true>(!((ccoarse < k.T || c_pre < k.T) && steps < guard))) {
           done = true;
           break;
         }
@@ -1003,14 +1013,14 @@ __device__ __forceinline__ void run_kd_bg_tp(const LevelDesc& d, uint32_t local)
         first = true;
         in_inner = true;
       }
-      if (c_pre >= k.T && !fine_done) {
+      if (when<true>(c_pre >= k.T && !fine_done)) {
         const double x_pre = j == 0 ? xf0 : lane_value(x_j, j - 1u);
         const double t_pre = j == 0 ? tf0 : lane_value(t_j, j - 1u);
         const double v_pre = j == 0 ? vf0 : k.mu + k.sigma * lane_value(nu_next, j - 1u);
         xf_end = t_pre < k.T ? x_pre + v_pre * (k.T - t_pre) : x_pre;
         fine_done = true;
       }
-      if (!first) {
+      if (when<true>(!first)) {
         num += lane_value(A1, j);
         den += lane_value(A2, j);
       }
@@ -1020,9 +1030,9 @@ __device__ __forceinline__ void run_kd_bg_tp(const LevelDesc& d, uint32_t local)
       if (!fine_done) ++cf;
       ++steps;
       ++taken;
-      if (!(!(lane_value(nfp, j) > end_c_fine) && steps < guard)) {  // the inner loop ends
+      if (when<true>(!(!(lane_value(nfp, j) > end_c_fine) && steps < guard))) {  // the inner loop ends
         in_inner = false;
-        if (ccoarse < k.T) {
+        if (when<true>(ccoarse < k.T)) {
           const double nu_e = lane_value(nu_next, j);
           const double xf_e = lane_value(x_j, j), tf_e = lane_value(t_j, j);
           const double vf_e = k.mu + k.sigma * nu_e;
@@ -1032,13 +1042,13 @@ __device__ __forceinline__ void run_kd_bg_tp(const LevelDesc& d, uint32_t local)
           const double rc = bg_rate(g, xc + vc * tauc);
           const double y = rc * theta;
           double a, dd, ir, cq;
-          bg_coeffs(rc, k.mu, k.sigma, theta, y, kd_em(y), vf_e, a, dd, ir, cq);
+          bg_coeffs<true>(rc, k.mu, k.sigma, theta, y, kd_em<true>(y), vf_e, a, dd, ir, cq);
           xc = xc + vc * tauc + (a + dd * chi_c);
           tc = t_next;
           vc = vf_e;
-          double ec = lane_value(E_next, j) - bg_rate_integral(g, xf_e, vf_e, tc - tf_e);
+          double ec = lane_value(E_next, j) - bg_rate_integral<true>(g, xf_e, vf_e, tc - tf_e);
           ec = ec < 0.0 ? 0.0 : ec;
-          tauc = bg_flight(g, xc, vc, ec);
+          tauc = bg_flight<true>(g, xc, vc, ec);
           ccoarse = tc + tauc;
           ++cc;
         }
