@@ -729,61 +729,87 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
     // inputs of the window's first step that come from the step before it
     const double tauf0 = tauf, vf0 = vf, nu_f0 = nu_f, zeta0 = zeta_prev;
 
-    // (B) the collision-time chain and the coarse steps
+    // (B) the collision-time chain and the coarse steps.  Lane j takes step
+    // j as if every step of the window ended on the grid point after the one
+    // before it (a flight shorter than a grid step, the rule at these rates):
+    // it rebuilds the pending collision from that grid point and its
+    // predecessor's flight number, then finds its own step's grid end.  The
+    // first lane whose grid end differs from the assumed one closes the
+    // window: its step is exact, the steps after it started from the wrong
+    // grid point and are taken again by the next window.  The coarse steps
+    // then go block by block on wave-uniform values, a ballot finding where
+    // each block of fine steps ends.  Every value comes from the operations
+    // of the per-lane loop on the same inputs.
     double theta = 0.0, theta_c = 0.0, pc = 0.0;
     uint64_t first_m = 0, exit_m = 0, upd_m = 0;
     uint32_t cnt = 0;
-#pragma unroll 1
-    for (uint32_t j = 0; j < (uint32_t)kLanes; ++j) {
-      double th;
+    {
+      const double n0 = COARSE ? nf : kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0;
+      const double E_up = __shfl(E_next, (int)(lane == 0 ? 0u : lane - 1u), kLanes);
+      const double n_j = n0 + (double)lane;  // assumed grid end of step j
+      const double c_l = lane == 0 ? cfine : (n_j - 1.0) * k.dtf + E_up * k.inv_r;
+      const double n_true = kd_grid_floor(c_l, k.dtf, k.inv_dtf, k.pow2_f) + 1.0;
+      const double t_next_l = n_true * k.dtf;
+      const double th_l = t_next_l - c_l;
+      const double cn_l = t_next_l + E_next * k.inv_r;  // pending collision after step j
+      const unsigned long long wrong = __ballot(!(n_true == n_j));
+      const uint32_t lim = wrong ? (uint32_t)__builtin_ctzll(wrong) + 1u : (uint32_t)kLanes;
+      double nn_l = 0.0;
       if constexpr (!COARSE) {
-        if (!(cfine < k.T && cf < k.guard)) {
-          done = true;
-          break;
-        }
-        const double t_next = (kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0) * k.dtf;
-        th = t_next - cfine;
-        tf = t_next;
-        tauf = lane_value(E_next, j) * k.inv_r;
-        cfine = tf + tauf;
+        const unsigned long long stop = __ballot(!(c_l < k.T && cf + lane < k.guard));
+        const uint32_t at = stop ? (uint32_t)__builtin_ctzll(stop) : (uint32_t)kLanes;
+        cnt = min(at, lim);
+        done = at < lim;
       } else {
-        if (!in_inner) {  // head of the per-lane loop's outer iteration
-          if (!((ccoarse < k.T || cfine < k.T) && cf < k.guard)) {
-            done = true;
-            break;
+        nn_l = kd_grid_floor(cn_l, k.dtf, k.inv_dtf, k.pow2_f) + 1.0;  // nf after step j
+        cnt = lim;
+        uint32_t j = 0;
+#pragma unroll 1
+        while (j < lim) {
+          if (!in_inner) {  // head of the per-lane loop's outer iteration
+            const double c_h = lane_value(c_l, j);
+            if (!((ccoarse < k.T || c_h < k.T) && cf + j < k.guard)) {
+              done = true;
+              cnt = j;
+              break;
+            }
+            end_c = kd_grid_floor(ccoarse, k.dtc, k.inv_dtc, k.pow2_c) + 1.0;
+            end_c_fine = end_c * (double)k.M;
+            first_m |= 1ull << j;
+            in_inner = true;
           }
-          end_c = kd_grid_floor(ccoarse, k.dtc, k.inv_dtc, k.pow2_c) + 1.0;
-          end_c_fine = end_c * (double)k.M;
-          first_m |= 1ull << j;
-          in_inner = true;
-        }
-        const double t_next = nf * k.dtf;
-        th = t_next - cfine;
-        tf = t_next;
-        tauf = lane_value(E_next, j) * k.inv_r;
-        cfine = tf + tauf;
-        nf = kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0;
-      }
-      theta = lane == j ? th : theta;
-      ++cf;
-      ++cnt;
-      if constexpr (COARSE) {
-        if (!(!(nf > end_c_fine) && cf < k.guard)) {  // the inner loop ends after step j
+          // the inner loop ends after the first step x >= j whose next grid
+          // end passes the coarse step
+          const unsigned long long ends =
+              __ballot(lane >= j && lane < lim &&
+                       !(!(nn_l > end_c_fine) && cf + lane + 1u < k.guard));
+          if (!ends) break;  // the block runs on past the window's exact steps
+          const uint32_t x = (uint32_t)__builtin_ctzll(ends);
           in_inner = false;
-          exit_m |= 1ull << j;
+          exit_m |= 1ull << x;
           if (ccoarse < k.T) {
             const double t_next_c = end_c * k.dtc;
             const double thc = t_next_c - ccoarse;
             const double p_c = vc * (ccoarse - tc);
-            theta_c = lane == j ? thc : theta_c;
-            pc = lane == j ? p_c : pc;
+            theta_c = lane == x ? thc : theta_c;
+            pc = lane == x ? p_c : pc;
             tc = t_next_c;
-            ccoarse = cfine;
-            vc = k.mu + k.sigma * lane_value(nu_next, j);
+            ccoarse = lane_value(cn_l, x);
+            vc = k.mu + k.sigma * lane_value(nu_next, x);
             ++cc;
-            upd_m |= 1ull << j;
+            upd_m |= 1ull << x;
           }
+          j = x + 1u;
         }
+      }
+      theta = lane < cnt ? th_l : 0.0;
+      if (cnt > 0) {
+        const uint32_t last = cnt - 1u;
+        tf = lane_value(t_next_l, last);
+        tauf = lane_value(E_next, last) * k.inv_r;
+        cfine = lane_value(cn_l, last);
+        if constexpr (COARSE) nf = lane_value(nn_l, last);
+        cf += cnt;
       }
     }
     if (cnt == 0) break;
@@ -819,26 +845,52 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
       kd_coeffs(k, theta_c, yc, kd_em(yc), v_next, ac, ddc);
     }
 
-    // (D) the sums in step order.  Lane j keeps the sums of the coarse step
-    // that step j ends; the coarse moves follow the pass, their divisions and
-    // square roots taken across the lanes instead of on the serial chain.
-    double num_j = 0.0, den_j = 0.0;
+    // (D) the sums in step order.  The position increments form one serial
+    // chain (a full window unrolled, so that the lane reads run ahead of
+    // it).  The sums of a coarse block are taken by the lane of the block's
+    // last step in the window, over the block's steps in order, starting
+    // from zero at the block's head or from the sums carried into the window;
+    // the lanes where a block ends keep them, and the coarse moves follow the
+    // pass, their divisions and square roots taken across the lanes.
+    if (cnt == (uint32_t)kLanes) {
+#pragma unroll
+      for (uint32_t j = 0; j < (uint32_t)kLanes; ++j) xf = xf + lane_value(p, j) + lane_value(q, j);
+    } else {
 #pragma unroll 1
-    for (uint32_t j = 0; j < cnt; ++j) {
-      xf = xf + lane_value(p, j) + lane_value(q, j);
-      if constexpr (COARSE) {
-        if (!((first_m >> j) & 1ull)) {
-          num += lane_value(A1, j);
-          den += lane_value(A2, j);
+      for (uint32_t j = 0; j < cnt; ++j) xf = xf + lane_value(p, j) + lane_value(q, j);
+    }
+    double num_j = 0.0, den_j = 0.0;
+    if constexpr (COARSE) {
+      const unsigned long long upto = lane == 63u ? ~0ull : (2ull << lane) - 1ull;  // lanes <= this one
+      const unsigned long long heads = first_m & upto;
+      const bool carried = heads == 0;
+      const uint32_t h = carried ? 0u : 63u - (uint32_t)__clzll((long long)heads);
+      const uint32_t len = lane < cnt ? lane + 1u - h : 0u;
+      uint32_t longest = len;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) longest = max(longest, (uint32_t)__shfl_xor((int)longest, o, kLanes));
+      longest = __builtin_amdgcn_readfirstlane(longest);
+      double s1 = carried ? num : 0.0, s2 = carried ? den : 0.0;
+#pragma unroll 1
+      for (uint32_t o = 0; o < longest; ++o) {
+        const int j = (int)min(h + o, (uint32_t)kLanes - 1u);
+        const double a1 = __shfl(A1, j, kLanes), a2 = __shfl(A2, j, kLanes);
+        const double b1 = __shfl(B1, j, kLanes), b2 = __shfl(B2, j, kLanes);
+        if (o < len) {
+          if (carried || o > 0) {  // every step of the block but its head
+            s1 += a1;
+            s2 += a2;
+          }
+          s1 += b1;
+          s2 += b2;
         }
-        num += lane_value(B1, j);
-        den += lane_value(B2, j);
-        if ((exit_m >> j) & 1ull) {
-          num_j = lane == j ? num : num_j;
-          den_j = lane == j ? den : den_j;
-          num = 0.0;
-          den = 0.0;
-        }
+      }
+      num_j = s1;
+      den_j = s2;
+      if (cnt > 0) {
+        const bool runs_on = !((exit_m >> (cnt - 1u)) & 1ull);
+        num = runs_on ? lane_value(s1, cnt - 1u) : 0.0;
+        den = runs_on ? lane_value(s2, cnt - 1u) : 0.0;
       }
     }
     if constexpr (COARSE) {
