@@ -1148,9 +1148,10 @@ template <typename Real, int P, int KIND>
 __device__ __forceinline__ void run_unit(const LevelDesc& d, uint32_t unit,
                                          Stats* __restrict__ partials) {
   const bool wide = (d.flags & kFlagWide) != 0;
-  // one trajectory per lane on the long levels (64-sample tiles)
+  // one trajectory per lane where a tile holds fewer samples per lane than P
+  // (the long levels' 64-sample tiles, and the narrowed tiles of small items)
   constexpr int P1 = 1;
-  if (d.spl == 1) {
+  if (d.spl < (uint32_t)P) {
     if (wide) run_tile_impl<Real, P1, KIND, true>(d, unit, partials);
     else run_tile_impl<Real, P1, KIND, false>(d, unit, partials);
   } else {

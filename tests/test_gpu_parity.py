@@ -260,6 +260,29 @@ def test_estimate_bitwise_across_modes_and_tunings():
         assert _key(r) == _key(base)
 
 
+# Level 0 in tiles of 1, 2, 8 and 32 samples per lane and level 1 in tiles
+# of 4 and 16 (the item's size picks the width): every particles-per-thread
+# shape runs each sample once, with the statistics of one trajectory per lane.
+@pytest.mark.parametrize("level,n", [(0, 100_000), (0, 300_000), (0, 1_000_000),
+                                     (0, 3_000_000), (1, 500_000), (1, 2_000_000)])
+def test_particles_per_thread_on_every_tile_width(level, n):
+    prob = W.cfg2(eps=0.05, stream_id=62)
+    ref = None
+    try:
+        for ppt in (1, 2, 4):
+            pkg.mlmc_ap_set_tuning(ppt=ppt)
+            st = pkg.mlmc_ap_simulate_level(prob, level, 0, n)
+            torch.cuda.synchronize()
+            say("level", level, "n", n, "ppt", ppt, "mean dQ", st["mean_dq"])
+            assert st["n"] == n
+            if ref is None:
+                ref = st
+            else:
+                assert st == ref, (ppt, st, ref)
+    finally:
+        pkg.mlmc_ap_set_tuning(ppt=1)
+
+
 def test_graph_replays_match_eager():
     prob = W.cfg2(eps=0.2, stream_id=9)
     eager = pkg.mlmc_ap_estimate(prob, 5e-3, pkg.options(batched=2))
