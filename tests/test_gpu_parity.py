@@ -174,12 +174,15 @@ def test_wide_thresholds_used():
 
 @pytest.mark.parametrize("level,n", [(0, 1), (0, 63), (0, 65), (0, 1024 * 1024 - 1),
                                      (0, 1024 * 1024 + 1), (0, 1025 * 1024 + 3),
+                                     (0, 2048 * 1024 + 7), (1, 1024 * 1024 + 5),
                                      (4, 1024 * 256 + 255), (5, 63), (5, 65), (5, 256 * 64),
                                      (5, 256 * 64 + 1), (5, 1025 * 64 + 3)])
 def test_tile_and_group_boundaries(level, n):
-    """Ragged tiles of every width (1024 samples below 16 fine steps, 256 below
-    64, 64 from there on, narrowed for items of fewer than 1024 such tiles),
-    one full 256-tile reduction group, and more than one group."""
+    """Ragged tiles of every width (2048 samples below 4 fine steps, 1024 below
+    16, 256 below 64, 64 from there on; an item of fewer than 1024 such tiles
+    takes a quarter of the width, repeatedly: 512-sample tiles for level 0
+    near 2^20 samples), one full 256-tile reduction group, and more than one
+    group."""
     prob = W.cfg2(eps=0.3)
     st = pkg.mlmc_ap_simulate_level(prob, level, 5, n)
     ref = O.simulate(prob, level, 5, n)
