@@ -530,6 +530,9 @@ __device__ __forceinline__ void run_kd_unit(const LevelDesc& d, uint32_t unit,
 constexpr int kTpBlocks = 49;                 // Philox blocks per 64-step chunk
 constexpr int kTpWords = 4 * kTpBlocks;       // 196 words; step j reads words 3j+2..3j+4
 constexpr int kTpWavesPerBlock = 4;           // kernels here run <= 256 threads
+// A KD window whose guessed collision-time chain holds for fewer steps than
+// this walks the chain serially instead.
+constexpr uint32_t kTpMinGuessed = 16;
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -755,7 +758,63 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
       const unsigned long long wrong = __ballot(!(n_true == n_j));
       const uint32_t lim = wrong ? (uint32_t)__builtin_ctzll(wrong) + 1u : (uint32_t)kLanes;
       double nn_l = 0.0;
-      if constexpr (!COARSE) {
+      if (lim < kTpMinGuessed) {
+        // flights longer than a grid step are common here (a low collision
+        // rate): the window walks the chain step by step instead
+#pragma unroll 1
+        for (uint32_t j = 0; j < (uint32_t)kLanes; ++j) {
+          double th;
+          if constexpr (!COARSE) {
+            if (!(cfine < k.T && cf < k.guard)) {
+              done = true;
+              break;
+            }
+            const double t_next = (kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0) * k.dtf;
+            th = t_next - cfine;
+            tf = t_next;
+            tauf = lane_value(E_next, j) * k.inv_r;
+            cfine = tf + tauf;
+          } else {
+            if (!in_inner) {  // head of the per-lane loop's outer iteration
+              if (!((ccoarse < k.T || cfine < k.T) && cf < k.guard)) {
+                done = true;
+                break;
+              }
+              end_c = kd_grid_floor(ccoarse, k.dtc, k.inv_dtc, k.pow2_c) + 1.0;
+              end_c_fine = end_c * (double)k.M;
+              first_m |= 1ull << j;
+              in_inner = true;
+            }
+            const double t_next = nf * k.dtf;
+            th = t_next - cfine;
+            tf = t_next;
+            tauf = lane_value(E_next, j) * k.inv_r;
+            cfine = tf + tauf;
+            nf = kd_grid_floor(cfine, k.dtf, k.inv_dtf, k.pow2_f) + 1.0;
+          }
+          theta = lane == j ? th : theta;
+          ++cf;
+          ++cnt;
+          if constexpr (COARSE) {
+            if (!(!(nf > end_c_fine) && cf < k.guard)) {  // the inner loop ends after step j
+              in_inner = false;
+              exit_m |= 1ull << j;
+              if (ccoarse < k.T) {
+                const double t_next_c = end_c * k.dtc;
+                const double thc = t_next_c - ccoarse;
+                const double p_c = vc * (ccoarse - tc);
+                theta_c = lane == j ? thc : theta_c;
+                pc = lane == j ? p_c : pc;
+                tc = t_next_c;
+                ccoarse = cfine;
+                vc = k.mu + k.sigma * lane_value(nu_next, j);
+                ++cc;
+                upd_m |= 1ull << j;
+              }
+            }
+          }
+        }
+      } else if constexpr (!COARSE) {
         const unsigned long long stop = __ballot(!(c_l < k.T && cf + lane < k.guard));
         const uint32_t at = stop ? (uint32_t)__builtin_ctzll(stop) : (uint32_t)kLanes;
         cnt = min(at, lim);
@@ -802,14 +861,16 @@ __device__ __forceinline__ void run_kd_tp(const LevelDesc& d, uint32_t local) {
           j = x + 1u;
         }
       }
-      theta = lane < cnt ? th_l : 0.0;
-      if (cnt > 0) {
-        const uint32_t last = cnt - 1u;
-        tf = lane_value(t_next_l, last);
-        tauf = lane_value(E_next, last) * k.inv_r;
-        cfine = lane_value(cn_l, last);
-        if constexpr (COARSE) nf = lane_value(nn_l, last);
-        cf += cnt;
+      if (lim >= kTpMinGuessed) {
+        theta = lane < cnt ? th_l : 0.0;
+        if (cnt > 0) {
+          const uint32_t last = cnt - 1u;
+          tf = lane_value(t_next_l, last);
+          tauf = lane_value(E_next, last) * k.inv_r;
+          cfine = lane_value(cn_l, last);
+          if constexpr (COARSE) nf = lane_value(nn_l, last);
+          cf += cnt;
+        }
       }
     }
     if (cnt == 0) break;
