@@ -323,8 +323,12 @@ mlmc_ap_status mlmc_ap_server_run_trace(mlmc_ap_server* srv, int32_t n, const do
     }
     if (idle) {
       if (next < n) {
+        // sleep through most of the gap and poll the clock for the rest: a
+        // sleep wakes tens of microseconds late, and the request's latency
+        // counts from its arrival
         const double wait = arrival_s[next] - (now_s() - t0);
-        if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.01)));
+        if (wait > 5e-4)
+          std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait - 3e-4, 0.01)));
       }
       continue;
     }
