@@ -286,6 +286,28 @@ def test_particles_per_thread_on_every_tile_width(level, n):
         pkg.mlmc_ap_set_tuning(ppt=1)
 
 
+# Every launch shape the tuning accepts, on the three particle kernels (FP32
+# and FP64 splitting, KD with its time-parallel warm-up): the same estimate,
+# bit for bit, as the default shape.
+SHAPES = [(64, 1, 1), (64, 4, 2), (128, 2, 4), (128, 4, 8), (256, 2, 1), (256, 4, 8)]
+
+
+@pytest.mark.parametrize("name,prob,tol", [
+    ("fp32", W.cfg2(eps=0.05, stream_id=63), 5e-3),
+    ("fp64", dict(W.cfg2(eps=0.05, stream_id=64), fp64_state=1), 5e-3),
+    ("kd", W.cfg_kd(eps=0.01, stream_id=65), 5e-3),
+], ids=["fp32", "fp64", "kd"])
+def test_estimate_bitwise_across_launch_shapes(name, prob, tol):
+    base = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=0, block=256, ppt=1,
+                                                       waves_per_simd=8))
+    say(name, "estimate", base["estimate"], "N", base["N"])
+    for b, p, w in SHAPES:
+        for batched in (0, -1):
+            r = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=batched, block=b, ppt=p,
+                                                            waves_per_simd=w))
+            assert _key(r) == _key(base), (name, b, p, w, batched)
+
+
 def test_graph_replays_match_eager():
     prob = W.cfg2(eps=0.2, stream_id=9)
     eager = pkg.mlmc_ap_estimate(prob, 5e-3, pkg.options(batched=2))
