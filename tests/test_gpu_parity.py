@@ -292,19 +292,22 @@ def test_particles_per_thread_on_every_tile_width(level, n):
 SHAPES = [(64, 1, 1), (64, 4, 2), (128, 2, 4), (128, 4, 8), (256, 2, 1), (256, 4, 8)]
 
 
-@pytest.mark.parametrize("name,prob,tol", [
-    ("fp32", W.cfg2(eps=0.05, stream_id=63), 5e-3),
-    ("fp64", dict(W.cfg2(eps=0.05, stream_id=64), fp64_state=1), 5e-3),
-    ("kd", W.cfg_kd(eps=0.01, stream_id=65), 5e-3),
-], ids=["fp32", "fp64", "kd"])
-def test_estimate_bitwise_across_launch_shapes(name, prob, tol):
+@pytest.mark.parametrize("name,prob,tol,extra", [
+    ("fp32", W.cfg2(eps=0.05, stream_id=63), 5e-3, {}),
+    ("fp64", dict(W.cfg2(eps=0.05, stream_id=64), fp64_state=1), 5e-3, {}),
+    ("kd", W.cfg_kd(eps=0.01, stream_id=65), 5e-3, {}),
+    ("fp32_heuristic_levels", W.cfg2(eps=0.01, stream_id=66), 3e-3,
+     dict(level_select=pkg.LEVELS_HEURISTIC)),
+    ("kd_b1", W.cfg_bg(W.BG_B1, 10.0, 1000.0, L=8, stream_id=67), 1e-3, {}),
+], ids=["fp32", "fp64", "kd", "fp32_heuristic_levels", "kd_b1"])
+def test_estimate_bitwise_across_launch_shapes(name, prob, tol, extra):
     base = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=0, block=256, ppt=1,
-                                                       waves_per_simd=8))
+                                                       waves_per_simd=8, **extra))
     say(name, "estimate", base["estimate"], "N", base["N"])
     for b, p, w in SHAPES:
         for batched in (0, -1):
             r = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=batched, block=b, ppt=p,
-                                                            waves_per_simd=w))
+                                                            waves_per_simd=w, **extra))
             assert _key(r) == _key(base), (name, b, p, w, batched)
 
 
