@@ -347,6 +347,35 @@ def test_estimate_matches_oracle_and_closed_form():
         assert g["m2_dq"] == pytest.approx(o["m2_dq"], rel=1e-3)
 
 
+def test_single_level_hierarchy_estimate():
+    """L = 0: the hierarchy is level 0 alone, the sum of eqs. Nopt1/Noptj has
+    one term, and N_0 = ceil(2/tol^2 V_0) from the warm-up's variance; the
+    device-planned and host-planned forms agree bit for bit, and the estimate
+    is within 4 standard errors of the exact E[Q_0]."""
+    prob = dict(W.cfg2(eps=0.05, stream_id=68), L=0)
+    tol = 5e-3
+    dev = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=0))
+    host = pkg.mlmc_ap_estimate(prob, tol, pkg.options(batched=3))
+    assert _key(dev) == _key(host)
+    assert dev["device_planned"] >= 1 and len(dev["N"]) == 1 and dev["converged"]
+    exact = CF.level_second_moment(prob, 0)
+    say("L=0: N %s estimate %.8f exact %.8f sd %.2e" % (dev["N"], dev["estimate"], exact,
+                                                        math.sqrt(dev["var_estimator"])))
+    assert abs(dev["estimate"] - exact) <= 4.0 * math.sqrt(dev["var_estimator"])
+    assert dev["var_estimator"] <= 0.5 * tol ** 2 * (1.0 + 1e-12)
+
+
+def test_estimate_with_warm_up_enough():
+    """A tolerance the warm-up already meets: the device-planned top-up has no
+    work (an empty table through the particle and reduction kernels), and the
+    result is the warm-up's, as when the host plans."""
+    prob = W.cfg2(eps=0.05, stream_id=69)
+    dev = pkg.mlmc_ap_estimate(prob, 1.0, pkg.options(batched=0))
+    host = pkg.mlmc_ap_estimate(prob, 1.0, pkg.options(batched=3))
+    assert _key(dev) == _key(host)
+    assert all(n == 1000 for n in dev["N"]) and dev["converged"]
+
+
 def test_plain_mc_estimate():
     prob = W.cfg2(eps=0.1, stream_id=41)
     res = pkg.mlmc_ap_plain_mc(prob, 1e-2)
