@@ -693,10 +693,14 @@ __device__ __forceinline__ Stats tp_tile_record(const LevelDesc& d, uint32_t til
 // position increment, its coefficients of eqs. advection and diffusion and
 // its aggregation weights depend only on its diffusive length theta and on
 // random numbers.  Per window: (A) lane j draws the numbers of step j; (B)
-// the chain is walked on wave-uniform values, lane j keeping theta of step j
-// (and, where step j ends a coarse step, that coarse step's theta and flight
-// increment); (C) every lane evaluates its step; (D) the increments and the
-// aggregation sums are added in step order on wave-uniform values.  Every
+// the chain is taken across the lanes (each lane guesses where its
+// predecessor's step ended and checks the guess; a window whose guesses fail
+// early walks the chain serially), lane j keeping theta of step j, and the
+// coarse steps follow block by block (where step j ends a coarse step, lane j
+// keeps that coarse step's theta and flight increment); (C) every lane
+// evaluates its step; (D) the position increments are added in step order on
+// wave-uniform values, each coarse block's aggregation sums by the lane where
+// the block ends, in step order.  Every
 // quantity is computed with the operations of the per-lane loop
 // (kd_sample_rec) on the same inputs, and the sums are taken in its order, so
 // both forms give bitwise identical paths.
