@@ -127,6 +127,12 @@ KD_CASES = [
     ("kd_pair_m4_l4", dict(W.cfg_kd(eps=0.05, stream_id=99), M=4, L=5), 4, 1, 90, False),
     ("kd_cosine_x0_l6", dict(W.cfg_kd(eps=0.05, stream_id=100), x0_kind=2), 6, 0, 80, False),
     ("kd_bg_a0_l10", W.cfg_bg(a=0.0, b=1000.0, L=12, stream_id=101), 10, 0, 64, False),
+    # collision rates where some windows keep their guessed chain and others
+    # walk it serially (flights crossing grid points now and then)
+    ("kd_pair_l8_mixed_windows", W.cfg_kd(eps=0.05, stream_id=105), 8, 0, 100, False),
+    ("kd_pair_l8_mixed_windows_2", W.cfg_kd(eps=0.03, stream_id=106), 8, 3, 70, False),
+    ("kd_single_l8_mixed_windows", W.cfg_kd(eps=0.1, stream_id=107), 8, 0, 64, True),
+    ("kd_pair_l8_windows_cut_short", W.cfg_kd(eps=0.02, stream_id=108), 8, 0, 80, False),
 ]
 
 
